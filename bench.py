@@ -1,0 +1,164 @@
+"""Throughput benchmark: sample-shift DOF-solves per second on one MI355X.
+
+One step = one grf_sample call on the 64x64 random-length lattice (4096
+vertices, 8064 edges, h = 1/256 rounded mesh, ~2.07M DOFs), kappa = 10,
+beta = 0.6, quadrature step 0.3 (116 shifts), 256 samples: noise, every
+shift's condensed solve, accumulation and the output layout, with the inputs
+(graph, mesh) resident on the device.  value = N_dof * shifts * samples /
+seconds per step.
+
+Prints one JSON line (rank 0).  Also reports the roofline of the dominant
+kernel (HIP-event durations recorded inside the timed steps) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sample-shift DOF-solves/sec at 1e-6 rel err: learned+batched vs plain, 1 GPU"
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, FMA = 2 flops
+FLOPS_PER_UNIT = {"acc_fwd": 4.0, "acc_bwd": 4.0, "ends_fwd": 2.0, "ends_bwd": 2.0}  # per (interior DOF, shift, sample)
+
+
+def cpu_baseline(cfg, L: int, S: int, n_shift_sample: int = 3, n_samp: int = 4) -> dict:
+    """Time the FP64 oracle (numpy Philox noise, one sparse LU per shift) on a
+    bounded sample and extrapolate the whole job linearly:
+        t_job = S t_noise + L (t_factor + S t_rhs),
+    with t_factor and t_rhs fitted from solves with 1 and n_samp right-hand sides."""
+    import numpy as np
+
+    from oracle import mesh as omesh
+    from oracle import noise as onoise
+    from oracle import quadrature as oquad
+    from oracle import solve as osolve
+
+    g = cfg["graph"]
+    m = omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    ML = omesh.lumped_mass(m)
+    t0 = time.perf_counter()
+    W = onoise.white_noise(ML, cfg["seed"], n_samp)
+    t_noise = (time.perf_counter() - t0) / n_samp
+    _, cI, cL = oquad.shifts(cfg["beta"], cfg["quad_step"])
+    idx = np.linspace(0, len(cI) - 1, n_shift_sample).round().astype(int)
+    times = {}
+    for ns in (1, n_samp):
+        t0 = time.perf_counter()
+        for i in idx:
+            osolve.solve_shifted(m, cfg["kappa"], float(cI[i]), float(cL[i]), W[:ns])
+        times[ns] = (time.perf_counter() - t0) / n_shift_sample
+    t_rhs = max(0.0, (times[n_samp] - times[1]) / (n_samp - 1))
+    t_factor = max(0.0, times[1] - t_rhs)
+    t_job = S * t_noise + L * (t_factor + S * t_rhs)
+    return {"value": m.n_dof * L * S / t_job, "unit": "DOF-shift-solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (numpy Philox noise, scipy splu per shift, 1 thread) on the same graph: noise for "
+                      f"{n_samp} samples ({t_noise:.2f} s/sample) and {n_shift_sample} shifts solved with 1 and "
+                      f"{n_samp} right-hand sides (factor+assemble {t_factor:.2f} s/shift, {t_rhs:.3f} s/rhs); "
+                      f"whole job ({S} samples x {L} shifts) extrapolated as S*t_noise + L*(t_factor + S*t_rhs)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--beta", type=float, default=0.6)
+    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--sweep-block", type=int, default=0)
+    ap.add_argument("--shift-block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built "
+              "(samples shard with no communication; see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2605_02670_amd import grf
+    from workloads import config_c2
+
+    grf.load()
+    torch.cuda.set_device(0)
+    cfg = config_c2(beta=args.beta, n_samples=args.samples)
+    g = cfg["graph"]
+    G = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    S = cfg["n_samples"]
+    km, kp, k = G.shift_count(cfg["beta"], cfg["quad_step"])
+    L = km + kp + 1
+    out = torch.empty((S, G.n_dof), dtype=torch.float64, device="cuda")
+    kw = dict(tol=cfg["tol"], sweep_block=args.sweep_block, shift_block=args.shift_block)
+
+    def step(timing=False):
+        _, st = G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=out, timing=timing, **kw)
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step(timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+
+    value = G.n_dof * L * S / dt
+    # dominant kernel over the timed steps (HIP events on the library's launch stream)
+    ktot = {k_: sum(s["kernel_ms"][k_] for s in stats) for k_ in stats[0]["kernel_ms"]}
+    kl = {k_: sum(s["kernel_launches"][k_] for s in stats) for k_ in stats[0]["kernel_launches"]}
+    dom = max(ktot, key=ktot.get)
+    roof = None
+    if dom in FLOPS_PER_UNIT and kl[dom] > 0:
+        avg_ms = ktot[dom] / kl[dom]
+        launches_per_step = kl[dom] / args.steps
+        flops = FLOPS_PER_UNIT[dom] * G.n_interior * L * S / launches_per_step
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": f"k_sweep_{dom}", "achieved": achieved,
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": None, "avg_launch_ms": avg_ms}
+
+    # correctness at full size: <diag M_L, u> = q_k(kappa^2) <1, W> per sample (any size, exact identity)
+    from oracle import quadrature as oquad
+
+    w = G.noise(8, cfg["seed"]).cpu().numpy()
+    u = out[:8].cpu().numpy()
+    from oracle import mesh as omesh
+
+    m = omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    ML = omesh.lumped_mass(m)
+    q = oquad.q_k(cfg["kappa"] ** 2, cfg["beta"], cfg["quad_step"])
+    lhs, rhs = (u * ML).sum(1), q * w.sum(1)
+    cons_err = float(np.max(np.abs(lhs - rhs)) / np.max(np.abs(rhs)))
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, L, S)
+    line = {
+        "metric": METRIC, "value": value, "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"lattice64x64 U[0.5,1.5] h=1/256 kappa=10 beta={cfg['beta']} k=0.3 "
+                               f"S={S} plain-fp64-jacobi",
+                   "n_dof": G.n_dof, "n_interior": G.n_interior, "shifts": L, "samples": S,
+                   "shift_block": stats[0]["shift_block"], "sweep_block": stats[0]["sweep_block"],
+                   "parallelism": "1 GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {k_: v / args.steps for k_, v in ktot.items() if v > 0},
+        "pcg": {"max_iterations": max(s["max_iterations"] for s in stats),
+                "mean_iterations": stats[0]["total_iterations"] / max(1, stats[0]["n_systems"])},
+        "check": {"conservation_rel_err": cons_err},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

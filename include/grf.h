@@ -1,0 +1,209 @@
+/*
+ * grf.h -- C ABI of libgrf, a sampler for Gaussian random fields on metric
+ * graphs for AMD Instinct MI355X (gfx950).
+ *
+ * A field solves the fractional SPDE (kappa^2 - Delta)^beta u = W on a metric
+ * graph (paper: eq. fractional_spde).  A sample is the sinc-quadrature sum of
+ * shifted lumped-mass finite-element solves
+ *     u = sum_{l=-K^-}^{K^+} ((c_I + c_L kappa^2) M_L + c_L G)^{-1} W,
+ * (paper: eq. balakrishnan_quadrature, eq. coefficients, eq. spde_approx_fem,
+ * with the kappa^2 M term of the discretised operator written out), driven by
+ * lumped white noise W = M_L^{1/2} xi (paper: eq. wh_def and "Mass Lumping").
+ * Each shifted solve is done by static condensation onto the graph vertices
+ * (paper: eq. global_schur and "Phase 3"-"Phase 5").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: every call returns a grf_status; no C++ exception crosses the
+ *   ABI.  grf_last_error() returns a thread-local description of the most
+ *   recent failure on the calling thread.
+ * - Memory: host pointers are named "host", device pointers "device".  The
+ *   caller owns every pointer it passes; the library copies what it keeps.
+ *   Device pointers must be HIP allocations on the device the graph was
+ *   created on.
+ * - Streams: work is enqueued on opts->stream (NULL = the null stream) and
+ *   the call returns after that stream has finished it (the library needs
+ *   the solver's convergence flags on the host).  A graph handle must not be
+ *   used from two threads at once.
+ * - DOF order ("canonical order"): interior DOFs first, edge-major in input
+ *   edge order, each edge's m_e = n_e - 1 interior nodes running from the
+ *   tail vertex u_e (x = 0) to the head vertex v_e (x = l_e); then vertex v
+ *   at index n_interior + v (paper: Phase 2, W = [W_I,1 ... W_I,|E| W_Gamma],
+ *   and "Quadrature Accumulation and Global Assembly").
+ * - Mesh (paper: "Phase 1: Initialization"): n_e = ceil(l_e / h) elements
+ *   (GRF_MESH_CEIL) or n_e = floor(l_e / h + 1/2) (GRF_MESH_ROUND), at least
+ *   1 (2 for a self-loop), h_e = l_e / n_e.
+ */
+#ifndef GRF_H
+#define GRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum grf_status {
+    GRF_OK = 0,
+    GRF_EINVAL = -1,  /* an argument is out of its documented domain */
+    GRF_ENOMEM = -2,  /* device or host allocation failed */
+    GRF_EDEVICE = -3, /* a HIP call failed (message names it) */
+    GRF_ENOCONV = -4, /* some vertex Schur PCG hit maxit; output still written */
+    GRF_EUNSUP = -5   /* a documented-but-unsupported combination */
+} grf_status;
+
+/* grf_graph_create flags */
+#define GRF_MESH_CEIL 0u  /* n_e = ceil(l_e/h)  (paper, Phase 1) */
+#define GRF_MESH_ROUND 1u /* n_e = floor(l_e/h + 1/2) */
+
+/* grf_opts.precision */
+#define GRF_PREC_FP64 0  /* every step in FP64 */
+#define GRF_PREC_MIXED 1 /* FP32 edge sweeps, FP64 Schur/PCG/residual/accumulation, refinement */
+
+/* grf_opts.precond */
+#define GRF_PRECOND_JACOBI 0  /* diagonal of the vertex Schur complement */
+#define GRF_PRECOND_LEARNED 1 /* learned diagonal-plus-neighbour operator (opts->learned) */
+
+typedef struct grf_graph grf_graph;
+typedef struct grf_learned grf_learned;
+
+/* Kernel classes of grf_stats.kernel_ms / kernel_launches. */
+enum grf_kernel_id {
+    GRF_K_NOISE = 0,     /* lumped white noise */
+    GRF_K_COEFF = 1,     /* per-(shift, edge) Thomas rows and Schur blocks */
+    GRF_K_ENDS_FWD = 2,  /* condensed-rhs sweep, head ends */
+    GRF_K_ENDS_BWD = 3,  /* condensed-rhs sweep, tail ends */
+    GRF_K_CONDENSE = 4,  /* vertex right-hand sides */
+    GRF_K_PCG = 5,       /* vertex Schur PCG */
+    GRF_K_SCATTER = 6,   /* vertex solutions to the sample layout */
+    GRF_K_ACC_FWD = 7,   /* interior recovery, forward part + accumulation */
+    GRF_K_ACC_BWD = 8,   /* interior recovery, backward part + accumulation */
+    GRF_K_LAYOUT = 9,    /* layout changes and fills */
+    GRF_K_MIXED = 10,    /* mixed-precision residual and refinement kernels */
+    GRF_K_LEARNED = 11,  /* learned preconditioner */
+    GRF_K_COUNT = 12
+};
+
+/* Solver statistics, filled when grf_opts.stats is non-NULL (host struct). */
+typedef struct grf_stats {
+    int32_t n_shifts;           /* quadrature nodes used */
+    int32_t n_systems;          /* vertex Schur systems solved (shifts x samples) */
+    int32_t n_unconverged;      /* systems that hit maxit */
+    int32_t max_iterations;     /* largest PCG iteration count */
+    int64_t total_iterations;   /* sum over systems */
+    double max_rel_residual;    /* max ||g - S u||_2 / ||g||_2 over systems */
+    int32_t refine_steps;       /* mixed precision: refinement sweeps run */
+    int32_t shift_block;        /* shifts processed per pass (as planned) */
+    int32_t sweep_block;        /* shifts held per wavefront in the sweeps */
+    int32_t reserved;
+    double kernel_ms[12];       /* with opts.timing: summed HIP-event time per grf_kernel_id */
+    int32_t kernel_launches[12];/* with opts.timing: launches per grf_kernel_id */
+} grf_stats;
+
+typedef struct grf_opts {
+    double tol;            /* PCG: stop when ||g - S u||_2 <= tol ||g||_2 on the
+                              recomputed residual; default 1e-12 */
+    int32_t maxit;         /* PCG iteration cap per system; default 10000 */
+    int32_t precision;     /* GRF_PREC_*; default GRF_PREC_FP64 */
+    int32_t precond;       /* GRF_PRECOND_*; default GRF_PRECOND_JACOBI */
+    int32_t k_minus;       /* quadrature limits; < 0 selects the paper's rule */
+    int32_t k_plus;        /*   K^- = ceil(pi^2/(4k^2 beta)), K^+ = ceil(pi^2/(4k^2(1-beta))) */
+    int32_t shift_block;   /* shifts per pass; 0 = plan from a memory budget */
+    int32_t sweep_block;   /* shifts per wavefront in the sweeps: 0 (auto), 8, 16, 32, 64 */
+    int32_t refine;        /* mixed precision: max refinement sweeps; < 0 = default (2) */
+    int32_t timing;        /* 1: time every kernel with HIP events into stats->kernel_ms */
+    int32_t reserved0;
+    int64_t sample_offset; /* global index of the first sample (noise key) */
+    void *stream;          /* hipStream_t; NULL = null stream */
+    const grf_learned *learned; /* required when precond = GRF_PRECOND_LEARNED */
+    grf_stats *stats;      /* optional output, host */
+} grf_opts;
+
+/* Fill *opts with the defaults listed above. */
+void grf_opts_init(grf_opts *opts);
+
+/*
+ * Create a graph and its mesh (paper: "Phase 1: Initialization").
+ *   n_vertices  |V| >= 1
+ *   n_edges     |E| >= 0
+ *   edges       host, int64 [n_edges][2], 0-based (tail u_e, head v_e);
+ *               self-loops and multi-edges are allowed
+ *   lengths     host, float64 [n_edges], finite and > 0
+ *   h           target mesh size, finite and > 0
+ *   flags       GRF_MESH_CEIL or GRF_MESH_ROUND
+ *   out         receives the handle; it owns device copies of the mesh
+ * Errors: GRF_EINVAL for a bad size, endpoint, length or h, or a vertex with
+ * no incident edge (its lumped mass is 0 and the shifted system singular).
+ * Uses the current HIP device.
+ */
+int grf_graph_create(int64_t n_vertices, int64_t n_edges, const int64_t *edges,
+                     const double *lengths, double h, uint32_t flags, grf_graph **out);
+
+/* Sizes of the canonical DOF vector.  dof_offsets (host, int64 [n_edges+1],
+ * may be NULL) receives the first interior DOF of every edge. */
+int grf_graph_info(const grf_graph *g, int64_t *n_dof, int64_t *n_interior, int64_t *dof_offsets);
+
+/* Release a graph and every device buffer it holds.  NULL is accepted. */
+int grf_graph_destroy(grf_graph *g);
+
+/*
+ * Quadrature limits for (beta, quad_step) on this graph: quad_step == 0
+ * selects the paper's step k = -1/(beta ln h); opts->k_minus/k_plus >= 0
+ * override the paper's limits (paper: "Strong error" subsection).  Host only.
+ */
+int grf_shift_count(const grf_graph *g, double beta, double quad_step, const grf_opts *opts,
+                    int32_t *k_minus, int32_t *k_plus, double *step_used);
+
+/*
+ * Lumped white noise W[s][j] = sqrt(M_L[j,j]) * Z(seed, sample_offset + s, j)
+ * (paper: eq. wh_def with R = M_L^{1/2}).  Z is Philox4x64-10 with key
+ * (seed, global sample index) and counter (j/4, 0, 0, 0) followed by the
+ * fixed-order Box-Muller transform specified in the project documentation;
+ * the same (seed, sample, j) always gives the same bits.
+ *   out   device, float64 [n_samples][n_dof], canonical order
+ */
+int grf_noise(grf_graph *g, int64_t n_samples, uint64_t seed, double *out, const grf_opts *opts);
+
+/*
+ * Draw n_samples fields: u[s] = sum_l A^(l)^{-1} W[s] with
+ * A^(l) = (c_I^(l) + c_L^(l) kappa^2) M_L + c_L^(l) G, y_l = l k,
+ * c_I = pi/(2 k sin(pi beta)) e^{-2 beta y_l}, c_L = c_I e^{2 y_l}, l
+ * increasing from -K^- to K^+ (paper: eq. coefficients, eq. spde_approx_fem).
+ *   kappa      > 0
+ *   beta       in (0, 1)
+ *   quad_step  k > 0, or 0 for the paper's k = -1/(beta ln h)
+ *   out        device, float64 [n_samples][n_dof], canonical order
+ * Returns GRF_ENOCONV (with out written) if a Schur system hit maxit.
+ */
+int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples,
+               uint64_t seed, double *out, const grf_opts *opts);
+
+/*
+ * One shifted solve for n_rhs right-hand sides:
+ *   out[r] = ((c_I + c_L kappa^2) M_L + c_L G)^{-1} rhs[r]
+ * (paper: eq. spde_approx_fem for a single l, solved by eq. global_schur).
+ *   c_I, c_L   > 0 and finite; kappa >= 0
+ *   rhs, out   device, float64 [n_rhs][n_dof], canonical order; may not alias
+ */
+int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_t n_rhs,
+                      const double *rhs, double *out, const grf_opts *opts);
+
+/*
+ * grf_sample for several graphs at once, one kappa per graph, sharing beta,
+ * quad_step (0 = the paper's rule, from the graphs' common h), n_samples and
+ * seed.  All graphs must share h and the mesh rule.  outs[i] is a device
+ * pointer to float64 [n_samples][n_dof(graphs[i])].  The graphs are laid out
+ * as one disjoint union and every step runs as one set of launches, captured
+ * once into a HIP graph and replayed for repeated calls with the same inputs.
+ */
+int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double *kappas,
+                       double beta, double quad_step, int64_t n_samples, uint64_t seed,
+                       double *const *outs, const grf_opts *opts);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *grf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRF_H */

@@ -1,0 +1,111 @@
+// Per-(shift, edge) coefficients of the condensed solve.
+//
+// Paper: eq. local_operator / eq. spde_local_quadrature_block (the local
+// operator of edge e for shift l), the tridiagonal storage of A_II and the
+// Thomas factorisation eq. thomas_coefficients, and eq. local_reduced_schur
+// (the edge's 2x2 Schur complement S^(l,e) and its condensed right-hand side).
+//
+// With alpha = c_I + c_L kappa^2, gamma = c_L and the lumped mass, the
+// interior block of an edge with m interior nodes is the constant-coefficient
+// tridiagonal T = tridiag(b, a, b), a = alpha h + 2 gamma / h, b = -gamma / h,
+// and each edge end adds delta = alpha h / 2 + gamma / h to its vertex.
+// Write tau = a / |b| = 2 + eps, eps = alpha h^2 / gamma.  The Thomas pivots
+// of T / |b| are pi_p = 1 + eps_p with
+//     eps_0 = 1 + eps,   eps_p = eps + eps_{p-1} / (1 + eps_{p-1}),
+// a form with no cancellation however close tau is to 2.  The kernel stores,
+// per interior position p = 0..m-1 (shift-fastest rows, [DOF][shift]):
+//   rho_p = 1 / pi_p                       (forward/backward multiplier)
+//   dg_p  = (T^{-1})_{pp} = 1 / (|b| (eps_p + eps_{m-1-p} - eps))
+//   of_p  = (T^{-1})_{p,p+1} = dg_p * rho_{m-2-p}
+// (the inverse of a symmetric tridiagonal matrix is semiseparable; the
+// diagonal follows from the twisted factorisation, which adds the pivots from
+// both ends; T is persymmetric, so the backward pivots are the forward ones
+// reversed).  Per edge: |b|, rho_{m-1}, and the Schur complement
+//   s_d = delta - b^2 (T^{-1})_{11} = alpha h / 2 + |b| eps_{m-1} / (1 + eps_{m-1})
+//   s_o = -b^2 (T^{-1})_{1m}        = -|b| prod_p rho_p
+// (an edge with no interior node has s_d = delta, s_o = b).
+#include "work.h"
+
+namespace grf {
+namespace {
+
+__global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restrict__ shift, int32_t LB, int32_t LBp,
+                                              double *__restrict__ rho, double *__restrict__ dg,
+                                              double *__restrict__ of, double *__restrict__ babs,
+                                              double *__restrict__ rhom, double *__restrict__ sd,
+                                              double *__restrict__ so, float *__restrict__ rho32,
+                                              float *__restrict__ dg32, float *__restrict__ of32) {
+    const int e = blockIdx.x;
+    const int l = blockIdx.y * 64 + threadIdx.x;
+    if (l >= LBp) return;
+    const int m = mv.m[e];
+    const int64_t off = mv.off[e];
+    const int64_t E = mv.E;
+    if (l >= LB) {  // padding shifts contribute nothing
+        for (int p = 0; p < m; ++p) {
+            rho[(off + p) * LBp + l] = 0.0;
+            dg[(off + p) * LBp + l] = 0.0;
+            of[(off + p) * LBp + l] = 0.0;
+            if (rho32) {
+                rho32[(off + p) * LBp + l] = 0.0f;
+                dg32[(off + p) * LBp + l] = 0.0f;
+                of32[(off + p) * LBp + l] = 0.0f;
+            }
+        }
+        babs[e * LBp + l] = 0.0;
+        rhom[e * LBp + l] = 0.0;
+        sd[(int64_t)l * E + e] = 1.0;
+        so[(int64_t)l * E + e] = 0.0;
+        return;
+    }
+    const double h = mv.he[e];
+    const double alpha = shift[2 * l] + shift[2 * l + 1] * mv.kap2[e];
+    const double gamma = shift[2 * l + 1];
+    const double bab = gamma / h;
+    const double eps = alpha * h * h / gamma;
+    // pass 1: pivots (eps_p kept in dg as scratch), multipliers, product
+    double ep = 1.0 + eps, prod = 1.0, ep_last = 0.0, r_last = 0.0;
+    for (int p = 0; p < m; ++p) {
+        const double r = 1.0 / (1.0 + ep);
+        rho[(off + p) * LBp + l] = r;
+        dg[(off + p) * LBp + l] = ep;
+        prod *= r;
+        ep_last = ep;
+        r_last = r;
+        ep = eps + ep * r;
+    }
+    babs[e * LBp + l] = bab;
+    rhom[e * LBp + l] = (m > 0) ? r_last : 0.0;
+    sd[(int64_t)l * E + e] = alpha * h * 0.5 + ((m > 0) ? bab * (ep_last * r_last) : bab);
+    so[(int64_t)l * E + e] = (m > 0) ? -bab * prod : -bab;
+    // pass 2: diagonal and first off-diagonal of T^{-1}, outside-in in pairs
+    for (int p = 0; 2 * p < m; ++p) {
+        const int q = m - 1 - p;
+        const double d = 1.0 / (bab * (dg[(off + p) * LBp + l] + dg[(off + q) * LBp + l] - eps));
+        dg[(off + p) * LBp + l] = d;
+        dg[(off + q) * LBp + l] = d;
+        if (p <= m - 2) of[(off + p) * LBp + l] = d * rho[(off + m - 2 - p) * LBp + l];
+        if (q != p && q <= m - 2) of[(off + q) * LBp + l] = d * rho[(off + m - 2 - q) * LBp + l];
+    }
+    if (m > 0) of[(off + m - 1) * LBp + l] = 0.0;
+    if (rho32) {
+        for (int p = 0; p < m; ++p) {
+            const int64_t i = (off + p) * LBp + l;
+            rho32[i] = (float)rho[i];
+            dg32[i] = (float)dg[i];
+            of32[i] = (float)of[i];
+        }
+    }
+}
+
+}  // namespace
+
+void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
+    if (mv.E == 0) return;
+    GRF_REQUIRE(a.LBp % 8 == 0 && a.LBp >= a.LB, "internal: bad padded shift count");
+    hipLaunchKernelGGL(k_coeff, dim3((unsigned)mv.E, (unsigned)((a.LBp + 63) / 64)), dim3(64), 0, st, mv, a.shift,
+                       a.LB, a.LBp, a.rho, a.dg, a.of, a.babs, a.rhom, a.sd, a.so, a.rho32, a.dg32, a.of32);
+    GRF_LAUNCH_CHECK();
+}
+
+}  // namespace grf

@@ -1,0 +1,140 @@
+// Internal declarations shared by the libgrf translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/grf.h"
+
+namespace grf {
+
+constexpr int kWave = 64;  // CDNA wavefront width; samples are laid out in blocks of 64
+
+// ---- error handling -------------------------------------------------------
+void set_error(const char *fmt, ...);
+
+struct Error {
+    int code;
+};
+
+#define GRF_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ::grf::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                             __FILE__, __LINE__);                                        \
+            throw ::grf::Error{e_ == hipErrorOutOfMemory ? GRF_ENOMEM : GRF_EDEVICE};    \
+        }                                                                                \
+    } while (0)
+
+#define GRF_REQUIRE(cond, ...)               \
+    do {                                     \
+        if (!(cond)) {                       \
+            ::grf::set_error(__VA_ARGS__);   \
+            throw ::grf::Error{GRF_EINVAL};  \
+        }                                    \
+    } while (0)
+
+#define GRF_LAUNCH_CHECK() GRF_HIP(hipGetLastError())
+
+// ---- device buffers ---------------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    void reserve(size_t n);  // grow-only; contents are not preserved
+    void release();
+    template <class T>
+    T *as() const { return static_cast<T *>(ptr); }
+};
+
+template <class T>
+void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
+    b.reserve(v.size() * sizeof(T) + 16);
+    if (!v.empty()) GRF_HIP(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ---- mesh as seen by kernels (plain device pointers, passed by value) ------
+struct MeshView {
+    int32_t V, E;
+    int64_t NI, N;        // interior DOFs, all DOFs
+    const int64_t *off;   // [E+1] first interior DOF of each edge
+    const int32_t *m;     // [E] interior DOF count
+    const int32_t *eu;    // [E] tail vertex
+    const int32_t *ev;    // [E] head vertex
+    const double *he;     // [E] local mesh size
+    const double *kap2;   // [E] kappa^2 of the edge's graph (per call)
+    const int64_t *vptr;  // [V+1] CSR over edge ends
+    const int32_t *adj_e; // [2E] edge of the end
+    const int32_t *adj_o; // [2E] vertex at the other end
+    const int8_t *adj_s;  // [2E] 0 = tail end (u_e), 1 = head end (v_e)
+    const double *msqrt;  // [N] sqrt of the lumped mass diagonal
+    const int32_t *vgraph;  // [V] component (sub-graph) id of each vertex, batched runs
+};
+
+}  // namespace grf
+
+// ---- the opaque handle ---------------------------------------------------------
+struct grf_graph {
+    int device = 0;
+    int64_t V = 0, E = 0, NI = 0, N = 0;
+    double h = 0;
+    uint32_t flags = 0;
+    std::vector<int64_t> eu, ev, off;
+    std::vector<int32_t> m;
+    std::vector<double> len, he, ml;
+    std::vector<int64_t> vptr;
+    std::vector<int32_t> adj_e, adj_o;
+    std::vector<int8_t> adj_s;
+    // device copies
+    grf::DevBuf d_off, d_m, d_eu, d_ev, d_he, d_kap2, d_vptr, d_adj_e, d_adj_o, d_adj_s, d_msqrt, d_vgraph;
+    double kap2_loaded = -1.0;
+    // workspace, grown on demand
+    struct Work;
+    Work *work = nullptr;
+    grf::MeshView view() const;
+};
+
+namespace grf {
+
+// host-side mesh construction shared by single and batched graphs
+void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const double *lengths, double h,
+                uint32_t flags);
+void upload_mesh(grf_graph &g, hipStream_t s);
+
+// quadrature schedule (host, FP64)
+struct Shifts {
+    double k = 0;
+    int32_t kminus = 0, kplus = 0;
+    std::vector<double> cI, cL;
+};
+Shifts make_shifts(double beta, double step, double h, const grf_opts &o);
+
+grf_opts resolve_opts(const grf_opts *o);
+
+// Optional per-kernel timing with HIP events on the launch stream.
+struct KTimer {
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<Rec> recs;
+    KTimer(bool enabled, hipStream_t s) : on(enabled), st(s) {}
+    KTimer(const KTimer &) = delete;
+    ~KTimer();
+    void begin(int id);
+    void end();
+    // after the stream is synchronised: add elapsed times to stats
+    void collect(grf_stats *stats);
+};
+
+}  // namespace grf

@@ -1,0 +1,321 @@
+// Graph handle, mesh and DOF numbering, quadrature schedule (host side).
+//
+// Mesh: paper section "Algorithmic Implementation", "Phase 1: Initialization"
+// (n_e uniform elements per edge, h_e = l_e / n_e, N = |V| + sum_e (N_e - 2)).
+// Lumped mass: "Phase 2", lumped case (h_e inside an edge, sum of h_e/2 at a
+// vertex) and "Mass Lumping" (R = element-wise square root).
+// Shift schedule: eq. coefficients and the limits K^-, K^+ of the "Strong
+// error" subsection.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+#include "work.h"
+
+namespace grf {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+DevBuf::~DevBuf() { release(); }
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void DevBuf::reserve(size_t n) {
+    if (n <= bytes) return;
+    release();
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        set_error("hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+        throw Error{GRF_ENOMEM};
+    }
+    bytes = n;
+}
+
+KTimer::~KTimer() {
+    for (auto &r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+}
+
+void KTimer::begin(int id) {
+    if (!on) return;
+    Rec r{id, nullptr, nullptr};
+    GRF_HIP(hipEventCreate(&r.a));
+    GRF_HIP(hipEventCreate(&r.b));
+    GRF_HIP(hipEventRecord(r.a, st));
+    recs.push_back(r);
+}
+
+void KTimer::end() {
+    if (!on || recs.empty()) return;
+    GRF_HIP(hipEventRecord(recs.back().b, st));
+}
+
+void KTimer::collect(grf_stats *stats) {
+    if (!on || !stats) return;
+    for (auto &r : recs) {
+        float ms = 0.f;
+        GRF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.id >= 0 && r.id < GRF_K_COUNT) {
+            stats->kernel_ms[r.id] += ms;
+            stats->kernel_launches[r.id] += 1;
+        }
+    }
+}
+
+void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const double *lengths, double h,
+                uint32_t flags) {
+    GRF_REQUIRE(V >= 1 && V < (int64_t(1) << 31), "n_vertices must be in [1, 2^31)");
+    GRF_REQUIRE(E >= 0 && E < (int64_t(1) << 30), "n_edges must be in [0, 2^30)");
+    GRF_REQUIRE(E == 0 || (edges && lengths), "edges and lengths must be non-NULL");
+    GRF_REQUIRE(std::isfinite(h) && h > 0, "h must be finite and > 0");
+    GRF_REQUIRE(flags == GRF_MESH_CEIL || flags == GRF_MESH_ROUND, "unknown mesh flag %u", flags);
+    g.V = V;
+    g.E = E;
+    g.h = h;
+    g.flags = flags;
+    g.eu.resize(E);
+    g.ev.resize(E);
+    g.len.resize(E);
+    g.m.resize(E);
+    g.he.resize(E);
+    g.off.resize(E + 1);
+    std::vector<int64_t> deg(V, 0);
+    g.off[0] = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t u = edges[2 * e], v = edges[2 * e + 1];
+        double L = lengths[e];
+        GRF_REQUIRE(u >= 0 && u < V && v >= 0 && v < V, "edge %lld endpoint out of range", (long long)e);
+        GRF_REQUIRE(std::isfinite(L) && L > 0, "edge %lld length must be finite and > 0", (long long)e);
+        double q = L / h;
+        double n = (flags == GRF_MESH_CEIL) ? std::ceil(q) : std::floor(q + 0.5);
+        double nmin = (u == v) ? 2.0 : 1.0;
+        if (n < nmin) n = nmin;
+        GRF_REQUIRE(n < 1e9, "edge %lld needs too many elements", (long long)e);
+        g.eu[e] = u;
+        g.ev[e] = v;
+        g.len[e] = L;
+        g.m[e] = (int32_t)(n - 1);
+        g.he[e] = L / n;
+        g.off[e + 1] = g.off[e] + g.m[e];
+        deg[u]++;
+        deg[v]++;
+    }
+    for (int64_t v = 0; v < V; ++v)
+        GRF_REQUIRE(deg[v] > 0, "vertex %lld has no incident edge (zero lumped mass, singular system)",
+                    (long long)v);
+    g.NI = g.off[E];
+    g.N = g.NI + V;
+    GRF_REQUIRE(g.N < (int64_t(1) << 40), "too many DOFs");
+    // lumped mass diagonal: interior h_e, vertices summed over edges in order, tail end first
+    g.ml.assign(g.N, 0.0);
+    for (int64_t e = 0; e < E; ++e)
+        for (int64_t p = g.off[e]; p < g.off[e + 1]; ++p) g.ml[p] = g.he[e];
+    for (int64_t e = 0; e < E; ++e) {
+        double half = g.he[e] * 0.5;
+        g.ml[g.NI + g.eu[e]] += half;
+        g.ml[g.NI + g.ev[e]] += half;
+    }
+    // CSR over edge ends, ends listed in increasing edge order
+    g.vptr.assign(V + 1, 0);
+    for (int64_t v = 0; v < V; ++v) g.vptr[v + 1] = g.vptr[v] + deg[v];
+    std::vector<int64_t> fill(g.vptr.begin(), g.vptr.end() - 1);
+    g.adj_e.resize(2 * E);
+    g.adj_o.resize(2 * E);
+    g.adj_s.resize(2 * E);
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t a = fill[g.eu[e]]++;
+        g.adj_e[a] = (int32_t)e;
+        g.adj_o[a] = (int32_t)g.ev[e];
+        g.adj_s[a] = 0;
+        int64_t b = fill[g.ev[e]]++;
+        g.adj_e[b] = (int32_t)e;
+        g.adj_o[b] = (int32_t)g.eu[e];
+        g.adj_s[b] = 1;
+    }
+}
+
+void upload_mesh(grf_graph &g, hipStream_t s) {
+    std::vector<int32_t> eu(g.E), ev(g.E);
+    for (int64_t e = 0; e < g.E; ++e) {
+        eu[e] = (int32_t)g.eu[e];
+        ev[e] = (int32_t)g.ev[e];
+    }
+    std::vector<double> msq(g.N);
+    for (int64_t j = 0; j < g.N; ++j) msq[j] = std::sqrt(g.ml[j]);
+    std::vector<int32_t> vg(g.V, 0);
+    upload(g.d_off, g.off, s);
+    upload(g.d_m, g.m, s);
+    upload(g.d_eu, eu, s);
+    upload(g.d_ev, ev, s);
+    upload(g.d_he, g.he, s);
+    upload(g.d_vptr, g.vptr, s);
+    upload(g.d_adj_e, g.adj_e, s);
+    upload(g.d_adj_o, g.adj_o, s);
+    upload(g.d_adj_s, g.adj_s, s);
+    upload(g.d_msqrt, msq, s);
+    upload(g.d_vgraph, vg, s);
+    g.d_kap2.reserve(sizeof(double) * (g.E + 1));
+    g.kap2_loaded = -1.0;
+    GRF_HIP(hipStreamSynchronize(s));
+}
+
+Shifts make_shifts(double beta, double step, double h, const grf_opts &o) {
+    GRF_REQUIRE(std::isfinite(beta) && beta > 0 && beta < 1, "beta must lie in (0, 1)");
+    GRF_REQUIRE(std::isfinite(step) && step >= 0, "quad_step must be >= 0 (0 = paper rule)");
+    Shifts sh;
+    sh.k = (step == 0) ? -1.0 / (beta * std::log(h)) : step;
+    GRF_REQUIRE(std::isfinite(sh.k) && sh.k > 0, "paper step rule needs h < 1; pass quad_step > 0");
+    const double pi = 3.14159265358979323846;
+    double km = std::ceil(pi * pi / (4.0 * sh.k * sh.k * beta));
+    double kp = std::ceil(pi * pi / (4.0 * sh.k * sh.k * (1.0 - beta)));
+    GRF_REQUIRE(km < 1e6 && kp < 1e6, "quadrature step too small: %g shifts", km + kp + 1);
+    sh.kminus = o.k_minus >= 0 ? o.k_minus : (int32_t)km;
+    sh.kplus = o.k_plus >= 0 ? o.k_plus : (int32_t)kp;
+    double cconst = pi / (2.0 * sh.k * std::sin(pi * beta));
+    for (int32_t l = -sh.kminus; l <= sh.kplus; ++l) {
+        double y = (double)l * sh.k;
+        double ci = cconst * std::exp(-2.0 * beta * y);
+        sh.cI.push_back(ci);
+        sh.cL.push_back(ci * std::exp(2.0 * y));
+    }
+    return sh;
+}
+
+grf_opts resolve_opts(const grf_opts *o) {
+    grf_opts r;
+    grf_opts_init(&r);
+    if (o) r = *o;
+    GRF_REQUIRE(std::isfinite(r.tol) && r.tol > 0, "tol must be > 0");
+    GRF_REQUIRE(r.maxit >= 1, "maxit must be >= 1");
+    GRF_REQUIRE(r.precision == GRF_PREC_FP64 || r.precision == GRF_PREC_MIXED, "unknown precision");
+    GRF_REQUIRE(r.precond == GRF_PRECOND_JACOBI || r.precond == GRF_PRECOND_LEARNED, "unknown precond");
+    GRF_REQUIRE(r.precond != GRF_PRECOND_LEARNED || r.learned, "learned preconditioner needs opts->learned");
+    GRF_REQUIRE(r.sample_offset >= 0, "sample_offset must be >= 0");
+    GRF_REQUIRE(r.sweep_block == 0 || r.sweep_block == 8 || r.sweep_block == 16 || r.sweep_block == 32 ||
+                    r.sweep_block == 64,
+                "sweep_block must be 0, 8, 16, 32 or 64");
+    GRF_REQUIRE(r.shift_block >= 0, "shift_block must be >= 0");
+    return r;
+}
+
+}  // namespace grf
+
+grf::MeshView grf_graph::view() const {
+    grf::MeshView v;
+    v.V = (int32_t)V;
+    v.E = (int32_t)E;
+    v.NI = NI;
+    v.N = N;
+    v.off = d_off.as<int64_t>();
+    v.m = d_m.as<int32_t>();
+    v.eu = d_eu.as<int32_t>();
+    v.ev = d_ev.as<int32_t>();
+    v.he = d_he.as<double>();
+    v.kap2 = d_kap2.as<double>();
+    v.vptr = d_vptr.as<int64_t>();
+    v.adj_e = d_adj_e.as<int32_t>();
+    v.adj_o = d_adj_o.as<int32_t>();
+    v.adj_s = d_adj_s.as<int8_t>();
+    v.msqrt = d_msqrt.as<double>();
+    v.vgraph = d_vgraph.as<int32_t>();
+    return v;
+}
+
+using namespace grf;
+
+#define GRF_API_BEGIN try {
+#define GRF_API_END                                     \
+    }                                                   \
+    catch (const ::grf::Error &err) { return err.code; } \
+    catch (const std::bad_alloc &) {                    \
+        ::grf::set_error("host allocation failed");      \
+        return GRF_ENOMEM;                              \
+    }                                                   \
+    catch (...) {                                       \
+        ::grf::set_error("unexpected internal error");   \
+        return GRF_EDEVICE;                             \
+    }                                                   \
+    return GRF_OK;
+
+extern "C" {
+
+const char *grf_last_error(void) { return g_err; }
+
+void grf_opts_init(grf_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-12;
+    o->maxit = 10000;
+    o->precision = GRF_PREC_FP64;
+    o->precond = GRF_PRECOND_JACOBI;
+    o->k_minus = -1;
+    o->k_plus = -1;
+    o->refine = -1;
+}
+
+int grf_graph_create(int64_t n_vertices, int64_t n_edges, const int64_t *edges, const double *lengths, double h,
+                     uint32_t flags, grf_graph **out) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(out, "out must be non-NULL");
+    *out = nullptr;
+    grf_graph *g = new grf_graph();
+    try {
+        build_mesh(*g, n_vertices, n_edges, edges, lengths, h, flags);
+        GRF_HIP(hipGetDevice(&g->device));
+        upload_mesh(*g, nullptr);
+    } catch (...) {
+        delete g;
+        throw;
+    }
+    *out = g;
+    GRF_API_END
+}
+
+int grf_graph_info(const grf_graph *g, int64_t *n_dof, int64_t *n_interior, int64_t *dof_offsets) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(g, "graph is NULL");
+    if (n_dof) *n_dof = g->N;
+    if (n_interior) *n_interior = g->NI;
+    if (dof_offsets)
+        for (int64_t e = 0; e <= g->E; ++e) dof_offsets[e] = g->off[e];
+    GRF_API_END
+}
+
+int grf_graph_destroy(grf_graph *g) {
+    GRF_API_BEGIN
+    if (g) {
+        free_work(*g);
+        delete g;
+    }
+    GRF_API_END
+}
+
+int grf_shift_count(const grf_graph *g, double beta, double quad_step, const grf_opts *opts, int32_t *k_minus,
+                    int32_t *k_plus, double *step_used) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(g, "graph is NULL");
+    grf_opts o = resolve_opts(opts);
+    Shifts sh = make_shifts(beta, quad_step, g->h, o);
+    if (k_minus) *k_minus = sh.kminus;
+    if (k_plus) *k_plus = sh.kplus;
+    if (step_used) *step_used = sh.k;
+    GRF_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Layout changes between the canonical [S][N] vectors of the ABI and the
+// sample-interleaved [nb][N][64] layout the sweeps use (lanes = samples, so a
+// wavefront's access to one DOF is one contiguous 512-byte row).
+#include "work.h"
+
+namespace grf {
+namespace {
+
+constexpr int kT = 64;  // tile: 64 DOFs x 64 samples, staged in LDS
+
+// in[s][j] -> X[b][j][lane]; padded samples (s >= S) are written as 0
+__global__ void __launch_bounds__(256) k_to_interleaved(const double *__restrict__ in, int64_t S, int64_t N,
+                                                        double *__restrict__ X) {
+    __shared__ double tile[kT][kT + 1];
+    const int64_t j0 = (int64_t)blockIdx.x * kT;
+    const int64_t b = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int si = ty; si < kT; si += 4) {
+        int64_t s = b * kT + si, j = j0 + tx;
+        tile[si][tx] = (s < S && j < N) ? in[s * N + j] : 0.0;
+    }
+    __syncthreads();
+    for (int ji = ty; ji < kT; ji += 4) {
+        int64_t j = j0 + ji;
+        if (j < N) X[(b * N + j) * 64 + tx] = tile[tx][ji];
+    }
+}
+
+// X[b][j][lane] -> out[s][j] for s < S
+__global__ void __launch_bounds__(256) k_from_interleaved(const double *__restrict__ X, int64_t S, int64_t N,
+                                                          double *__restrict__ out) {
+    __shared__ double tile[kT][kT + 1];
+    const int64_t j0 = (int64_t)blockIdx.x * kT;
+    const int64_t b = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int ji = ty; ji < kT; ji += 4) {
+        int64_t j = j0 + ji;
+        tile[ji][tx] = (j < N) ? X[(b * N + j) * 64 + tx] : 0.0;
+    }
+    __syncthreads();
+    for (int si = ty; si < kT; si += 4) {
+        int64_t s = b * kT + si, j = j0 + tx;
+        if (s < S && j < N) out[s * N + j] = tile[tx][si];
+    }
+}
+
+__global__ void k_fill(double *__restrict__ p, size_t n, double v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+void launch_to_interleaved(const double *in, int64_t S, int64_t N, double *X, hipStream_t st) {
+    int64_t nb = (S + 63) / 64;
+    if (nb == 0 || N == 0) return;
+    GRF_REQUIRE((N + kT - 1) / kT < (int64_t(1) << 31) && nb < 65536, "vector too large");
+    hipLaunchKernelGGL(k_to_interleaved, dim3((unsigned)((N + kT - 1) / kT), (unsigned)nb), dim3(256), 0, st, in, S,
+                       N, X);
+    GRF_LAUNCH_CHECK();
+}
+
+void launch_from_interleaved(const double *X, int64_t S, int64_t N, double *out, hipStream_t st) {
+    int64_t nb = (S + 63) / 64;
+    if (nb == 0 || N == 0) return;
+    GRF_REQUIRE((N + kT - 1) / kT < (int64_t(1) << 31) && nb < 65536, "vector too large");
+    hipLaunchKernelGGL(k_from_interleaved, dim3((unsigned)((N + kT - 1) / kT), (unsigned)nb), dim3(256), 0, st, X,
+                       S, N, out);
+    GRF_LAUNCH_CHECK();
+}
+
+void launch_fill(double *p, size_t n, double v, hipStream_t st) {
+    if (n == 0) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    GRF_LAUNCH_CHECK();
+}
+
+}  // namespace grf

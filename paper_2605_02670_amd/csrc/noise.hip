@@ -1,0 +1,179 @@
+// Lumped white noise W = M_L^{1/2} xi (paper: eq. wh_def; "Mass Lumping":
+// the Cholesky factor of the diagonal lumped mass is its element-wise square
+// root, so the noise costs O(N)).
+//
+// xi is this project's counter-based definition, identical bit for bit on any
+// IEEE-754 machine that evaluates the same operations in the same order:
+//   * Philox4x64-10 (Salmon et al., SC'11), key = (seed, global sample),
+//     counter = (j / 4, 0, 0, 0) for DOF j;
+//   * 53-bit uniforms u = (x >> 11) 2^-53;
+//   * Box-Muller, r = sqrt(-2 log(1 - u_a)), (r cos 2 pi u_b, r sin 2 pi u_b),
+//     with log and sin/cos evaluated by the fixed polynomial schemes below;
+//   * DOF j takes component j % 4 of [r_a cos, r_a sin, r_b cos, r_b sin].
+// This file is compiled with -ffp-contract=off: no multiply-add is fused, so
+// every operation rounds exactly once, as written.
+#include "work.h"
+
+namespace grf {
+namespace {
+
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kWeyl0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kWeyl1 = 0xBB67AE8584CAA73Bull;
+
+struct Words {
+    uint64_t x[4];
+};
+
+__device__ __forceinline__ Words philox4x64_10(uint64_t ctr, uint64_t key0, uint64_t key1) {
+    uint64_t c0 = ctr, c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+        uint64_t hi1 = __umul64hi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ key0;
+        uint64_t n2 = hi0 ^ c3 ^ key1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        key0 += kWeyl0;
+        key1 += kWeyl1;
+    }
+    return Words{{c0, c1, c2, c3}};
+}
+
+__device__ __forceinline__ double unit53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+// log on (0, 1]: x = m 2^e with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s),
+// s = (m - 1)/(m + 1), atanh by its odd power series through s^25.
+__device__ __forceinline__ double log_fixed(double x) {
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0x1.6a09e667f3bcdp-1) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double ed = (double)e;
+    double f = m - 1.0;
+    double s = f / (m + 1.0);
+    double s2 = s * s;
+    // q = sum_{k=1}^{12} s2^{k-1} / (2k + 1), by Horner from the top term
+    double q = 1.0 / 25.0;
+    q = q * s2 + 1.0 / 23.0;
+    q = q * s2 + 1.0 / 21.0;
+    q = q * s2 + 1.0 / 19.0;
+    q = q * s2 + 1.0 / 17.0;
+    q = q * s2 + 1.0 / 15.0;
+    q = q * s2 + 1.0 / 13.0;
+    q = q * s2 + 1.0 / 11.0;
+    q = q * s2 + 1.0 / 9.0;
+    q = q * s2 + 1.0 / 7.0;
+    q = q * s2 + 1.0 / 5.0;
+    q = q * s2 + 1.0 / 3.0;
+    double r = s2 * q;
+    double lm = s + s * r;
+    double t1 = 2.0 * lm;
+    double t2 = ed * 0x1.a39ef35793c76p-33;  // ln2 - ln2_hi
+    double t3 = t1 + t2;
+    double t4 = ed * 0x1.62e42fee00000p-1;   // ln2_hi (21 trailing zero bits: e * ln2_hi is exact)
+    return t4 + t3;
+}
+
+// (sin 2 pi u, cos 2 pi u) for u in [0, 1) a multiple of 2^-53: octant o and
+// fraction f of 8u are exact; the polynomial runs on a in [0, pi/4].
+__device__ __forceinline__ void sincos_2pi_fixed(double u, double &sn, double &cs) {
+    double t = u * 8.0;
+    double of = floor(t);
+    double f = t - of;
+    int o = (int)of;
+    if (o & 1) f = 1.0 - f;
+    double a = f * 0x1.921fb54442d18p-1;  // nearest double to pi/4
+    double a2 = a * a;
+    // sin a = a + a (a2 ps), ps = sum_{k=1}^{10} (-1)^k a2^{k-1} / (2k+1)!
+    double ps = 1.0 / 51090942171709440000.0;                 // +1/21!
+    ps = ps * a2 + (-1.0 / 121645100408832000.0);             // -1/19!
+    ps = ps * a2 + (1.0 / 355687428096000.0);                 // +1/17!
+    ps = ps * a2 + (-1.0 / 1307674368000.0);                  // -1/15!
+    ps = ps * a2 + (1.0 / 6227020800.0);                      // +1/13!
+    ps = ps * a2 + (-1.0 / 39916800.0);                       // -1/11!
+    ps = ps * a2 + (1.0 / 362880.0);                          // +1/9!
+    ps = ps * a2 + (-1.0 / 5040.0);                           // -1/7!
+    ps = ps * a2 + (1.0 / 120.0);                             // +1/5!
+    ps = ps * a2 + (-1.0 / 6.0);                              // -1/3!
+    // cos a = 1 + a2 pc, pc = sum_{k=1}^{10} (-1)^k a2^{k-1} / (2k)!
+    double pc = 1.0 / 2432902008176640000.0;                  // +1/20!
+    pc = pc * a2 + (-1.0 / 6402373705728000.0);               // -1/18!
+    pc = pc * a2 + (1.0 / 20922789888000.0);                  // +1/16!
+    pc = pc * a2 + (-1.0 / 87178291200.0);                    // -1/14!
+    pc = pc * a2 + (1.0 / 479001600.0);                       // +1/12!
+    pc = pc * a2 + (-1.0 / 3628800.0);                        // -1/10!
+    pc = pc * a2 + (1.0 / 40320.0);                           // +1/8!
+    pc = pc * a2 + (-1.0 / 720.0);                            // -1/6!
+    pc = pc * a2 + (1.0 / 24.0);                              // +1/4!
+    pc = pc * a2 + (-1.0 / 2.0);                              // -1/2!
+    double sa = a + a * (a2 * ps);
+    double ca = 1.0 + a2 * pc;
+    // angle = o pi/4 + theta; a = theta for even o, pi/4 - theta for odd o
+    switch (o) {
+        case 0: sn = sa; cs = ca; break;
+        case 1: sn = ca; cs = sa; break;
+        case 2: sn = ca; cs = -sa; break;
+        case 3: sn = sa; cs = -ca; break;
+        case 4: sn = -sa; cs = -ca; break;
+        case 5: sn = -ca; cs = -sa; break;
+        case 6: sn = -ca; cs = sa; break;
+        default: sn = -sa; cs = ca; break;
+    }
+}
+
+__device__ __forceinline__ void box_muller(uint64_t xa, uint64_t xb, double &z_cos, double &z_sin) {
+    double u1 = 1.0 - unit53(xa);
+    double u2 = unit53(xb);
+    double r = sqrt(-2.0 * log_fixed(u1));
+    double sn, cs;
+    sincos_2pi_fixed(u2, sn, cs);
+    z_cos = r * cs;
+    z_sin = r * sn;
+}
+
+// One wavefront = 64 samples of one block of 4 DOFs; lanes are samples, so
+// the four stores of a wavefront are each one contiguous 512-byte row.
+__global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt, int64_t N, int64_t S, int64_t soff,
+                                               uint64_t seed, double *__restrict__ X) {
+    const int lane = threadIdx.x & 63;
+    const int64_t ngrp = (N + 3) / 4;
+    const int64_t b = blockIdx.y;
+    const int64_t s = b * 64 + lane;
+    const bool live = s < S;
+    double *Xb = X + b * N * 64 + lane;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < ngrp; g += (int64_t)gridDim.x * 4) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live) {
+            Words w = philox4x64_10((uint64_t)g, seed, (uint64_t)(soff + s));
+            box_muller(w.x[0], w.x[1], z[0], z[1]);
+            box_muller(w.x[2], w.x[3], z[2], z[3]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int64_t j = 4 * g + c;
+            if (j < N) Xb[j * 64] = msqrt[j] * z[c];
+        }
+    }
+}
+
+}  // namespace
+
+void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, double *X, hipStream_t st) {
+    int64_t nb = (S + 63) / 64;
+    int64_t ngrp = (mv.N + 3) / 4;
+    int64_t gx = (ngrp + 3) / 4;
+    if (gx > 8192) gx = 8192;
+    if (gx < 1) gx = 1;
+    GRF_REQUIRE(nb < 65536, "too many samples in one call");
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)gx, (unsigned)nb), dim3(256), 0, st, mv.msqrt, mv.N, S, soff, seed, X);
+    GRF_LAUNCH_CHECK();
+}
+
+}  // namespace grf

@@ -1,0 +1,249 @@
+// Vertex Schur-complement system of every (shift, sample) pair.
+//
+// Paper: eq. global_schur (S u_Gamma = g_Gamma), the condensed right-hand
+// side g = W_Gamma - A_Gamma,I A_II^{-1} W_I assembled by the scatter S(.) of
+// the edge contributions (eq. local_reduced_schur), and "Phase 4: The Inside
+// Loop (PCG solver)": S is never assembled; its product is the sum of the
+// edge 2x2 Schur blocks (eq. goal_func_1, eq. goalfunction), here with the
+// blocks precomputed per (shift, edge) by coeff.hip.
+//
+// Readings (the paper leaves them open): x_0 = 0; Jacobi preconditioner (the
+// diagonal of S); stop when ||g - S x||_2 <= tol ||g||_2 on the residual
+// recomputed from x; g = 0 gives x = 0.
+#include "work.h"
+
+namespace grf {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NV values over the workgroup; every thread gets the same result (the
+// partial sums are combined in a fixed order, so the result is deterministic).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds, int nwaves) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int i = 0; i < NV; ++i) lds[i * 16 + (threadIdx.x >> 6)] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = 0.0;
+        for (int w = 0; w < nwaves; ++w) t += lds[i * 16 + w];
+        v[i] = t;
+    }
+}
+
+// g[l][s][v] = W_v + sum over edge ends at v of |b| w_end; tiles of 64 vertices
+// x 64 samples are transposed through LDS so both sides are contiguous.
+__global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__restrict__ X,
+                                                  const double *__restrict__ ends, int32_t Sp, int64_t S,
+                                                  double *__restrict__ gT) {
+    __shared__ double tile[64][65];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int v0 = blockIdx.x * 64;
+    const int b = blockIdx.y;
+    const int l = blockIdx.z;
+    const int64_t E = mv.E;
+    for (int vi = wv; vi < 64; vi += 4) {
+        const int v = v0 + vi;
+        double g = 0.0;
+        if (v < mv.V) {
+            g = X[((int64_t)b * mv.N + mv.NI + v) * 64 + lane];
+            for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+                const int e = mv.adj_e[k];
+                const int side = mv.adj_s[k];
+                g += ends[(((int64_t)l * E + e) * 2 + side) * Sp + (int64_t)b * 64 + lane];
+            }
+        }
+        tile[vi][lane] = g;
+    }
+    __syncthreads();
+    for (int si = wv; si < 64; si += 4) {
+        const int64_t s = (int64_t)b * 64 + si;
+        const int v = v0 + lane;
+        if (s < S && v < mv.V) gT[((int64_t)l * S + s) * mv.V + v] = tile[lane][si];
+    }
+}
+
+// (S p)_v over the edge ends at v
+__device__ __forceinline__ double schur_apply(const MeshView &mv, const double *__restrict__ sdl,
+                                              const double *__restrict__ sol, const double *p, int v) {
+    const double pv = p[v];
+    double acc = 0.0;
+    for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+        const int e = mv.adj_e[k];
+        acc += sdl[e] * pv + sol[e] * p[mv.adj_o[k]];
+    }
+    return acc;
+}
+
+// One workgroup per (shift, sample) system, vectors in global scratch
+// (x, r, p, q, jac: 5 V doubles per resident workgroup).
+__global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so,
+                                             const double *__restrict__ gT, double *__restrict__ xT,
+                                             double *__restrict__ scr, int32_t *__restrict__ its,
+                                             double *__restrict__ res, int32_t LB, int64_t S, double tol,
+                                             int32_t maxit) {
+    __shared__ double red[64];
+    const int V = mv.V;
+    const int64_t E = mv.E;
+    const int nw = blockDim.x >> 6;
+    double *x = scr + (int64_t)blockIdx.x * 5 * V;
+    double *r = x + V, *p = r + V, *q = p + V, *jac = q + V;
+    const int64_t nsys = (int64_t)LB * S;
+    for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
+        const int l = (int)(sys / S);
+        const double *g = gT + sys * V;
+        const double *sdl = sd + (int64_t)l * E;
+        const double *sol = so + (int64_t)l * E;
+        double t2[2] = {0.0, 0.0};  // r.z, g.g
+        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            double d = 0.0;
+            for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+                const int e = mv.adj_e[k];
+                d += sdl[e] + (mv.adj_o[k] == v ? sol[e] : 0.0);
+            }
+            const double gv = g[v];
+            jac[v] = d;
+            x[v] = 0.0;
+            r[v] = gv;
+            const double z = gv / d;
+            p[v] = z;
+            t2[0] += gv * z;
+            t2[1] += gv * gv;
+        }
+        block_sum<2>(t2, red, nw);
+        double rz = t2[0];
+        const double gg = t2[1];
+        const double tol2 = tol * tol * gg;
+        int it = 0;
+        double rel = 0.0;
+        if (gg > 0.0) {
+            rel = 1.0;
+            for (it = 1; it <= maxit; ++it) {
+                __syncthreads();  // p complete
+                double t1[1] = {0.0};
+                for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                    const double qv = schur_apply(mv, sdl, sol, p, v);
+                    q[v] = qv;
+                    t1[0] += p[v] * qv;
+                }
+                block_sum<1>(t1, red, nw);
+                const double alpha = rz / t1[0];
+                double t3[2] = {0.0, 0.0};  // r.z, r.r
+                for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                    x[v] += alpha * p[v];
+                    const double rv = r[v] - alpha * q[v];
+                    r[v] = rv;
+                    t3[0] += rv * (rv / jac[v]);
+                    t3[1] += rv * rv;
+                }
+                block_sum<2>(t3, red, nw);
+                double rz_new = t3[0];
+                double beta;
+                if (t3[1] <= tol2) {
+                    __syncthreads();  // x complete
+                    double tt[2] = {0.0, 0.0};  // true r.r, r.z
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                        const double rv = g[v] - schur_apply(mv, sdl, sol, x, v);
+                        r[v] = rv;
+                        tt[0] += rv * rv;
+                        tt[1] += rv * (rv / jac[v]);
+                    }
+                    block_sum<2>(tt, red, nw);
+                    rel = sqrt(tt[0] / gg);
+                    if (tt[0] <= tol2) break;
+                    rz_new = tt[1];  // restart from the true residual
+                    beta = 0.0;
+                } else {
+                    rel = sqrt(t3[1] / gg);
+                    beta = rz_new / rz;
+                }
+                rz = rz_new;
+                __syncthreads();  // all reads of p (schur_apply on x aside) done
+                for (int v = threadIdx.x; v < V; v += blockDim.x) p[v] = r[v] / jac[v] + beta * p[v];
+            }
+            if (it > maxit) it = maxit + 1;  // flags non-convergence
+        }
+        __syncthreads();
+        double *xo = xT + sys * V;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? x[v] : 0.0;
+        if (threadIdx.x == 0) {
+            its[sys] = it;
+            res[sys] = rel;
+        }
+        __syncthreads();
+    }
+}
+
+// ug[l][v][s] = xT[l][s][v] (padded samples 0) and U[b][NI+v][s] += sum_l xT[l][s][v],
+// shifts summed in increasing order.
+__global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const double *__restrict__ xT, int32_t LB,
+                                                        int64_t S, int32_t Sp, double *__restrict__ ug,
+                                                        double *__restrict__ U) {
+    __shared__ double tile[64][65];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int v0 = blockIdx.x * 64;
+    const int b = blockIdx.y;
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int l = 0; l < LB; ++l) {
+        __syncthreads();
+        for (int si = wv; si < 64; si += 4) {
+            const int64_t s = (int64_t)b * 64 + si;
+            const int v = v0 + lane;
+            tile[si][lane] = (s < S && v < mv.V) ? xT[((int64_t)l * S + s) * mv.V + v] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int vi = wv + 4 * i;
+            const int v = v0 + vi;
+            const double val = tile[lane][vi];
+            if (v < mv.V) ug[((int64_t)l * mv.V + v) * Sp + (int64_t)b * 64 + lane] = val;
+            acc[i] += val;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int v = v0 + wv + 4 * i;
+        if (v < mv.V) U[((int64_t)b * mv.N + mv.NI + v) * 64 + lane] += acc[i];
+    }
+}
+
+}  // namespace
+
+size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) { return (size_t)blocks * 5 * mv.V * sizeof(double); }
+
+void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    if (a.LB == 0 || a.S == 0) return;
+    GRF_REQUIRE(a.LB < 65536 && a.nb < 65536, "internal: grid too large");
+    hipLaunchKernelGGL(k_condense, dim3((unsigned)((mv.V + 63) / 64), (unsigned)a.nb, (unsigned)a.LB), dim3(256), 0,
+                       st, mv, a.X, a.ends, a.Sp, a.S, a.gT);
+    GRF_LAUNCH_CHECK();
+}
+
+void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    if (a.LB == 0 || a.S == 0) return;
+    int64_t nsys = (int64_t)a.LB * a.S;
+    int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
+    hipLaunchKernelGGL(k_pcg, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr, a.its,
+                       a.res, a.LB, a.S, a.tol, a.maxit);
+    GRF_LAUNCH_CHECK();
+}
+
+void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    if (a.LB == 0 || a.S == 0) return;
+    hipLaunchKernelGGL(k_vertex_scatter, dim3((unsigned)((mv.V + 63) / 64), (unsigned)a.nb), dim3(256), 0, st, mv,
+                       a.xT, a.LB, a.S, a.Sp, a.ug, a.U);
+    GRF_LAUNCH_CHECK();
+}
+
+}  // namespace grf

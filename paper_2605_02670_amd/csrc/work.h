@@ -1,0 +1,86 @@
+// Workspace of a graph handle and the kernel launchers of each step.
+#pragma once
+
+#include "common.h"
+
+struct grf_graph::Work {
+    grf::DevBuf X, U;             // sample-interleaved [nb][N][64]: input (noise / rhs) and accumulator
+    grf::DevBuf rho, dg, of;      // per-DOF Thomas rows [NI][LBp]
+    grf::DevBuf babs, rhom;       // per-edge [E][LBp]: |b| = gamma/h_e, rho_{m-1}
+    grf::DevBuf sd, so;           // per-edge Schur 2x2 [LBp][E]: diagonal, off-diagonal
+    grf::DevBuf shift;            // [LBp][2]: c_I, c_L of the shifts in the block
+    grf::DevBuf ends;             // [LB][E][2][Sp]: |b| * (A_II^{-1} W_I) at both ends of every edge
+    grf::DevBuf gT, xT;           // [LB][S][V]: condensed right-hand sides / vertex solutions
+    grf::DevBuf ug;               // [LB][V][Sp]: vertex solutions, sample-interleaved
+    grf::DevBuf pcg_scr;          // PCG vectors in global memory (large graphs)
+    grf::DevBuf its, res;         // [LB][S] int32 iterations, double relative residual
+    grf::DevBuf flt;              // mixed precision: FP32 tables and vectors
+    std::vector<int32_t> h_its;
+    std::vector<double> h_res;
+};
+
+namespace grf {
+
+void free_work(grf_graph &g);
+grf_graph::Work &work(grf_graph &g);
+
+// ---- launchers (each .hip file implements its own) -------------------------
+// noise: X[b][j][lane] = msqrt[j] * Z(seed, soff + b*64 + lane, j) for b*64+lane < S, 0 otherwise
+void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, double *X, hipStream_t st);
+
+// layout transforms between canonical [S][N] and sample-interleaved [nb][N][64]
+void launch_to_interleaved(const double *in, int64_t S, int64_t N, double *X, hipStream_t st);
+void launch_from_interleaved(const double *X, int64_t S, int64_t N, double *out, hipStream_t st);
+void launch_fill(double *p, size_t n, double v, hipStream_t st);
+
+// per-(shift, edge) coefficients: Thomas rows, |b|, rho_{m-1}, Schur 2x2
+struct CoeffArgs {
+    const double *shift;  // [LBp][2] c_I, c_L
+    int32_t LB, LBp;
+    double *rho, *dg, *of;  // [NI][LBp]
+    double *babs, *rhom;    // [E][LBp]
+    double *sd, *so;        // [LBp][E]
+    float *rho32, *dg32, *of32;  // optional FP32 copies (mixed precision), may be null
+};
+void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
+
+// sweeps over edge interiors (lanes = samples, shifts in registers)
+struct SweepArgs {
+    const double *X;        // [nb][N][64] right-hand sides (noise)
+    double *U;              // [nb][N][64] accumulator (acc mode)
+    const double *rho, *dg, *of;  // [NI][LBp]
+    const float *rho32, *dg32, *of32;
+    const double *babs, *rhom;    // [E][LBp]
+    const double *ug;       // [LB][V][Sp] vertex solutions (acc mode)
+    double *ends;           // [LB][E][2][Sp] (ends mode)
+    int32_t LB, LBp, nb, Sp;
+    int32_t bl;             // shifts per wavefront: 8, 16, 32, 64
+    int32_t fp32;           // run the recurrences in FP32
+};
+void launch_sweep_ends(const MeshView &mv, const SweepArgs &a, bool fwd, hipStream_t st);
+void launch_sweep_acc(const MeshView &mv, const SweepArgs &a, bool fwd, hipStream_t st);
+
+// vertex Schur complement: condensed rhs, PCG, layout changes, accumulation
+struct SchurArgs {
+    const double *X;      // [nb][N][64] noise (vertex part used)
+    const double *ends;   // [LB][E][2][Sp]
+    const double *sd, *so;  // [LBp][E]
+    double *gT, *xT;      // [LB][S][V]
+    double *ug;           // [LB][V][Sp]
+    double *U;            // [nb][N][64]
+    double *scr;          // PCG scratch (large graphs)
+    int32_t *its;         // [LB][S]
+    double *res;          // [LB][S]
+    int32_t LB, LBp, nb, Sp;
+    int64_t S;
+    double tol;
+    int32_t maxit;
+    int32_t pcg_blocks;   // resident workgroups for the global-memory PCG
+    const float *learned_P;  // learned preconditioner operator (optional): [LB][V + 2E]... see learned.hip
+};
+void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);
+void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);
+void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st);
+size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);
+
+}  // namespace grf

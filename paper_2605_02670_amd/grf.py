@@ -1,0 +1,221 @@
+"""Thin ctypes binding of libgrf (include/grf.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+PyTorch supplies device memory and the current stream.  If the library has
+not been built, every call raises: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgrf.so")
+_lib = None
+
+GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP = 0, -1, -2, -3, -4, -5
+MESH = {"ceil": 0, "round": 1}
+PREC = {"fp64": 0, "mixed": 1}
+PRECOND = {"jacobi": 0, "learned": 1}
+KERNELS = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd",
+           "layout", "mixed", "learned"]
+
+
+class GrfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libgrf error {code}: {msg}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_shifts", C.c_int32), ("n_systems", C.c_int32), ("n_unconverged", C.c_int32),
+                ("max_iterations", C.c_int32), ("total_iterations", C.c_int64),
+                ("max_rel_residual", C.c_double), ("refine_steps", C.c_int32),
+                ("shift_block", C.c_int32), ("sweep_block", C.c_int32), ("reserved", C.c_int32),
+                ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int32 * 12)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "kernel_ms", "kernel_launches")}
+        d["kernel_ms"] = {KERNELS[i]: self.kernel_ms[i] for i in range(12)}
+        d["kernel_launches"] = {KERNELS[i]: self.kernel_launches[i] for i in range(12)}
+        return d
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
+                ("k_minus", C.c_int32), ("k_plus", C.c_int32), ("shift_block", C.c_int32),
+                ("sweep_block", C.c_int32), ("refine", C.c_int32), ("timing", C.c_int32),
+                ("reserved0", C.c_int32), ("sample_offset", C.c_int64),
+                ("stream", C.c_void_p), ("learned", C.c_void_p), ("stats", C.POINTER(Stats))]
+
+
+# (name, restype, argtypes) for every function declared in include/grf.h
+_SIGS = [
+    ("grf_opts_init", None, [C.POINTER(Opts)]),
+    ("grf_graph_create", C.c_int, [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_double, C.c_uint32,
+                                   C.POINTER(C.c_void_p)]),
+    ("grf_graph_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p]),
+    ("grf_graph_destroy", C.c_int, [C.c_void_p]),
+    ("grf_shift_count", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(Opts), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("grf_noise", C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.POINTER(Opts)]),
+    ("grf_sample", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_uint64, C.c_void_p,
+                             C.POINTER(Opts)]),
+    ("grf_solve_shifted", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p,
+                                    C.c_void_p, C.POINTER(Opts)]),
+    ("grf_sample_batched", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_int64,
+                                     C.c_uint64, C.c_void_p, C.POINTER(Opts)]),
+    ("grf_last_error", C.c_char_p, []),
+]
+
+
+def load():
+    """Load libgrf.so from the package directory (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2605_02670_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code: int, allow=(GRF_OK,)) -> int:
+    if code not in allow:
+        raise GrfError(code, load().grf_last_error().decode())
+    return code
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_opts(tol=1e-12, maxit=10000, precision="fp64", precond="jacobi", k_minus=-1, k_plus=-1,
+              shift_block=0, sweep_block=0, refine=-1, sample_offset=0, stream=None, learned=None,
+              stats: Stats | None = None, timing=False) -> Opts:
+    o = Opts()
+    load().grf_opts_init(C.byref(o))
+    o.tol = tol
+    o.maxit = maxit
+    o.precision = PREC[precision]
+    o.precond = PRECOND[precond]
+    o.k_minus = k_minus
+    o.k_plus = k_plus
+    o.shift_block = shift_block
+    o.sweep_block = sweep_block
+    o.refine = refine
+    o.timing = 1 if timing else 0
+    o.sample_offset = sample_offset
+    o.stream = C.c_void_p(_stream_handle(stream)) if stream is not False else None
+    o.learned = C.c_void_p(learned.handle) if learned is not None else None
+    if stats is not None:
+        o.stats = C.pointer(stats)
+    return o
+
+
+class Graph:
+    """A metric graph and its mesh on the current HIP device."""
+
+    def __init__(self, n_vertices: int, edges, lengths, h: float, rule: str = "ceil"):
+        lib = load()
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
+        L = np.ascontiguousarray(np.asarray(lengths, dtype=np.float64).reshape(-1))
+        self.n_vertices = int(n_vertices)
+        self.n_edges = int(e.shape[0])
+        self.h = float(h)
+        self.rule = rule
+        handle = C.c_void_p()
+        _check(lib.grf_graph_create(self.n_vertices, self.n_edges, e.ctypes.data, L.ctypes.data, self.h,
+                                    MESH[rule], C.byref(handle)))
+        self.handle = handle.value
+        nd, ni = C.c_int64(), C.c_int64()
+        offs = np.zeros(self.n_edges + 1, dtype=np.int64)
+        _check(lib.grf_graph_info(self.handle, C.byref(nd), C.byref(ni), offs.ctypes.data))
+        self.n_dof, self.n_interior, self.offsets = nd.value, ni.value, offs
+
+    @classmethod
+    def from_workload(cls, g, h: float, rule: str = "ceil") -> "Graph":
+        return cls(g.n_vertices, g.edges, g.lengths, h, rule)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().grf_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shift_count(self, beta: float, quad_step: float, k_minus: int = -1, k_plus: int = -1):
+        o = make_opts(k_minus=k_minus, k_plus=k_plus, stream=False)
+        km, kp, k = C.c_int32(), C.c_int32(), C.c_double()
+        _check(load().grf_shift_count(self.handle, beta, quad_step, C.byref(o), C.byref(km), C.byref(kp),
+                                      C.byref(k)))
+        return km.value, kp.value, k.value
+
+    def noise(self, n_samples: int, seed: int, out=None, **kw):
+        import torch
+
+        if out is None:
+            out = torch.empty((n_samples, self.n_dof), dtype=torch.float64, device="cuda")
+        o = make_opts(**kw)
+        _check(load().grf_noise(self.handle, n_samples, seed, out.data_ptr(), C.byref(o)))
+        return out
+
+    def sample(self, kappa: float, beta: float, quad_step: float, n_samples: int, seed: int, out=None,
+               allow_noconv: bool = False, **kw):
+        """Returns (samples [n_samples, n_dof] float64 on cuda, stats dict)."""
+        import torch
+
+        if out is None:
+            out = torch.empty((n_samples, self.n_dof), dtype=torch.float64, device="cuda")
+        st = Stats()
+        o = make_opts(stats=st, **kw)
+        allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
+        _check(load().grf_sample(self.handle, kappa, beta, quad_step, n_samples, seed, out.data_ptr(), C.byref(o)),
+               allow)
+        return out, st.as_dict()
+
+    def solve_shifted(self, kappa: float, c_I: float, c_L: float, rhs, out=None, allow_noconv=False, **kw):
+        import torch
+
+        rhs = rhs.contiguous()
+        assert rhs.dtype == torch.float64 and rhs.is_cuda and rhs.shape[-1] == self.n_dof
+        r2 = rhs.reshape(-1, self.n_dof)
+        if out is None:
+            out = torch.empty_like(r2)
+        st = Stats()
+        o = make_opts(stats=st, **kw)
+        allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
+        _check(load().grf_solve_shifted(self.handle, kappa, c_I, c_L, r2.shape[0], r2.data_ptr(), out.data_ptr(),
+                                        C.byref(o)), allow)
+        return out.reshape(rhs.shape), st.as_dict()
+
+
+def sample_batched(graphs, kappas, beta: float, quad_step: float, n_samples: int, seed: int, outs=None, **kw):
+    """grf_sample_batched over a list of Graph objects; returns (list of outputs, stats dict)."""
+    import torch
+
+    n = len(graphs)
+    if outs is None:
+        outs = [torch.empty((n_samples, g.n_dof), dtype=torch.float64, device="cuda") for g in graphs]
+    harr = (C.c_void_p * n)(*[g.handle for g in graphs])
+    karr = (C.c_double * n)(*[float(k) for k in kappas])
+    oarr = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    st = Stats()
+    o = make_opts(stats=st, **kw)
+    _check(load().grf_sample_batched(harr, n, karr, beta, quad_step, n_samples, seed, oarr, C.byref(o)))
+    return outs, st.as_dict()

@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every function include/grf.h declares,
+and validates its inputs on the host (CPU only: no compute call)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_02670_amd import grf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "grf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["grf_graph_create", "grf_graph_info", "grf_graph_destroy", "grf_noise", "grf_sample",
+              "grf_solve_shifted", "grf_sample_batched", "grf_last_error", "grf_opts_init", "grf_shift_count"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(grf.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in grf._SIGS}
+    assert set(_declared()) <= bound, "binding misses a declared function"
+
+
+def test_struct_layouts_match_header():
+    # grf_opts: double, 10 x int32, int64, 3 pointers
+    assert C.sizeof(grf.Opts) == 8 + 10 * 4 + 8 + 3 * 8
+    # grf_stats: 4 int32, int64, double, 4 int32, 12 double, 12 int32
+    assert C.sizeof(grf.Stats) == 4 * 4 + 8 + 8 + 4 * 4 + 12 * 8 + 12 * 4
+
+
+def test_opts_defaults():
+    o = grf.Opts()
+    grf.load().grf_opts_init(C.byref(o))
+    assert o.tol == 1e-12 and o.maxit == 10000 and o.precision == 0 and o.precond == 0
+    assert o.k_minus == -1 and o.k_plus == -1 and o.sample_offset == 0
+
+
+@pytest.mark.parametrize("case", ["isolated", "endpoint", "length", "h", "flags", "nan"])
+def test_graph_create_rejects_bad_input(case):
+    lib = grf.load()
+    V, e, L, h, flags = 3, np.array([[0, 1], [1, 2]], dtype=np.int64), np.array([1.0, 0.5]), 0.1, 0
+    if case == "isolated":
+        V = 4
+    elif case == "endpoint":
+        e = np.array([[0, 1], [1, 3]], dtype=np.int64)
+    elif case == "length":
+        L = np.array([1.0, 0.0])
+    elif case == "h":
+        h = -1.0
+    elif case == "flags":
+        flags = 7
+    elif case == "nan":
+        L = np.array([1.0, np.nan])
+    out = C.c_void_p()
+    rc = lib.grf_graph_create(V, e.shape[0], e.ctypes.data, L.ctypes.data, h, flags, C.byref(out))
+    assert rc == grf.GRF_EINVAL
+    assert out.value is None
+    assert len(lib.grf_last_error()) > 0
+
+
+def test_null_handles_are_rejected():
+    lib = grf.load()
+    assert lib.grf_graph_destroy(None) == grf.GRF_OK
+    assert lib.grf_sample(None, 1.0, 0.5, 0.3, 1, 0, None, None) == grf.GRF_EINVAL
+    assert lib.grf_noise(None, 1, 0, None, None) == grf.GRF_EINVAL
+    assert lib.grf_solve_shifted(None, 1.0, 1.0, 1.0, 1, None, None, None) == grf.GRF_EINVAL
