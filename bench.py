@@ -76,6 +76,8 @@ def main() -> int:
     ap.add_argument("--sweep-block", type=int, default=0)
     ap.add_argument("--shift-block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built "
@@ -90,6 +92,13 @@ def main() -> int:
 
     grf.load()
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = config_c2(beta=args.beta, n_samples=args.samples)
     g = cfg["graph"]
     G = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])

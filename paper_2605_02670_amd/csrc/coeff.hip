@@ -17,6 +17,10 @@
 //   rho_p = 1 / pi_p                       (forward/backward multiplier)
 //   dg_p  = (T^{-1})_{pp} = 1 / (|b| (eps_p + eps_{m-1-p} - eps))
 //   of_p  = (T^{-1})_{p,p+1} = dg_p * rho_{m-2-p}
+// as rho[p] and either the step rows of the two streamed recovery sweeps,
+//   fwdt[k] = (rho_{k-1}, dg_k),  bwdt[k] = (rho_{k-1}, of_k),
+// or the plain rows dg[p], of[p] and zt[p] = (T^{-1})_{p,0} = dg_p prod_{k<p} rho_k
+// that blocked.hip turns into matrix-core operand tables,
 // (the inverse of a symmetric tridiagonal matrix is semiseparable; the
 // diagonal follows from the twisted factorisation, which adds the pivots from
 // both ends; T is persymmetric, so the backward pivots are the forward ones
@@ -30,26 +34,29 @@ namespace grf {
 namespace {
 
 __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restrict__ shift, int32_t LB, int32_t LBp,
-                                              double *__restrict__ rho, double *__restrict__ dg,
-                                              double *__restrict__ of, double *__restrict__ babs,
-                                              double *__restrict__ rhom, double *__restrict__ sd,
-                                              double *__restrict__ so, float *__restrict__ rho32,
-                                              float *__restrict__ dg32, float *__restrict__ of32) {
+                                              double *__restrict__ rho, double2 *__restrict__ fwdt,
+                                              double2 *__restrict__ bwdt, double *__restrict__ dgp,
+                                              double *__restrict__ ofp, double *__restrict__ ztp,
+                                              double *__restrict__ babs, double *__restrict__ rhom,
+                                              double *__restrict__ sd, double *__restrict__ so) {
     const int e = blockIdx.x;
     const int l = blockIdx.y * 64 + threadIdx.x;
     if (l >= LBp) return;
     const int m = mv.m[e];
     const int64_t off = mv.off[e];
     const int64_t E = mv.E;
+    auto at = [&](int p) -> int64_t { return (off + p) * LBp + l; };
     if (l >= LB) {  // padding shifts contribute nothing
         for (int p = 0; p < m; ++p) {
-            rho[(off + p) * LBp + l] = 0.0;
-            dg[(off + p) * LBp + l] = 0.0;
-            of[(off + p) * LBp + l] = 0.0;
-            if (rho32) {
-                rho32[(off + p) * LBp + l] = 0.0f;
-                dg32[(off + p) * LBp + l] = 0.0f;
-                of32[(off + p) * LBp + l] = 0.0f;
+            rho[at(p)] = 0.0;
+            if (fwdt) {
+                fwdt[at(p)] = make_double2(0.0, 0.0);
+                bwdt[at(p)] = make_double2(0.0, 0.0);
+            }
+            if (dgp) {
+                dgp[at(p)] = 0.0;
+                ofp[at(p)] = 0.0;
+                ztp[at(p)] = 0.0;
             }
         }
         babs[e * LBp + l] = 0.0;
@@ -63,38 +70,58 @@ __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restr
     const double gamma = shift[2 * l + 1];
     const double bab = gamma / h;
     const double eps = alpha * h * h / gamma;
-    // pass 1: pivots (eps_p kept in dg as scratch), multipliers, product
-    double ep = 1.0 + eps, prod = 1.0, ep_last = 0.0, r_last = 0.0;
+    // pass 1: pivots eps_p (kept in the dg row as scratch), multipliers rho_p,
+    // prefix products prod_{k<p} rho_k (kept in the zt row as scratch)
+    double *dgs = dgp ? dgp : nullptr;
+    double ep = 1.0 + eps, prod = 1.0, ep_last = 0.0, r_last = 0.0, r_prev = 0.0;
     for (int p = 0; p < m; ++p) {
         const double r = 1.0 / (1.0 + ep);
-        rho[(off + p) * LBp + l] = r;
-        dg[(off + p) * LBp + l] = ep;
+        rho[at(p)] = r;
+        if (fwdt) {
+            fwdt[at(p)] = make_double2(r_prev, ep);  // .x = rho_{p-1}
+            bwdt[at(p)].x = r_prev;
+        }
+        if (dgs) {
+            dgs[at(p)] = ep;
+            ztp[at(p)] = prod;
+        }
         prod *= r;
         ep_last = ep;
         r_last = r;
+        r_prev = r;
         ep = eps + ep * r;
     }
     babs[e * LBp + l] = bab;
     rhom[e * LBp + l] = (m > 0) ? r_last : 0.0;
     sd[(int64_t)l * E + e] = alpha * h * 0.5 + ((m > 0) ? bab * (ep_last * r_last) : bab);
     so[(int64_t)l * E + e] = (m > 0) ? -bab * prod : -bab;
-    // pass 2: diagonal and first off-diagonal of T^{-1}, outside-in in pairs
+    // pass 2: diagonal and first off-diagonal of T^{-1}, outside-in in pairs;
+    // first column (T^{-1})_{p,0} = dg_p prod_{k<p} rho_k
     for (int p = 0; 2 * p < m; ++p) {
         const int q = m - 1 - p;
-        const double d = 1.0 / (bab * (dg[(off + p) * LBp + l] + dg[(off + q) * LBp + l] - eps));
-        dg[(off + p) * LBp + l] = d;
-        dg[(off + q) * LBp + l] = d;
-        if (p <= m - 2) of[(off + p) * LBp + l] = d * rho[(off + m - 2 - p) * LBp + l];
-        if (q != p && q <= m - 2) of[(off + q) * LBp + l] = d * rho[(off + m - 2 - q) * LBp + l];
-    }
-    if (m > 0) of[(off + m - 1) * LBp + l] = 0.0;
-    if (rho32) {
-        for (int p = 0; p < m; ++p) {
-            const int64_t i = (off + p) * LBp + l;
-            rho32[i] = (float)rho[i];
-            dg32[i] = (float)dg[i];
-            of32[i] = (float)of[i];
+        const double ep_p = dgs ? dgs[at(p)] : fwdt[at(p)].y;
+        const double ep_q = dgs ? dgs[at(q)] : fwdt[at(q)].y;
+        const double d = 1.0 / (bab * (ep_p + ep_q - eps));
+        const double ofpv = (p <= m - 2) ? d * rho[at(m - 2 - p)] : 0.0;
+        const double ofqv = (q <= m - 2) ? d * rho[at(m - 2 - q)] : 0.0;
+        if (fwdt) {
+            fwdt[at(p)].y = d;
+            fwdt[at(q)].y = d;
+            if (p <= m - 2) bwdt[at(p)].y = ofpv;
+            if (q != p && q <= m - 2) bwdt[at(q)].y = ofqv;
         }
+        if (dgs) {
+            dgs[at(p)] = d;
+            dgs[at(q)] = d;
+            ofp[at(p)] = ofpv;
+            ofp[at(q)] = ofqv;
+            ztp[at(p)] *= d;
+            if (q != p) ztp[at(q)] *= d;
+        }
+    }
+    if (m > 0) {
+        if (fwdt) bwdt[at(m - 1)].y = 0.0;
+        if (dgs) ofp[at(m - 1)] = 0.0;
     }
 }
 
@@ -104,7 +131,7 @@ void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
     if (mv.E == 0) return;
     GRF_REQUIRE(a.LBp % 8 == 0 && a.LBp >= a.LB, "internal: bad padded shift count");
     hipLaunchKernelGGL(k_coeff, dim3((unsigned)mv.E, (unsigned)((a.LBp + 63) / 64)), dim3(64), 0, st, mv, a.shift,
-                       a.LB, a.LBp, a.rho, a.dg, a.of, a.babs, a.rhom, a.sd, a.so, a.rho32, a.dg32, a.of32);
+                       a.LB, a.LBp, a.rho, a.fwdt, a.bwdt, a.dg, a.of, a.zt, a.babs, a.rhom, a.sd, a.so);
     GRF_LAUNCH_CHECK();
 }
 

@@ -10,6 +10,8 @@
 // Readings (the paper leaves them open): x_0 = 0; Jacobi preconditioner (the
 // diagonal of S); stop when ||g - S x||_2 <= tol ||g||_2 on the residual
 // recomputed from x; g = 0 gives x = 0.
+#include <algorithm>
+
 #include "work.h"
 
 namespace grf {
@@ -182,6 +184,149 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
     }
 }
 
+// Same algorithm with the vectors on chip, for V <= TPB K: each thread keeps
+// x, r, q, the Schur diagonal and the Jacobi inverse of its K vertices in
+// registers; the search direction p (and x, for the recomputed residual) live
+// in LDS where neighbours read them.  Only g is read and x written in HBM.
+template <int K, int TPB>
+__global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__restrict__ sd,
+                                                 const double *__restrict__ so, const double *__restrict__ gT,
+                                                 double *__restrict__ xT, int32_t *__restrict__ its,
+                                                 double *__restrict__ res, int32_t LB, int64_t S, double tol,
+                                                 int32_t maxit) {
+    extern __shared__ double sv[];
+    __shared__ double red[64];
+    const int V = mv.V;
+    const int64_t E = mv.E;
+    double *ps = sv;      // [V] search direction
+    double *xs = sv + V;  // [V] iterate, for the recomputed residual
+    const int nw = blockDim.x >> 6;
+    const int64_t nsys = (int64_t)LB * S;
+    for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
+        const int l = (int)(sys / S);
+        const double *g = gT + sys * V;
+        const double *sdl = sd + (int64_t)l * E;
+        const double *sol = so + (int64_t)l * E;
+        double x[K], r[K], ds[K], ji[K], q[K];
+        double t2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int v = threadIdx.x + TPB * i;
+            x[i] = 0.0;
+            r[i] = 0.0;
+            ds[i] = 0.0;
+            ji[i] = 0.0;
+            q[i] = 0.0;
+            if (v < V) {
+                double d = 0.0, dj = 0.0;
+                for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+                    const int e = mv.adj_e[k];
+                    d += sdl[e];
+                    dj += (mv.adj_o[k] == v) ? sol[e] : 0.0;
+                }
+                ds[i] = d;
+                ji[i] = 1.0 / (d + dj);
+                const double gv = g[v];
+                r[i] = gv;
+                const double z = gv * ji[i];
+                ps[v] = z;
+                t2[0] += gv * z;
+                t2[1] += gv * gv;
+            }
+        }
+        block_sum<2>(t2, red, nw);
+        double rz = t2[0];
+        const double gg = t2[1];
+        const double tol2 = tol * tol * gg;
+        int it = 0;
+        double rel = 0.0;
+        if (gg > 0.0) {
+            rel = 1.0;
+            for (it = 1; it <= maxit; ++it) {
+                __syncthreads();  // p complete
+                double t1[1] = {0.0};
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const int v = threadIdx.x + TPB * i;
+                    if (v < V) {
+                        const double pv = ps[v];
+                        double acc = ds[i] * pv;
+                        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k)
+                            acc += sol[mv.adj_e[k]] * ps[mv.adj_o[k]];
+                        q[i] = acc;
+                        t1[0] += pv * acc;
+                    }
+                }
+                block_sum<1>(t1, red, nw);
+                const double alpha = rz / t1[0];
+                double t3[2] = {0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const int v = threadIdx.x + TPB * i;
+                    if (v < V) {
+                        x[i] += alpha * ps[v];
+                        r[i] -= alpha * q[i];
+                        t3[0] += r[i] * r[i] * ji[i];
+                        t3[1] += r[i] * r[i];
+                    }
+                }
+                block_sum<2>(t3, red, nw);
+                double rz_new = t3[0];
+                double beta;
+                if (t3[1] <= tol2) {
+#pragma unroll
+                    for (int i = 0; i < K; ++i) {
+                        const int v = threadIdx.x + TPB * i;
+                        if (v < V) xs[v] = x[i];
+                    }
+                    __syncthreads();
+                    double tt[2] = {0.0, 0.0};
+#pragma unroll
+                    for (int i = 0; i < K; ++i) {
+                        const int v = threadIdx.x + TPB * i;
+                        if (v < V) {
+                            double acc = ds[i] * xs[v];
+                            for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k)
+                                acc += sol[mv.adj_e[k]] * xs[mv.adj_o[k]];
+                            const double rv = g[v] - acc;
+                            r[i] = rv;
+                            tt[0] += rv * rv;
+                            tt[1] += rv * rv * ji[i];
+                        }
+                    }
+                    block_sum<2>(tt, red, nw);
+                    rel = sqrt(tt[0] / gg);
+                    if (tt[0] <= tol2) break;
+                    rz_new = tt[1];
+                    beta = 0.0;
+                } else {
+                    rel = sqrt(t3[1] / gg);
+                    beta = rz_new / rz;
+                }
+                rz = rz_new;
+                __syncthreads();  // every read of p done
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const int v = threadIdx.x + TPB * i;
+                    if (v < V) ps[v] = r[i] * ji[i] + beta * ps[v];
+                }
+            }
+            if (it > maxit) it = maxit + 1;
+        }
+        double *xo = xT + sys * V;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int v = threadIdx.x + TPB * i;
+            if (v < V) xo[v] = (gg > 0.0) ? x[i] : 0.0;
+        }
+        if (threadIdx.x == 0) {
+            its[sys] = it;
+            res[sys] = rel;
+        }
+        __syncthreads();  // LDS reused by the next system
+    }
+}
+
 // ug[l][v][s] = xT[l][s][v] (padded samples 0) and U[b][NI+v][s] += sum_l xT[l][s][v],
 // shifts summed in increasing order.
 __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const double *__restrict__ xT, int32_t LB,
@@ -230,9 +375,30 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
+template <int K, int TPB>
+static void pcg_lds(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    const int64_t nsys = (int64_t)a.LB * a.S;
+    const size_t lds = 2 * sizeof(double) * (size_t)mv.V;
+    static bool attr_set = false;
+    if (!attr_set) {
+        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    65536));
+        attr_set = true;
+    }
+    const int64_t blocks = std::min<int64_t>(nsys, 256 * (2048 / TPB));
+    hipLaunchKernelGGL((k_pcg_lds<K, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a.sd, a.so, a.gT, a.xT,
+                       a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+    GRF_LAUNCH_CHECK();
+}
+
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
     int64_t nsys = (int64_t)a.LB * a.S;
+    if (mv.V <= 256) return pcg_lds<1, 256>(mv, a, st);
+    if (mv.V <= 512) return pcg_lds<2, 256>(mv, a, st);
+    if (mv.V <= 1024) return pcg_lds<2, 512>(mv, a, st);
+    if (mv.V <= 2048) return pcg_lds<2, 1024>(mv, a, st);
+    if (mv.V <= 4096) return pcg_lds<4, 1024>(mv, a, st);
     int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
     hipLaunchKernelGGL(k_pcg, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr, a.its,
                        a.res, a.LB, a.S, a.tol, a.maxit);

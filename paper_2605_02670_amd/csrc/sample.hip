@@ -35,8 +35,9 @@ static void set_kappa2(grf_graph &g, double kappa, hipStream_t st) {
 }
 
 struct Plan {
-    int32_t LB = 0;   // shifts per pass
-    int32_t BL = 0;   // shifts per wavefront
+    bool blocked = true;  // matrix-core sweeps (otherwise streamed recurrences)
+    int32_t LB = 0;       // shifts per pass
+    int32_t BL = 0;       // streamed: shifts per wavefront; blocked: padding granule (16)
     int32_t pcg_blocks = 0;
 };
 
@@ -49,14 +50,19 @@ static int32_t auto_bl(int32_t L) {
 
 static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &o) {
     Plan p;
-    p.BL = o.sweep_block ? o.sweep_block : auto_bl(L);
+    p.blocked = (o.sweep_block == 0);
+    p.BL = p.blocked ? 16 : o.sweep_block;
     const int64_t nb = (S + 63) / 64, Sp = 64 * nb;
-    const double per_shift = 8.0 * (3.0 * g.NI + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V + (double)g.V * Sp) +
-                             12.0 * S;
+    // bytes per shift of the per-pass buffers
+    const double rows = p.blocked ? 4.0 : 5.0;
+    const double btab = p.blocked ? (1536.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
+    const double per_shift = 8.0 * (rows * g.NI + btab + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V +
+                                    (double)g.V * Sp) + 12.0 * S;
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)64 << 30;
     double budget = 0.5 * (double)freeb;
     int64_t lb = o.shift_block > 0 ? o.shift_block : (int64_t)std::floor(budget / per_shift);
+    if (p.blocked) lb = std::min<int64_t>(lb, 128);
     lb = std::min<int64_t>(lb, L);
     if (lb < L) lb = std::max<int64_t>(p.BL, (lb / p.BL) * p.BL);
     lb = std::max<int64_t>(1, std::min<int64_t>(lb, L));
@@ -65,6 +71,13 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     int64_t blocks = (int64_t)std::min(2048.0, std::max(1.0, std::floor((2.0 * (1 << 30)) / vbytes)));
     p.pcg_blocks = (int32_t)blocks;
     return p;
+}
+
+static void ensure_block_offsets(grf_graph &g, grf_graph::Work &w, hipStream_t st, int64_t &nblocks) {
+    std::vector<int32_t> bo(g.E + 1, 0);
+    for (int64_t e = 0; e < g.E; ++e) bo[e + 1] = bo[e] + (g.m[e] + 15) / 16;
+    nblocks = bo[g.E];
+    upload(w.boff, bo, st);
 }
 
 // Runs shifts (cI[i], cL[i]) on the right-hand sides in w.X, accumulating into
@@ -81,7 +94,7 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
     double max_res = 0.0;
     for (int32_t l0 = 0; l0 < L; l0 += p.LB) {
         const int32_t lb = std::min(p.LB, L - l0);
-        const int32_t LBp = ((lb + p.BL - 1) / p.BL) * p.BL;
+        const int32_t LBp = ((lb + p.BL - 1) / p.BL) * p.BL;  // blocked: multiple of 16
         std::vector<double> sh(2 * (size_t)LBp, 0.0);
         for (int32_t i = 0; i < lb; ++i) {
             sh[2 * i] = cI[l0 + i];
@@ -89,9 +102,16 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         }
         for (int32_t i = lb; i < LBp; ++i) sh[2 * i + 1] = 1.0;  // padding: never used as a divisor of 0
         upload(w.shift, sh, st);
-        w.rho.reserve(8 * (size_t)std::max<int64_t>(g.NI, 1) * LBp);
-        w.dg.reserve(8 * (size_t)std::max<int64_t>(g.NI, 1) * LBp);
-        w.of.reserve(8 * (size_t)std::max<int64_t>(g.NI, 1) * LBp);
+        const size_t nir = (size_t)std::max<int64_t>(g.NI, 1) * LBp;
+        w.rho.reserve(8 * nir);
+        if (p.blocked) {
+            w.dgp.reserve(8 * nir);
+            w.ofp.reserve(8 * nir);
+            w.ztp.reserve(8 * nir);
+        } else {
+            w.fwdt.reserve(16 * nir);
+            w.bwdt.reserve(16 * nir);
+        }
         w.babs.reserve(8 * (size_t)g.E * LBp + 8);
         w.rhom.reserve(8 * (size_t)g.E * LBp + 8);
         w.sd.reserve(8 * (size_t)g.E * LBp + 8);
@@ -109,8 +129,11 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         ca.LB = lb;
         ca.LBp = LBp;
         ca.rho = w.rho.as<double>();
-        ca.dg = w.dg.as<double>();
-        ca.of = w.of.as<double>();
+        ca.fwdt = p.blocked ? nullptr : w.fwdt.as<double2>();
+        ca.bwdt = p.blocked ? nullptr : w.bwdt.as<double2>();
+        ca.dg = p.blocked ? w.dgp.as<double>() : nullptr;
+        ca.of = p.blocked ? w.ofp.as<double>() : nullptr;
+        ca.zt = p.blocked ? w.ztp.as<double>() : nullptr;
         ca.babs = w.babs.as<double>();
         ca.rhom = w.rhom.as<double>();
         ca.sd = w.sd.as<double>();
@@ -123,8 +146,8 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         sa.X = w.X.as<double>();
         sa.U = w.U.as<double>();
         sa.rho = ca.rho;
-        sa.dg = ca.dg;
-        sa.of = ca.of;
+        sa.fwdt = ca.fwdt;
+        sa.bwdt = ca.bwdt;
         sa.babs = ca.babs;
         sa.rhom = ca.rhom;
         sa.ug = w.ug.as<double>();
@@ -134,12 +157,47 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         sa.nb = nb;
         sa.Sp = Sp;
         sa.bl = p.BL;
-        T.begin(GRF_K_ENDS_FWD);
-        launch_sweep_ends(mv, sa, true, st);
-        T.end();
-        T.begin(GRF_K_ENDS_BWD);
-        launch_sweep_ends(mv, sa, false, st);
-        T.end();
+
+        BlockArgs ba{};
+        if (p.blocked) {
+            int64_t nblocks = 0;
+            ensure_block_offsets(g, w, st, nblocks);
+            ba.boff = w.boff.as<int32_t>();
+            ba.nblocks = nblocks;
+            ba.NT = LBp / 16;
+            ba.LB = lb;
+            ba.LBp = LBp;
+            ba.rho = ca.rho;
+            ba.dg = ca.dg;
+            ba.of = ca.of;
+            ba.zt = ca.zt;
+            ba.babs = ca.babs;
+            ba.rhom = ca.rhom;
+            w.btab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * block_tab_doubles(ba.NT));
+            ba.tab = w.btab.as<double>();
+            ba.X = sa.X;
+            ba.U = sa.U;
+            ba.ends = sa.ends;
+            ba.ug = sa.ug;
+            ba.nb = nb;
+            ba.Sp = Sp;
+            T.begin(GRF_K_COEFF);
+            launch_blocktab(mv, ba, st);
+            T.end();
+            T.begin(GRF_K_ENDS_FWD);
+            launch_sweep_blocked(mv, ba, true, st);
+            T.end();
+            T.begin(GRF_K_ENDS_BWD);
+            launch_sweep_blocked(mv, ba, false, st);
+            T.end();
+        } else {
+            T.begin(GRF_K_ENDS_FWD);
+            launch_sweep_ends(mv, sa, true, st);
+            T.end();
+            T.begin(GRF_K_ENDS_BWD);
+            launch_sweep_ends(mv, sa, false, st);
+            T.end();
+        }
 
         SchurArgs sc{};
         sc.X = sa.X;
@@ -170,12 +228,18 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         T.begin(GRF_K_SCATTER);
         launch_vertex_scatter(mv, sc, st);
         T.end();
-        T.begin(GRF_K_ACC_FWD);
-        launch_sweep_acc(mv, sa, true, st);
-        T.end();
-        T.begin(GRF_K_ACC_BWD);
-        launch_sweep_acc(mv, sa, false, st);
-        T.end();
+        if (p.blocked) {
+            T.begin(GRF_K_ACC_FWD);
+            launch_corr_blocked(mv, ba, st);
+            T.end();
+        } else {
+            T.begin(GRF_K_ACC_FWD);
+            launch_sweep_acc(mv, sa, true, st);
+            T.end();
+            T.begin(GRF_K_ACC_BWD);
+            launch_sweep_acc(mv, sa, false, st);
+            T.end();
+        }
 
         w.h_its.resize((size_t)lb * S);
         w.h_res.resize((size_t)lb * S);
@@ -199,7 +263,7 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         stats->max_rel_residual = max_res;
         stats->refine_steps = 0;
         stats->shift_block = p.LB;
-        stats->sweep_block = p.BL;
+        stats->sweep_block = p.blocked ? 0 : p.BL;
     }
     if (n_unconv > 0) {
         set_error("%lld vertex Schur systems did not reach tol=%g within maxit=%d", (long long)n_unconv, o.tol,

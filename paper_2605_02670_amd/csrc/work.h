@@ -5,7 +5,11 @@
 
 struct grf_graph::Work {
     grf::DevBuf X, U;             // sample-interleaved [nb][N][64]: input (noise / rhs) and accumulator
-    grf::DevBuf rho, dg, of;      // per-DOF Thomas rows [NI][LBp]
+    grf::DevBuf rho;              // per-DOF multipliers [NI][LBp]
+    grf::DevBuf fwdt, bwdt;       // per-DOF step rows [NI][LBp] of (rho_{k-1}, dg_k) / (rho_{k-1}, of_k)
+    grf::DevBuf dgp, ofp, ztp;    // per-DOF plain rows [NI][LBp] (blocked sweeps)
+    grf::DevBuf btab;             // matrix-core operand tables per 16-position edge block
+    grf::DevBuf boff;             // [E+1] first block of every edge
     grf::DevBuf babs, rhom;       // per-edge [E][LBp]: |b| = gamma/h_e, rho_{m-1}
     grf::DevBuf sd, so;           // per-edge Schur 2x2 [LBp][E]: diagonal, off-diagonal
     grf::DevBuf shift;            // [LBp][2]: c_I, c_L of the shifts in the block
@@ -37,10 +41,11 @@ void launch_fill(double *p, size_t n, double v, hipStream_t st);
 struct CoeffArgs {
     const double *shift;  // [LBp][2] c_I, c_L
     int32_t LB, LBp;
-    double *rho, *dg, *of;  // [NI][LBp]
+    double *rho;            // [NI][LBp]
+    double2 *fwdt, *bwdt;   // [NI][LBp] streamed-sweep rows, or null
+    double *dg, *of, *zt;   // [NI][LBp] plain rows for the blocked sweeps, or null
     double *babs, *rhom;    // [E][LBp]
     double *sd, *so;        // [LBp][E]
-    float *rho32, *dg32, *of32;  // optional FP32 copies (mixed precision), may be null
 };
 void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
 
@@ -48,8 +53,8 @@ void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
 struct SweepArgs {
     const double *X;        // [nb][N][64] right-hand sides (noise)
     double *U;              // [nb][N][64] accumulator (acc mode)
-    const double *rho, *dg, *of;  // [NI][LBp]
-    const float *rho32, *dg32, *of32;
+    const double *rho;      // [NI][LBp]
+    const double2 *fwdt, *bwdt;  // [NI][LBp]
     const double *babs, *rhom;    // [E][LBp]
     const double *ug;       // [LB][V][Sp] vertex solutions (acc mode)
     double *ends;           // [LB][E][2][Sp] (ends mode)
@@ -59,6 +64,26 @@ struct SweepArgs {
 };
 void launch_sweep_ends(const MeshView &mv, const SweepArgs &a, bool fwd, hipStream_t st);
 void launch_sweep_acc(const MeshView &mv, const SweepArgs &a, bool fwd, hipStream_t st);
+
+// blocked (matrix-core) sweeps: 16-position edge blocks, shifts padded to 16*NT
+struct BlockArgs {
+    const int32_t *boff;    // [E+1] first block of every edge
+    int64_t nblocks;        // blocks of the whole graph
+    int32_t NT;             // shift tiles of 16
+    int32_t LB, LBp;        // real / padded shifts (LBp = 16 NT)
+    const double *rho, *dg, *of, *zt;  // plain rows [NI][LBp]
+    const double *babs, *rhom;         // [E][LBp]
+    double *tab;            // operand tables, tab_doubles(NT) per block
+    const double *X;        // [nb][N][64]
+    double *U;              // [nb][N][64]
+    double *ends;           // [LB][E][2][Sp]
+    const double *ug;       // [LB][V][Sp]
+    int32_t nb, Sp;
+};
+int64_t block_tab_doubles(int32_t NT);
+void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st);
+void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st);
+void launch_corr_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st);
 
 // vertex Schur complement: condensed rhs, PCG, layout changes, accumulation
 struct SchurArgs {

@@ -92,7 +92,7 @@ def test_solve_shifted_ragged(grf, kappa, cI, cL):
     assert st["n_unconverged"] == 0 and st["max_rel_residual"] <= 1e-12
 
 
-@pytest.mark.parametrize("sweep_block", [8, 16, 32, 64])
+@pytest.mark.parametrize("sweep_block", [0, 8, 16, 32, 64])  # 0 = blocked matrix-core sweeps
 def test_sample_c1(grf, c1, sweep_block):
     cfg, m, G = c1
     u, st = G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], cfg["n_samples"], cfg["seed"],
@@ -103,7 +103,7 @@ def test_sample_c1(grf, c1, sweep_block):
     assert _rel_ml(u.cpu().numpy(), ref, omesh.lumped_mass(m)) <= TOL
 
 
-@pytest.mark.parametrize("shift_block,sweep_block", [(0, 0), (7, 8), (16, 16), (3, 32)])
+@pytest.mark.parametrize("shift_block,sweep_block", [(0, 0), (16, 0), (40, 0), (7, 8), (16, 16), (3, 32)])
 def test_sample_ragged_multipass(grf, shift_block, sweep_block):
     V, E, L = _ragged_graph()
     m = omesh.build_mesh(V, E, L, 0.05, "round")
