@@ -52,11 +52,9 @@ struct TabLayout {
     __host__ __device__ int64_t DT() const { return 256 * NT; }           // [t][r][64]: d[16t + 4r + L/16]
     __host__ __device__ int64_t HF() const { return 512 * NT; }           // [t][r][64]: H_fwd[L%16][16t + 4r + L/16]
     __host__ __device__ int64_t HB() const { return 768 * NT; }           // [t][r][64]: H_bwd[...]
-    __host__ __device__ int64_t ZT() const { return 1024 * NT; }          // [t][r][64]: (T^-1)_{16b + L%16, 0}
-    __host__ __device__ int64_t ZH() const { return 1280 * NT; }          // [t][r][64]: (T^-1)_{16b + L%16, m-1}
-    __host__ __device__ int64_t GF() const { return 1536 * NT; }          // [c][64]: Ghat_fwd[L%16][4c + L/16]
-    __host__ __device__ int64_t GB() const { return 1536 * NT + 256; }    // [c][64]: Ghat_bwd
-    __host__ __device__ int64_t size() const { return 1536 * (int64_t)NT + 512; }
+    __host__ __device__ int64_t GF() const { return 1024 * NT; }          // [c][64]: Ghat_fwd[L%16][4c + L/16]
+    __host__ __device__ int64_t GB() const { return 1024 * NT + 256; }    // [c][64]: Ghat_bwd
+    __host__ __device__ int64_t size() const { return 1024 * (int64_t)NT + 512; }
 };
 
 __device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk) {
@@ -69,13 +67,12 @@ __device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk
 }
 
 // One workgroup per edge block: stage the block's rows in LDS, then
-//   phase 1 (thread = shift): C, d, H_fwd, H_bwd, Z rows,
+//   phase 1 (thread = shift): C, d, H_fwd, H_bwd,
 //   phase 2 (thread = (i, j)): Ghat_fwd, Ghat_bwd, summed over shifts in order.
 __global__ void __launch_bounds__(256) k_blocktab(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
                                                   const int32_t *__restrict__ boff, int32_t E, int32_t LBp, int32_t NT,
                                                   const double *__restrict__ rho, const double *__restrict__ dg,
-                                                  const double *__restrict__ of, const double *__restrict__ zt,
-                                                  double *__restrict__ tab) {
+                                                  const double *__restrict__ of, double *__restrict__ tab) {
     extern __shared__ double sm[];
     double *srho = sm;               // [17][LBp]: rho_{16b-1 .. 16b+15}
     double *sdg = sm + 17 * LBp;     // [16][LBp]
@@ -126,9 +123,6 @@ __global__ void __launch_bounds__(256) k_blocktab(const int64_t *__restrict__ of
             const int64_t o = ((int64_t)t * 4 + r) * 64 + i + 16 * kk;
             T[TL.HF() + o] = sdg[i * LBp + l] * li;
             T[TL.HB() + o] = sof[i * LBp + l] * li;
-            const int p = base + i;
-            T[TL.ZT() + o] = (p < m) ? zt[(off + p) * LBp + l] : 0.0;
-            T[TL.ZH() + o] = (p < m) ? zt[(off + (m - 1 - p)) * LBp + l] : 0.0;
             if (i < 15) lam *= r_at(base + i, l);
         }
         for (int n = 0; n < 16; ++n) T[TL.DT() + ((int64_t)t * 4 + r) * 64 + 16 * kk + n] = dv;
@@ -273,14 +267,16 @@ __global__ void __launch_bounds__(256) k_sweep_blocked(const int64_t *__restrict
         }
 }
 
-// Pass B: u_I += sum_l |b_l| (u_tail^l Z_tail^l + u_head^l Z_head^l)
+// Pass B: u_I += sum_l |b_l| (u_tail^l Z_tail^l + u_head^l Z_head^l), with
+// Z_tail = (T^{-1})_{.,0} and Z_head = (T^{-1})_{.,m-1} in operand layout
+// (written by the coefficient kernel: [t][r][64] tail, then [t][r][64] head).
 template <int NT>
 __global__ void __launch_bounds__(256) k_corr_blocked(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
                                                       const int32_t *__restrict__ eu_,
                                                       const int32_t *__restrict__ ev_,
                                                       const int32_t *__restrict__ boff, int32_t E, int32_t V,
                                                       int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
-                                                      const double *__restrict__ tab,
+                                                      const double *__restrict__ ztab,
                                                       const double *__restrict__ babs,
                                                       const double *__restrict__ ug, double *__restrict__ U) {
     const int L = threadIdx.x & 63;
@@ -297,7 +293,6 @@ __global__ void __launch_bounds__(256) k_corr_blocked(const int64_t *__restrict_
     const int64_t off = off_[e];
     double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     const int vt = eu_[e], vh = ev_[e];
-    const TabLayout TL{NT};
     double ct[NT][4], ch[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -313,19 +308,19 @@ __global__ void __launch_bounds__(256) k_corr_blocked(const int64_t *__restrict_
     const int64_t eb0 = boff[e];
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
-        const double *T = tab + (eb0 + beta) * TL.size();
+        const double *Z = ztab + (eb0 + beta) * (int64_t)(512 * NT);
         d4 F0 = d4{0.0, 0.0, 0.0, 0.0}, F1 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                F0 = mfma(T[TL.ZT() + (t * 4 + r) * 64 + L], ct[t][r], F0);
-                F1 = mfma(T[TL.ZH() + (t * 4 + r) * 64 + L], ch[t][r], F1);
+                F0 = mfma(Z[(t * 4 + r) * 64 + L], ct[t][r], F0);
+                F1 = mfma(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F1);
             }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int p = 16 * beta + 4 * r + kq;
-            if (p < m) ub[(int64_t)p * 64] += F0[r] + F1[r];
+            const int pp = 16 * beta + 4 * r + kq;
+            if (pp < m) ub[(int64_t)pp * 64] += F0[r] + F1[r];
         }
     }
 }
@@ -348,7 +343,7 @@ void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const int64_t waves = (int64_t)mv.E * 4 * a.nb;
     dim3 grid((unsigned)((waves + 3) / 4));
     hipLaunchKernelGGL((k_corr_blocked<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E, mv.V,
-                       mv.N, a.nb, a.Sp, a.LB, a.LBp, a.tab, a.babs, a.ug, a.U);
+                       mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U);
     GRF_LAUNCH_CHECK();
 }
 
@@ -362,7 +357,7 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
     const size_t lds = sizeof(double) * 49 * (size_t)a.LBp;
     hipLaunchKernelGGL(k_blocktab, dim3((unsigned)a.nblocks), dim3(256), lds, st, mv.off, mv.m, a.boff, mv.E, a.LBp,
-                       a.NT, a.rho, a.dg, a.of, a.zt, a.tab);
+                       a.NT, a.rho, a.dg, a.of, a.tab);
     GRF_LAUNCH_CHECK();
 }
 

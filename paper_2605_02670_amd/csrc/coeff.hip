@@ -28,6 +28,8 @@
 //   s_d = delta - b^2 (T^{-1})_{11} = alpha h / 2 + |b| eps_{m-1} / (1 + eps_{m-1})
 //   s_o = -b^2 (T^{-1})_{1m}        = -|b| prod_p rho_p
 // (an edge with no interior node has s_d = delta, s_o = b).
+#include <algorithm>
+
 #include "work.h"
 
 namespace grf {
@@ -37,6 +39,7 @@ __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restr
                                               double *__restrict__ rho, double2 *__restrict__ fwdt,
                                               double2 *__restrict__ bwdt, double *__restrict__ dgp,
                                               double *__restrict__ ofp, double *__restrict__ ztp,
+                                              double *__restrict__ epsp,
                                               double *__restrict__ babs, double *__restrict__ rhom,
                                               double *__restrict__ sd, double *__restrict__ so) {
     const int e = blockIdx.x;
@@ -82,7 +85,7 @@ __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restr
             bwdt[at(p)].x = r_prev;
         }
         if (dgs) {
-            dgs[at(p)] = ep;
+            epsp[at(p)] = ep;
             ztp[at(p)] = prod;
         }
         prod *= r;
@@ -95,8 +98,8 @@ __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restr
     rhom[e * LBp + l] = (m > 0) ? r_last : 0.0;
     sd[(int64_t)l * E + e] = alpha * h * 0.5 + ((m > 0) ? bab * (ep_last * r_last) : bab);
     so[(int64_t)l * E + e] = (m > 0) ? -bab * prod : -bab;
-    // pass 2: diagonal and first off-diagonal of T^{-1}, outside-in in pairs;
-    // first column (T^{-1})_{p,0} = dg_p prod_{k<p} rho_k
+    if (dgs) return;  // the blocked path finishes the rows in k_coeff_finish (parallel over positions)
+    // pass 2: diagonal and first off-diagonal of T^{-1}, outside-in in pairs
     for (int p = 0; 2 * p < m; ++p) {
         const int q = m - 1 - p;
         const double ep_p = dgs ? dgs[at(p)] : fwdt[at(p)].y;
@@ -125,14 +128,73 @@ __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restr
     }
 }
 
+// Finish the plain rows, one thread per (interior DOF, shift): with eps_p in
+// the eps scratch and prod_{k<p} rho_k in the prefix scratch from the
+// sequential pass,
+//   dg_p = 1 / (|b| (eps_p + eps_{m-1-p} - eps)),  of_p = dg_p rho_{m-2-p},
+//   (T^{-1})_{p,0} = dg_p prod_{k<p} rho_k.
+// eps_p >= eps, so eps_p + eps_{m-1-p} - eps >= eps_{m-1-p} > 0 (no cancellation).
+__global__ void __launch_bounds__(256) k_coeff_finish(MeshView mv, const int32_t *__restrict__ dof_edge,
+                                                      const double *__restrict__ shift, int32_t LB, int32_t LBp,
+                                                      const double *__restrict__ rho, const double *__restrict__ eps_in,
+                                                      double *__restrict__ dg, double *__restrict__ of,
+                                                      const double *__restrict__ prefix,
+                                                      const int32_t *__restrict__ boff, int32_t NT,
+                                                      double *__restrict__ ztab) {
+    const int64_t n = mv.NI * LBp;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pos = idx / LBp;
+        const int l = (int)(idx - pos * LBp);
+        const int e = dof_edge[pos];
+        const int64_t off = mv.off[e];
+        const int m = mv.m[e];
+        const int p = (int)(pos - off);
+        double z = 0.0;  // padding shifts: zero operands (their dg/of rows were zeroed by k_coeff)
+        if (l < LB) {
+            const double h = mv.he[e];
+            const double alpha = shift[2 * l] + shift[2 * l + 1] * mv.kap2[e];
+            const double gamma = shift[2 * l + 1];
+            const double bab = gamma / h;
+            const double eps = alpha * h * h / gamma;
+            const double ep = eps_in[idx];
+            const double eq = eps_in[(off + (m - 1 - p)) * LBp + l];
+            const double d = 1.0 / (bab * (ep + eq - eps));
+            of[idx] = (p <= m - 2) ? d * rho[(off + (m - 2 - p)) * LBp + l] : 0.0;
+            dg[idx] = d;
+            z = d * prefix[idx];
+        }
+        // z = (T^{-1})_{p,0} = dg_p prod_{k<p} rho_k, stored in the pass-B operand
+        // layout of the block of p (row p%16, shift slot 16t + 4r + k <-> lane row + 16k),
+        // and, by persymmetry, as (T^{-1})_{m-1-p, m-1} in the block of m-1-p
+        const int t = l >> 4, r = (l & 15) >> 2, k = l & 3;
+        const int64_t base_t = (boff[e] + (p >> 4)) * (int64_t)(512 * NT);
+        ztab[base_t + ((int64_t)t * 4 + r) * 64 + (p & 15) + 16 * k] = z;
+        const int ph = m - 1 - p;
+        const int64_t base_h = (boff[e] + (ph >> 4)) * (int64_t)(512 * NT) + 256 * NT;
+        ztab[base_h + ((int64_t)t * 4 + r) * 64 + (ph & 15) + 16 * k] = z;
+    }
+}
+
 }  // namespace
 
 void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
     if (mv.E == 0) return;
     GRF_REQUIRE(a.LBp % 8 == 0 && a.LBp >= a.LB, "internal: bad padded shift count");
     hipLaunchKernelGGL(k_coeff, dim3((unsigned)mv.E, (unsigned)((a.LBp + 63) / 64)), dim3(64), 0, st, mv, a.shift,
-                       a.LB, a.LBp, a.rho, a.fwdt, a.bwdt, a.dg, a.of, a.zt, a.babs, a.rhom, a.sd, a.so);
+                       a.LB, a.LBp, a.rho, a.fwdt, a.bwdt, a.dg, a.of, a.zt, a.eps, a.babs, a.rhom, a.sd, a.so);
     GRF_LAUNCH_CHECK();
+    if (a.dg) {
+        GRF_REQUIRE(a.eps && a.dof_edge && a.boff && a.ztab && a.LBp == 16 * a.NT,
+                    "internal: blocked rows need the eps scratch, the DOF-edge map and the block layout");
+        const int64_t n = mv.NI * (int64_t)a.LBp;
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+        if (n > 0) {
+            hipLaunchKernelGGL(k_coeff_finish, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.dof_edge, a.shift, a.LB,
+                               a.LBp, a.rho, a.eps, a.dg, a.of, a.zt, a.boff, a.NT, a.ztab);
+            GRF_LAUNCH_CHECK();
+        }
+    }
 }
 
 }  // namespace grf

@@ -54,7 +54,7 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     p.BL = p.blocked ? 16 : o.sweep_block;
     const int64_t nb = (S + 63) / 64, Sp = 64 * nb;
     // bytes per shift of the per-pass buffers
-    const double rows = p.blocked ? 4.0 : 5.0;
+    const double rows = p.blocked ? 5.0 : 5.0;
     const double btab = p.blocked ? (1536.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
     const double per_shift = 8.0 * (rows * g.NI + btab + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V +
                                     (double)g.V * Sp) + 12.0 * S;
@@ -108,6 +108,7 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
             w.dgp.reserve(8 * nir);
             w.ofp.reserve(8 * nir);
             w.ztp.reserve(8 * nir);
+            w.epsp.reserve(8 * nir);
         } else {
             w.fwdt.reserve(16 * nir);
             w.bwdt.reserve(16 * nir);
@@ -124,6 +125,11 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         w.res.reserve(8 * (size_t)lb * S);
         w.pcg_scr.reserve(pcg_scratch_bytes(mv, p.pcg_blocks));
 
+        int64_t nblocks = 0;
+        if (p.blocked) {
+            ensure_block_offsets(g, w, st, nblocks);
+            w.ztab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * 512 * (LBp / 16));
+        }
         CoeffArgs ca{};
         ca.shift = w.shift.as<double>();
         ca.LB = lb;
@@ -134,6 +140,11 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         ca.dg = p.blocked ? w.dgp.as<double>() : nullptr;
         ca.of = p.blocked ? w.ofp.as<double>() : nullptr;
         ca.zt = p.blocked ? w.ztp.as<double>() : nullptr;
+        ca.eps = p.blocked ? w.epsp.as<double>() : nullptr;
+        ca.dof_edge = g.d_dofedge.as<int32_t>();
+        ca.boff = p.blocked ? w.boff.as<int32_t>() : nullptr;
+        ca.NT = LBp / 16;
+        ca.ztab = p.blocked ? w.ztab.as<double>() : nullptr;
         ca.babs = w.babs.as<double>();
         ca.rhom = w.rhom.as<double>();
         ca.sd = w.sd.as<double>();
@@ -160,8 +171,6 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
 
         BlockArgs ba{};
         if (p.blocked) {
-            int64_t nblocks = 0;
-            ensure_block_offsets(g, w, st, nblocks);
             ba.boff = w.boff.as<int32_t>();
             ba.nblocks = nblocks;
             ba.NT = LBp / 16;
@@ -175,6 +184,7 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
             ba.rhom = ca.rhom;
             w.btab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * block_tab_doubles(ba.NT));
             ba.tab = w.btab.as<double>();
+            ba.ztab = w.ztab.as<double>();
             ba.X = sa.X;
             ba.U = sa.U;
             ba.ends = sa.ends;

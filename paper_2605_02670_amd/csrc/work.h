@@ -8,7 +8,9 @@ struct grf_graph::Work {
     grf::DevBuf rho;              // per-DOF multipliers [NI][LBp]
     grf::DevBuf fwdt, bwdt;       // per-DOF step rows [NI][LBp] of (rho_{k-1}, dg_k) / (rho_{k-1}, of_k)
     grf::DevBuf dgp, ofp, ztp;    // per-DOF plain rows [NI][LBp] (blocked sweeps)
+    grf::DevBuf epsp;             // pivot scratch [NI][LBp]
     grf::DevBuf btab;             // matrix-core operand tables per 16-position edge block
+    grf::DevBuf ztab;             // pass-B operand tables per edge block
     grf::DevBuf boff;             // [E+1] first block of every edge
     grf::DevBuf babs, rhom;       // per-edge [E][LBp]: |b| = gamma/h_e, rho_{m-1}
     grf::DevBuf sd, so;           // per-edge Schur 2x2 [LBp][E]: diagonal, off-diagonal
@@ -44,6 +46,11 @@ struct CoeffArgs {
     double *rho;            // [NI][LBp]
     double2 *fwdt, *bwdt;   // [NI][LBp] streamed-sweep rows, or null
     double *dg, *of, *zt;   // [NI][LBp] plain rows for the blocked sweeps, or null
+    double *eps;            // [NI][LBp] pivot scratch (blocked sweeps)
+    const int32_t *dof_edge;  // [NI] edge of every interior DOF (blocked sweeps)
+    const int32_t *boff;    // [E+1] first block of every edge (blocked sweeps)
+    int32_t NT;             // shift tiles (blocked sweeps)
+    double *ztab;           // pass-B operands, 512 NT doubles per block (blocked sweeps)
     double *babs, *rhom;    // [E][LBp]
     double *sd, *so;        // [LBp][E]
 };
@@ -74,6 +81,7 @@ struct BlockArgs {
     const double *rho, *dg, *of, *zt;  // plain rows [NI][LBp]
     const double *babs, *rhom;         // [E][LBp]
     double *tab;            // operand tables, tab_doubles(NT) per block
+    const double *ztab;     // pass-B operands (first/last columns of T^{-1}), 512 NT per block
     const double *X;        // [nb][N][64]
     double *U;              // [nb][N][64]
     double *ends;           // [LB][E][2][Sp]
