@@ -32,6 +32,8 @@
 // A D-layout register r of shift tile t is used directly as a B operand with
 // K-slot k <-> shift 16t + 4r + k, so the carried state never changes layout;
 // the tables store H, Z in that shift order.
+#include <algorithm>
+
 #include "work.h"
 
 namespace grf {
@@ -45,16 +47,84 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// table section offsets (doubles) within one block's table
+// Closed form of the interior block.  T / |b| = tridiag(-1, 2 cosh(theta), -1)
+// with cosh(theta) = 1 + eps / 2, so with s_k = sinh(k theta) (Chebyshev
+// recurrence s_{k+1} = 2 cosh(theta) s_k - s_{k-1}) the Thomas pivots are
+// pi_p = s_{p+2} / s_{p+1}, the multipliers rho_p = s_{p+1} / s_{p+2}, every
+// product of consecutive multipliers telescopes,
+//     prod_{k=a}^{c-1} rho_k = s_{a+1} / s_{c+1},
+// and the inverse is
+//     (T^{-1})_{pq} = s_{min(p,q)+1} s_{m-max(p,q)} / (|b| s_1 s_{m+1}).
+// Every quantity is evaluated as an expression in w = e^{-theta} and
+// E(k) = 1 - e^{-2 k theta} = 2 e^{-k theta} s_k (expm1, no cancellation for
+// small theta, no overflow for large theta); there is no sequential pass over
+// the positions of an edge.
+struct EdgeShift {
+    double bab;  // |b| = gamma / h
+    double th;   // theta = 2 asinh(sqrt(eps) / 2)
+    double w;    // e^{-theta}
+    double E1;   // E(1)
+    double sh2;  // 2 sinh(theta) = 2 sqrt(eps (1 + eps / 4))
+    double ah;   // alpha h / 2
+};
+
+__device__ __forceinline__ EdgeShift edge_shift(double cI, double cL, double kap2, double h) {
+    EdgeShift s;
+    const double alpha = cI + cL * kap2;
+    s.bab = cL / h;
+    const double eps = alpha * h * h / cL;
+    const double se = sqrt(eps);
+    s.th = 2.0 * asinh(0.5 * se);
+    s.w = exp(-s.th);
+    s.E1 = -expm1(-2.0 * s.th);
+    s.sh2 = 2.0 * se * sqrt(1.0 + 0.25 * eps);
+    s.ah = 0.5 * alpha * h;
+    return s;
+}
+
+__device__ __forceinline__ double Ek(double th, int k) { return -expm1(-2.0 * th * (double)k); }
+
+// Per-(edge, shift) quantities of eq. local_reduced_schur, closed form:
+//   rho_{m-1} = w E(m) / E(m+1),
+//   s_d = alpha h / 2 + |b| (1 - rho_{m-1}) = alpha h / 2 + |b| (1 - w)(1 + w^{2m+1}) / E(m+1),
+//   s_o = -|b| prod_p rho_p = -|b| w^m E(1) / E(m+1)
+// (m = 0 gives s_d = delta, s_o = b).  Thread = (shift, edge), edge fastest.
+__global__ void __launch_bounds__(256) k_edge_coeff(MeshView mv, const double *__restrict__ shift, int32_t LB,
+                                                    int32_t LBp, double *__restrict__ babs,
+                                                    double *__restrict__ rhom, double *__restrict__ sd,
+                                                    double *__restrict__ so) {
+    const int64_t n = mv.E * (int64_t)LBp;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(idx / mv.E);
+        const int64_t e = idx - (int64_t)l * mv.E;
+        if (l >= LB) {
+            babs[e * LBp + l] = 0.0;
+            rhom[e * LBp + l] = 0.0;
+            sd[idx] = 1.0;
+            so[idx] = 0.0;
+            continue;
+        }
+        const int m = mv.m[e];
+        const EdgeShift s = edge_shift(shift[2 * l], shift[2 * l + 1], mv.kap2[e], mv.he[e]);
+        const double Em1 = Ek(s.th, m + 1);
+        babs[e * LBp + l] = s.bab;
+        rhom[e * LBp + l] = (m > 0) ? s.w * Ek(s.th, m) / Em1 : 0.0;
+        sd[idx] = s.ah + s.bab * (-expm1(-s.th)) * (1.0 + exp(-(2.0 * m + 1.0) * s.th)) / Em1;
+        so[idx] = -s.bab * exp(-(double)m * s.th) * s.E1 / Em1;
+    }
+}
+
+// table section offsets (doubles) within one block's pass-A table
 struct TabLayout {
     int NT;
     __host__ __device__ int64_t CT() const { return 0; }                  // [t][c][64]: C[16t + L%16][4c + L/16]
-    __host__ __device__ int64_t DT() const { return 256 * NT; }           // [t][r][64]: d[16t + 4r + L/16]
-    __host__ __device__ int64_t HF() const { return 512 * NT; }           // [t][r][64]: H_fwd[L%16][16t + 4r + L/16]
-    __host__ __device__ int64_t HB() const { return 768 * NT; }           // [t][r][64]: H_bwd[...]
-    __host__ __device__ int64_t GF() const { return 1024 * NT; }          // [c][64]: Ghat_fwd[L%16][4c + L/16]
-    __host__ __device__ int64_t GB() const { return 1024 * NT + 256; }    // [c][64]: Ghat_bwd
-    __host__ __device__ int64_t size() const { return 1024 * (int64_t)NT + 512; }
+    __host__ __device__ int64_t HF() const { return 256 * NT; }           // [t][r][64]: H_fwd[L%16][16t + 4r + L/16]
+    __host__ __device__ int64_t HB() const { return 512 * NT; }           // [t][r][64]: H_bwd[...]
+    __host__ __device__ int64_t GF() const { return 768 * NT; }           // [c][64]: Ghat_fwd[L%16][4c + L/16]
+    __host__ __device__ int64_t GB() const { return 768 * NT + 256; }     // [c][64]: Ghat_bwd
+    __host__ __device__ int64_t DT() const { return 768 * NT + 512; }     // [LBp]: d[l]
+    __host__ __device__ int64_t size() const { return 784 * (int64_t)NT + 512; }
 };
 
 __device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk) {
@@ -66,103 +136,163 @@ __device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk
     return lo;
 }
 
-// One workgroup per edge block: stage the block's rows in LDS, then
-//   phase 1 (thread = shift): C, d, H_fwd, H_bwd,
-//   phase 2 (thread = (i, j)): Ghat_fwd, Ghat_bwd, summed over shifts in order.
-__global__ void __launch_bounds__(256) k_blocktab(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
-                                                  const int32_t *__restrict__ boff, int32_t E, int32_t LBp, int32_t NT,
-                                                  const double *__restrict__ rho, const double *__restrict__ dg,
-                                                  const double *__restrict__ of, double *__restrict__ tab) {
-    extern __shared__ double sm[];
-    double *srho = sm;               // [17][LBp]: rho_{16b-1 .. 16b+15}
-    double *sdg = sm + 17 * LBp;     // [16][LBp]
-    double *sof = sdg + 16 * LBp;    // [16][LBp]
+constexpr int kTabThreads = 128;          // one thread per (padded) shift, LBp <= 128
+constexpr int kSPad = kTabThreads + 4;    // LDS row stride of the Ghat operands
+constexpr double kThetaSplit = 40.0;      // see k_blocktab
+
+// Writes the 16 per-position values v[i] of every shift of this wave as 16
+// contiguous 64-lane operand vectors: H/Z layout (lane i + 16 k of vector
+// (t, r) <- shift 16t + 4r + k, position i) or C layout (lane n + 16 q of
+// vector (t, c) <- shift 16t + n, position 4c + q).
+template <bool CLAYOUT>
+__device__ __forceinline__ void emit16(double (*tile)[17], const double (&v)[16], double *dst, int wv, int NT) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) tile[lane][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        if (4 * wv + (o >> 2) >= NT) break;
+        const double x = CLAYOUT ? tile[16 * (o >> 2) + (lane & 15)][4 * (o & 3) + (lane >> 4)]
+                                 : tile[4 * o + (lane >> 4)][lane & 15];
+        dst[(int64_t)(16 * wv + o) * 64 + lane] = x;
+    }
+    __syncthreads();
+}
+
+// One workgroup per 16-position edge block, thread = shift l (base = 16 beta,
+// i* = last position of the block, all products from the closed form above):
+//   Lam[i][j] = w^{i-j} E(base+j+1) / E(base+i+1)       (j <= i)
+//   lam[i]    = w^{i+1} E(base) / E(base+i+1)
+//   dg_p = E(p+1) E(m-p) / (2 sinh(theta) |b| E(m+1)),  of_p = w E(p+1) E(m-p-1) / (...)
+//   C[l][j] = Lam[i*][j], d[l] = lam[i*], H_fwd[i][l] = dg lam, H_bwd[i][l] = of lam,
+//   Z_tail[i][l] = (T^{-1})_{p,0}   = w^{p+1} E(m-p) / (|b| E(m+1)),
+//   Z_head[i][l] = (T^{-1})_{p,m-1} = w^{m-p} E(p+1) / (|b| E(m+1)),
+// and Ghat_fwd[i][j] = sum_l dg Lam, Ghat_bwd[i][j] = sum_l of Lam on the
+// matrix cores: w^{i-j} = w^{i-7.5} w^{7.5-j} splits Ghat into a product of
+// a [16 x LBp] and an [LBp x 16] operand, exact on the diagonal.  With theta
+// clamped to 40 in the split factors, |exponents| <= 300 (no overflow), and the
+// off-diagonal Lam of a shift with theta > 40 (relative size below e^{-40}, far
+// under the rounding of its own diagonal term) is replaced by an equally
+// negligible value.
+__global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int32_t *__restrict__ boff,
+                                                          const double *__restrict__ shift, int32_t LB, int32_t LBp,
+                                                          int32_t NT, double *__restrict__ tab,
+                                                          double *__restrict__ ztab) {
+    __shared__ double sAf[17][kSPad];   // dg / (w^i E(base+i+1)) split factor, rows 0..16
+    __shared__ double sBm[16][kSPad];   // E(base+j+1) split factor
+    __shared__ double srw[kSPad];       // w / w_split
+    __shared__ double tile[2][64][17];
+    const int tid = threadIdx.x, wv = tid >> 6;
     const int64_t blk = blockIdx.x;
-    const int e = find_edge(boff, E, blk);
+    const int e = find_edge(boff, (int)mv.E, blk);
     const int beta = (int)(blk - boff[e]);
-    const int m = m_[e];
-    const int64_t off = off_[e];
+    const int m = mv.m[e];
     const int base = 16 * beta;
     const int istar = min(15, m - 1 - base);
-    for (int idx = threadIdx.x; idx < 49 * LBp; idx += blockDim.x) {
-        const int row = idx / LBp, l = idx - row * LBp;
-        double v = 0.0;
-        if (row < 17) {
-            const int p = base - 1 + row;
-            if (p >= 0 && p < m) v = rho[(off + p) * LBp + l];
-        } else {
-            const int rr = row < 33 ? row - 17 : row - 33;
-            const int p = base + rr;
-            if (p < m) v = (row < 33 ? dg : of)[(off + p) * LBp + l];
-        }
-        sm[idx] = v;
-    }
-    __syncthreads();
     const TabLayout TL{NT};
     double *T = tab + blk * TL.size();
-    auto r_at = [&](int k, int l) -> double { return srho[(k - base + 1) * LBp + l]; };  // rho_k, k in [base-1, base+15]
-    if ((int)threadIdx.x < LBp) {
-        const int l = threadIdx.x;
-        const int t = l >> 4, r = (l & 15) >> 2, kk = l & 3;
-        // C[l][j] = prod_{k=base+j}^{base+istar-1} rho_k for j <= istar
-        double c = 1.0;
+    double *Z = ztab + blk * (int64_t)(512 * NT);
+    const int l = tid;
+    const bool live = l < LB;
+    double th = 0.0, w = 0.0, E1 = 0.0, K = 0.0, ascale = 0.0;
+    if (live) {
+        const EdgeShift s = edge_shift(shift[2 * l], shift[2 * l + 1], mv.kap2[e], mv.he[e]);
+        th = s.th;
+        w = s.w;
+        E1 = s.E1;
+        K = 1.0 / (s.bab * Ek(th, m + 1));
+        ascale = K / s.sh2;
+    }
+    // Ef[k] = E(base + k), k = 0..16 (E(k+1) = E(k) + (1 - E(k)) E(1): positive terms only)
+    double Ef[17];
+    Ef[0] = live ? Ek(th, base) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Ef[k + 1] = Ef[k] + (1.0 - Ef[k]) * E1;
+    // Q[i] = E(m - base - i), i = 0..16 (rows past the edge are never used unmasked)
+    double Q[17];
+#pragma unroll
+    for (int i = 0; i < 17; ++i) Q[i] = live ? Ek(th, max(m - base - i, 0)) : 0.0;
+    double wp[18];
+    wp[0] = 1.0;
+#pragma unroll
+    for (int d = 0; d < 17; ++d) wp[d + 1] = wp[d] * w;
+    const double lam0 = Ef[0] * ascale;  // E(base) / (2 sinh(theta) |b| E(m+1))
+
+    double v[16];
+    // H_fwd[i] = dg_i lam_i = w^{i+1} E(base) E(m-base-i) / (2 sinh |b| E(m+1))
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wp[i + 1] * lam0 * Q[i] : 0.0;
+    emit16<false>(tile[wv], v, T + TL.HF(), wv, NT);
+    // H_bwd[i] = of_i lam_i = w^{i+2} E(base) E(m-base-i-1) / (...)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wp[i + 2] * lam0 * Q[i + 1] : 0.0;
+    emit16<false>(tile[wv], v, T + TL.HB(), wv, NT);
+    // Z_tail[i] = w^{base+1+i} E(m-base-i) K
+    {
+        const double wb = live ? exp(-(double)(base + 1) * th) * K : 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wb * wp[i] * Q[i] : 0.0;
+    }
+    emit16<false>(tile[wv], v, Z, wv, NT);
+    // C[j] = w^{i*-j} E(base+j+1) / E(base+i*+1), d = w^{i*+1} E(base) / E(base+i*+1), and
+    // Z_head[i] = w^{m-base-i} E(base+i+1) K: descending chains from i*
+    double dval = 0.0;
+    {
+        double pw = 1.0, inv = 0.0;
+        double zh = live ? exp(-(double)(m - base - istar) * th) * K : 0.0;
+        double vz[16];
+#pragma unroll
         for (int j = 15; j >= 0; --j) {
-            double v = 0.0;
+            if (j == istar) inv = 1.0 / Ef[j + 1];
+            const bool ok = live && j <= istar;
+            v[j] = ok ? pw * Ef[j + 1] * inv : 0.0;
+            vz[j] = ok ? zh * Ef[j + 1] : 0.0;
             if (j <= istar) {
-                if (j < istar) c *= r_at(base + j, l);
-                v = c;
+                pw *= w;
+                zh *= w;
             }
-            T[TL.CT() + ((int64_t)t * 4 + (j >> 2)) * 64 + (l & 15) + 16 * (j & 3)] = v;
         }
-        // lam[i] = prod_{k=base-1}^{base+i-1} rho_k (no carry into the first block)
-        double lam = beta > 0 ? r_at(base - 1, l) : 0.0;
-        double dv = 0.0;
-        for (int i = 0; i < 16; ++i) {
-            const double li = (i <= istar) ? lam : 0.0;
-            if (i == istar) dv = li;
-            const int64_t o = ((int64_t)t * 4 + r) * 64 + i + 16 * kk;
-            T[TL.HF() + o] = sdg[i * LBp + l] * li;
-            T[TL.HB() + o] = sof[i * LBp + l] * li;
-            if (i < 15) lam *= r_at(base + i, l);
+        dval = live ? pw * Ef[0] * inv : 0.0;  // pw = w^{i*+1}
+        emit16<true>(tile[wv], v, T + TL.CT(), wv, NT);
+        emit16<false>(tile[wv], vz, Z + 256 * NT, wv, NT);
+    }
+    if (l < LBp) T[TL.DT() + l] = dval;
+    // Ghat operands (split factors); rows past i*+1 (Af) / i* (Bm) are zero
+    {
+        const double thc = fmin(th, kThetaSplit);
+        const double wc = live ? exp(-thc) : 0.0;
+        double fa = live ? exp(7.5 * thc) : 0.0;   // w_c^{i-7.5}
+        double fb = live ? exp(-7.5 * thc) : 0.0;  // w_c^{7.5-j}
+        const double iwc = live ? exp(thc) : 0.0;
+#pragma unroll
+        for (int i = 0; i < 17; ++i) {
+            sAf[i][l] = (live && i <= istar + 1) ? Q[i] * ascale * fa : 0.0;
+            if (i < 16) sBm[i][l] = (live && i <= istar) ? Ef[i + 1] * fb : 0.0;
+            fa *= wc;
+            fb *= iwc;
         }
-        for (int n = 0; n < 16; ++n) T[TL.DT() + ((int64_t)t * 4 + r) * 64 + 16 * kk + n] = dv;
-        // Lam[i][j] = P_i / P_j with the in-block prefix products P_i = prod_{k<i} rho_{base+k}
-        // (P_j >= rho_min^15 > 0 for the positions of the block): store g_i P_i over
-        // the dg/of rows and 1/P_j over rho rows 1..16 of this shift's column
-        double P[16];
-        P[0] = 1.0;
-        for (int i = 1; i < 16; ++i) P[i] = (i <= istar) ? P[i - 1] * r_at(base + i - 1, l) : 0.0;
-        // padded shifts have rho = 0, hence P = 0: they contribute nothing
-        const bool live = P[istar] > 0.0;
-        const double inv_last = live ? 1.0 / P[istar] : 0.0;
-        double inv = inv_last;
-        double invs[16];
-        for (int j = istar; j >= 0; --j) {
-            invs[j] = inv;
-            if (j > 0) inv *= r_at(base + j - 1, l);
-        }
-        for (int i = 0; i < 16; ++i) {
-            const bool ok = live && i <= istar;
-            sdg[i * LBp + l] = ok ? sdg[i * LBp + l] * P[i] : 0.0;
-            sof[i * LBp + l] = ok ? sof[i * LBp + l] * P[i] : 0.0;
-            srho[(1 + i) * LBp + l] = ok ? invs[i] : 0.0;
-        }
+        srw[l] = live ? exp(thc - th) : 0.0;  // w / w_c
     }
     __syncthreads();
+    // Ghat^T = B^T A^T (D layout of the transpose = the A-operand table layout):
+    // wave 0 the forward operand (A = Af rows i), wave 1 the backward one (A = Af rows i+1 times w/w_c)
     {
-        // Ghat[i][j] = sum_l g^l_i P^l_i / P^l_j  (j <= i <= istar), shifts in increasing order
-        const int i = threadIdx.x >> 4, j = threadIdx.x & 15;  // 256 threads = 16 x 16 pairs
-        double gf = 0.0, gb = 0.0;
-        if (j <= i && i <= istar) {
-            for (int l = 0; l < LBp; ++l) {
-                const double bj = srho[(1 + j) * LBp + l];
-                gf = fma(sdg[i * LBp + l], bj, gf);
-                gb = fma(sof[i * LBp + l], bj, gb);
-            }
+        const int lane = tid & 63;
+        const int n = lane & 15, q = lane >> 4;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < LBp / 4; ++c) {
+            const int ll = 4 * c + q;
+            const double a = sBm[n][ll];
+            const double b = (wv == 0) ? sAf[n][ll] : sAf[n + 1][ll] * srw[ll];
+            acc = mfma(a, b, acc);
         }
-        const int64_t o = (int64_t)(j >> 2) * 64 + i + 16 * (j & 3);
-        T[TL.GF() + o] = gf;
-        T[TL.GB() + o] = gb;
+        double *G = T + (wv == 0 ? TL.GF() : TL.GB());
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int jj = 4 * r + q;  // D row of the transpose = column j of Ghat; lane row n = i
+            G[r * 64 + lane] = (jj <= n && n <= istar) ? acc[r] : 0.0;
+        }
     }
 }
 
@@ -237,7 +367,7 @@ __global__ void __launch_bounds__(256) k_sweep_blocked(const int64_t *__restrict
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Y[t][r] *= T[TL.DT() + (t * 4 + r) * 64 + L];
+            for (int r = 0; r < 4; ++r) Y[t][r] *= T[TL.DT() + 16 * t + 4 * r + kq];
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -351,13 +481,22 @@ void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
 
 int64_t block_tab_doubles(int32_t NT) { return TabLayout{NT}.size(); }
 
+void launch_edge_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
+    if (mv.E == 0) return;
+    GRF_REQUIRE(a.LBp >= a.LB, "internal: bad padded shift count");
+    const int64_t n = mv.E * (int64_t)a.LBp;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_edge_coeff, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.shift, a.LB, a.LBp, a.babs,
+                       a.rhom, a.sd, a.so);
+    GRF_LAUNCH_CHECK();
+}
+
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return;
     GRF_REQUIRE(a.LBp == 16 * a.NT && a.NT >= 1 && a.NT <= 8, "internal: blocked sweeps need 16..128 padded shifts");
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
-    const size_t lds = sizeof(double) * 49 * (size_t)a.LBp;
-    hipLaunchKernelGGL(k_blocktab, dim3((unsigned)a.nblocks), dim3(256), lds, st, mv.off, mv.m, a.boff, mv.E, a.LBp,
-                       a.NT, a.rho, a.dg, a.of, a.tab);
+    hipLaunchKernelGGL(k_blocktab, dim3((unsigned)a.nblocks), dim3(kTabThreads), 0, st, mv, a.boff, a.shift, a.LB,
+                       a.LBp, a.NT, a.tab, a.ztab);
     GRF_LAUNCH_CHECK();
 }
 

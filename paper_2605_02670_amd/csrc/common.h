@@ -94,7 +94,7 @@ struct grf_graph {
     std::vector<int32_t> adj_e, adj_o;
     std::vector<int8_t> adj_s;
     // device copies
-    grf::DevBuf d_off, d_m, d_eu, d_ev, d_he, d_kap2, d_vptr, d_adj_e, d_adj_o, d_adj_s, d_msqrt, d_vgraph, d_dofedge;
+    grf::DevBuf d_off, d_m, d_eu, d_ev, d_he, d_kap2, d_vptr, d_adj_e, d_adj_o, d_adj_s, d_msqrt, d_vgraph;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;

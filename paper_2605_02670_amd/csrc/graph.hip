@@ -159,10 +159,6 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     std::vector<double> msq(g.N);
     for (int64_t j = 0; j < g.N; ++j) msq[j] = std::sqrt(g.ml[j]);
     std::vector<int32_t> vg(g.V, 0);
-    std::vector<int32_t> de(g.NI);
-    for (int64_t e = 0; e < g.E; ++e)
-        for (int64_t p = g.off[e]; p < g.off[e + 1]; ++p) de[p] = (int32_t)e;
-    upload(g.d_dofedge, de, s);
     upload(g.d_off, g.off, s);
     upload(g.d_m, g.m, s);
     upload(g.d_eu, eu, s);

@@ -54,8 +54,9 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     p.BL = p.blocked ? 16 : o.sweep_block;
     const int64_t nb = (S + 63) / 64, Sp = 64 * nb;
     // bytes per shift of the per-pass buffers
-    const double rows = p.blocked ? 5.0 : 5.0;
-    const double btab = p.blocked ? (1536.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
+    // streamed: rho + two double2 step rows per interior DOF; blocked: per-block operand tables
+    const double rows = p.blocked ? 0.0 : 5.0;
+    const double btab = p.blocked ? (1296.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
     const double per_shift = 8.0 * (rows * g.NI + btab + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V +
                                     (double)g.V * Sp) + 12.0 * S;
     size_t freeb = 0, totalb = 0;
@@ -103,13 +104,8 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         for (int32_t i = lb; i < LBp; ++i) sh[2 * i + 1] = 1.0;  // padding: never used as a divisor of 0
         upload(w.shift, sh, st);
         const size_t nir = (size_t)std::max<int64_t>(g.NI, 1) * LBp;
-        w.rho.reserve(8 * nir);
-        if (p.blocked) {
-            w.dgp.reserve(8 * nir);
-            w.ofp.reserve(8 * nir);
-            w.ztp.reserve(8 * nir);
-            w.epsp.reserve(8 * nir);
-        } else {
+        if (!p.blocked) {
+            w.rho.reserve(8 * nir);
             w.fwdt.reserve(16 * nir);
             w.bwdt.reserve(16 * nir);
         }
@@ -125,32 +121,22 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         w.res.reserve(8 * (size_t)lb * S);
         w.pcg_scr.reserve(pcg_scratch_bytes(mv, p.pcg_blocks));
 
-        int64_t nblocks = 0;
-        if (p.blocked) {
-            ensure_block_offsets(g, w, st, nblocks);
-            w.ztab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * 512 * (LBp / 16));
-        }
         CoeffArgs ca{};
         ca.shift = w.shift.as<double>();
         ca.LB = lb;
         ca.LBp = LBp;
-        ca.rho = w.rho.as<double>();
+        ca.rho = p.blocked ? nullptr : w.rho.as<double>();
         ca.fwdt = p.blocked ? nullptr : w.fwdt.as<double2>();
         ca.bwdt = p.blocked ? nullptr : w.bwdt.as<double2>();
-        ca.dg = p.blocked ? w.dgp.as<double>() : nullptr;
-        ca.of = p.blocked ? w.ofp.as<double>() : nullptr;
-        ca.zt = p.blocked ? w.ztp.as<double>() : nullptr;
-        ca.eps = p.blocked ? w.epsp.as<double>() : nullptr;
-        ca.dof_edge = g.d_dofedge.as<int32_t>();
-        ca.boff = p.blocked ? w.boff.as<int32_t>() : nullptr;
-        ca.NT = LBp / 16;
-        ca.ztab = p.blocked ? w.ztab.as<double>() : nullptr;
         ca.babs = w.babs.as<double>();
         ca.rhom = w.rhom.as<double>();
         ca.sd = w.sd.as<double>();
         ca.so = w.so.as<double>();
         T.begin(GRF_K_COEFF);
-        launch_coeff(mv, ca, st);
+        if (p.blocked)
+            launch_edge_coeff(mv, ca, st);
+        else
+            launch_coeff(mv, ca, st);
         T.end();
 
         SweepArgs sa{};
@@ -171,18 +157,18 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
 
         BlockArgs ba{};
         if (p.blocked) {
+            int64_t nblocks = 0;
+            ensure_block_offsets(g, w, st, nblocks);
             ba.boff = w.boff.as<int32_t>();
             ba.nblocks = nblocks;
             ba.NT = LBp / 16;
             ba.LB = lb;
             ba.LBp = LBp;
-            ba.rho = ca.rho;
-            ba.dg = ca.dg;
-            ba.of = ca.of;
-            ba.zt = ca.zt;
+            ba.shift = ca.shift;
             ba.babs = ca.babs;
             ba.rhom = ca.rhom;
             w.btab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * block_tab_doubles(ba.NT));
+            w.ztab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * 512 * ba.NT);
             ba.tab = w.btab.as<double>();
             ba.ztab = w.ztab.as<double>();
             ba.X = sa.X;

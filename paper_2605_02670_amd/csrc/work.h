@@ -5,10 +5,8 @@
 
 struct grf_graph::Work {
     grf::DevBuf X, U;             // sample-interleaved [nb][N][64]: input (noise / rhs) and accumulator
-    grf::DevBuf rho;              // per-DOF multipliers [NI][LBp]
+    grf::DevBuf rho;              // per-DOF multipliers [NI][LBp] (streamed sweeps)
     grf::DevBuf fwdt, bwdt;       // per-DOF step rows [NI][LBp] of (rho_{k-1}, dg_k) / (rho_{k-1}, of_k)
-    grf::DevBuf dgp, ofp, ztp;    // per-DOF plain rows [NI][LBp] (blocked sweeps)
-    grf::DevBuf epsp;             // pivot scratch [NI][LBp]
     grf::DevBuf btab;             // matrix-core operand tables per 16-position edge block
     grf::DevBuf ztab;             // pass-B operand tables per edge block
     grf::DevBuf boff;             // [E+1] first block of every edge
@@ -39,22 +37,19 @@ void launch_to_interleaved(const double *in, int64_t S, int64_t N, double *X, hi
 void launch_from_interleaved(const double *X, int64_t S, int64_t N, double *out, hipStream_t st);
 void launch_fill(double *p, size_t n, double v, hipStream_t st);
 
-// per-(shift, edge) coefficients: Thomas rows, |b|, rho_{m-1}, Schur 2x2
+// per-(shift, edge) coefficients: Thomas rows (streamed sweeps), |b|, rho_{m-1}, Schur 2x2
 struct CoeffArgs {
     const double *shift;  // [LBp][2] c_I, c_L
     int32_t LB, LBp;
-    double *rho;            // [NI][LBp]
-    double2 *fwdt, *bwdt;   // [NI][LBp] streamed-sweep rows, or null
-    double *dg, *of, *zt;   // [NI][LBp] plain rows for the blocked sweeps, or null
-    double *eps;            // [NI][LBp] pivot scratch (blocked sweeps)
-    const int32_t *dof_edge;  // [NI] edge of every interior DOF (blocked sweeps)
-    const int32_t *boff;    // [E+1] first block of every edge (blocked sweeps)
-    int32_t NT;             // shift tiles (blocked sweeps)
-    double *ztab;           // pass-B operands, 512 NT doubles per block (blocked sweeps)
+    double *rho;            // [NI][LBp] (streamed sweeps)
+    double2 *fwdt, *bwdt;   // [NI][LBp] (streamed sweeps)
     double *babs, *rhom;    // [E][LBp]
     double *sd, *so;        // [LBp][E]
 };
+// recurrence form: Thomas rows and the per-edge quantities
 void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
+// closed form: the per-edge quantities only (the blocked sweeps build their operands in blocked.hip)
+void launch_edge_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
 
 // sweeps over edge interiors (lanes = samples, shifts in registers)
 struct SweepArgs {
@@ -78,10 +73,10 @@ struct BlockArgs {
     int64_t nblocks;        // blocks of the whole graph
     int32_t NT;             // shift tiles of 16
     int32_t LB, LBp;        // real / padded shifts (LBp = 16 NT)
-    const double *rho, *dg, *of, *zt;  // plain rows [NI][LBp]
+    const double *shift;    // [LBp][2] c_I, c_L
     const double *babs, *rhom;         // [E][LBp]
-    double *tab;            // operand tables, tab_doubles(NT) per block
-    const double *ztab;     // pass-B operands (first/last columns of T^{-1}), 512 NT per block
+    double *tab;            // pass-A operands, block_tab_doubles(NT) per block
+    double *ztab;           // pass-B operands (first/last columns of T^{-1}), 512 NT per block
     const double *X;        // [nb][N][64]
     double *U;              // [nb][N][64]
     double *ends;           // [LB][E][2][Sp]
