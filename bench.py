@@ -26,8 +26,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "sample-shift DOF-solves/sec at 1e-6 rel err: learned+batched vs plain, 1 GPU"
-FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, FMA = 2 flops
-FLOPS_PER_UNIT = {"acc_fwd": 4.0, "acc_bwd": 4.0, "ends_fwd": 2.0, "ends_bwd": 2.0}  # per (interior DOF, shift, sample)
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64, matrix cores (dense) and vector units alike; FMA = 2 flops
+
+# Algorithmic FP64 flops per (interior DOF, real shift, sample) of each timed
+# edge kernel: the Thomas recurrences themselves (forward elimination
+# y = r + rho y and the output update x += g y are one FMA each), whatever the
+# blocking.  Padding shifts and the blocked form's extra work are not counted.
+#   blocked (matrix cores): pass A per direction = elimination + output (4),
+#                           pass B = two end-column updates (4)
+#   streamed (vector ALU):  end sweeps = elimination (2), recovery sweeps = 4
+EDGE_FLOPS = {
+    "blocked": {"ends_fwd": 4.0, "ends_bwd": 4.0, "acc_fwd": 4.0},
+    "streamed": {"ends_fwd": 2.0, "ends_bwd": 2.0, "acc_fwd": 4.0, "acc_bwd": 4.0},
+}
+HIP_KERNEL = {
+    "blocked": {"ends_fwd": "k_sweep_blocked<8, true>", "ends_bwd": "k_sweep_blocked<8, false>",
+                "acc_fwd": "k_corr_blocked<8>"},
+    "streamed": {"ends_fwd": "k_sweep_ends<BL, true>", "ends_bwd": "k_sweep_ends<BL, false>",
+                 "acc_fwd": "k_sweep_acc<BL, true>", "acc_bwd": "k_sweep_acc<BL, false>"},
+}
+# HBM bytes per launch of the pass-A forward kernel on this workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by the plain-copy calibration),
+# valid only for the kernel source they were taken on.
+TRAFFIC = {"kernel": "ends_fwd", "source": "paper_2605_02670_amd/csrc/blocked.hip", "sha256": None,
+           "fetch_bytes": None, "write_bytes": None}
+
+
+def _traffic(dom: str, mode: str):
+    import hashlib
+
+    if mode != "blocked" or dom != TRAFFIC["kernel"] or TRAFFIC["sha256"] is None:
+        return None
+    with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["sha256"]:
+            return None  # kernel changed since the counters were taken
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
 def cpu_baseline(cfg, L: int, S: int, n_shift_sample: int = 3, n_samp: int = 4) -> dict:
@@ -35,6 +68,13 @@ def cpu_baseline(cfg, L: int, S: int, n_shift_sample: int = 3, n_samp: int = 4) 
     bounded sample and extrapolate the whole job linearly:
         t_job = S t_noise + L (t_factor + S t_rhs),
     with t_factor and t_rhs fitted from solves with 1 and n_samp right-hand sides."""
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(cfg, L, S, n_shift_sample, n_samp)
+
+
+def _cpu_baseline(cfg, L: int, S: int, n_shift_sample: int, n_samp: int) -> dict:
     import numpy as np
 
     from oracle import mesh as omesh
@@ -125,15 +165,17 @@ def main() -> int:
     ktot = {k_: sum(s["kernel_ms"][k_] for s in stats) for k_ in stats[0]["kernel_ms"]}
     kl = {k_: sum(s["kernel_launches"][k_] for s in stats) for k_ in stats[0]["kernel_launches"]}
     dom = max(ktot, key=ktot.get)
+    mode = "blocked" if stats[0]["sweep_block"] == 0 else "streamed"
     roof = None
-    if dom in FLOPS_PER_UNIT and kl[dom] > 0:
+    if dom in EDGE_FLOPS[mode] and kl[dom] > 0:
         avg_ms = ktot[dom] / kl[dom]
         launches_per_step = kl[dom] / args.steps
-        flops = FLOPS_PER_UNIT[dom] * G.n_interior * L * S / launches_per_step
+        flops = EDGE_FLOPS[mode][dom] * G.n_interior * L * S / launches_per_step
         achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": f"k_sweep_{dom}", "achieved": achieved,
-                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": None, "avg_launch_ms": avg_ms}
+        roof = {"bound": "mfma" if mode == "blocked" else "alu", "kernel": HIP_KERNEL[mode][dom],
+                "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": _traffic(dom, mode),
+                "avg_launch_ms": avg_ms, "flops_per_launch": flops}
 
     # correctness at full size: <diag M_L, u> = q_k(kappa^2) <1, W> per sample (any size, exact identity)
     from oracle import quadrature as oquad

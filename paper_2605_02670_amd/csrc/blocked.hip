@@ -40,12 +40,23 @@ namespace grf {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2):
+// hardware workgroup b runs on XCD b % 8.  Renumber them so that each XCD gets a
+// contiguous range of logical workgroups; the workgroups of one edge (which
+// read the same operand tables) then share an L2.
+__device__ __forceinline__ int64_t xcd_logical_block() {
+    const int64_t n = gridDim.x, b = blockIdx.x;
+    const int64_t x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
 
 // Closed form of the interior block.  T / |b| = tridiag(-1, 2 cosh(theta), -1)
 // with cosh(theta) = 1 + eps / 2, so with s_k = sinh(k theta) (Chebyshev
@@ -115,15 +126,17 @@ __global__ void __launch_bounds__(256) k_edge_coeff(MeshView mv, const double *_
     }
 }
 
-// table section offsets (doubles) within one block's pass-A table
+// table section offsets (doubles) within one block's pass-A table; each
+// direction reads two contiguous ranges: forward [HF CT] + [GF DT],
+// backward [CT HB] + [DT GB]
 struct TabLayout {
     int NT;
-    __host__ __device__ int64_t CT() const { return 0; }                  // [t][c][64]: C[16t + L%16][4c + L/16]
-    __host__ __device__ int64_t HF() const { return 256 * NT; }           // [t][r][64]: H_fwd[L%16][16t + 4r + L/16]
+    __host__ __device__ int64_t HF() const { return 0; }                  // [t][r][64]: H_fwd[L%16][16t + 4r + L/16]
+    __host__ __device__ int64_t CT() const { return 256 * NT; }           // [t][c][64]: C[16t + L%16][4c + L/16]
     __host__ __device__ int64_t HB() const { return 512 * NT; }           // [t][r][64]: H_bwd[...]
     __host__ __device__ int64_t GF() const { return 768 * NT; }           // [c][64]: Ghat_fwd[L%16][4c + L/16]
-    __host__ __device__ int64_t GB() const { return 768 * NT + 256; }     // [c][64]: Ghat_bwd
-    __host__ __device__ int64_t DT() const { return 768 * NT + 512; }     // [LBp]: d[l]
+    __host__ __device__ int64_t DT() const { return 768 * NT + 256; }     // [LBp]: d[l]
+    __host__ __device__ int64_t GB() const { return 784 * NT + 256; }     // [c][64]: Ghat_bwd
     __host__ __device__ int64_t size() const { return 784 * (int64_t)NT + 512; }
 };
 
@@ -296,22 +309,57 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     }
 }
 
-// Pass A: one wavefront = one edge x 16 samples, all (padded) shifts.
+// Staging of one block's operands in LDS, shared by the four wavefronts of a
+// workgroup (one edge, 64 samples): every thread loads its share of the next
+// block into registers while the current block is computed, then writes it to
+// the other LDS buffer.
+template <int NV2>
+constexpr int stage_per() { return (NV2 + 255) / 256; }
+
+// copy [src1, src1 + n1) ++ [src2, ...) (n1 even, both 16-byte aligned) into registers
+template <int NV2>
+__device__ __forceinline__ void stage_load(d2 (&r)[stage_per<NV2>()], const double *src1, int n1,
+                                           const double *src2) {
+#pragma unroll
+    for (int k = 0; k < stage_per<NV2>(); ++k) {
+        const int i = (int)threadIdx.x + 256 * k;
+        const int d = 2 * min(i, NV2 - 1);
+        const double *p = d < n1 ? src1 + d : src2 + (d - n1);
+        r[k] = *reinterpret_cast<const d2 *>(p);
+    }
+}
+
+template <int NV2>
+__device__ __forceinline__ void stage_store(const d2 (&r)[stage_per<NV2>()], double *dst) {
+#pragma unroll
+    for (int k = 0; k < stage_per<NV2>(); ++k) {
+        const int i = (int)threadIdx.x + 256 * k;
+        if (i < NV2) reinterpret_cast<d2 *>(dst)[i] = r[k];
+    }
+}
+
+// Pass A: workgroup = (edge, 64 samples), wavefront = 16 samples, all
+// (padded) shifts.  LDS per buffer (doubles), forward: H 0, C 256NT, G 512NT,
+// d 512NT+256; backward: C 0, H 256NT, d 512NT, G 528NT.  With first set
+// (the forward pass of the first shift block) the accumulator is written,
+// not updated.
 template <int NT, bool FWD>
-__global__ void __launch_bounds__(256) k_sweep_blocked(const int64_t *__restrict__ off_,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sweep_blocked(const int64_t *__restrict__ off_,
                                                        const int32_t *__restrict__ m_,
                                                        const int32_t *__restrict__ boff, int32_t E, int64_t N,
                                                        int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
                                                        const double *__restrict__ tab, const double *__restrict__ X,
                                                        double *__restrict__ U, const double *__restrict__ rhom,
-                                                       double *__restrict__ ends) {
+                                                       double *__restrict__ ends, int32_t first) {
+    constexpr int TS = 528 * NT + 256;  // doubles per buffer
+    constexpr int N1 = 512 * NT;        // first contiguous range
+    __shared__ double sbuf[2 * TS];
     const int L = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + wave_id();
-    const int ng = 4 * nb;
-    if (q >= (int64_t)E * ng) return;
-    const int e = (int)(q / ng);
-    const int g = (int)(q - (int64_t)e * ng);
-    const int b = g >> 2;
+    const int wv = wave_id();
+    const int64_t wg = xcd_logical_block();
+    const int e = (int)(wg / nb);
+    const int b = (int)(wg - (int64_t)e * nb);
+    const int g = 4 * b + wv;
     const int s0 = 16 * g;
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
@@ -319,7 +367,7 @@ __global__ void __launch_bounds__(256) k_sweep_blocked(const int64_t *__restrict
     double *endp = ends + ((int64_t)e * 2 + side) * Sp + s0 + n;
     const int64_t endstride = (int64_t)E * 2 * Sp;
     const TabLayout TL{NT};
-    if (m == 0) {
+    if (m == 0) {  // uniform over the workgroup
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -333,58 +381,82 @@ __global__ void __launch_bounds__(256) k_sweep_blocked(const int64_t *__restrict
     const double *xb = X + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     const int nblk = (m + 15) >> 4;
-    const int64_t eb0 = boff[e];
+    const double *tab0 = tab + (int64_t)boff[e] * TL.size();
+    auto src1 = [&](int beta) { return tab0 + beta * TL.size() + (FWD ? TL.HF() : TL.CT()); };
+    auto src2 = [&](int beta) { return tab0 + beta * TL.size() + (FWD ? TL.GF() : TL.DT()); };
+    // position read at step p, and where its output goes (backward: T^{-1}'s upper part lands one before)
+    auto inpos = [&](int p) -> int64_t { return FWD ? (int64_t)p : (int64_t)(m - 1 - p); };
+    auto outpos = [&](int p) -> int { return FWD ? p : m - 2 - p; };
+    d2 stg[stage_per<TS / 2>()];
+    stage_load<TS / 2>(stg, src1(0), N1, src2(0));
+    double R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int p = 4 * c + kq;
+        R[c] = (p < m) ? xb[inpos(p) * 64] : 0.0;
+    }
+    stage_store<TS / 2>(stg, sbuf);
+    __syncthreads();
     d4 Y[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) Y[t] = d4{0.0, 0.0, 0.0, 0.0};
-    auto pos = [&](int p) -> int64_t { return FWD ? (int64_t)p : (int64_t)(m - 1 - p); };
+    const bool store_only = FWD && first;
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
-        const double *T = tab + (eb0 + beta) * TL.size();
-        double R[4];
+        const double *sb = sbuf + (beta & 1) * TS;
+        const bool more = beta + 1 < nblk;
+        double Rn[4] = {0.0, 0.0, 0.0, 0.0};
+        if (more) {
+            stage_load<TS / 2>(stg, src1(beta + 1), N1, src2(beta + 1));
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int p = 16 * beta + 4 * c + kq;
-            R[c] = (p < m) ? xb[pos(p) * 64] : 0.0;
+            for (int c = 0; c < 4; ++c) {
+                const int p = 16 * (beta + 1) + 4 * c + kq;
+                if (p < m) Rn[c] = xb[inpos(p) * 64];
+            }
         }
-        const double *G = T + (FWD ? TL.GF() : TL.GB());
-        const double *H = T + (FWD ? TL.HF() : TL.HB());
-        d4 F0 = d4{0.0, 0.0, 0.0, 0.0}, F1 = d4{0.0, 0.0, 0.0, 0.0};
-        F0 = mfma(G[0 * 64 + L], R[0], F0);
-        F1 = mfma(G[1 * 64 + L], R[1], F1);
-        F0 = mfma(G[2 * 64 + L], R[2], F0);
-        F1 = mfma(G[3 * 64 + L], R[3], F1);
+        double uo[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!store_only) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = 16 * beta + 4 * r + kq;
+                const int op = outpos(p);
+                if (p < m && op >= 0) uo[r] = ub[(int64_t)op * 64];
+            }
+        }
+        const double *G = sb + (FWD ? 512 * NT : 528 * NT);
+        const double *H = sb + (FWD ? 0 : 256 * NT);
+        const double *C = sb + (FWD ? 256 * NT : 0);
+        const double *D = sb + (FWD ? 512 * NT + 256 : 512 * NT);
+        d4 F[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F[c] = mfma(G[c * 64 + L], R[c], d4{0.0, 0.0, 0.0, 0.0});
         if (beta > 0) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                F0 = mfma(H[(t * 4 + 0) * 64 + L], Y[t][0], F0);
-                F1 = mfma(H[(t * 4 + 1) * 64 + L], Y[t][1], F1);
-                F0 = mfma(H[(t * 4 + 2) * 64 + L], Y[t][2], F0);
-                F1 = mfma(H[(t * 4 + 3) * 64 + L], Y[t][3], F1);
-            }
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) F[r] = mfma(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
         }
         // carry: Y <- d .* Y + C R
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Y[t][r] *= T[TL.DT() + 16 * t + 4 * r + kq];
-        }
+            for (int r = 0; r < 4; ++r) Y[t][r] *= D[16 * t + 4 * r + kq];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) Y[t] = mfma(T[TL.CT() + (t * 4 + c) * 64 + L], R[c], Y[t]);
-        // accumulate the block's output rows 4r + kq
+            for (int t = 0; t < NT; ++t) Y[t] = mfma(C[(t * 4 + c) * 64 + L], R[c], Y[t]);
+        // the block's output rows 4r + kq
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int p = 16 * beta + 4 * r + kq;
-            const double f = F0[r] + F1[r];
-            if (FWD) {
-                if (p < m) ub[(int64_t)p * 64] += f;
-            } else {
-                const int op = m - 2 - p;  // output position of reversed step p
-                if (p < m && op >= 0) ub[(int64_t)op * 64] += f;
-            }
+            const int op = outpos(p);
+            const double f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
+            if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + f;
         }
+        if (more) stage_store<TS / 2>(stg, sbuf + ((beta + 1) & 1) * TS);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) R[c] = Rn[c];
     }
     // end values |b| w = rho_{m-1} * (carry at the last position)
     const double *rm = rhom + (int64_t)e * LBp;
@@ -399,9 +471,10 @@ __global__ void __launch_bounds__(256) k_sweep_blocked(const int64_t *__restrict
 
 // Pass B: u_I += sum_l |b_l| (u_tail^l Z_tail^l + u_head^l Z_head^l), with
 // Z_tail = (T^{-1})_{.,0} and Z_head = (T^{-1})_{.,m-1} in operand layout
-// (written by the coefficient kernel: [t][r][64] tail, then [t][r][64] head).
+// ([t][r][64] tail, then [t][r][64] head, 512 NT doubles per block), staged
+// through LDS like pass A.
 template <int NT>
-__global__ void __launch_bounds__(256) k_corr_blocked(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_corr_blocked(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
                                                       const int32_t *__restrict__ eu_,
                                                       const int32_t *__restrict__ ev_,
                                                       const int32_t *__restrict__ boff, int32_t E, int32_t V,
@@ -409,20 +482,24 @@ __global__ void __launch_bounds__(256) k_corr_blocked(const int64_t *__restrict_
                                                       const double *__restrict__ ztab,
                                                       const double *__restrict__ babs,
                                                       const double *__restrict__ ug, double *__restrict__ U) {
+    constexpr int TS = 512 * NT;
+    __shared__ double sbuf[2 * TS];
     const int L = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + wave_id();
-    const int ng = 4 * nb;
-    if (q >= (int64_t)E * ng) return;
-    const int e = (int)(q / ng);
-    const int g = (int)(q - (int64_t)e * ng);
-    const int b = g >> 2;
+    const int wv = wave_id();
+    const int64_t wg = xcd_logical_block();
+    const int e = (int)(wg / nb);
+    const int b = (int)(wg - (int64_t)e * nb);
+    const int g = 4 * b + wv;
     const int s0 = 16 * g;
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
-    if (m == 0) return;
+    if (m == 0) return;  // uniform over the workgroup
     const int64_t off = off_[e];
     double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     const int vt = eu_[e], vh = ev_[e];
+    const double *z0 = ztab + (int64_t)boff[e] * TS;
+    d2 stg[stage_per<TS / 2>()];
+    stage_load<TS / 2>(stg, z0, TS, z0);
     double ct[NT][4], ch[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -434,44 +511,55 @@ __global__ void __launch_bounds__(256) k_corr_blocked(const int64_t *__restrict_
             ct[t][r] = bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n];
             ch[t][r] = bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n];
         }
+    stage_store<TS / 2>(stg, sbuf);
+    __syncthreads();
     const int nblk = (m + 15) >> 4;
-    const int64_t eb0 = boff[e];
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
-        const double *Z = ztab + (eb0 + beta) * (int64_t)(512 * NT);
-        d4 F0 = d4{0.0, 0.0, 0.0, 0.0}, F1 = d4{0.0, 0.0, 0.0, 0.0};
+        const double *Z = sbuf + (beta & 1) * TS;
+        const bool more = beta + 1 < nblk;
+        if (more) stage_load<TS / 2>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        double uo[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = 16 * beta + 4 * r + kq;
+            uo[r] = (pp < m) ? ub[(int64_t)pp * 64] : 0.0;
+        }
+        d4 F[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F[c] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                F0 = mfma(Z[(t * 4 + r) * 64 + L], ct[t][r], F0);
-                F1 = mfma(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F1);
+                F[r & 1] = mfma(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
+                F[2 + (r & 1)] = mfma(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
             }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pp = 16 * beta + 4 * r + kq;
-            if (pp < m) ub[(int64_t)pp * 64] += F0[r] + F1[r];
+            if (pp < m) ub[(int64_t)pp * 64] = uo[r] + ((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
         }
+        if (more) stage_store<TS / 2>(stg, sbuf + ((beta + 1) & 1) * TS);
+        __syncthreads();
     }
 }
 
 template <int NT>
 void sweep_nt(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
-    const int64_t waves = (int64_t)mv.E * 4 * a.nb;
-    dim3 grid((unsigned)((waves + 3) / 4));
+    dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
     if (fwd)
         hipLaunchKernelGGL((k_sweep_blocked<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends);
+                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first);
     else
         hipLaunchKernelGGL((k_sweep_blocked<NT, false>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends);
+                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, 0);
     GRF_LAUNCH_CHECK();
 }
 
 template <int NT>
 void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
-    const int64_t waves = (int64_t)mv.E * 4 * a.nb;
-    dim3 grid((unsigned)((waves + 3) / 4));
+    dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
     hipLaunchKernelGGL((k_corr_blocked<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E, mv.V,
                        mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U);
     GRF_LAUNCH_CHECK();
@@ -515,6 +603,7 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
 
 void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
     if (mv.E == 0 || a.LB == 0) return;
+    GRF_REQUIRE(mv.E * (int64_t)a.nb < (int64_t(1) << 31), "too many edge x sample-block workgroups");
 #define CALL_SWEEP(K) sweep_nt<K>(mv, a, fwd, st)
     GRF_NT_SWITCH(a.NT, CALL_SWEEP)
 #undef CALL_SWEEP
@@ -522,6 +611,7 @@ void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipS
 
 void launch_corr_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (mv.E == 0 || a.LB == 0) return;
+    GRF_REQUIRE(mv.E * (int64_t)a.nb < (int64_t(1) << 31), "too many edge x sample-block workgroups");
 #define CALL_CORR(K) corr_nt<K>(mv, a, st)
     GRF_NT_SWITCH(a.NT, CALL_CORR)
 #undef CALL_CORR

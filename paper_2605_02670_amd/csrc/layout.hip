@@ -1,6 +1,8 @@
 // Layout changes between the canonical [S][N] vectors of the ABI and the
 // sample-interleaved [nb][N][64] layout the sweeps use (lanes = samples, so a
 // wavefront's access to one DOF is one contiguous 512-byte row).
+#include <algorithm>
+
 #include "work.h"
 
 namespace grf {
@@ -49,7 +51,25 @@ __global__ void k_fill(double *__restrict__ p, size_t n, double v) {
         p[i] = v;
 }
 
+// rows [r0, r0 + nrows) of every 64-sample block of a [nb][N][64] array
+__global__ void k_fill_rows(double *__restrict__ p, int64_t nb, int64_t N, int64_t r0, int64_t nrows) {
+    const int64_t per = nrows * 64, n = nb * per;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / per, k = i - b * per;
+        p[(b * N + r0) * 64 + k] = 0.0;
+    }
+}
+
 }  // namespace
+
+void launch_fill_rows(double *p, int64_t nb, int64_t N, int64_t r0, int64_t nrows, hipStream_t st) {
+    const int64_t n = nb * nrows * 64;
+    if (n == 0) return;
+    GRF_REQUIRE(r0 >= 0 && r0 + nrows <= N, "internal: row range outside the array");
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)blocks), dim3(256), 0, st, p, nb, N, r0, nrows);
+    GRF_LAUNCH_CHECK();
+}
 
 void launch_to_interleaved(const double *in, int64_t S, int64_t N, double *X, hipStream_t st) {
     int64_t nb = (S + 63) / 64;

@@ -82,7 +82,8 @@ static void ensure_block_offsets(grf_graph &g, grf_graph::Work &w, hipStream_t s
 }
 
 // Runs shifts (cI[i], cL[i]) on the right-hand sides in w.X, accumulating into
-// w.U (which the caller zeroes).  Returns the number of unconverged systems.
+// w.U (zeroed here: the blocked forward pass of the first shift block writes
+// the interior rows, so only the vertex rows are cleared).
 static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::vector<double> &cL, int64_t S,
                        const grf_opts &o, hipStream_t st, grf_stats *stats, KTimer &T) {
     grf_graph::Work &w = work(g);
@@ -93,6 +94,12 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
     int64_t n_unconv = 0, tot_it = 0;
     int32_t max_it = 0;
     double max_res = 0.0;
+    T.begin(GRF_K_LAYOUT);
+    if (p.blocked)
+        launch_fill_rows(w.U.as<double>(), nb, g.N, g.NI, g.V, st);
+    else
+        launch_fill(w.U.as<double>(), (size_t)nb * g.N * 64, 0.0, st);
+    T.end();
     for (int32_t l0 = 0; l0 < L; l0 += p.LB) {
         const int32_t lb = std::min(p.LB, L - l0);
         const int32_t LBp = ((lb + p.BL - 1) / p.BL) * p.BL;  // blocked: multiple of 16
@@ -177,6 +184,7 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
             ba.ug = sa.ug;
             ba.nb = nb;
             ba.Sp = Sp;
+            ba.first = (l0 == 0) ? 1 : 0;
             T.begin(GRF_K_COEFF);
             launch_blocktab(mv, ba, st);
             T.end();
@@ -330,9 +338,6 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
     T.begin(GRF_K_NOISE);
     launch_noise(mv, n_samples, o.sample_offset, seed, w.X.as<double>(), st);
     T.end();
-    T.begin(GRF_K_LAYOUT);
-    launch_fill(w.U.as<double>(), (size_t)nb * g->N * 64, 0.0, st);
-    T.end();
     int code = GRF_OK;
     try {
         run_shifts(*g, sh.cI, sh.cL, n_samples, o, st, o.stats, T);
@@ -372,7 +377,6 @@ int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_
     KTimer T(o.timing != 0, st);
     T.begin(GRF_K_LAYOUT);
     launch_to_interleaved(rhs, n_rhs, g->N, w.X.as<double>(), st);
-    launch_fill(w.U.as<double>(), (size_t)nb * g->N * 64, 0.0, st);
     T.end();
     std::vector<double> cI(1, c_I), cL(1, c_L);
     int code = GRF_OK;

@@ -36,6 +36,8 @@ void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, do
 void launch_to_interleaved(const double *in, int64_t S, int64_t N, double *X, hipStream_t st);
 void launch_from_interleaved(const double *X, int64_t S, int64_t N, double *out, hipStream_t st);
 void launch_fill(double *p, size_t n, double v, hipStream_t st);
+// zero rows [r0, r0 + nrows) of each of the nb sample blocks of a [nb][N][64] array
+void launch_fill_rows(double *p, int64_t nb, int64_t N, int64_t r0, int64_t nrows, hipStream_t st);
 
 // per-(shift, edge) coefficients: Thomas rows (streamed sweeps), |b|, rho_{m-1}, Schur 2x2
 struct CoeffArgs {
@@ -82,6 +84,7 @@ struct BlockArgs {
     double *ends;           // [LB][E][2][Sp]
     const double *ug;       // [LB][V][Sp]
     int32_t nb, Sp;
+    int32_t first;          // first shift block: the forward pass writes (not updates) the interior accumulator
 };
 int64_t block_tab_doubles(int32_t NT);
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st);
