@@ -64,6 +64,7 @@ void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 // ---- mesh as seen by kernels (plain device pointers, passed by value) ------
 struct MeshView {
     int32_t V, E;
+    int32_t max_deg;      // largest vertex degree (edge ends)
     int64_t NI, N;        // interior DOFs, all DOFs
     const int64_t *off;   // [E+1] first interior DOF of each edge
     const int32_t *m;     // [E] interior DOF count

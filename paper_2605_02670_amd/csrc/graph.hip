@@ -11,6 +11,8 @@
 #include <cstring>
 
 #include "common.h"
+#include <algorithm>
+
 #include "work.h"
 
 namespace grf {
@@ -220,6 +222,8 @@ grf::MeshView grf_graph::view() const {
     grf::MeshView v;
     v.V = (int32_t)V;
     v.E = (int32_t)E;
+    v.max_deg = 0;
+    for (int64_t u = 0; u < V; ++u) v.max_deg = std::max<int32_t>(v.max_deg, (int32_t)(vptr[u + 1] - vptr[u]));
     v.NI = NI;
     v.N = N;
     v.off = d_off.as<int64_t>();

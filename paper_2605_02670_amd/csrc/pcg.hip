@@ -184,52 +184,95 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
     }
 }
 
-// Same algorithm with the vectors on chip, for V <= TPB K: each thread keeps
-// x, r, q, the Schur diagonal and the Jacobi inverse of its K vertices in
-// registers; the search direction p (and x, for the recomputed residual) live
-// in LDS where neighbours read them.  Only g is read and x written in HBM.
-template <int K, int TPB>
+// Same algorithm with the vectors on chip, for V <= TPB K.  A workgroup takes
+// a contiguous range of systems (mostly of one shift) and keeps the operator
+// of its K vertices per thread in registers, reloaded only when the shift
+// changes: the Schur diagonal, the Jacobi inverse and the first D
+// (neighbour, coefficient) pairs of each vertex in CSR order (further
+// neighbours, if any, are read from the CSR arrays).  r stays in registers;
+// p, x and q = S p live in LDS.  Only g is read and x written in HBM.
+template <int K, int TPB, int D>
 __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__restrict__ sd,
                                                  const double *__restrict__ so, const double *__restrict__ gT,
                                                  double *__restrict__ xT, int32_t *__restrict__ its,
                                                  double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                                  int32_t maxit) {
-    extern __shared__ double sv[];
+    extern __shared__ double sv[];  // p [V], x [V], q [V]
     __shared__ double red[64];
     const int V = mv.V;
     const int64_t E = mv.E;
-    double *ps = sv;      // [V] search direction
-    double *xs = sv + V;  // [V] iterate, for the recomputed residual
     const int nw = blockDim.x >> 6;
     const int64_t nsys = (int64_t)LB * S;
-    for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
+    const int64_t per = (nsys + gridDim.x - 1) / gridDim.x;
+    const int64_t sys0 = (int64_t)blockIdx.x * per;
+    const int64_t sys1 = min(nsys, sys0 + per);
+    double ds[K], ji[K], cf[K][D];
+    int nbr[K][D];
+    int ovb[K], ove[K];  // CSR range of the neighbours beyond the first D (2E < 2^31)
+    const double *sol = so;
+    int lcur = -1;
+    for (int64_t sys = sys0; sys < sys1; ++sys) {
         const int l = (int)(sys / S);
+        if (l != lcur) {  // uniform over the workgroup
+            lcur = l;
+            const double *sdl = sd + (int64_t)l * E;
+            sol = so + (int64_t)l * E;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int v = threadIdx.x + TPB * i;
+                ds[i] = 0.0;
+                ji[i] = 0.0;
+                ovb[i] = 0;
+                ove[i] = 0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    cf[i][d] = 0.0;
+                    nbr[i][d] = 0;
+                }
+                if (v < V) {
+                    const int k0 = (int)mv.vptr[v], k1 = (int)mv.vptr[v + 1];
+                    double dsum = 0.0, dj = 0.0;
+                    for (int k = k0; k < k1; ++k) {
+                        const int e = mv.adj_e[k];
+                        dsum += sdl[e];
+                        dj += (mv.adj_o[k] == v) ? sol[e] : 0.0;
+                    }
+                    ds[i] = dsum;
+                    ji[i] = 1.0 / (dsum + dj);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        const int k = k0 + d;
+                        if (k < k1) {
+                            cf[i][d] = sol[mv.adj_e[k]];
+                            nbr[i][d] = mv.adj_o[k];
+                        }
+                    }
+                    ovb[i] = k0 + D;
+                    ove[i] = k1;
+                }
+            }
+        }
+        // (S y)_v, y = sv[yo ..] in LDS, summed in CSR order
+        auto apply = [&](int yo, int i, int v) -> double {
+            double acc = ds[i] * sv[yo + v];
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc += cf[i][d] * sv[yo + nbr[i][d]];
+            for (int k = ovb[i]; k < ove[i]; ++k) acc += sol[mv.adj_e[k]] * sv[yo + mv.adj_o[k]];
+            return acc;
+        };
         const double *g = gT + sys * V;
-        const double *sdl = sd + (int64_t)l * E;
-        const double *sol = so + (int64_t)l * E;
-        double x[K], r[K], ds[K], ji[K], q[K];
+        double r[K];
         double t2[2] = {0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int v = threadIdx.x + TPB * i;
-            x[i] = 0.0;
             r[i] = 0.0;
-            ds[i] = 0.0;
-            ji[i] = 0.0;
-            q[i] = 0.0;
             if (v < V) {
-                double d = 0.0, dj = 0.0;
-                for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
-                    const int e = mv.adj_e[k];
-                    d += sdl[e];
-                    dj += (mv.adj_o[k] == v) ? sol[e] : 0.0;
-                }
-                ds[i] = d;
-                ji[i] = 1.0 / (d + dj);
                 const double gv = g[v];
                 r[i] = gv;
                 const double z = gv * ji[i];
-                ps[v] = z;
+                sv[v] = z;
+                sv[V + v] = 0.0;
                 t2[0] += gv * z;
                 t2[1] += gv * gv;
             }
@@ -249,12 +292,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
                 for (int i = 0; i < K; ++i) {
                     const int v = threadIdx.x + TPB * i;
                     if (v < V) {
-                        const double pv = ps[v];
-                        double acc = ds[i] * pv;
-                        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k)
-                            acc += sol[mv.adj_e[k]] * ps[mv.adj_o[k]];
-                        q[i] = acc;
-                        t1[0] += pv * acc;
+                        const double acc = apply(0, i, v);
+                        sv[2 * V + v] = acc;
+                        t1[0] += sv[v] * acc;
                     }
                 }
                 block_sum<1>(t1, red, nw);
@@ -264,8 +304,8 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
                 for (int i = 0; i < K; ++i) {
                     const int v = threadIdx.x + TPB * i;
                     if (v < V) {
-                        x[i] += alpha * ps[v];
-                        r[i] -= alpha * q[i];
+                        sv[V + v] += alpha * sv[v];
+                        r[i] -= alpha * sv[2 * V + v];
                         t3[0] += r[i] * r[i] * ji[i];
                         t3[1] += r[i] * r[i];
                     }
@@ -274,21 +314,13 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
                 double rz_new = t3[0];
                 double beta;
                 if (t3[1] <= tol2) {
-#pragma unroll
-                    for (int i = 0; i < K; ++i) {
-                        const int v = threadIdx.x + TPB * i;
-                        if (v < V) xs[v] = x[i];
-                    }
-                    __syncthreads();
+                    __syncthreads();  // x complete
                     double tt[2] = {0.0, 0.0};
 #pragma unroll
                     for (int i = 0; i < K; ++i) {
                         const int v = threadIdx.x + TPB * i;
                         if (v < V) {
-                            double acc = ds[i] * xs[v];
-                            for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k)
-                                acc += sol[mv.adj_e[k]] * xs[mv.adj_o[k]];
-                            const double rv = g[v] - acc;
+                            const double rv = g[v] - apply(V, i, v);
                             r[i] = rv;
                             tt[0] += rv * rv;
                             tt[1] += rv * rv * ji[i];
@@ -308,7 +340,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     const int v = threadIdx.x + TPB * i;
-                    if (v < V) ps[v] = r[i] * ji[i] + beta * ps[v];
+                    if (v < V) sv[v] = r[i] * ji[i] + beta * sv[v];
                 }
             }
             if (it > maxit) it = maxit + 1;
@@ -317,7 +349,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int v = threadIdx.x + TPB * i;
-            if (v < V) xo[v] = (gg > 0.0) ? x[i] : 0.0;
+            if (v < V) xo[v] = (gg > 0.0) ? sv[V + v] : 0.0;
         }
         if (threadIdx.x == 0) {
             its[sys] = it;
@@ -375,20 +407,26 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
-template <int K, int TPB>
-static void pcg_lds(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+template <int K, int TPB, int D>
+static void pcg_lds_d(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     const int64_t nsys = (int64_t)a.LB * a.S;
-    const size_t lds = 2 * sizeof(double) * (size_t)mv.V;
+    const size_t lds = 3 * sizeof(double) * (size_t)mv.V;
     static bool attr_set = false;
     if (!attr_set) {
-        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    65536));
+        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    3 * 8 * 4096));
         attr_set = true;
     }
     const int64_t blocks = std::min<int64_t>(nsys, 256 * (2048 / TPB));
-    hipLaunchKernelGGL((k_pcg_lds<K, TPB>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a.sd, a.so, a.gT, a.xT,
-                       a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+    hipLaunchKernelGGL((k_pcg_lds<K, TPB, D>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a.sd, a.so, a.gT,
+                       a.xT, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
+}
+
+template <int K, int TPB>
+static void pcg_lds(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    if (mv.max_deg <= 4) return pcg_lds_d<K, TPB, 4>(mv, a, st);
+    return pcg_lds_d<K, TPB, 8>(mv, a, st);
 }
 
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
