@@ -184,95 +184,99 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
     }
 }
 
-// Same algorithm with the vectors on chip, for V <= TPB K.  A workgroup takes
-// a contiguous range of systems (mostly of one shift) and keeps the operator
-// of its K vertices per thread in registers, reloaded only when the shift
-// changes: the Schur diagonal, the Jacobi inverse and the first D
-// (neighbour, coefficient) pairs of each vertex in CSR order (further
-// neighbours, if any, are read from the CSR arrays).  r stays in registers;
-// p, x and q = S p live in LDS.  Only g is read and x written in HBM.
+// Same algorithm with the vectors on chip, for V <= TPB K vertices of degree
+// <= D, V, E < 2^16 and (2V + E) doubles of LDS.  A workgroup takes a
+// contiguous range of systems (mostly of one shift).  LDS holds p, x and the
+// shift's edge coefficients s_o (reloaded only when the shift changes); each
+// thread keeps, for its K vertices, the (neighbour, edge) pairs in CSR order
+// packed in 16-bit halves (shift-independent), the Schur diagonal, the Jacobi
+// inverse, r and q = S p in registers.  Only g is read and x written in HBM.
 template <int K, int TPB, int D>
 __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__restrict__ sd,
                                                  const double *__restrict__ so, const double *__restrict__ gT,
                                                  double *__restrict__ xT, int32_t *__restrict__ its,
                                                  double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                                  int32_t maxit) {
-    extern __shared__ double sv[];  // p [V], x [V], q [V]
+    extern __shared__ double sv[];  // p [V], x [V], s_o [E]
     __shared__ double red[64];
     const int V = mv.V;
-    const int64_t E = mv.E;
+    const int E = mv.E;
+    double *ps = sv, *xs = sv + V, *sos = sv + 2 * V;
     const int nw = blockDim.x >> 6;
     const int64_t nsys = (int64_t)LB * S;
     const int64_t per = (nsys + gridDim.x - 1) / gridDim.x;
     const int64_t sys0 = (int64_t)blockIdx.x * per;
     const int64_t sys1 = min(nsys, sys0 + per);
-    double ds[K], ji[K], cf[K][D];
-    int nbr[K][D];
-    int ovb[K], ove[K];  // CSR range of the neighbours beyond the first D (2E < 2^31)
-    const double *sol = so;
+    uint32_t nbr[K][D];  // other vertex | edge << 16; 0 with a zero coefficient slot for padding
+    int nd[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int v = threadIdx.x + TPB * i;
+        nd[i] = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) nbr[i][d] = 0;
+        if (v < V) {
+            const int k0 = (int)mv.vptr[v], k1 = (int)mv.vptr[v + 1];
+            nd[i] = k1 - k0;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                if (k0 + d < k1) nbr[i][d] = (uint32_t)mv.adj_o[k0 + d] | ((uint32_t)mv.adj_e[k0 + d] << 16);
+        }
+    }
+    double ds[K], ji[K];
     int lcur = -1;
     for (int64_t sys = sys0; sys < sys1; ++sys) {
         const int l = (int)(sys / S);
         if (l != lcur) {  // uniform over the workgroup
             lcur = l;
+            __syncthreads();  // previous coefficients no longer read
             const double *sdl = sd + (int64_t)l * E;
-            sol = so + (int64_t)l * E;
+            const double *sol = so + (int64_t)l * E;
+            for (int e = threadIdx.x; e < E; e += TPB) sos[e] = sol[e];
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const int v = threadIdx.x + TPB * i;
-                ds[i] = 0.0;
-                ji[i] = 0.0;
-                ovb[i] = 0;
-                ove[i] = 0;
+                double dsum = 0.0, dj = 0.0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    cf[i][d] = 0.0;
-                    nbr[i][d] = 0;
-                }
-                if (v < V) {
-                    const int k0 = (int)mv.vptr[v], k1 = (int)mv.vptr[v + 1];
-                    double dsum = 0.0, dj = 0.0;
-                    for (int k = k0; k < k1; ++k) {
-                        const int e = mv.adj_e[k];
+                    if (d < nd[i]) {
+                        const int e = (int)(nbr[i][d] >> 16), o = (int)(nbr[i][d] & 0xffff);
                         dsum += sdl[e];
-                        dj += (mv.adj_o[k] == v) ? sol[e] : 0.0;
+                        dj += (o == v) ? sol[e] : 0.0;
                     }
-                    ds[i] = dsum;
-                    ji[i] = 1.0 / (dsum + dj);
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const int k = k0 + d;
-                        if (k < k1) {
-                            cf[i][d] = sol[mv.adj_e[k]];
-                            nbr[i][d] = mv.adj_o[k];
-                        }
-                    }
-                    ovb[i] = k0 + D;
-                    ove[i] = k1;
                 }
+                ds[i] = dsum;
+                ji[i] = (v < V) ? 1.0 / (dsum + dj) : 0.0;
             }
+            __syncthreads();  // s_o in LDS
         }
-        // (S y)_v, y = sv[yo ..] in LDS, summed in CSR order
+        // (S y)_v, y = sv[yo ..] in LDS, summed in CSR order.  The packed ids are
+        // decoded at each use (the empty asm keeps the compiler from hoisting the
+        // decoded ids and their LDS addresses out of the loop into registers).
         auto apply = [&](int yo, int i, int v) -> double {
             double acc = ds[i] * sv[yo + v];
 #pragma unroll
-            for (int d = 0; d < D; ++d) acc += cf[i][d] * sv[yo + nbr[i][d]];
-            for (int k = ovb[i]; k < ove[i]; ++k) acc += sol[mv.adj_e[k]] * sv[yo + mv.adj_o[k]];
+            for (int d = 0; d < D; ++d) {
+                uint32_t pk = nbr[i][d];
+                asm volatile("" : "+v"(pk));
+                if (d < nd[i]) acc += sos[pk >> 16] * sv[yo + (int)(pk & 0xffff)];
+            }
             return acc;
         };
         const double *g = gT + sys * V;
-        double r[K];
+        double r[K], q[K];
         double t2[2] = {0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int v = threadIdx.x + TPB * i;
             r[i] = 0.0;
+            q[i] = 0.0;
             if (v < V) {
                 const double gv = g[v];
                 r[i] = gv;
                 const double z = gv * ji[i];
-                sv[v] = z;
-                sv[V + v] = 0.0;
+                ps[v] = z;
+                xs[v] = 0.0;
                 t2[0] += gv * z;
                 t2[1] += gv * gv;
             }
@@ -292,9 +296,8 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
                 for (int i = 0; i < K; ++i) {
                     const int v = threadIdx.x + TPB * i;
                     if (v < V) {
-                        const double acc = apply(0, i, v);
-                        sv[2 * V + v] = acc;
-                        t1[0] += sv[v] * acc;
+                        q[i] = apply(0, i, v);
+                        t1[0] += ps[v] * q[i];
                     }
                 }
                 block_sum<1>(t1, red, nw);
@@ -304,8 +307,8 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
                 for (int i = 0; i < K; ++i) {
                     const int v = threadIdx.x + TPB * i;
                     if (v < V) {
-                        sv[V + v] += alpha * sv[v];
-                        r[i] -= alpha * sv[2 * V + v];
+                        xs[v] += alpha * ps[v];
+                        r[i] -= alpha * q[i];
                         t3[0] += r[i] * r[i] * ji[i];
                         t3[1] += r[i] * r[i];
                     }
@@ -340,16 +343,17 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     const int v = threadIdx.x + TPB * i;
-                    if (v < V) sv[v] = r[i] * ji[i] + beta * sv[v];
+                    if (v < V) ps[v] = r[i] * ji[i] + beta * ps[v];
                 }
             }
             if (it > maxit) it = maxit + 1;
         }
+        __syncthreads();  // x complete
         double *xo = xT + sys * V;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int v = threadIdx.x + TPB * i;
-            if (v < V) xo[v] = (gg > 0.0) ? sv[V + v] : 0.0;
+            if (v < V) xo[v] = (gg > 0.0) ? xs[v] : 0.0;
         }
         if (threadIdx.x == 0) {
             its[sys] = it;
@@ -407,40 +411,60 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+
 template <int K, int TPB, int D>
-static void pcg_lds_d(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+static bool pcg_lds_d(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     const int64_t nsys = (int64_t)a.LB * a.S;
-    const size_t lds = 3 * sizeof(double) * (size_t)mv.V;
-    static bool attr_set = false;
-    if (!attr_set) {
-        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    3 * 8 * 4096));
-        attr_set = true;
+    const size_t lds = sizeof(double) * (2 * (size_t)mv.V + (size_t)mv.E);
+    if (lds > kMaxLds - 1024) return false;
+    static size_t attr = 0;  // largest dynamic LDS size granted so far
+    if (lds > attr) {
+        if (hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        attr = lds;
     }
     const int64_t blocks = std::min<int64_t>(nsys, 256 * (2048 / TPB));
     hipLaunchKernelGGL((k_pcg_lds<K, TPB, D>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a.sd, a.so, a.gT,
                        a.xT, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
+    return true;
 }
 
 template <int K, int TPB>
-static void pcg_lds(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+static bool pcg_lds(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (mv.max_deg <= 4) return pcg_lds_d<K, TPB, 4>(mv, a, st);
     return pcg_lds_d<K, TPB, 8>(mv, a, st);
 }
 
-void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
-    if (a.LB == 0 || a.S == 0) return;
-    int64_t nsys = (int64_t)a.LB * a.S;
-    if (mv.V <= 256) return pcg_lds<1, 256>(mv, a, st);
-    if (mv.V <= 512) return pcg_lds<2, 256>(mv, a, st);
-    if (mv.V <= 1024) return pcg_lds<2, 512>(mv, a, st);
-    if (mv.V <= 2048) return pcg_lds<2, 1024>(mv, a, st);
-    if (mv.V <= 4096) return pcg_lds<4, 1024>(mv, a, st);
-    int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
+static void pcg_global(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    const int64_t nsys = (int64_t)a.LB * a.S;
+    const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
     hipLaunchKernelGGL(k_pcg, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr, a.its,
                        a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
+}
+
+void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    if (a.LB == 0 || a.S == 0) return;
+    bool done = false;
+    // on-chip variants: every neighbour of a vertex in registers, 16-bit vertex and edge ids
+    if (mv.max_deg <= 8 && mv.V < 65536 && mv.E < 65536) {
+        if (mv.V <= 256)
+            done = pcg_lds<1, 256>(mv, a, st);
+        else if (mv.V <= 512)
+            done = pcg_lds<2, 256>(mv, a, st);
+        else if (mv.V <= 1024)
+            done = pcg_lds<2, 512>(mv, a, st);
+        else if (mv.V <= 2048)
+            done = pcg_lds<2, 1024>(mv, a, st);
+        else if (mv.V <= 4096)
+            done = pcg_lds<4, 1024>(mv, a, st);
+    }
+    if (!done) pcg_global(mv, a, st);
 }
 
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
