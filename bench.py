@@ -45,65 +45,29 @@ HIP_KERNEL = {
     "streamed": {"ends_fwd": "k_sweep_ends<BL, true>", "ends_bwd": "k_sweep_ends<BL, false>",
                  "acc_fwd": "k_sweep_acc<BL, true>", "acc_bwd": "k_sweep_acc<BL, false>"},
 }
-# HBM bytes per launch of the pass-A forward kernel on this workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by the plain-copy calibration),
-# valid only for the kernel source they were taken on.
-TRAFFIC = {"kernel": "ends_fwd", "source": "paper_2605_02670_amd/csrc/blocked.hip", "sha256": None,
-           "fetch_bytes": None, "write_bytes": None}
+# HBM bytes per launch of the blocked edge kernels on this workload (rocprofv3
+# FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0 KiB: the factors a 1 GiB plain copy
+# reads on these counters), valid only for the kernel source they were taken on.
+TRAFFIC_SOURCE = "paper_2605_02670_amd/csrc/blocked.hip"
+TRAFFIC_SHA256 = "1c107201bf45fe8f95f0a18ee4548d0a91db706cc49fd55366341437ad9fbd24"
+TRAFFIC = {  # kernel id: (fetch KiB, write KiB) per launch
+    "ends_fwd": (4471735.5, 5996584.0),
+    "ends_bwd": (6674479.1875, 5980456.0),
+    "acc_fwd": (5630185.3125, 4125736.0),
+}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
 def _traffic(dom: str, mode: str):
     import hashlib
 
-    if mode != "blocked" or dom != TRAFFIC["kernel"] or TRAFFIC["sha256"] is None:
+    if mode != "blocked" or dom not in TRAFFIC:
         return None
-    with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["sha256"]:
+    with open(os.path.join(ROOT, TRAFFIC_SOURCE), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC_SHA256:
             return None  # kernel changed since the counters were taken
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
-
-
-def cpu_baseline(cfg, L: int, S: int, n_shift_sample: int = 3, n_samp: int = 4) -> dict:
-    """Time the FP64 oracle (numpy Philox noise, one sparse LU per shift) on a
-    bounded sample and extrapolate the whole job linearly:
-        t_job = S t_noise + L (t_factor + S t_rhs),
-    with t_factor and t_rhs fitted from solves with 1 and n_samp right-hand sides."""
-    from threadpoolctl import threadpool_limits
-
-    with threadpool_limits(limits=1):
-        return _cpu_baseline(cfg, L, S, n_shift_sample, n_samp)
-
-
-def _cpu_baseline(cfg, L: int, S: int, n_shift_sample: int, n_samp: int) -> dict:
-    import numpy as np
-
-    from oracle import mesh as omesh
-    from oracle import noise as onoise
-    from oracle import quadrature as oquad
-    from oracle import solve as osolve
-
-    g = cfg["graph"]
-    m = omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
-    ML = omesh.lumped_mass(m)
-    t0 = time.perf_counter()
-    W = onoise.white_noise(ML, cfg["seed"], n_samp)
-    t_noise = (time.perf_counter() - t0) / n_samp
-    _, cI, cL = oquad.shifts(cfg["beta"], cfg["quad_step"])
-    idx = np.linspace(0, len(cI) - 1, n_shift_sample).round().astype(int)
-    times = {}
-    for ns in (1, n_samp):
-        t0 = time.perf_counter()
-        for i in idx:
-            osolve.solve_shifted(m, cfg["kappa"], float(cI[i]), float(cL[i]), W[:ns])
-        times[ns] = (time.perf_counter() - t0) / n_shift_sample
-    t_rhs = max(0.0, (times[n_samp] - times[1]) / (n_samp - 1))
-    t_factor = max(0.0, times[1] - t_rhs)
-    t_job = S * t_noise + L * (t_factor + S * t_rhs)
-    return {"value": m.n_dof * L * S / t_job, "unit": "DOF-shift-solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle (numpy Philox noise, scipy splu per shift, 1 thread) on the same graph: noise for "
-                      f"{n_samp} samples ({t_noise:.2f} s/sample) and {n_shift_sample} shifts solved with 1 and "
-                      f"{n_samp} right-hand sides (factor+assemble {t_factor:.2f} s/shift, {t_rhs:.3f} s/rhs); "
-                      f"whole job ({S} samples x {L} shifts) extrapolated as S*t_noise + L*(t_factor + S*t_rhs)"}
+    fetch, write = TRAFFIC[dom]
+    return 1024.0 * (FETCH_FACTOR * fetch + WRITE_FACTOR * write)
 
 
 def main() -> int:
@@ -121,7 +85,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built "
-              "(samples shard with no communication; see DESIGN.md)", file=sys.stderr)
+              "(samples shard across GPUs with no communication)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -13,7 +13,7 @@ Paper passages followed:
   partition of the DOF vector into per-edge interior blocks followed by the
   vertex block ([W_I,1 ... W_I,|E| W_Gamma]).
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
 
 * ``rule="round"`` uses n_e = floor(l_e/h + 1/2) (half-up) instead of the
   ceiling; both clamp n_e >= 1, and a self-loop gets n_e >= 2.

@@ -8,7 +8,7 @@ Paper passages followed:
   element-wise square root of the diagonal, so W_j = sqrt(M_jj) xi_j.
 
 The paper does not say how xi is drawn.  The generator below is this
-project's definition (written out in DESIGN.md, "Noise definition"), built so
+project's definition, built so
 that the CPU and the GPU produce bit-identical values:
 
 * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as

@@ -10,7 +10,7 @@ Paper passages followed:
 * "Strong error" subsection: the default step k = -1/(beta ln h) and the
   limits K^- = ceil(pi^2 / (4 k^2 beta)), K^+ = ceil(pi^2 / (4 k^2 (1-beta))).
 
-Reading (DESIGN.md): the sum runs over l = -K^- .. K^+ in increasing order.
+Reading: the sum runs over l = -K^- .. K^+ in increasing order.
 """
 
 from __future__ import annotations

@@ -7,7 +7,7 @@ Paper passages followed:
 * "Quadrature Accumulation and Global Assembly": u = sum_l u^(l), with u^(l)
   laid out as [u_I(e_1) ... u_I(e_|E|) u_Gamma].
 
-Readings (DESIGN.md): the operator L = kappa^2 - Delta of eq. fractional_spde
+Readings: the operator L = kappa^2 - Delta of eq. fractional_spde
 discretises to kappa^2 M + G, so the shifted matrix is
 A^(l) = (c_I + c_L kappa^2) M + c_L G; M is the same mass matrix as the noise
 (lumped unless ``mass="consistent"``).  No blocking, condensation or

@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libgrf.so")
 ARCH = os.environ.get("GRF_OFFLOAD_ARCH", "gfx950")
 COMMON = [
     "-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
-    # packed FP32 instructions stay off ("Compiler settings")
+    # no packed FP32 instructions: FP32 arithmetic is issued as plain (unpacked) VALU operations
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
