@@ -41,9 +41,16 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// FP32 16x16x4 (mixed precision): same A/B lane layout, but accumulator item r
+// of lane L holds D[4 (L/16) + r][L%16] (verified on gfx950).
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -154,11 +161,13 @@ constexpr int kSPad = kTabThreads + 4;    // LDS row stride of the Ghat operands
 constexpr double kThetaSplit = 40.0;      // see k_blocktab
 
 // Writes the 16 per-position values v[i] of every shift of this wave as 16
-// contiguous 64-lane operand vectors: H/Z layout (lane i + 16 k of vector
-// (t, r) <- shift 16t + 4r + k, position i) or C layout (lane n + 16 q of
-// vector (t, c) <- shift 16t + n, position 4c + q).
-template <bool CLAYOUT>
-__device__ __forceinline__ void emit16(double (*tile)[17], const double (&v)[16], double *dst, int wv, int NT) {
+// contiguous 64-lane operand vectors, in one of three layouts:
+//   C layout: lane n + 16 q of vector (t, c) <- shift 16t + n, position 4c + q;
+//   H/Z layout, FP64 (F32L false): lane i + 16 k of vector (t, r) <- shift 16t + 4r + k, position i;
+//   H/Z layout, FP32 (F32L true):  lane i + 16 k of vector (t, r) <- shift 16t + 4k + r, position i
+// (the shift order of the accumulator registers used as B operands).
+template <bool CLAYOUT, bool F32L, typename OT>
+__device__ __forceinline__ void emit16(double (*tile)[17], const double (&v)[16], OT *dst, int wv, int NT) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int i = 0; i < 16; ++i) tile[lane][i] = v[i];
@@ -167,8 +176,9 @@ __device__ __forceinline__ void emit16(double (*tile)[17], const double (&v)[16]
     for (int o = 0; o < 16; ++o) {
         if (4 * wv + (o >> 2) >= NT) break;
         const double x = CLAYOUT ? tile[16 * (o >> 2) + (lane & 15)][4 * (o & 3) + (lane >> 4)]
+                         : F32L  ? tile[16 * (o >> 2) + 4 * (lane >> 4) + (o & 3)][lane & 15]
                                  : tile[4 * o + (lane >> 4)][lane & 15];
-        dst[(int64_t)(16 * wv + o) * 64 + lane] = x;
+        dst[(int64_t)(16 * wv + o) * 64 + lane] = (OT)x;
     }
     __syncthreads();
 }
@@ -188,10 +198,11 @@ __device__ __forceinline__ void emit16(double (*tile)[17], const double (&v)[16]
 // off-diagonal Lam of a shift with theta > 40 (relative size below e^{-40}, far
 // under the rounding of its own diagonal term) is replaced by an equally
 // negligible value.
+template <typename OT>
 __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int32_t *__restrict__ boff,
                                                           const double *__restrict__ shift, int32_t LB, int32_t LBp,
-                                                          int32_t NT, double *__restrict__ tab,
-                                                          double *__restrict__ ztab) {
+                                                          int32_t NT, OT *__restrict__ tab, OT *__restrict__ ztab) {
+    constexpr bool F32L = sizeof(OT) == 4;  // FP32 operand tables for the mixed-precision sweeps
     __shared__ double sAf[17][kSPad];   // dg / (w^i E(base+i+1)) split factor, rows 0..16
     __shared__ double sBm[16][kSPad];   // E(base+j+1) split factor
     __shared__ double srw[kSPad];       // w / w_split
@@ -204,8 +215,8 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     const int base = 16 * beta;
     const int istar = min(15, m - 1 - base);
     const TabLayout TL{NT};
-    double *T = tab + blk * TL.size();
-    double *Z = ztab + blk * (int64_t)(512 * NT);
+    OT *T = tab + blk * TL.size();
+    OT *Z = ztab + blk * (int64_t)(512 * NT);
     const int l = tid;
     const bool live = l < LB;
     double th = 0.0, w = 0.0, E1 = 0.0, K = 0.0, ascale = 0.0;
@@ -236,18 +247,18 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     // H_fwd[i] = dg_i lam_i = w^{i+1} E(base) E(m-base-i) / (2 sinh |b| E(m+1))
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wp[i + 1] * lam0 * Q[i] : 0.0;
-    emit16<false>(tile[wv], v, T + TL.HF(), wv, NT);
+    emit16<false, F32L>(tile[wv], v, T + TL.HF(), wv, NT);
     // H_bwd[i] = of_i lam_i = w^{i+2} E(base) E(m-base-i-1) / (...)
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wp[i + 2] * lam0 * Q[i + 1] : 0.0;
-    emit16<false>(tile[wv], v, T + TL.HB(), wv, NT);
+    emit16<false, F32L>(tile[wv], v, T + TL.HB(), wv, NT);
     // Z_tail[i] = w^{base+1+i} E(m-base-i) K
     {
         const double wb = live ? exp(-(double)(base + 1) * th) * K : 0.0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wb * wp[i] * Q[i] : 0.0;
     }
-    emit16<false>(tile[wv], v, Z, wv, NT);
+    emit16<false, F32L>(tile[wv], v, Z, wv, NT);
     // C[j] = w^{i*-j} E(base+j+1) / E(base+i*+1), d = w^{i*+1} E(base) / E(base+i*+1), and
     // Z_head[i] = w^{m-base-i} E(base+i+1) K: descending chains from i*
     double dval = 0.0;
@@ -267,10 +278,10 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
             }
         }
         dval = live ? pw * Ef[0] * inv : 0.0;  // pw = w^{i*+1}
-        emit16<true>(tile[wv], v, T + TL.CT(), wv, NT);
-        emit16<false>(tile[wv], vz, Z + 256 * NT, wv, NT);
+        emit16<true, F32L>(tile[wv], v, T + TL.CT(), wv, NT);
+        emit16<false, F32L>(tile[wv], vz, Z + 256 * NT, wv, NT);
     }
-    if (l < LBp) T[TL.DT() + l] = dval;
+    if (l < LBp) T[TL.DT() + l] = (OT)dval;
     // Ghat operands (split factors); rows past i*+1 (Af) / i* (Bm) are zero
     {
         const double thc = fmin(th, kThetaSplit);
@@ -300,11 +311,11 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
             const double b = (wv == 0) ? sAf[n][ll] : sAf[n + 1][ll] * srw[ll];
             acc = mfma(a, b, acc);
         }
-        double *G = T + (wv == 0 ? TL.GF() : TL.GB());
+        OT *G = T + (wv == 0 ? TL.GF() : TL.GB());
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int jj = 4 * r + q;  // D row of the transpose = column j of Ghat; lane row n = i
-            G[r * 64 + lane] = (jj <= n && n <= istar) ? acc[r] : 0.0;
+            G[r * 64 + lane] = (OT)((jj <= n && n <= istar) ? acc[r] : 0.0);
         }
     }
 }
@@ -313,28 +324,37 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
 // workgroup (one edge, 64 samples): every thread loads its share of the next
 // block into registers while the current block is computed, then writes it to
 // the other LDS buffer.
-template <int NV2>
-constexpr int stage_per() { return (NV2 + 255) / 256; }
+// 16-byte vectors of the table element type
+template <typename ET> struct V16;
+template <> struct V16<double> { typedef d2 type; };
+template <> struct V16<float> { typedef f4 type; };
 
-// copy [src1, src1 + n1) ++ [src2, ...) (n1 even, both 16-byte aligned) into registers
-template <int NV2>
-__device__ __forceinline__ void stage_load(d2 (&r)[stage_per<NV2>()], const double *src1, int n1,
-                                           const double *src2) {
+template <typename ET, int NE>
+constexpr int stage_per() { return (NE * (int)sizeof(ET) / 16 + 255) / 256; }
+
+template <typename ET, int NE>
+using StageRegs = typename V16<ET>::type[stage_per<ET, NE>()];
+
+// copy NE elements [src1, src1 + n1) ++ [src2, ...) (n1 and both sources 16-byte aligned) into registers
+template <typename ET, int NE>
+__device__ __forceinline__ void stage_load(StageRegs<ET, NE> &r, const ET *src1, int n1, const ET *src2) {
+    constexpr int EPV = 16 / (int)sizeof(ET), NV = NE / EPV;
 #pragma unroll
-    for (int k = 0; k < stage_per<NV2>(); ++k) {
+    for (int k = 0; k < stage_per<ET, NE>(); ++k) {
         const int i = (int)threadIdx.x + 256 * k;
-        const int d = 2 * min(i, NV2 - 1);
-        const double *p = d < n1 ? src1 + d : src2 + (d - n1);
-        r[k] = *reinterpret_cast<const d2 *>(p);
+        const int d = EPV * min(i, NV - 1);
+        const ET *p = d < n1 ? src1 + d : src2 + (d - n1);
+        r[k] = *reinterpret_cast<const typename V16<ET>::type *>(p);
     }
 }
 
-template <int NV2>
-__device__ __forceinline__ void stage_store(const d2 (&r)[stage_per<NV2>()], double *dst) {
+template <typename ET, int NE>
+__device__ __forceinline__ void stage_store(const StageRegs<ET, NE> &r, ET *dst) {
+    constexpr int EPV = 16 / (int)sizeof(ET), NV = NE / EPV;
 #pragma unroll
-    for (int k = 0; k < stage_per<NV2>(); ++k) {
+    for (int k = 0; k < stage_per<ET, NE>(); ++k) {
         const int i = (int)threadIdx.x + 256 * k;
-        if (i < NV2) reinterpret_cast<d2 *>(dst)[i] = r[k];
+        if (i < NV) reinterpret_cast<typename V16<ET>::type *>(dst)[i] = r[k];
     }
 }
 
@@ -387,15 +407,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     // position read at step p, and where its output goes (backward: T^{-1}'s upper part lands one before)
     auto inpos = [&](int p) -> int64_t { return FWD ? (int64_t)p : (int64_t)(m - 1 - p); };
     auto outpos = [&](int p) -> int { return FWD ? p : m - 2 - p; };
-    d2 stg[stage_per<TS / 2>()];
-    stage_load<TS / 2>(stg, src1(0), N1, src2(0));
+    StageRegs<double, TS> stg;
+    stage_load<double, TS>(stg, src1(0), N1, src2(0));
     double R[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int p = 4 * c + kq;
         R[c] = (p < m) ? xb[inpos(p) * 64] : 0.0;
     }
-    stage_store<TS / 2>(stg, sbuf);
+    stage_store<double, TS>(stg, sbuf);
     __syncthreads();
     d4 Y[NT];
 #pragma unroll
@@ -407,7 +427,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         const bool more = beta + 1 < nblk;
         double Rn[4] = {0.0, 0.0, 0.0, 0.0};
         if (more) {
-            stage_load<TS / 2>(stg, src1(beta + 1), N1, src2(beta + 1));
+            stage_load<double, TS>(stg, src1(beta + 1), N1, src2(beta + 1));
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 16 * (beta + 1) + 4 * c + kq;
@@ -453,7 +473,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             const double f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
             if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + f;
         }
-        if (more) stage_store<TS / 2>(stg, sbuf + ((beta + 1) & 1) * TS);
+        if (more) stage_store<double, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) R[c] = Rn[c];
@@ -498,8 +518,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     const int vt = eu_[e], vh = ev_[e];
     const double *z0 = ztab + (int64_t)boff[e] * TS;
-    d2 stg[stage_per<TS / 2>()];
-    stage_load<TS / 2>(stg, z0, TS, z0);
+    StageRegs<double, TS> stg;
+    stage_load<double, TS>(stg, z0, TS, z0);
     double ct[NT][4], ch[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -511,14 +531,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             ct[t][r] = bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n];
             ch[t][r] = bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n];
         }
-    stage_store<TS / 2>(stg, sbuf);
+    stage_store<double, TS>(stg, sbuf);
     __syncthreads();
     const int nblk = (m + 15) >> 4;
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
         const double *Z = sbuf + (beta & 1) * TS;
         const bool more = beta + 1 < nblk;
-        if (more) stage_load<TS / 2>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        if (more) stage_load<double, TS>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
         double uo[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -540,7 +560,200 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             const int pp = 16 * beta + 4 * r + kq;
             if (pp < m) ub[(int64_t)pp * 64] = uo[r] + ((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
         }
-        if (more) stage_store<TS / 2>(stg, sbuf + ((beta + 1) & 1) * TS);
+        if (more) stage_store<double, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
+        __syncthreads();
+    }
+}
+
+// Mixed precision (FP32 operand tables and matrix-core products, FP64 noise,
+// accumulator and end values).  Same structure as the FP64 kernels; the
+// carried state Y[t] item r of lane L is shift 16t + 4 (L/16) + r and the
+// block output item r of lane L is position 4 (L/16) + r.
+template <int NT, bool FWD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
+k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
+                  int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
+                  const float *__restrict__ tab, const double *__restrict__ X, double *__restrict__ U,
+                  const double *__restrict__ rhom, double *__restrict__ ends, int32_t first) {
+    constexpr int TS = 528 * NT + 256;  // floats per buffer
+    constexpr int N1 = 512 * NT;
+    __shared__ float sbuf[2 * TS];
+    const int L = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int64_t wg = xcd_logical_block();
+    const int e = (int)(wg / nb);
+    const int b = (int)(wg - (int64_t)e * nb);
+    const int g = 4 * b + wv;
+    const int s0 = 16 * g;
+    const int n = L & 15, kq = L >> 4;
+    const int m = m_[e];
+    const int side = FWD ? 1 : 0;
+    double *endp = ends + ((int64_t)e * 2 + side) * Sp + s0 + n;
+    const int64_t endstride = (int64_t)E * 2 * Sp;
+    const TabLayout TL{NT};
+    if (m == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int sh = 16 * t + 4 * kq + r;
+                if (sh < LB) endp[sh * endstride] = 0.0;
+            }
+        return;
+    }
+    const int64_t off = off_[e];
+    const double *xb = X + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
+    double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
+    const int nblk = (m + 15) >> 4;
+    const float *tab0 = tab + (int64_t)boff[e] * TL.size();
+    auto src1 = [&](int beta) { return tab0 + beta * TL.size() + (FWD ? TL.HF() : TL.CT()); };
+    auto src2 = [&](int beta) { return tab0 + beta * TL.size() + (FWD ? TL.GF() : TL.DT()); };
+    auto inpos = [&](int p) -> int64_t { return FWD ? (int64_t)p : (int64_t)(m - 1 - p); };
+    auto outpos = [&](int p) -> int { return FWD ? p : m - 2 - p; };
+    StageRegs<float, TS> stg;
+    stage_load<float, TS>(stg, src1(0), N1, src2(0));
+    float R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int p = 4 * c + kq;
+        R[c] = (p < m) ? (float)xb[inpos(p) * 64] : 0.0f;
+    }
+    stage_store<float, TS>(stg, sbuf);
+    __syncthreads();
+    f4 Y[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Y[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bool store_only = FWD && first;
+#pragma unroll 1
+    for (int beta = 0; beta < nblk; ++beta) {
+        const float *sb = sbuf + (beta & 1) * TS;
+        const bool more = beta + 1 < nblk;
+        float Rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (more) {
+            stage_load<float, TS>(stg, src1(beta + 1), N1, src2(beta + 1));
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int p = 16 * (beta + 1) + 4 * c + kq;
+                if (p < m) Rn[c] = (float)xb[inpos(p) * 64];
+            }
+        }
+        double uo[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!store_only) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = 16 * beta + 4 * kq + r;
+                const int op = outpos(p);
+                if (p < m && op >= 0) uo[r] = ub[(int64_t)op * 64];
+            }
+        }
+        const float *G = sb + (FWD ? 512 * NT : 528 * NT);
+        const float *H = sb + (FWD ? 0 : 256 * NT);
+        const float *C = sb + (FWD ? 256 * NT : 0);
+        const float *D = sb + (FWD ? 512 * NT + 256 : 512 * NT);
+        f4 F[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F[c] = mfma32(G[c * 64 + L], R[c], f4{0.0f, 0.0f, 0.0f, 0.0f});
+        if (beta > 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) F[r] = mfma32(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Y[t][r] *= D[16 * t + 4 * kq + r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) Y[t] = mfma32(C[(t * 4 + c) * 64 + L], R[c], Y[t]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * beta + 4 * kq + r;
+            const int op = outpos(p);
+            const float f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
+            if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + (double)f;
+        }
+        if (more) stage_store<float, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) R[c] = Rn[c];
+    }
+    const double *rm = rhom + (int64_t)e * LBp;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int sh = 16 * t + 4 * kq + r;
+            if (sh < LB) endp[sh * endstride] = rm[sh] * (double)Y[t][r];
+        }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
+k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ eu_,
+                 const int32_t *__restrict__ ev_, const int32_t *__restrict__ boff, int32_t E, int32_t V, int64_t N,
+                 int32_t nb, int32_t Sp, int32_t LB, int32_t LBp, const float *__restrict__ ztab,
+                 const double *__restrict__ babs, const double *__restrict__ ug, double *__restrict__ U) {
+    constexpr int TS = 512 * NT;
+    __shared__ float sbuf[2 * TS];
+    const int L = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int64_t wg = xcd_logical_block();
+    const int e = (int)(wg / nb);
+    const int b = (int)(wg - (int64_t)e * nb);
+    const int g = 4 * b + wv;
+    const int s0 = 16 * g;
+    const int n = L & 15, kq = L >> 4;
+    const int m = m_[e];
+    if (m == 0) return;
+    const int64_t off = off_[e];
+    double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
+    const int vt = eu_[e], vh = ev_[e];
+    const float *z0 = ztab + (int64_t)boff[e] * TS;
+    StageRegs<float, TS> stg;
+    stage_load<float, TS>(stg, z0, TS, z0);
+    float ct[NT][4], ch[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int sh = 16 * t + 4 * kq + r;
+            const int shc = min(sh, LB - 1);
+            const double bb = (sh < LB) ? babs[(int64_t)e * LBp + sh] : 0.0;
+            ct[t][r] = (float)(bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n]);
+            ch[t][r] = (float)(bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n]);
+        }
+    stage_store<float, TS>(stg, sbuf);
+    __syncthreads();
+    const int nblk = (m + 15) >> 4;
+#pragma unroll 1
+    for (int beta = 0; beta < nblk; ++beta) {
+        const float *Z = sbuf + (beta & 1) * TS;
+        const bool more = beta + 1 < nblk;
+        if (more) stage_load<float, TS>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        double uo[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = 16 * beta + 4 * kq + r;
+            uo[r] = (pp < m) ? ub[(int64_t)pp * 64] : 0.0;
+        }
+        f4 F[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) F[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F[r & 1] = mfma32(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
+                F[2 + (r & 1)] = mfma32(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = 16 * beta + 4 * kq + r;
+            if (pp < m) ub[(int64_t)pp * 64] = uo[r] + (double)((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
+        }
+        if (more) stage_store<float, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
         __syncthreads();
     }
 }
@@ -548,6 +761,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 template <int NT>
 void sweep_nt(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
     dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
+    if (a.mixed) {
+        if (fwd)
+            hipLaunchKernelGGL((k_sweep_blocked32<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
+                               a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first);
+        else
+            hipLaunchKernelGGL((k_sweep_blocked32<NT, false>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E,
+                               mv.N, a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, 0);
+        GRF_LAUNCH_CHECK();
+        return;
+    }
     if (fwd)
         hipLaunchKernelGGL((k_sweep_blocked<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
                            a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first);
@@ -560,6 +783,12 @@ void sweep_nt(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) 
 template <int NT>
 void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
+    if (a.mixed) {
+        hipLaunchKernelGGL((k_corr_blocked32<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E,
+                           mv.V, mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug, a.U);
+        GRF_LAUNCH_CHECK();
+        return;
+    }
     hipLaunchKernelGGL((k_corr_blocked<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E, mv.V,
                        mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U);
     GRF_LAUNCH_CHECK();
@@ -583,8 +812,12 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return;
     GRF_REQUIRE(a.LBp == 16 * a.NT && a.NT >= 1 && a.NT <= 8, "internal: blocked sweeps need 16..128 padded shifts");
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
-    hipLaunchKernelGGL(k_blocktab, dim3((unsigned)a.nblocks), dim3(kTabThreads), 0, st, mv, a.boff, a.shift, a.LB,
-                       a.LBp, a.NT, a.tab, a.ztab);
+    if (a.mixed)
+        hipLaunchKernelGGL(k_blocktab<float>, dim3((unsigned)a.nblocks), dim3(kTabThreads), 0, st, mv, a.boff, a.shift,
+                           a.LB, a.LBp, a.NT, a.tab32, a.ztab32);
+    else
+        hipLaunchKernelGGL(k_blocktab<double>, dim3((unsigned)a.nblocks), dim3(kTabThreads), 0, st, mv, a.boff,
+                           a.shift, a.LB, a.LBp, a.NT, a.tab, a.ztab);
     GRF_LAUNCH_CHECK();
 }
 

@@ -185,6 +185,9 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
             ba.nb = nb;
             ba.Sp = Sp;
             ba.first = (l0 == 0) ? 1 : 0;
+            ba.mixed = (o.precision == GRF_PREC_MIXED) ? 1 : 0;
+            ba.tab32 = w.btab.as<float>();
+            ba.ztab32 = w.ztab.as<float>();
             T.begin(GRF_K_COEFF);
             launch_blocktab(mv, ba, st);
             T.end();
@@ -324,7 +327,8 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
     Shifts sh = make_shifts(beta, quad_step, g->h, o);
     if (n_samples == 0) return GRF_OK;
     GRF_REQUIRE(out, "out is NULL");
-    GRF_REQUIRE(o.precision == GRF_PREC_FP64, "mixed precision is not available in this build");
+    GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
+                "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
     GRF_REQUIRE(o.precond == GRF_PRECOND_JACOBI, "learned preconditioner is not available in this build");
     hipStream_t st = (hipStream_t)o.stream;
     set_kappa2(*g, kappa, st);
@@ -365,29 +369,88 @@ int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_
     if (n_rhs == 0) return GRF_OK;
     GRF_REQUIRE(rhs && out, "rhs/out is NULL");
     GRF_REQUIRE(rhs != out, "rhs and out may not alias");
-    GRF_REQUIRE(o.precision == GRF_PREC_FP64, "mixed precision is not available in this build");
+    GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
+                "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
     GRF_REQUIRE(o.precond == GRF_PRECOND_JACOBI, "learned preconditioner is not available in this build");
     hipStream_t st = (hipStream_t)o.stream;
     set_kappa2(*g, kappa, st);
     grf_graph::Work &w = work(*g);
     const int64_t nb = (n_rhs + 63) / 64;
-    w.X.reserve(8 * (size_t)nb * g->N * 64);
-    w.U.reserve(8 * (size_t)nb * g->N * 64);
+    const size_t nel = (size_t)nb * g->N * 64;
+    w.X.reserve(8 * nel);
+    w.U.reserve(8 * nel);
+    const bool mixed = o.precision == GRF_PREC_MIXED;
+    const int32_t nref = mixed ? (o.refine < 0 ? 2 : o.refine) : 0;
     if (o.stats) *o.stats = grf_stats{};
     KTimer T(o.timing != 0, st);
     T.begin(GRF_K_LAYOUT);
     launch_to_interleaved(rhs, n_rhs, g->N, w.X.as<double>(), st);
     T.end();
     std::vector<double> cI(1, c_I), cL(1, c_L);
+    const MeshView mv = g->view();
     int code = GRF_OK;
-    try {
-        run_shifts(*g, cI, cL, n_rhs, o, st, o.stats, T);
-    } catch (const Error &err) {
-        if (err.code != GRF_ENOCONV) throw;
-        code = GRF_ENOCONV;
+    auto solve = [&]() {
+        try {
+            run_shifts(*g, cI, cL, n_rhs, o, st, o.stats, T);
+        } catch (const Error &err) {
+            if (err.code != GRF_ENOCONV) throw;
+            code = GRF_ENOCONV;
+        }
+    };
+    double *result = w.U.as<double>();
+    if (nref > 0) {
+        // x_0 = A^{-1} b with FP32 sweeps; then x <- x + A^{-1} (b - A x), residual in FP64
+        w.Bm.reserve(8 * nel);
+        w.Xacc.reserve(8 * nel);
+        const int64_t chunks = colnorm_chunks(g->N);
+        w.nrm.reserve(8 * (size_t)nb * chunks * 64);
+        GRF_HIP(hipMemcpyAsync(w.Bm.ptr, w.X.ptr, 8 * nel, hipMemcpyDeviceToDevice, st));
+        solve();
+        GRF_HIP(hipMemcpyAsync(w.Xacc.ptr, w.U.ptr, 8 * nel, hipMemcpyDeviceToDevice, st));
+        auto rel_residual = [&]() -> double {  // max over rhs of ||b - A x|| / ||b||
+            std::vector<double> pr((size_t)nb * chunks * 64), pb((size_t)nb * chunks * 64);
+            launch_colnorm2(w.X.as<double>(), g->N, (int32_t)nb, w.nrm.as<double>(), st);
+            GRF_HIP(hipMemcpyAsync(pr.data(), w.nrm.ptr, 8 * pr.size(), hipMemcpyDeviceToHost, st));
+            GRF_HIP(hipStreamSynchronize(st));
+            launch_colnorm2(w.Bm.as<double>(), g->N, (int32_t)nb, w.nrm.as<double>(), st);
+            GRF_HIP(hipMemcpyAsync(pb.data(), w.nrm.ptr, 8 * pb.size(), hipMemcpyDeviceToHost, st));
+            GRF_HIP(hipStreamSynchronize(st));
+            double worst = 0.0;
+            for (int64_t s = 0; s < n_rhs; ++s) {
+                const int64_t b = s / 64, lane = s % 64;
+                double rr = 0.0, bb = 0.0;
+                for (int64_t c = 0; c < chunks; ++c) {
+                    rr += pr[(b * chunks + c) * 64 + lane];
+                    bb += pb[(b * chunks + c) * 64 + lane];
+                }
+                if (bb > 0.0) worst = std::max(worst, std::sqrt(rr / bb));
+            }
+            return worst;
+        };
+        double rel = 0.0;
+        int32_t done = 0;
+        for (int32_t it = 0; it < nref; ++it) {
+            T.begin(GRF_K_MIXED);
+            launch_residual(mv, c_I, c_L, w.Bm.as<double>(), w.Xacc.as<double>(), w.X.as<double>(), (int32_t)nb, st);
+            T.end();
+            solve();
+            T.begin(GRF_K_MIXED);
+            launch_axpy1(w.U.as<double>(), w.Xacc.as<double>(), (int64_t)nel, st);
+            T.end();
+            done++;
+        }
+        launch_residual(mv, c_I, c_L, w.Bm.as<double>(), w.Xacc.as<double>(), w.X.as<double>(), (int32_t)nb, st);
+        rel = rel_residual();
+        if (o.stats) {
+            o.stats->refine_steps = done;
+            o.stats->max_rel_residual = rel;  // of the refined solution in the full system
+        }
+        result = w.Xacc.as<double>();
+    } else {
+        solve();
     }
     T.begin(GRF_K_LAYOUT);
-    launch_from_interleaved(w.U.as<double>(), n_rhs, g->N, out, st);
+    launch_from_interleaved(result, n_rhs, g->N, out, st);
     T.end();
     GRF_HIP(hipStreamSynchronize(st));
     T.collect(o.stats);

@@ -18,7 +18,7 @@ struct grf_graph::Work {
     grf::DevBuf ug;               // [LB][V][Sp]: vertex solutions, sample-interleaved
     grf::DevBuf pcg_scr;          // PCG vectors in global memory (large graphs)
     grf::DevBuf its, res;         // [LB][S] int32 iterations, double relative residual
-    grf::DevBuf flt;              // mixed precision: FP32 tables and vectors
+    grf::DevBuf Bm, Xacc, nrm;    // mixed-precision refinement: right-hand sides, iterate, norm partials
     std::vector<int32_t> h_its;
     std::vector<double> h_res;
 };
@@ -85,11 +85,21 @@ struct BlockArgs {
     const double *ug;       // [LB][V][Sp]
     int32_t nb, Sp;
     int32_t first;          // first shift block: the forward pass writes (not updates) the interior accumulator
+    int32_t mixed;          // FP32 operand tables and matrix-core products (mixed precision)
+    float *tab32, *ztab32;  // the FP32 tables (same layout sizes as tab / ztab)
 };
 int64_t block_tab_doubles(int32_t NT);
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st);
 void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st);
 void launch_corr_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st);
+
+// mixed-precision refinement (mixed.hip): R = B - A X on the interleaved layout (A of one shift),
+// Y += X, and per-column partial sums of squares P[nb][colnorm_chunks(N)][64]
+void launch_residual(const MeshView &mv, double cI, double cL, const double *B, const double *X, double *R, int32_t nb,
+                     hipStream_t st);
+void launch_axpy1(const double *X, double *Y, int64_t n, hipStream_t st);
+int64_t colnorm_chunks(int64_t N);
+void launch_colnorm2(const double *X, int64_t N, int32_t nb, double *P, hipStream_t st);
 
 // vertex Schur complement: condensed rhs, PCG, layout changes, accumulation
 struct SchurArgs {
