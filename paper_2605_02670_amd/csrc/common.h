@@ -77,7 +77,14 @@ struct MeshView {
     const int32_t *adj_o; // [2E] vertex at the other end
     const int8_t *adj_s;  // [2E] 0 = tail end (u_e), 1 = head end (v_e)
     const double *msqrt;  // [N] sqrt of the lumped mass diagonal
-    const int32_t *vgraph;  // [V] component (sub-graph) id of each vertex, batched runs
+    // graphs of a batch (one graph: ng = 1): vertices gv0[g] .. gv0[g+1]-1 and edges
+    // ge0[g] .. ge0[g+1]-1; segs[4g..4g+3] = (local DOFs, local interior DOFs, first
+    // interior row, first vertex row) of graph g in this mesh's DOF order
+    int32_t ng;
+    const int32_t *gv0, *ge0;
+    const int64_t *segs;
+    int32_t maxVg, maxEg;  // largest graph of the batch (host-side dispatch)
+    int64_t maxNg;
 };
 
 }  // namespace grf
@@ -85,6 +92,7 @@ struct MeshView {
 // ---- the opaque handle ---------------------------------------------------------
 struct grf_graph {
     int device = 0;
+    uint64_t serial = 0;  // unique per created handle (batch cache key)
     int64_t V = 0, E = 0, NI = 0, N = 0;
     double h = 0;
     uint32_t flags = 0;
@@ -95,7 +103,13 @@ struct grf_graph {
     std::vector<int32_t> adj_e, adj_o;
     std::vector<int8_t> adj_s;
     // device copies
-    grf::DevBuf d_off, d_m, d_eu, d_ev, d_he, d_kap2, d_vptr, d_adj_e, d_adj_o, d_adj_s, d_msqrt, d_vgraph;
+    grf::DevBuf d_off, d_m, d_eu, d_ev, d_he, d_kap2, d_vptr, d_adj_e, d_adj_o, d_adj_s, d_msqrt;
+    // graphs of a batch (a single graph is a batch of one)
+    std::vector<int32_t> gv0, ge0;
+    std::vector<int64_t> segs;
+    int32_t max_deg = 0, maxVg = 0, maxEg = 0;
+    int64_t maxNg = 0;
+    grf::DevBuf d_gv0, d_ge0, d_segs;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;
@@ -119,6 +133,9 @@ struct Shifts {
 Shifts make_shifts(double beta, double step, double h, const grf_opts &o);
 
 grf_opts resolve_opts(const grf_opts *o);
+
+// drops cached batches that contain the graph with this serial (batch.hip)
+void batch_forget(uint64_t serial);
 
 // Optional per-kernel timing with HIP events on the launch stream.
 struct KTimer {

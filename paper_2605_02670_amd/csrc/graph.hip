@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include <algorithm>
+#include <atomic>
 
 #include "work.h"
 
@@ -160,7 +161,6 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     std::vector<double> msq(g.N);
     for (int64_t j = 0; j < g.N; ++j) msq[j] = std::sqrt(g.ml[j]);
-    std::vector<int32_t> vg(g.V, 0);
     upload(g.d_off, g.off, s);
     upload(g.d_m, g.m, s);
     upload(g.d_eu, eu, s);
@@ -171,7 +171,30 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     upload(g.d_adj_o, g.adj_o, s);
     upload(g.d_adj_s, g.adj_s, s);
     upload(g.d_msqrt, msq, s);
-    upload(g.d_vgraph, vg, s);
+    if (g.gv0.empty()) {
+        g.gv0 = {0, (int32_t)g.V};
+        g.ge0 = {0, (int32_t)g.E};
+    }
+    const int64_t ng = (int64_t)g.gv0.size() - 1;
+    g.segs.assign(4 * ng, 0);
+    g.maxVg = g.maxEg = 0;
+    g.maxNg = 0;
+    for (int64_t k = 0; k < ng; ++k) {
+        const int64_t i0 = g.off[g.ge0[k]], i1 = g.off[g.ge0[k + 1]];
+        const int64_t vk = g.gv0[k + 1] - g.gv0[k];
+        g.segs[4 * k + 0] = (i1 - i0) + vk;
+        g.segs[4 * k + 1] = i1 - i0;
+        g.segs[4 * k + 2] = i0;
+        g.segs[4 * k + 3] = g.NI + g.gv0[k];
+        g.maxVg = std::max<int32_t>(g.maxVg, (int32_t)vk);
+        g.maxEg = std::max<int32_t>(g.maxEg, g.ge0[k + 1] - g.ge0[k]);
+        g.maxNg = std::max<int64_t>(g.maxNg, g.segs[4 * k]);
+    }
+    g.max_deg = 0;
+    for (int64_t u = 0; u < g.V; ++u) g.max_deg = std::max<int32_t>(g.max_deg, (int32_t)(g.vptr[u + 1] - g.vptr[u]));
+    upload(g.d_gv0, g.gv0, s);
+    upload(g.d_ge0, g.ge0, s);
+    upload(g.d_segs, g.segs, s);
     g.d_kap2.reserve(sizeof(double) * (g.E + 1));
     g.kap2_loaded = -1.0;
     GRF_HIP(hipStreamSynchronize(s));
@@ -222,8 +245,7 @@ grf::MeshView grf_graph::view() const {
     grf::MeshView v;
     v.V = (int32_t)V;
     v.E = (int32_t)E;
-    v.max_deg = 0;
-    for (int64_t u = 0; u < V; ++u) v.max_deg = std::max<int32_t>(v.max_deg, (int32_t)(vptr[u + 1] - vptr[u]));
+    v.max_deg = max_deg;
     v.NI = NI;
     v.N = N;
     v.off = d_off.as<int64_t>();
@@ -237,7 +259,13 @@ grf::MeshView grf_graph::view() const {
     v.adj_o = d_adj_o.as<int32_t>();
     v.adj_s = d_adj_s.as<int8_t>();
     v.msqrt = d_msqrt.as<double>();
-    v.vgraph = d_vgraph.as<int32_t>();
+    v.ng = (int32_t)gv0.size() - 1;
+    v.gv0 = d_gv0.as<int32_t>();
+    v.ge0 = d_ge0.as<int32_t>();
+    v.segs = d_segs.as<int64_t>();
+    v.maxVg = maxVg;
+    v.maxEg = maxEg;
+    v.maxNg = maxNg;
     return v;
 }
 
@@ -278,7 +306,9 @@ int grf_graph_create(int64_t n_vertices, int64_t n_edges, const int64_t *edges, 
     GRF_API_BEGIN
     GRF_REQUIRE(out, "out must be non-NULL");
     *out = nullptr;
+    static std::atomic<uint64_t> next_serial{1};
     grf_graph *g = new grf_graph();
+    g->serial = next_serial++;
     try {
         build_mesh(*g, n_vertices, n_edges, edges, lengths, h, flags);
         GRF_HIP(hipGetDevice(&g->device));
@@ -304,6 +334,7 @@ int grf_graph_info(const grf_graph *g, int64_t *n_dof, int64_t *n_interior, int6
 int grf_graph_destroy(grf_graph *g) {
     GRF_API_BEGIN
     if (g) {
+        batch_forget(g->serial);
         free_work(*g);
         delete g;
     }

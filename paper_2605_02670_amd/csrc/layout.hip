@@ -51,6 +51,31 @@ __global__ void k_fill(double *__restrict__ p, size_t n, double v) {
         p[i] = v;
 }
 
+// Graph z of a batch (blockIdx.z): X[b][row(j)][lane] -> outs[z][s][j], local DOF j
+// of the graph at row ri + j (interior) or rv + j - ni (vertices)
+__global__ void __launch_bounds__(256) k_from_interleaved_seg(const double *__restrict__ X, int64_t S, int64_t N,
+                                                              const int64_t *__restrict__ segs,
+                                                              double *const *__restrict__ outs) {
+    __shared__ double tile[kT][kT + 1];
+    const int64_t z = blockIdx.z;
+    const int64_t n = segs[4 * z], ni = segs[4 * z + 1], ri = segs[4 * z + 2], rv = segs[4 * z + 3];
+    const int64_t j0 = (int64_t)blockIdx.x * kT;
+    if (j0 >= n) return;  // uniform over the workgroup
+    double *out = outs[z];
+    const int64_t b = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int ji = ty; ji < kT; ji += 4) {
+        const int64_t j = j0 + ji;
+        const int64_t row = j < ni ? ri + j : rv + (j - ni);
+        tile[ji][tx] = (j < n) ? X[(b * N + row) * 64 + tx] : 0.0;
+    }
+    __syncthreads();
+    for (int si = ty; si < kT; si += 4) {
+        const int64_t s = b * kT + si, j = j0 + tx;
+        if (s < S && j < n) out[s * n + j] = tile[tx][si];
+    }
+}
+
 // rows [r0, r0 + nrows) of every 64-sample block of a [nb][N][64] array
 __global__ void k_fill_rows(double *__restrict__ p, int64_t nb, int64_t N, int64_t r0, int64_t nrows) {
     const int64_t per = nrows * 64, n = nb * per;
@@ -68,6 +93,17 @@ void launch_fill_rows(double *p, int64_t nb, int64_t N, int64_t r0, int64_t nrow
     GRF_REQUIRE(r0 >= 0 && r0 + nrows <= N, "internal: row range outside the array");
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
     hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)blocks), dim3(256), 0, st, p, nb, N, r0, nrows);
+    GRF_LAUNCH_CHECK();
+}
+
+void launch_from_interleaved_seg(const MeshView &mv, const double *X, int64_t S, double *const *outs,
+                                 hipStream_t st) {
+    const int64_t nb = (S + 63) / 64;
+    if (nb == 0 || mv.maxNg == 0) return;
+    GRF_REQUIRE((mv.maxNg + kT - 1) / kT < (int64_t(1) << 31) && nb < 65536 && mv.ng < 65536, "batch too large");
+    hipLaunchKernelGGL(k_from_interleaved_seg, dim3((unsigned)((mv.maxNg + kT - 1) / kT), (unsigned)nb,
+                                                    (unsigned)mv.ng),
+                       dim3(256), 0, st, X, S, mv.N, mv.segs, outs);
     GRF_LAUNCH_CHECK();
 }
 

@@ -140,25 +140,34 @@ __device__ __forceinline__ void box_muller(uint64_t xa, uint64_t xb, double &z_c
 
 // One wavefront = 64 samples of one block of 4 DOFs; lanes are samples, so
 // the four stores of a wavefront are each one contiguous 512-byte row.
-__global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt, int64_t N, int64_t S, int64_t soff,
-                                               uint64_t seed, double *__restrict__ X) {
+// Graph z of the batch (blockIdx.z): local DOF j (the counter index of the
+// noise definition) lives at row j of its interior range or, for j >= NI_z, at
+// row (j - NI_z) of its vertex range.
+__global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt, const int64_t *__restrict__ segs,
+                                               int64_t N, int64_t S, int64_t soff, uint64_t seed,
+                                               double *__restrict__ X) {
     const int lane = threadIdx.x & 63;
-    const int64_t ngrp = (N + 3) / 4;
+    const int64_t z = blockIdx.z;
+    const int64_t n = segs[4 * z], ni = segs[4 * z + 1], ri = segs[4 * z + 2], rv = segs[4 * z + 3];
+    const int64_t ngrp = (n + 3) / 4;
     const int64_t b = blockIdx.y;
     const int64_t s = b * 64 + lane;
     const bool live = s < S;
     double *Xb = X + b * N * 64 + lane;
     for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < ngrp; g += (int64_t)gridDim.x * 4) {
-        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        double zz[4] = {0.0, 0.0, 0.0, 0.0};
         if (live) {
             Words w = philox4x64_10((uint64_t)g, seed, (uint64_t)(soff + s));
-            box_muller(w.x[0], w.x[1], z[0], z[1]);
-            box_muller(w.x[2], w.x[3], z[2], z[3]);
+            box_muller(w.x[0], w.x[1], zz[0], zz[1]);
+            box_muller(w.x[2], w.x[3], zz[2], zz[3]);
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            int64_t j = 4 * g + c;
-            if (j < N) Xb[j * 64] = msqrt[j] * z[c];
+            const int64_t j = 4 * g + c;
+            if (j < n) {
+                const int64_t row = j < ni ? ri + j : rv + (j - ni);
+                Xb[row * 64] = msqrt[row] * zz[c];
+            }
         }
     }
 }
@@ -167,12 +176,13 @@ __global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt,
 
 void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, double *X, hipStream_t st) {
     int64_t nb = (S + 63) / 64;
-    int64_t ngrp = (mv.N + 3) / 4;
+    int64_t ngrp = (mv.maxNg + 3) / 4;
     int64_t gx = (ngrp + 3) / 4;
     if (gx > 8192) gx = 8192;
     if (gx < 1) gx = 1;
-    GRF_REQUIRE(nb < 65536, "too many samples in one call");
-    hipLaunchKernelGGL(k_noise, dim3((unsigned)gx, (unsigned)nb), dim3(256), 0, st, mv.msqrt, mv.N, S, soff, seed, X);
+    GRF_REQUIRE(nb < 65536 && mv.ng < 65536, "too many samples or graphs in one call");
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)gx, (unsigned)nb, (unsigned)mv.ng), dim3(256), 0, st, mv.msqrt,
+                       mv.segs, mv.N, S, soff, seed, X);
     GRF_LAUNCH_CHECK();
 }
 

@@ -73,43 +73,49 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     }
 }
 
-// (S p)_v over the edge ends at v
+// (S p)_u over the edge ends at vertex u; p holds the graph's vertices from u0
 __device__ __forceinline__ double schur_apply(const MeshView &mv, const double *__restrict__ sdl,
-                                              const double *__restrict__ sol, const double *p, int v) {
-    const double pv = p[v];
+                                              const double *__restrict__ sol, const double *p, int u, int u0) {
+    const double pv = p[u - u0];
     double acc = 0.0;
-    for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+    for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
         const int e = mv.adj_e[k];
-        acc += sdl[e] * pv + sol[e] * p[mv.adj_o[k]];
+        acc += sdl[e] * pv + sol[e] * p[mv.adj_o[k] - u0];
     }
     return acc;
 }
 
-// One workgroup per (shift, sample) system, vectors in global scratch
-// (x, r, p, q, jac: 5 V doubles per resident workgroup).
+// One workgroup per (graph, shift, sample) system, vectors in global scratch
+// (x, r, p, q, jac: 5 maxVg doubles per resident workgroup).  Systems are
+// numbered ((graph * LB) + shift) * S + sample; the vectors of system (g, l, s)
+// are the graph's vertex range of gT / xT[l][s].
 __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so,
                                              const double *__restrict__ gT, double *__restrict__ xT,
                                              double *__restrict__ scr, int32_t *__restrict__ its,
                                              double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                              int32_t maxit) {
     __shared__ double red[64];
-    const int V = mv.V;
     const int64_t E = mv.E;
     const int nw = blockDim.x >> 6;
-    double *x = scr + (int64_t)blockIdx.x * 5 * V;
-    double *r = x + V, *p = r + V, *q = p + V, *jac = q + V;
-    const int64_t nsys = (int64_t)LB * S;
+    double *x = scr + (int64_t)blockIdx.x * 5 * mv.maxVg;
+    double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg, *jac = q + mv.maxVg;
+    const int64_t nsys = (int64_t)mv.ng * LB * S;
     for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
-        const int l = (int)(sys / S);
-        const double *g = gT + sys * V;
+        const int64_t tl = sys / S;
+        const int64_t smp = sys - tl * S;
+        const int l = (int)(tl % LB);
+        const int gi = (int)(tl / LB);
+        const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
+        const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
         const double *sdl = sd + (int64_t)l * E;
         const double *sol = so + (int64_t)l * E;
         double t2[2] = {0.0, 0.0};  // r.z, g.g
         for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            const int u = u0 + v;
             double d = 0.0;
-            for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
                 const int e = mv.adj_e[k];
-                d += sdl[e] + (mv.adj_o[k] == v ? sol[e] : 0.0);
+                d += sdl[e] + (mv.adj_o[k] == u ? sol[e] : 0.0);
             }
             const double gv = g[v];
             jac[v] = d;
@@ -132,7 +138,7 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
                 __syncthreads();  // p complete
                 double t1[1] = {0.0};
                 for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                    const double qv = schur_apply(mv, sdl, sol, p, v);
+                    const double qv = schur_apply(mv, sdl, sol, p, u0 + v, u0);
                     q[v] = qv;
                     t1[0] += p[v] * qv;
                 }
@@ -153,7 +159,7 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
                     __syncthreads();  // x complete
                     double tt[2] = {0.0, 0.0};  // true r.r, r.z
                     for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                        const double rv = g[v] - schur_apply(mv, sdl, sol, x, v);
+                        const double rv = g[v] - schur_apply(mv, sdl, sol, x, u0 + v, u0);
                         r[v] = rv;
                         tt[0] += rv * rv;
                         tt[1] += rv * (rv / jac[v]);
@@ -174,7 +180,7 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
             if (it > maxit) it = maxit + 1;  // flags non-convergence
         }
         __syncthreads();
-        double *xo = xT + sys * V;
+        double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
         for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? x[v] : 0.0;
         if (threadIdx.x == 0) {
             its[sys] = it;
@@ -184,55 +190,67 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
     }
 }
 
-// Same algorithm with the vectors on chip, for V <= TPB K vertices of degree
-// <= D, V, E < 2^16 and (2V + E) doubles of LDS.  A workgroup takes a
-// contiguous range of systems (mostly of one shift).  LDS holds p, x and the
-// shift's edge coefficients s_o (reloaded only when the shift changes); each
-// thread keeps, for its K vertices, the (neighbour, edge) pairs in CSR order
-// packed in 16-bit halves (shift-independent), the Schur diagonal, the Jacobi
-// inverse, r and q = S p in registers.  Only g is read and x written in HBM.
+// Same algorithm with the vectors on chip, for graphs of at most TPB K
+// vertices of degree <= D, fewer than 2^16 vertices and edges, and (2 V + E)
+// doubles of LDS.  A workgroup takes a contiguous range of systems (mostly of
+// one graph and shift).  LDS holds p, x and the shift's edge coefficients s_o
+// of the graph (reloaded when the shift or the graph changes); each thread
+// keeps, for its K vertices, the graph-local (neighbour, edge) pairs in CSR
+// order packed in 16-bit halves, the Schur diagonal, the Jacobi inverse, r and
+// q = S p in registers.  Only g is read and x written in HBM.
 template <int K, int TPB, int D>
 __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__restrict__ sd,
                                                  const double *__restrict__ so, const double *__restrict__ gT,
                                                  double *__restrict__ xT, int32_t *__restrict__ its,
                                                  double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                                  int32_t maxit) {
-    extern __shared__ double sv[];  // p [V], x [V], s_o [E]
+    extern __shared__ double sv[];  // p [maxVg], x [maxVg], s_o [maxEg]
     __shared__ double red[64];
-    const int V = mv.V;
     const int E = mv.E;
-    double *ps = sv, *xs = sv + V, *sos = sv + 2 * V;
+    double *ps = sv, *xs = sv + mv.maxVg, *sos = sv + 2 * mv.maxVg;
     const int nw = blockDim.x >> 6;
-    const int64_t nsys = (int64_t)LB * S;
+    const int64_t nsys = (int64_t)mv.ng * LB * S;
     const int64_t per = (nsys + gridDim.x - 1) / gridDim.x;
     const int64_t sys0 = (int64_t)blockIdx.x * per;
     const int64_t sys1 = min(nsys, sys0 + per);
-    uint32_t nbr[K][D];  // other vertex | edge << 16; 0 with a zero coefficient slot for padding
+    uint32_t nbr[K][D];  // local other vertex | local edge << 16
     int nd[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int v = threadIdx.x + TPB * i;
-        nd[i] = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) nbr[i][d] = 0;
-        if (v < V) {
-            const int k0 = (int)mv.vptr[v], k1 = (int)mv.vptr[v + 1];
-            nd[i] = k1 - k0;
-#pragma unroll
-            for (int d = 0; d < D; ++d)
-                if (k0 + d < k1) nbr[i][d] = (uint32_t)mv.adj_o[k0 + d] | ((uint32_t)mv.adj_e[k0 + d] << 16);
-        }
-    }
     double ds[K], ji[K];
-    int lcur = -1;
+    int gcur = -1, lcur = -1, u0 = 0, V = 0, e0 = 0, Eg = 0;
     for (int64_t sys = sys0; sys < sys1; ++sys) {
-        const int l = (int)(sys / S);
+        const int64_t tl = sys / S;
+        const int64_t smp = sys - tl * S;
+        const int l = (int)(tl % LB);
+        const int gi = (int)(tl / LB);
+        if (gi != gcur) {  // uniform over the workgroup: the graph's adjacency, local ids
+            gcur = gi;
+            lcur = -1;
+            u0 = mv.gv0[gi];
+            V = mv.gv0[gi + 1] - u0;
+            e0 = mv.ge0[gi];
+            Eg = mv.ge0[gi + 1] - e0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int v = threadIdx.x + TPB * i;
+                nd[i] = 0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) nbr[i][d] = 0;
+                if (v < V) {
+                    const int k0 = (int)mv.vptr[u0 + v], k1 = (int)mv.vptr[u0 + v + 1];
+                    nd[i] = k1 - k0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        if (k0 + d < k1)
+                            nbr[i][d] = (uint32_t)(mv.adj_o[k0 + d] - u0) | ((uint32_t)(mv.adj_e[k0 + d] - e0) << 16);
+                }
+            }
+        }
         if (l != lcur) {  // uniform over the workgroup
             lcur = l;
             __syncthreads();  // previous coefficients no longer read
-            const double *sdl = sd + (int64_t)l * E;
-            const double *sol = so + (int64_t)l * E;
-            for (int e = threadIdx.x; e < E; e += TPB) sos[e] = sol[e];
+            const double *sdl = sd + (int64_t)l * E + e0;
+            const double *sol = so + (int64_t)l * E + e0;
+            for (int e = threadIdx.x; e < Eg; e += TPB) sos[e] = sol[e];
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const int v = threadIdx.x + TPB * i;
@@ -263,7 +281,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
             }
             return acc;
         };
-        const double *g = gT + sys * V;
+        const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
         double r[K], q[K];
         double t2[2] = {0.0, 0.0};
 #pragma unroll
@@ -323,7 +341,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
                     for (int i = 0; i < K; ++i) {
                         const int v = threadIdx.x + TPB * i;
                         if (v < V) {
-                            const double rv = g[v] - apply(V, i, v);
+                            const double rv = g[v] - apply(mv.maxVg, i, v);
                             r[i] = rv;
                             tt[0] += rv * rv;
                             tt[1] += rv * rv * ji[i];
@@ -349,7 +367,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__re
             if (it > maxit) it = maxit + 1;
         }
         __syncthreads();  // x complete
-        double *xo = xT + sys * V;
+        double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int v = threadIdx.x + TPB * i;
@@ -401,7 +419,9 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
 
 }  // namespace
 
-size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) { return (size_t)blocks * 5 * mv.V * sizeof(double); }
+size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
+    return (size_t)blocks * 5 * mv.maxVg * sizeof(double);
+}
 
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
@@ -413,58 +433,71 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
 
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
+// Dynamic LDS needed by the on-chip kernel for this mesh, 0 if it does not fit.
+size_t pcg_lds_bytes(const MeshView &mv) {
+    const size_t lds = sizeof(double) * (2 * (size_t)mv.maxVg + (size_t)mv.maxEg);
+    return lds > kMaxLds - 1024 ? 0 : lds;
+}
+
+// Grants the on-chip kernel variant its dynamic LDS (before any graph capture:
+// the attribute call is not a stream operation).  Returns false if refused.
 template <int K, int TPB, int D>
-static bool pcg_lds_d(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
-    const int64_t nsys = (int64_t)a.LB * a.S;
-    const size_t lds = sizeof(double) * (2 * (size_t)mv.V + (size_t)mv.E);
-    if (lds > kMaxLds - 1024) return false;
-    static size_t attr = 0;  // largest dynamic LDS size granted so far
-    if (lds > attr) {
-        if (hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        attr = lds;
+bool pcg_lds_attr(size_t lds) {
+    static size_t granted = 0;  // largest dynamic LDS size granted so far
+    if (lds <= granted) return true;
+    if (hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
     }
+    granted = lds;
+    return true;
+}
+
+template <int K, int TPB, int D>
+static bool pcg_lds_d(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
+    const size_t lds = pcg_lds_bytes(mv);
+    if (lds == 0 || !pcg_lds_attr<K, TPB, D>(lds)) return false;
+    if (!a) return true;  // preparation only
+    const int64_t nsys = (int64_t)mv.ng * a->LB * a->S;
     const int64_t blocks = std::min<int64_t>(nsys, 256 * (2048 / TPB));
-    hipLaunchKernelGGL((k_pcg_lds<K, TPB, D>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a.sd, a.so, a.gT,
-                       a.xT, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+    hipLaunchKernelGGL((k_pcg_lds<K, TPB, D>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a->sd, a->so, a->gT,
+                       a->xT, a->its, a->res, a->LB, a->S, a->tol, a->maxit);
     GRF_LAUNCH_CHECK();
     return true;
 }
 
 template <int K, int TPB>
-static bool pcg_lds(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+static bool pcg_lds(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
     if (mv.max_deg <= 4) return pcg_lds_d<K, TPB, 4>(mv, a, st);
     return pcg_lds_d<K, TPB, 8>(mv, a, st);
 }
 
+// the on-chip variant for this mesh (a = null: only grant its LDS); false if none applies
+static bool pcg_onchip(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
+    // every neighbour of a vertex in registers, 16-bit graph-local vertex and edge ids
+    if (!(mv.max_deg <= 8 && mv.maxVg < 65536 && mv.maxEg < 65536)) return false;
+    if (mv.maxVg <= 256) return pcg_lds<1, 256>(mv, a, st);
+    if (mv.maxVg <= 512) return pcg_lds<2, 256>(mv, a, st);
+    if (mv.maxVg <= 1024) return pcg_lds<2, 512>(mv, a, st);
+    if (mv.maxVg <= 2048) return pcg_lds<2, 1024>(mv, a, st);
+    if (mv.maxVg <= 4096) return pcg_lds<4, 1024>(mv, a, st);
+    return false;
+}
+
 static void pcg_global(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
-    const int64_t nsys = (int64_t)a.LB * a.S;
+    const int64_t nsys = (int64_t)mv.ng * a.LB * a.S;
     const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
     hipLaunchKernelGGL(k_pcg, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr, a.its,
                        a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
 }
 
+void prepare_pcg(const MeshView &mv) { (void)pcg_onchip(mv, nullptr, nullptr); }
+
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
-    bool done = false;
-    // on-chip variants: every neighbour of a vertex in registers, 16-bit vertex and edge ids
-    if (mv.max_deg <= 8 && mv.V < 65536 && mv.E < 65536) {
-        if (mv.V <= 256)
-            done = pcg_lds<1, 256>(mv, a, st);
-        else if (mv.V <= 512)
-            done = pcg_lds<2, 256>(mv, a, st);
-        else if (mv.V <= 1024)
-            done = pcg_lds<2, 512>(mv, a, st);
-        else if (mv.V <= 2048)
-            done = pcg_lds<2, 1024>(mv, a, st);
-        else if (mv.V <= 4096)
-            done = pcg_lds<4, 1024>(mv, a, st);
-    }
-    if (!done) pcg_global(mv, a, st);
+    if (!pcg_onchip(mv, &a, st)) pcg_global(mv, a, st);
 }
 
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st) {

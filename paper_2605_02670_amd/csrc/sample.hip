@@ -9,6 +9,8 @@
 // step runs for a whole block of shifts before the next step starts, so the
 // noise is read once per block instead of once per shift.
 #include <algorithm>
+#include <mutex>
+#include <memory>
 #include <cmath>
 
 #include "work.h"
@@ -58,7 +60,7 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     const double rows = p.blocked ? 0.0 : 5.0;
     const double btab = p.blocked ? (1296.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
     const double per_shift = 8.0 * (rows * g.NI + btab + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V +
-                                    (double)g.V * Sp) + 12.0 * S;
+                                    (double)g.V * Sp) + 12.0 * S * (double)(g.gv0.size() - 1);
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)64 << 30;
     double budget = 0.5 * (double)freeb;
@@ -68,7 +70,7 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     if (lb < L) lb = std::max<int64_t>(p.BL, (lb / p.BL) * p.BL);
     lb = std::max<int64_t>(1, std::min<int64_t>(lb, L));
     p.LB = (int32_t)lb;
-    const double vbytes = 40.0 * std::max<int64_t>(g.V, 1);
+    const double vbytes = 40.0 * std::max<int32_t>(g.maxVg, 1);
     int64_t blocks = (int64_t)std::min(2048.0, std::max(1.0, std::floor((2.0 * (1 << 30)) / vbytes)));
     p.pcg_blocks = (int32_t)blocks;
     return p;
@@ -81,55 +83,89 @@ static void ensure_block_offsets(grf_graph &g, grf_graph::Work &w, hipStream_t s
     upload(w.boff, bo, st);
 }
 
-// Runs shifts (cI[i], cL[i]) on the right-hand sides in w.X, accumulating into
-// w.U (zeroed here: the blocked forward pass of the first shift block writes
-// the interior rows, so only the vertex rows are cleared).
-static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::vector<double> &cL, int64_t S,
-                       const grf_opts &o, hipStream_t st, grf_stats *stats, KTimer &T) {
+// One run of the shift schedule over the right-hand sides in w.X, in three
+// phases: prepare (planning, buffers, every upload), enqueue (kernels only, no
+// host synchronisation: the part a caller may capture in a HIP graph) and
+// finish (iteration counts back to the host).
+struct Pass {
+    Plan p;
+    int32_t L = 0, nb = 0, Sp = 0, ng = 1;
+    int64_t S = 0, nblocks = 0;
+    int32_t LBmax = 0;  // padded shifts of the largest shift block
+    std::vector<int32_t> l0s, lbs, LBps;
+};
+
+static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std::vector<double> &cL, int64_t S,
+                         const grf_opts &o, hipStream_t st) {
     grf_graph::Work &w = work(g);
     const MeshView mv = g.view();
-    const int32_t L = (int32_t)cI.size();
-    const int32_t nb = (int32_t)((S + 63) / 64), Sp = 64 * nb;
-    const Plan p = plan_pass(g, L, S, o);
-    int64_t n_unconv = 0, tot_it = 0;
-    int32_t max_it = 0;
-    double max_res = 0.0;
+    Pass ps;
+    ps.L = (int32_t)cI.size();
+    ps.S = S;
+    ps.nb = (int32_t)((S + 63) / 64);
+    ps.Sp = 64 * ps.nb;
+    ps.ng = mv.ng;
+    ps.p = plan_pass(g, ps.L, S, o);
+    for (int32_t l0 = 0; l0 < ps.L; l0 += ps.p.LB) {
+        const int32_t lb = std::min(ps.p.LB, ps.L - l0);
+        ps.l0s.push_back(l0);
+        ps.lbs.push_back(lb);
+        ps.LBps.push_back(((lb + ps.p.BL - 1) / ps.p.BL) * ps.p.BL);  // blocked: multiple of 16
+        ps.LBmax = std::max(ps.LBmax, ps.LBps.back());
+    }
+    // all shift blocks' (c_I, c_L), block k at 2 LBmax k; padding c_L = 1 (never a divisor of 0)
+    std::vector<double> sh(2 * (size_t)ps.LBmax * ps.l0s.size(), 0.0);
+    for (size_t k = 0; k < ps.l0s.size(); ++k) {
+        double *d = sh.data() + 2 * (size_t)ps.LBmax * k;
+        for (int32_t i = 0; i < ps.LBps[k]; ++i) {
+            d[2 * i] = i < ps.lbs[k] ? cI[ps.l0s[k] + i] : 0.0;
+            d[2 * i + 1] = i < ps.lbs[k] ? cL[ps.l0s[k] + i] : 1.0;
+        }
+    }
+    upload(w.shift, sh, st);
+    const int32_t LBp = ps.LBmax, lb = ps.p.LB;
+    const size_t nir = (size_t)std::max<int64_t>(g.NI, 1) * LBp;
+    if (!ps.p.blocked) {
+        w.rho.reserve(8 * nir);
+        w.fwdt.reserve(16 * nir);
+        w.bwdt.reserve(16 * nir);
+    } else {
+        ensure_block_offsets(g, w, st, ps.nblocks);
+        w.btab.reserve(8 * (size_t)std::max<int64_t>(ps.nblocks, 1) * block_tab_doubles(LBp / 16));
+        w.ztab.reserve(8 * (size_t)std::max<int64_t>(ps.nblocks, 1) * 512 * (LBp / 16));
+    }
+    w.babs.reserve(8 * (size_t)g.E * LBp + 8);
+    w.rhom.reserve(8 * (size_t)g.E * LBp + 8);
+    w.sd.reserve(8 * (size_t)g.E * LBp + 8);
+    w.so.reserve(8 * (size_t)g.E * LBp + 8);
+    w.ends.reserve(8 * (size_t)lb * g.E * 2 * ps.Sp + 8);
+    w.gT.reserve(8 * (size_t)lb * S * g.V);
+    w.xT.reserve(8 * (size_t)lb * S * g.V);
+    w.ug.reserve(8 * (size_t)lb * g.V * ps.Sp);
+    w.its.reserve(4 * (size_t)ps.ng * ps.L * S);
+    w.res.reserve(8 * (size_t)ps.ng * ps.L * S);
+    w.pcg_scr.reserve(pcg_scratch_bytes(mv, ps.p.pcg_blocks));
+    prepare_pcg(mv);
+    GRF_HIP(hipStreamSynchronize(st));  // uploads from host memory complete
+    return ps;
+}
+
+static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStream_t st, KTimer &T) {
+    grf_graph::Work &w = work(g);
+    const MeshView mv = g.view();
+    const Plan &p = ps.p;
+    const int32_t nb = ps.nb, Sp = ps.Sp;
+    const int64_t S = ps.S;
     T.begin(GRF_K_LAYOUT);
     if (p.blocked)
         launch_fill_rows(w.U.as<double>(), nb, g.N, g.NI, g.V, st);
     else
         launch_fill(w.U.as<double>(), (size_t)nb * g.N * 64, 0.0, st);
     T.end();
-    for (int32_t l0 = 0; l0 < L; l0 += p.LB) {
-        const int32_t lb = std::min(p.LB, L - l0);
-        const int32_t LBp = ((lb + p.BL - 1) / p.BL) * p.BL;  // blocked: multiple of 16
-        std::vector<double> sh(2 * (size_t)LBp, 0.0);
-        for (int32_t i = 0; i < lb; ++i) {
-            sh[2 * i] = cI[l0 + i];
-            sh[2 * i + 1] = cL[l0 + i];
-        }
-        for (int32_t i = lb; i < LBp; ++i) sh[2 * i + 1] = 1.0;  // padding: never used as a divisor of 0
-        upload(w.shift, sh, st);
-        const size_t nir = (size_t)std::max<int64_t>(g.NI, 1) * LBp;
-        if (!p.blocked) {
-            w.rho.reserve(8 * nir);
-            w.fwdt.reserve(16 * nir);
-            w.bwdt.reserve(16 * nir);
-        }
-        w.babs.reserve(8 * (size_t)g.E * LBp + 8);
-        w.rhom.reserve(8 * (size_t)g.E * LBp + 8);
-        w.sd.reserve(8 * (size_t)g.E * LBp + 8);
-        w.so.reserve(8 * (size_t)g.E * LBp + 8);
-        w.ends.reserve(8 * (size_t)lb * g.E * 2 * Sp + 8);
-        w.gT.reserve(8 * (size_t)lb * S * g.V);
-        w.xT.reserve(8 * (size_t)lb * S * g.V);
-        w.ug.reserve(8 * (size_t)lb * g.V * Sp);
-        w.its.reserve(4 * (size_t)lb * S);
-        w.res.reserve(8 * (size_t)lb * S);
-        w.pcg_scr.reserve(pcg_scratch_bytes(mv, p.pcg_blocks));
-
+    for (size_t k = 0; k < ps.l0s.size(); ++k) {
+        const int32_t l0 = ps.l0s[k], lb = ps.lbs[k], LBp = ps.LBps[k];
         CoeffArgs ca{};
-        ca.shift = w.shift.as<double>();
+        ca.shift = w.shift.as<double>() + 2 * (size_t)ps.LBmax * k;
         ca.LB = lb;
         ca.LBp = LBp;
         ca.rho = p.blocked ? nullptr : w.rho.as<double>();
@@ -164,18 +200,14 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
 
         BlockArgs ba{};
         if (p.blocked) {
-            int64_t nblocks = 0;
-            ensure_block_offsets(g, w, st, nblocks);
             ba.boff = w.boff.as<int32_t>();
-            ba.nblocks = nblocks;
+            ba.nblocks = ps.nblocks;
             ba.NT = LBp / 16;
             ba.LB = lb;
             ba.LBp = LBp;
             ba.shift = ca.shift;
             ba.babs = ca.babs;
             ba.rhom = ca.rhom;
-            w.btab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * block_tab_doubles(ba.NT));
-            w.ztab.reserve(8 * (size_t)std::max<int64_t>(nblocks, 1) * 512 * ba.NT);
             ba.tab = w.btab.as<double>();
             ba.ztab = w.ztab.as<double>();
             ba.X = sa.X;
@@ -216,8 +248,8 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
         sc.ug = w.ug.as<double>();
         sc.U = sa.U;
         sc.scr = w.pcg_scr.as<double>();
-        sc.its = w.its.as<int32_t>();
-        sc.res = w.res.as<double>();
+        sc.its = w.its.as<int32_t>() + (size_t)ps.ng * l0 * S;  // [ng][lb][S] per shift block
+        sc.res = w.res.as<double>() + (size_t)ps.ng * l0 * S;
         sc.LB = lb;
         sc.LBp = LBp;
         sc.nb = nb;
@@ -247,35 +279,172 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
             launch_sweep_acc(mv, sa, false, st);
             T.end();
         }
+    }
+}
 
-        w.h_its.resize((size_t)lb * S);
-        w.h_res.resize((size_t)lb * S);
-        GRF_HIP(hipMemcpyAsync(w.h_its.data(), w.its.ptr, 4 * (size_t)lb * S, hipMemcpyDeviceToHost, st));
-        GRF_HIP(hipMemcpyAsync(w.h_res.data(), w.res.ptr, 8 * (size_t)lb * S, hipMemcpyDeviceToHost, st));
-        GRF_HIP(hipStreamSynchronize(st));
-        for (size_t i = 0; i < w.h_its.size(); ++i) {
-            const int32_t it = w.h_its[i];
+// Copies the iteration counts back, fills stats, throws GRF_ENOCONV if any
+// system hit maxit.  Per-graph iteration totals go to graph_its if given.
+static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStream_t st, grf_stats *stats,
+                        std::vector<int64_t> *graph_its = nullptr) {
+    grf_graph::Work &w = work(g);
+    const size_t n = (size_t)ps.ng * ps.L * ps.S;
+    w.h_its.resize(n);
+    w.h_res.resize(n);
+    if (n > 0) {
+        GRF_HIP(hipMemcpyAsync(w.h_its.data(), w.its.ptr, 4 * n, hipMemcpyDeviceToHost, st));
+        GRF_HIP(hipMemcpyAsync(w.h_res.data(), w.res.ptr, 8 * n, hipMemcpyDeviceToHost, st));
+    }
+    GRF_HIP(hipStreamSynchronize(st));
+    int64_t n_unconv = 0, tot_it = 0;
+    int32_t max_it = 0;
+    double max_res = 0.0;
+    if (graph_its) graph_its->assign(ps.ng, 0);
+    for (size_t k = 0; k < ps.l0s.size(); ++k) {
+        const size_t base = (size_t)ps.ng * ps.l0s[k] * ps.S, cnt = (size_t)ps.ng * ps.lbs[k] * ps.S;
+        for (size_t i = 0; i < cnt; ++i) {
+            const int32_t it = w.h_its[base + i];
             if (it > o.maxit) n_unconv++;
             tot_it += std::min(it, o.maxit);
             max_it = std::max(max_it, std::min(it, o.maxit));
-            max_res = std::max(max_res, w.h_res[i]);
+            max_res = std::max(max_res, w.h_res[base + i]);
+            if (graph_its) (*graph_its)[i / ((size_t)ps.lbs[k] * ps.S)] += std::min(it, o.maxit);
         }
     }
     if (stats) {
-        stats->n_shifts = L;
-        stats->n_systems = (int32_t)std::min<int64_t>((int64_t)L * S, INT32_MAX);
+        stats->n_shifts = ps.L;
+        stats->n_systems = (int32_t)std::min<int64_t>((int64_t)n, INT32_MAX);
         stats->n_unconverged = (int32_t)n_unconv;
         stats->max_iterations = max_it;
         stats->total_iterations = tot_it;
         stats->max_rel_residual = max_res;
         stats->refine_steps = 0;
-        stats->shift_block = p.LB;
-        stats->sweep_block = p.blocked ? 0 : p.BL;
+        stats->shift_block = ps.p.LB;
+        stats->sweep_block = ps.p.blocked ? 0 : ps.p.BL;
     }
     if (n_unconv > 0) {
         set_error("%lld vertex Schur systems did not reach tol=%g within maxit=%d", (long long)n_unconv, o.tol,
                   o.maxit);
         throw Error{GRF_ENOCONV};
+    }
+}
+
+// Runs shifts (cI[i], cL[i]) on the right-hand sides in w.X into w.U (zeroed
+// here: the blocked forward pass of the first shift block writes the interior
+// rows, so only the vertex rows are cleared).
+static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::vector<double> &cL, int64_t S,
+                       const grf_opts &o, hipStream_t st, grf_stats *stats, KTimer &T) {
+    const Pass ps = prepare_pass(g, cI, cL, S, o, st);
+    enqueue_pass(g, ps, o, st, T);
+    finish_pass(g, ps, o, st, stats);
+}
+
+// ---- batches of graphs ----------------------------------------------------------
+// A batch is the disjoint union of its graphs (graph k's edges and vertices in
+// order after those of graphs 0..k-1), with its own workspace, the options the
+// autotuner chose, and the HIP graph of its last run.
+namespace {
+
+struct Batch {
+    std::vector<uint64_t> ids;
+    grf_graph U;
+    std::vector<double> kap2;     // per-edge kappa^2 on the device
+    bool tuned = false;
+    int32_t sweep_block = 0, shift_block = 0;
+    hipStream_t stream = nullptr;  // capture and replay stream (default priority)
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> exec_key;  // parameters the captured graph was recorded with
+    Pass exec_pass;
+    DevBuf d_outs;
+    ~Batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (stream) (void)hipStreamDestroy(stream);
+        free_work(U);
+    }
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<Batch>> g_batches;  // least recently used first
+constexpr size_t kMaxBatches = 4;
+
+Batch *get_batch(grf_graph *const *graphs, int32_t ng) {
+    std::vector<uint64_t> ids(ng);
+    for (int32_t k = 0; k < ng; ++k) ids[k] = graphs[k]->serial;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t i = 0; i < g_batches.size(); ++i)
+        if (g_batches[i]->ids == ids) {
+            std::unique_ptr<Batch> b = std::move(g_batches[i]);
+            g_batches.erase(g_batches.begin() + i);
+            g_batches.push_back(std::move(b));
+            return g_batches.back().get();
+        }
+    const grf_graph &g0 = *graphs[0];
+    int64_t V = 0, E = 0;
+    for (int32_t k = 0; k < ng; ++k) {
+        const grf_graph &g = *graphs[k];
+        GRF_REQUIRE(g.h == g0.h && g.flags == g0.flags, "the graphs of a batch must share h and the mesh rule");
+        GRF_REQUIRE(g.device == g0.device, "the graphs of a batch must live on one device");
+        V += g.V;
+        E += g.E;
+    }
+    GRF_REQUIRE(V < (int64_t(1) << 31) && 2 * E < (int64_t(1) << 31), "batch too large");
+    std::vector<int64_t> edges(2 * (size_t)E);
+    std::vector<double> lengths(E);
+    std::vector<int32_t> gv0(ng + 1, 0), ge0(ng + 1, 0);
+    for (int32_t k = 0; k < ng; ++k) {
+        const grf_graph &g = *graphs[k];
+        for (int64_t e = 0; e < g.E; ++e) {
+            edges[2 * (ge0[k] + e)] = g.eu[e] + gv0[k];
+            edges[2 * (ge0[k] + e) + 1] = g.ev[e] + gv0[k];
+            lengths[ge0[k] + e] = g.len[e];
+        }
+        gv0[k + 1] = gv0[k] + (int32_t)g.V;
+        ge0[k + 1] = ge0[k] + (int32_t)g.E;
+    }
+    auto b = std::make_unique<Batch>();
+    b->ids = ids;
+    build_mesh(b->U, V, E, edges.data(), lengths.data(), g0.h, g0.flags);
+    b->U.device = g0.device;
+    b->U.gv0 = gv0;
+    b->U.ge0 = ge0;
+    upload_mesh(b->U, nullptr);
+    GRF_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    g_batches.push_back(std::move(b));
+    if (g_batches.size() > kMaxBatches) g_batches.erase(g_batches.begin());
+    return g_batches.back().get();
+}
+
+// One uncaptured run of the batch with the given options; returns its device time in ms.
+double timed_run(Batch &B, const Shifts &sh, int64_t S, uint64_t seed, const grf_opts &o) {
+    grf_graph &U = B.U;
+    grf_graph::Work &w = work(U);
+    hipStream_t cs = B.stream;
+    const Pass ps = prepare_pass(U, sh.cI, sh.cL, S, o, cs);
+    hipEvent_t a, b;
+    GRF_HIP(hipEventCreate(&a));
+    GRF_HIP(hipEventCreate(&b));
+    KTimer T(false, cs);
+    GRF_HIP(hipEventRecord(a, cs));
+    launch_noise(U.view(), S, o.sample_offset, seed, w.X.as<double>(), cs);
+    enqueue_pass(U, ps, o, cs, T);
+    GRF_HIP(hipEventRecord(b, cs));
+    GRF_HIP(hipEventSynchronize(b));
+    float ms = 0.0f;
+    GRF_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+}  // namespace
+
+void batch_forget(uint64_t serial) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t i = 0; i < g_batches.size();) {
+        const auto &ids = g_batches[i]->ids;
+        if (std::find(ids.begin(), ids.end(), serial) != ids.end())
+            g_batches.erase(g_batches.begin() + i);
+        else
+            ++i;
     }
 }
 
@@ -461,10 +630,137 @@ int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_
 int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double *kappas, double beta,
                        double quad_step, int64_t n_samples, uint64_t seed, double *const *outs, const grf_opts *opts) {
     GRF_API_BEGIN
-    (void)graphs; (void)n_graphs; (void)kappas; (void)beta; (void)quad_step; (void)n_samples; (void)seed;
-    (void)outs; (void)opts;
-    set_error("grf_sample_batched is not available in this build");
-    return GRF_EUNSUP;
+    GRF_REQUIRE(graphs && n_graphs > 0, "graphs must be a non-empty array");
+    GRF_REQUIRE(kappas, "kappas is NULL");
+    for (int32_t k = 0; k < n_graphs; ++k) {
+        GRF_REQUIRE(graphs[k], "graphs[%d] is NULL", k);
+        GRF_REQUIRE(std::isfinite(kappas[k]) && kappas[k] > 0, "kappas[%d] must be finite and > 0", k);
+    }
+    GRF_REQUIRE(n_samples >= 0, "n_samples must be >= 0");
+    grf_opts o = resolve_opts(opts);
+    if (n_samples == 0) return GRF_OK;
+    GRF_REQUIRE(outs, "outs is NULL");
+    for (int32_t k = 0; k < n_graphs; ++k) GRF_REQUIRE(outs[k], "outs[%d] is NULL", k);
+    GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
+                "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
+    GRF_REQUIRE(o.precond == GRF_PRECOND_JACOBI, "learned preconditioner is not available in this build");
+    hipStream_t st = (hipStream_t)o.stream;
+    Batch &B = *get_batch(graphs, n_graphs);
+    grf_graph &U = B.U;
+    const Shifts sh = make_shifts(beta, quad_step, U.h, o);
+    const MeshView mv = U.view();
+    // per-edge kappa^2 of each edge's graph
+    std::vector<double> k2(U.E + 1, 0.0);
+    for (int32_t k = 0; k < n_graphs; ++k)
+        for (int32_t e = U.ge0[k]; e < U.ge0[k + 1]; ++e) k2[e] = kappas[k] * kappas[k];
+    if (k2 != B.kap2) {
+        upload(U.d_kap2, k2, B.stream);
+        GRF_HIP(hipStreamSynchronize(B.stream));
+        B.kap2 = k2;
+    }
+    grf_graph::Work &w = work(U);
+    const int64_t nb = (n_samples + 63) / 64;
+    w.X.reserve(8 * (size_t)nb * U.N * 64);
+    w.U.reserve(8 * (size_t)nb * U.N * 64);
+    GRF_HIP(hipStreamSynchronize(st));  // the caller's earlier work on its stream
+    // options: the autotuner picks the sweep form and shift block unless the caller fixed them
+    grf_opts run = o;
+    run.timing = 0;
+    if (o.sweep_block == 0 && o.shift_block == 0) {
+        if (!B.tuned) {
+            std::vector<std::pair<int32_t, int32_t>> cand = {{0, 0}, {0, 64}};
+            if (o.precision == GRF_PREC_FP64) {
+                cand.push_back({32, 0});
+                cand.push_back({64, 0});
+            }
+            double best = 0.0;
+            for (size_t c = 0; c < cand.size(); ++c) {
+                grf_opts t = run;
+                t.sweep_block = cand[c].first;
+                t.shift_block = cand[c].second;
+                if (c == 0) (void)timed_run(B, sh, n_samples, seed, t);  // first launches of the kernels
+                const double ms = timed_run(B, sh, n_samples, seed, t);
+                if (c == 0 || ms < best) {
+                    best = ms;
+                    B.sweep_block = t.sweep_block;
+                    B.shift_block = t.shift_block;
+                }
+            }
+            B.tuned = true;
+            if (B.exec) {
+                (void)hipGraphExecDestroy(B.exec);
+                B.exec = nullptr;
+            }
+        }
+        run.sweep_block = B.sweep_block;
+        run.shift_block = B.shift_block;
+    }
+    std::vector<double> key = {beta, sh.k, (double)sh.kminus, (double)sh.kplus, (double)n_samples,
+                               (double)(seed >> 32), (double)(seed & 0xffffffffu), (double)run.sample_offset,
+                               run.tol, (double)run.maxit, (double)run.precision, (double)run.sweep_block,
+                               (double)run.shift_block};
+    key.insert(key.end(), kappas, kappas + n_graphs);
+    hipStream_t cs = B.stream;
+    if (!B.exec || key != B.exec_key) {
+        if (B.exec) {
+            (void)hipGraphExecDestroy(B.exec);
+            B.exec = nullptr;
+        }
+        // every upload and allocation happens here, before the capture
+        B.exec_pass = prepare_pass(U, sh.cI, sh.cL, n_samples, run, cs);
+        KTimer T(false, cs);
+        hipGraph_t graph = nullptr;
+        GRF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        try {
+            launch_noise(mv, n_samples, run.sample_offset, seed, w.X.as<double>(), cs);
+            enqueue_pass(U, B.exec_pass, run, cs, T);
+        } catch (...) {
+            (void)hipStreamEndCapture(cs, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        GRF_HIP(hipStreamEndCapture(cs, &graph));
+        const hipError_t ie = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            B.exec = nullptr;
+            set_error("HIP graph instantiation failed: %s", hipGetErrorString(ie));
+            throw Error{GRF_EDEVICE};
+        }
+        B.exec_key = key;
+    }
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (o.timing) {
+        GRF_HIP(hipEventCreate(&ea));
+        GRF_HIP(hipEventCreate(&eb));
+        GRF_HIP(hipEventRecord(ea, cs));
+    }
+    GRF_HIP(hipGraphLaunch(B.exec, cs));
+    if (o.timing) GRF_HIP(hipEventRecord(eb, cs));
+    if (o.stats) *o.stats = grf_stats{};
+    int code = GRF_OK;
+    try {
+        finish_pass(U, B.exec_pass, run, cs, o.stats);
+    } catch (const Error &err) {
+        if (err.code != GRF_ENOCONV) throw;
+        code = GRF_ENOCONV;
+    }
+    if (o.timing) {
+        float ms = 0.0f;
+        GRF_HIP(hipEventElapsedTime(&ms, ea, eb));
+        if (o.stats) {
+            o.stats->kernel_ms[GRF_K_ENDS_FWD] += ms;  // the whole captured pass (noise and all shifts)
+            o.stats->kernel_launches[GRF_K_ENDS_FWD] += 1;
+        }
+        (void)hipEventDestroy(ea);
+        (void)hipEventDestroy(eb);
+    }
+    // outputs, on the caller's stream
+    std::vector<double *> op(outs, outs + n_graphs);
+    upload(B.d_outs, op, st);
+    launch_from_interleaved_seg(mv, w.U.as<double>(), n_samples, B.d_outs.as<double *>(), st);
+    GRF_HIP(hipStreamSynchronize(st));
+    return code;
     GRF_API_END
 }
 

@@ -35,6 +35,8 @@ void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, do
 // layout transforms between canonical [S][N] and sample-interleaved [nb][N][64]
 void launch_to_interleaved(const double *in, int64_t S, int64_t N, double *X, hipStream_t st);
 void launch_from_interleaved(const double *X, int64_t S, int64_t N, double *out, hipStream_t st);
+// batch: graph g's DOFs of X (mesh of the batch) -> outs[g][s][j] (device array of device pointers)
+void launch_from_interleaved_seg(const MeshView &mv, const double *X, int64_t S, double *const *outs, hipStream_t st);
 void launch_fill(double *p, size_t n, double v, hipStream_t st);
 // zero rows [r0, r0 + nrows) of each of the nb sample blocks of a [nb][N][64] array
 void launch_fill_rows(double *p, int64_t nb, int64_t N, int64_t r0, int64_t nrows, hipStream_t st);
@@ -121,6 +123,7 @@ struct SchurArgs {
 };
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);
+void prepare_pcg(const MeshView &mv);  // one-time kernel attributes, before any graph capture
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);
 
