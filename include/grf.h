@@ -200,6 +200,51 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
                        double beta, double quad_step, int64_t n_samples, uint64_t seed,
                        double *const *outs, const grf_opts *opts);
 
+/*
+ * ---- Learned preconditioner of the vertex Schur solve ----------------------------
+ * This build's addition to "Phase 4" (PCG on eq. global_schur).  A
+ * message-passing network (3 layers of width 64 over vertex features: degree,
+ * incident edge lengths, log(c_L / c_I), log kappa, Jacobi-scaled couplings)
+ * predicts per (graph, shift) a scale-free SPD operator P_hat = diag(delta) +
+ * sum over edges of PSD 2x2 blocks and an initial-guess operator Q_hat; the PCG
+ * applies z = D^{-1/2} P_hat D^{-1/2} r and starts from x0 = D^{-1/2} Q_hat
+ * D^{-1/2} g (D = diag S).  P_hat = I is exactly the Jacobi preconditioner,
+ * which is also the fallback: a system not converged after maxit/2 iterations
+ * restarts from its iterate with Jacobi; the recomputed true residual decides
+ * convergence as for Jacobi.  Weights are bfloat16 (products on the FP32
+ * matrix cores); training runs on the GPU (own forward / backward kernels,
+ * Adam) on the method's own condensed right-hand sides and FP64 Schur solutions.
+ * A network handle is used by one call at a time (its workspace is shared).
+ */
+/* Number of float parameters of the network. */
+int grf_learned_param_count(int64_t *n_params);
+/* Create from host FP32 parameters (copied; n_params must equal grf_learned_param_count). */
+int grf_learned_create(const float *params, int64_t n_params, grf_learned **out);
+/* Current FP32 master parameters to host memory. */
+int grf_learned_params(const grf_learned *net, float *out, int64_t n_params);
+int grf_learned_destroy(grf_learned *net);
+/*
+ * Training loss and its gradient (host FP32, n_params values) for the systems
+ * S x_r = g_r of one shift (c_I, c_L) on graph g:
+ *   rhs, sol   device, float64 [n_rhs][V] (g_r and the solutions x_r)
+ *   loss       mean over r of (||P_hat g_hat - x_hat||^2 + ||Q_hat g_hat - x_hat||^2) / ||x_hat||^2,
+ *              g_hat = D^{-1/2} g_r, x_hat = D^{1/2} x_r
+ */
+int grf_learned_loss_grad(grf_learned *net, grf_graph *g, double kappa, double c_I, double c_L,
+                          int64_t n_rhs, const double *rhs, const double *sol, double *loss,
+                          float *grad, const grf_opts *opts);
+/*
+ * Train in place: draws n_samples noise samples per graph (seed + graph index),
+ * runs the method with Jacobi PCG (FP64, opts->tol) over every shift of the
+ * schedule (beta, quad_step) to collect (g, x) pairs, then takes n_steps Adam
+ * steps (learning rate lr), step t on graph t mod n_graphs and a window of
+ * shifts_per_step consecutive shifts.  losses (host, [n_steps]) may be NULL.
+ */
+int grf_learned_train(grf_learned *net, grf_graph *const *graphs, int32_t n_graphs,
+                      const double *kappas, double beta, double quad_step, int64_t n_samples,
+                      uint64_t seed, int32_t n_steps, int32_t shifts_per_step, double lr,
+                      double *losses, const grf_opts *opts);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char *grf_last_error(void);
 

@@ -1,0 +1,896 @@
+// Learned vertex preconditioner: network forward / backward, training, and the
+// operators the PCG applies.
+//
+// The paper solves each shift's vertex Schur system S u = g (eq. global_schur)
+// by PCG ("Phase 4"); this module is this project's addition to that step.  A
+// message-passing network predicts, per (graph, shift), a scale-free SPD
+// operator P_hat and an initial-guess operator Q_hat on the Jacobi-scaled
+// system D^{-1/2} S D^{-1/2} (D = diag S):
+//   P_hat = diag(delta) + sum_e [[p_u, q], [q, p_v]],  q = rho sqrt(p_u p_v), |rho| < 1,
+//   Q_hat = diag(gamma) + sum_e [[0, eta], [eta, 0]],
+// applied as z = D^{-1/2} P_hat D^{-1/2} r and x0 = D^{-1/2} Q_hat D^{-1/2} g
+// (P_hat = I is Jacobi).  Vertex features (8): log(1 + deg), mean / min / max
+// incident edge length, log(c_L / c_I) / 10, log(kappa) / 3, sum of incident
+// w_e = |s_o| / sqrt(D_u D_v), 1.  Layers h' = relu(W_s h + W_n m + b) with
+// m_v = sum over edge ends at v of w_e h_u (8 -> 64 -> 64 -> 64); heads
+//   delta = softplus(a_d.h_v + c_d), gamma = a_g.h_v + c_g,
+//   p_u = softplus(a_p1.h_u + a_p2.h_v + c_p), p_v = softplus(a_p1.h_v + a_p2.h_u + c_p),
+//   rho = 0.95 tanh(a_r.(h_u + h_v) + c_r), eta = a_e.(h_u + h_v) + c_e.
+// Weights (matrices, head vectors) are stored and used as bfloat16; biases,
+// activations and accumulation are FP32 (the layer products on the FP32
+// matrix cores).  Training minimises, over Schur solutions x* of the method,
+//   (||P_hat g_hat - x_hat||^2 + ||Q_hat g_hat - x_hat||^2) / ||x_hat||^2,
+// g_hat = D^{-1/2} g, x_hat = D^{1/2} x*, with Adam on FP32 master weights.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "work.h"
+
+namespace grf {
+
+// ---- parameter layout (flat, float) ---------------------------------------------
+constexpr int F_IN = 8, HID = 64;
+enum PIdx {
+    P_W1S = 0,
+    P_W1N = P_W1S + HID * F_IN,
+    P_B1 = P_W1N + HID * F_IN,
+    P_W2S = P_B1 + HID,
+    P_W2N = P_W2S + HID * HID,
+    P_B2 = P_W2N + HID * HID,
+    P_W3S = P_B2 + HID,
+    P_W3N = P_W3S + HID * HID,
+    P_B3 = P_W3N + HID * HID,
+    P_AD = P_B3 + HID,
+    P_CD = P_AD + HID,
+    P_AG = P_CD + 1,
+    P_CG = P_AG + HID,
+    P_AP1 = P_CG + 1,
+    P_AP2 = P_AP1 + HID,
+    P_CP = P_AP2 + HID,
+    P_AR = P_CP + 1,
+    P_CR = P_AR + HID,
+    P_AE = P_CR + 1,
+    P_CE = P_AE + HID,
+    P_COUNT = P_CE + 1
+};
+constexpr float RHO_MAX = 0.95f;
+
+static bool is_bias(int i) {
+    return (i >= P_B1 && i < P_B1 + HID) || (i >= P_B2 && i < P_B2 + HID) || (i >= P_B3 && i < P_B3 + HID) ||
+           i == P_CD || i == P_CG || i == P_CP || i == P_CR || i == P_CE;
+}
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float bf(const uint16_t *w, int i) { return __uint_as_float((uint32_t)w[i] << 16); }
+__device__ __forceinline__ float softplusf(float z) { return z > 20.0f ? z : log1pf(expf(z)); }
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__host__ __device__ inline uint16_t to_bf16(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    const uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+__global__ void k_refresh_bf16(const float *__restrict__ w, uint16_t *__restrict__ wb, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = to_bf16(w[i]);
+}
+
+// ---- Jacobi scaling, edge weights, features (rows = (shift, vertex)) -------------
+// Dh[l][v] = D_v^{-1/2}, D_v = sum over the edge ends at v of s_d (+ s_o for a self-loop end)
+__global__ void k_lrn_scale(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
+                            double *__restrict__ Dh) {
+    const int64_t n = (int64_t)LB * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), v = (int)(i - (int64_t)l * mv.V);
+        const double *sdl = sd + (int64_t)l * mv.E, *sol = so + (int64_t)l * mv.E;
+        double d = 0.0;
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            const int e = mv.adj_e[k];
+            d += sdl[e] + (mv.adj_o[k] == v ? sol[e] : 0.0);
+        }
+        Dh[i] = 1.0 / sqrt(d);
+    }
+}
+
+// w[l][e] = |s_o| Dh_u Dh_v
+__global__ void k_lrn_edgew(MeshView mv, const double *__restrict__ so, const double *__restrict__ Dh, int32_t LB,
+                            float *__restrict__ w) {
+    const int64_t n = (int64_t)LB * mv.E;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.E), e = (int)(i - (int64_t)l * mv.E);
+        const double *dh = Dh + (int64_t)l * mv.V;
+        w[i] = (float)(fabs(so[(int64_t)l * mv.E + e]) * dh[mv.eu[e]] * dh[mv.ev[e]]);
+    }
+}
+
+__global__ void k_lrn_features(MeshView mv, const double *__restrict__ shift, const float *__restrict__ w,
+                               int32_t LB, float *__restrict__ X) {
+    const int64_t n = (int64_t)LB * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), v = (int)(i - (int64_t)l * mv.V);
+        const int64_t k0 = mv.vptr[v], k1 = mv.vptr[v + 1];
+        double ls = 0.0, lmin = 1e300, lmax = -1e300, ws = 0.0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const int e = mv.adj_e[k];
+            const double len = mv.he[e] * (double)(mv.m[e] + 1);
+            ls += len;
+            lmin = fmin(lmin, len);
+            lmax = fmax(lmax, len);
+            ws += w[(int64_t)l * mv.E + e];
+        }
+        const double deg = (double)(k1 - k0);
+        const double cI = shift[2 * l], cL = shift[2 * l + 1];
+        float *x = X + i * F_IN;
+        x[0] = (float)log1p(deg);
+        x[1] = (float)(ls / deg);
+        x[2] = (float)lmin;
+        x[3] = (float)lmax;
+        x[4] = (float)(log(cL / cI) / 10.0);
+        x[5] = (float)(log(sqrt(mv.kap2[mv.adj_e[k0]])) / 3.0);
+        x[6] = (float)ws;
+        x[7] = 1.0f;
+    }
+}
+
+// M[l][v][c] = sum over the edge ends at v of w_e H[l][other][c]   (C channels)
+__global__ void k_lrn_agg(MeshView mv, const float *__restrict__ w, const float *__restrict__ H, int32_t LB, int C,
+                          float *__restrict__ M) {
+    const int64_t n = (int64_t)LB * mv.V * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / C;
+        const int c = (int)(i - row * C);
+        const int l = (int)(row / mv.V), v = (int)(row - (int64_t)l * mv.V);
+        const float *Hl = H + (int64_t)l * mv.V * C;
+        float acc = 0.0f;
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k)
+            acc += w[(int64_t)l * mv.E + mv.adj_e[k]] * Hl[(int64_t)mv.adj_o[k] * C + c];
+        M[i] = acc;
+    }
+}
+
+// ---- layer products on the FP32 matrix cores ------------------------------------
+// Out[r][n] = relu?( sum_k A[r][k] Ws[n][k] + sum_k B[r][k] Wn[n][k] + bias[n] ), n < 64,
+// K in {8, 64}.  One wavefront per 16 rows; accumulator item j of lane L is
+// row 4 (L/16) + j, column L%16 of its 16x16 tile.
+template <int K>
+__global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ A, const float *__restrict__ B,
+                                                      const uint16_t *__restrict__ Ws, const uint16_t *__restrict__ Wn,
+                                                      const float *__restrict__ bias, int64_t R,
+                                                      float *__restrict__ Out) {
+    const int L = threadIdx.x & 63;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (r0 >= R) return;
+    const int64_t ra = r0 + (L & 15);
+    const bool rok = ra < R;
+    f4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + (L >> 4);
+        const float a = rok ? A[ra * K + k] : 0.0f;
+        const float b = rok ? B[ra * K + k] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int n = 16 * t + (L & 15);
+            acc[t] = mfma32(a, bf(Ws, n * K + k), acc[t]);
+            acc[t] = mfma32(b, bf(Wn, n * K + k), acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t r = r0 + 4 * (L >> 4) + j;
+            const int n = 16 * t + (L & 15);
+            if (r < R) Out[r * HID + n] = fmaxf(acc[t][j] + bias[n], 0.0f);
+        }
+}
+
+// Out[r][k] = sum_n G[r][n] W[n][k]  (input gradient of a layer, K in {8, 64})
+template <int K>
+__global__ void __launch_bounds__(256) k_lrn_gemm_bwd(const float *__restrict__ G, const uint16_t *__restrict__ W,
+                                                      int64_t R, float *__restrict__ Out) {
+    const int L = threadIdx.x & 63;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (r0 >= R) return;
+    const int64_t ra = r0 + (L & 15);
+    const bool rok = ra < R;
+    constexpr int NT = K / 16 > 0 ? K / 16 : 1;
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int n0 = 0; n0 < HID; n0 += 4) {
+        const int n = n0 + (L >> 4);
+        const float a = rok ? G[ra * HID + n] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int k = 16 * t + (L & 15);
+            acc[t] = mfma32(a, (k < K) ? bf(W, n * K + k) : 0.0f, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t r = r0 + 4 * (L >> 4) + j;
+            const int k = 16 * t + (L & 15);
+            if (r < R && k < K) Out[r * K + k] = acc[t][j];
+        }
+}
+
+// Partial weight gradients P[chunk][n][k] = sum over the chunk's rows of G[r][n] A[r][k]
+// (one wavefront per chunk of rows; 64 x K outputs in registers).
+template <int K>
+__global__ void __launch_bounds__(64) k_lrn_gemm_wgrad(const float *__restrict__ G, const float *__restrict__ A,
+                                                       int64_t R, int64_t rows_per, float *__restrict__ P) {
+    const int L = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int64_t rb = c * rows_per, re = min(R, rb + rows_per);
+    constexpr int KT = K / 16 > 0 ? K / 16 : 1;
+    f4 acc[4][KT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < KT; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t r0 = rb; r0 < re; r0 += 4) {
+        const int64_t r = r0 + (L >> 4);
+        const bool ok = r < re;
+        float a[4], b[KT];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = ok ? G[r * HID + 16 * t + (L & 15)] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < KT; ++u) {
+            const int k = 16 * u + (L & 15);
+            b[u] = (ok && k < K) ? A[r * K + k] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < KT; ++u) acc[t][u] = mfma32(a[t], b[u], acc[t][u]);
+    }
+    float *out = P + c * (int64_t)HID * K;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < KT; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = 16 * t + 4 * (L >> 4) + j;
+                const int k = 16 * u + (L & 15);
+                if (k < K) out[n * K + k] = acc[t][u][j];
+            }
+}
+
+// out[i] (+)= sum over chunks of P[chunk][i], i < n (fixed order)
+__global__ void k_lrn_reduce(const float *__restrict__ P, int64_t chunks, int64_t n, float *__restrict__ out,
+                             int accumulate) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int64_t c = 0; c < chunks; ++c) s += P[c * n + i];
+        out[i] = accumulate ? out[i] + s : s;
+    }
+}
+
+// column sums of G [R][HID] in chunks: P[chunk][n]
+__global__ void __launch_bounds__(64) k_lrn_colsum(const float *__restrict__ G, int64_t R, int64_t rows_per,
+                                                   float *__restrict__ P) {
+    const int n = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int64_t rb = c * rows_per, re = min(R, rb + rows_per);
+    float s = 0.0f;
+    for (int64_t r = rb; r < re; ++r) s += G[r * HID + n];
+    P[c * HID + n] = s;
+}
+
+// dZ = dH where H > 0 (relu), in place
+__global__ void k_lrn_relu_bwd(const float *__restrict__ H, float *__restrict__ G, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!(H[i] > 0.0f)) G[i] = 0.0f;
+}
+
+// ---- heads and the operators ---------------------------------------------------
+struct Heads {
+    float *zd, *gam;                // [rows]
+    float *zt, *zh, *zr, *eta;      // [LB][E]
+    double *Pd, *Pq, *Qd, *Qe;      // [LB][V], [LB][E], [LB][V], [LB][E]
+};
+
+__global__ void k_lrn_ehead(MeshView mv, const float *__restrict__ H, const uint16_t *__restrict__ wb,
+                            const float *__restrict__ w32, int32_t LB, Heads hd) {
+    const int64_t n = (int64_t)LB * mv.E;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.E), e = (int)(i - (int64_t)l * mv.E);
+        const float *hu = H + ((int64_t)l * mv.V + mv.eu[e]) * HID;
+        const float *hv = H + ((int64_t)l * mv.V + mv.ev[e]) * HID;
+        float zt = w32[P_CP], zh = w32[P_CP], zr = w32[P_CR], et = w32[P_CE];
+        for (int c = 0; c < HID; ++c) {
+            const float a1 = bf(wb, P_AP1 + c), a2 = bf(wb, P_AP2 + c);
+            zt += a1 * hu[c] + a2 * hv[c];
+            zh += a1 * hv[c] + a2 * hu[c];
+            zr += bf(wb, P_AR + c) * (hu[c] + hv[c]);
+            et += bf(wb, P_AE + c) * (hu[c] + hv[c]);
+        }
+        hd.zt[i] = zt;
+        hd.zh[i] = zh;
+        hd.zr[i] = zr;
+        hd.eta[i] = et;
+        const double pt = softplusf(zt), ph = softplusf(zh);
+        hd.Pq[i] = (double)(RHO_MAX * tanhf(zr)) * sqrt(pt * ph);
+        hd.Qe[i] = et;
+    }
+}
+
+__global__ void k_lrn_vhead(MeshView mv, const float *__restrict__ H, const uint16_t *__restrict__ wb,
+                            const float *__restrict__ w32, int32_t LB, Heads hd) {
+    const int64_t n = (int64_t)LB * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), v = (int)(i - (int64_t)l * mv.V);
+        const float *h = H + i * HID;
+        float zd = w32[P_CD], g = w32[P_CG];
+        for (int c = 0; c < HID; ++c) {
+            zd += bf(wb, P_AD + c) * h[c];
+            g += bf(wb, P_AG + c) * h[c];
+        }
+        hd.zd[i] = zd;
+        hd.gam[i] = g;
+        double pd = softplusf(zd), qd = g;
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            const int e = mv.adj_e[k];
+            const int64_t ie = (int64_t)l * mv.E + e;
+            pd += softplusf(mv.adj_s[k] == 0 ? hd.zt[ie] : hd.zh[ie]);
+            if (mv.adj_o[k] == v) {  // one end of a self-loop: its coupling lands on the diagonal
+                pd += hd.Pq[ie];
+                qd += hd.Qe[ie];
+            }
+        }
+        hd.Pd[i] = pd;
+        hd.Qd[i] = qd;
+    }
+}
+
+// ---- loss and its gradient with respect to the operators -----------------------
+// per system (l, s): eP = P_hat g_hat - x_hat, eQ = Q_hat g_hat - x_hat (stored),
+// n2[l][s] = ||x_hat||^2, loss terms (||eP||^2 + ||eQ||^2) / n2 -> lsys
+__global__ void k_lrn_resid(MeshView mv, const double *__restrict__ Dh, const double *__restrict__ g,
+                            const double *__restrict__ xs, int32_t LB, int64_t S, Heads hd, double *__restrict__ eP,
+                            double *__restrict__ eQ) {
+    const int64_t n = (int64_t)LB * S * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sys = i / mv.V;
+        const int v = (int)(i - sys * mv.V);
+        const int l = (int)(sys / S);
+        const double *dh = Dh + (int64_t)l * mv.V;
+        const double *gs = g + sys * mv.V;
+        const double gv = gs[v] * dh[v];
+        double p = hd.Pd[(int64_t)l * mv.V + v] * gv, q = hd.Qd[(int64_t)l * mv.V + v] * gv;
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            const int o = mv.adj_o[k];
+            if (o == v) continue;
+            const int64_t ie = (int64_t)l * mv.E + mv.adj_e[k];
+            const double go = gs[o] * dh[o];
+            p += hd.Pq[ie] * go;
+            q += hd.Qe[ie] * go;
+        }
+        const double xh = xs[i] / dh[v];
+        eP[i] = p - xh;
+        eQ[i] = q - xh;
+    }
+}
+
+// per system: n2 = ||x_hat||^2 and the loss term (one wavefront per system)
+__global__ void __launch_bounds__(64) k_lrn_sysnorm(MeshView mv, const double *__restrict__ Dh,
+                                                    const double *__restrict__ xs, const double *__restrict__ eP,
+                                                    const double *__restrict__ eQ, int64_t S,
+                                                    double *__restrict__ n2, double *__restrict__ lsys) {
+    const int64_t sys = blockIdx.x;
+    const int l = (int)(sys / S);
+    const double *dh = Dh + (int64_t)l * mv.V;
+    double a = 0.0, b = 0.0;
+    for (int v = threadIdx.x; v < mv.V; v += 64) {
+        const double xh = xs[sys * mv.V + v] / dh[v];
+        a += xh * xh;
+        const double p = eP[sys * mv.V + v], q = eQ[sys * mv.V + v];
+        b += p * p + q * q;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        n2[sys] = a;
+        lsys[sys] = a > 0.0 ? b / a : 0.0;
+    }
+}
+
+// dL/dPd[l][v], dL/dQd[l][v]: sum over samples of 2 e_v g_hat_v / (n2 NS)
+__global__ void k_lrn_gdiag(MeshView mv, const double *__restrict__ Dh, const double *__restrict__ g,
+                            const double *__restrict__ eP, const double *__restrict__ eQ,
+                            const double *__restrict__ n2, int32_t LB, int64_t S, double inv_ns,
+                            double *__restrict__ gPd, double *__restrict__ gQd) {
+    const int64_t n = (int64_t)LB * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), v = (int)(i - (int64_t)l * mv.V);
+        const double dh = Dh[i];
+        double a = 0.0, b = 0.0;
+        for (int64_t s = 0; s < S; ++s) {
+            const int64_t sys = (int64_t)l * S + s;
+            if (!(n2[sys] > 0.0)) continue;
+            const double c = 2.0 * inv_ns / n2[sys];
+            const double gv = g[sys * mv.V + v] * dh;
+            a += c * eP[sys * mv.V + v] * gv;
+            b += c * eQ[sys * mv.V + v] * gv;
+        }
+        gPd[i] = a;
+        gQd[i] = b;
+    }
+}
+
+// dL/dq[l][e], dL/deta[l][e] (a self-loop's coupling is on the diagonal twice)
+__global__ void k_lrn_gedge(MeshView mv, const double *__restrict__ Dh, const double *__restrict__ g,
+                            const double *__restrict__ eP, const double *__restrict__ eQ,
+                            const double *__restrict__ n2, const double *__restrict__ gPd,
+                            const double *__restrict__ gQd, int32_t LB, int64_t S, double inv_ns,
+                            double *__restrict__ gq, double *__restrict__ geta) {
+    const int64_t n = (int64_t)LB * mv.E;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.E), e = (int)(i - (int64_t)l * mv.E);
+        const int u = mv.eu[e], v = mv.ev[e];
+        if (u == v) {
+            gq[i] = 2.0 * gPd[(int64_t)l * mv.V + u];
+            geta[i] = 2.0 * gQd[(int64_t)l * mv.V + u];
+            continue;
+        }
+        const double du = Dh[(int64_t)l * mv.V + u], dv = Dh[(int64_t)l * mv.V + v];
+        double a = 0.0, b = 0.0;
+        for (int64_t s = 0; s < S; ++s) {
+            const int64_t sys = (int64_t)l * S + s;
+            if (!(n2[sys] > 0.0)) continue;
+            const double c = 2.0 * inv_ns / n2[sys];
+            const double gu = g[sys * mv.V + u] * du, gv = g[sys * mv.V + v] * dv;
+            a += c * (eP[sys * mv.V + u] * gv + eP[sys * mv.V + v] * gu);
+            b += c * (eQ[sys * mv.V + u] * gv + eQ[sys * mv.V + v] * gu);
+        }
+        gq[i] = a;
+        geta[i] = b;
+    }
+}
+
+// Head backward, edges: pre-activation gradients dz[l][e][4] = (zt, zh, zr, eta)
+__global__ void k_lrn_ehead_bwd(MeshView mv, const double *__restrict__ gPd, const double *__restrict__ gq,
+                                const double *__restrict__ geta, int32_t LB, Heads hd, float *__restrict__ dz) {
+    const int64_t n = (int64_t)LB * mv.E;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.E), e = (int)(i - (int64_t)l * mv.E);
+        const float zt = hd.zt[i], zh = hd.zh[i], zr = hd.zr[i];
+        const double pt = softplusf(zt), ph = softplusf(zh);
+        const double th = tanhf(zr);
+        const double rho = RHO_MAX * th;
+        const double sq = sqrt(pt * ph);
+        const double dq = gq[i];
+        // q = rho sqrt(pt ph): dq/dpt = rho sqrt(ph / pt) / 2
+        const double dpt = gPd[(int64_t)l * mv.V + mv.eu[e]] + dq * 0.5 * rho * sqrt(ph / pt);
+        const double dph = gPd[(int64_t)l * mv.V + mv.ev[e]] + dq * 0.5 * rho * sqrt(pt / ph);
+        const double drho = dq * sq;
+        dz[4 * i + 0] = (float)(dpt * sigmoidf(zt));
+        dz[4 * i + 1] = (float)(dph * sigmoidf(zh));
+        dz[4 * i + 2] = (float)(drho * RHO_MAX * (1.0 - th * th));
+        dz[4 * i + 3] = (float)geta[i];
+    }
+}
+
+// Head backward, vertices: dzv[row][2] = (d zd, d gamma) and dH[row][c]
+__global__ void k_lrn_vhead_bwd(MeshView mv, const double *__restrict__ gPd, const double *__restrict__ gQd,
+                                const float *__restrict__ dz, const uint16_t *__restrict__ wb, int32_t LB, Heads hd,
+                                float *__restrict__ dzv, float *__restrict__ dH) {
+    const int64_t n = (int64_t)LB * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), v = (int)(i - (int64_t)l * mv.V);
+        const float dd = (float)gPd[i] * sigmoidf(hd.zd[i]);
+        const float dg = (float)gQd[i];
+        dzv[2 * i] = dd;
+        dzv[2 * i + 1] = dg;
+        float acc[HID];
+#pragma unroll
+        for (int c = 0; c < HID; ++c) acc[c] = dd * bf(wb, P_AD + c) + dg * bf(wb, P_AG + c);
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            const int64_t ie = (int64_t)l * mv.E + mv.adj_e[k];
+            const float d_t = dz[4 * ie], d_h = dz[4 * ie + 1], d_r = dz[4 * ie + 2], d_e = dz[4 * ie + 3];
+            // this end is the tail (u) or the head (v) of the edge
+            const float c1 = mv.adj_s[k] == 0 ? d_t : d_h, c2 = mv.adj_s[k] == 0 ? d_h : d_t;
+#pragma unroll
+            for (int c = 0; c < HID; ++c)
+                acc[c] += c1 * bf(wb, P_AP1 + c) + c2 * bf(wb, P_AP2 + c) + d_r * bf(wb, P_AR + c) +
+                          d_e * bf(wb, P_AE + c);
+        }
+#pragma unroll
+        for (int c = 0; c < HID; ++c) dH[i * HID + c] = acc[c];
+    }
+}
+
+// head parameter gradients, chunked over rows / edges: Pv[chunk][2 * 65], Pe[chunk][4 * 65 + 65]
+__global__ void __launch_bounds__(64) k_lrn_vhead_wgrad(const float *__restrict__ H, const float *__restrict__ dzv,
+                                                        int64_t R, int64_t rows_per, float *__restrict__ P) {
+    const int c = threadIdx.x;
+    const int64_t ch = blockIdx.x;
+    const int64_t rb = ch * rows_per, re = min(R, rb + rows_per);
+    float ad = 0.f, ag = 0.f, cd = 0.f, cg = 0.f;
+    for (int64_t r = rb; r < re; ++r) {
+        const float h = H[r * HID + c];
+        ad += dzv[2 * r] * h;
+        ag += dzv[2 * r + 1] * h;
+        cd += dzv[2 * r];
+        cg += dzv[2 * r + 1];
+    }
+    float *o = P + ch * 2 * (HID + 1);
+    o[c] = ad;
+    o[HID + 1 + c] = ag;
+    if (c == 0) {
+        o[HID] = cd;
+        o[2 * HID + 1] = cg;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_lrn_ehead_wgrad(MeshView mv, const float *__restrict__ H,
+                                                        const float *__restrict__ dz, int32_t LB, int64_t per,
+                                                        float *__restrict__ P) {
+    const int c = threadIdx.x;
+    const int64_t ch = blockIdx.x;
+    const int64_t n = (int64_t)LB * mv.E;
+    const int64_t ib = ch * per, ie_ = min(n, ib + per);
+    float a1 = 0.f, a2 = 0.f, ar = 0.f, ae = 0.f, cp = 0.f, cr = 0.f, ce = 0.f;
+    for (int64_t i = ib; i < ie_; ++i) {
+        const int l = (int)(i / mv.E), e = (int)(i - (int64_t)l * mv.E);
+        const float hu = H[((int64_t)l * mv.V + mv.eu[e]) * HID + c];
+        const float hv = H[((int64_t)l * mv.V + mv.ev[e]) * HID + c];
+        const float dt = dz[4 * i], dh = dz[4 * i + 1], dr = dz[4 * i + 2], de = dz[4 * i + 3];
+        a1 += dt * hu + dh * hv;
+        a2 += dt * hv + dh * hu;
+        ar += dr * (hu + hv);
+        ae += de * (hu + hv);
+        cp += dt + dh;
+        cr += dr;
+        ce += de;
+    }
+    float *o = P + ch * 4 * (HID + 1);
+    o[c] = a1;
+    o[(HID + 1) + c] = a2;
+    o[2 * (HID + 1) + c] = ar;
+    o[3 * (HID + 1) + c] = ae;
+    if (c == 0) {
+        o[HID] = cp;
+        o[2 * (HID + 1) - 1] = 0.0f;  // (a_p2 has no bias of its own)
+        o[3 * (HID + 1) - 1] = cr;
+        o[4 * (HID + 1) - 1] = ce;
+    }
+}
+
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m1,
+                       float *__restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * gi;
+    const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    w[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+int64_t blocks_for(int64_t n, int per_block = 256) {
+    return std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, 65536));
+}
+
+}  // namespace
+}  // namespace grf
+
+// ---- the network handle and its workspace ----------------------------------------
+struct grf_learned {
+    int device = 0;
+    std::vector<float> host;        // FP32 master parameters (host copy, refreshed on demand)
+    grf::DevBuf w32, wbf, m1, m2, grad;
+    int64_t adam_t = 0;
+    // activations and gradients of the last forward (rows = shifts x vertices)
+    grf::DevBuf Dh, w, X0, M0, H1, M1, H2, M2, H3, zd, gam, zt, zh, zr, eta, Pd, Pq, Qd, Qe;
+    grf::DevBuf eP, eQ, n2, lsys, gPd, gQd, gq, geta, dz, dzv, dH, dZ, T0, T1, part;
+};
+
+namespace grf {
+
+// Workspace of a forward over LB shifts of the mesh (allocations only: call before any graph capture).
+void learned_reserve(grf_learned &net, const MeshView &mv, int32_t LB) {
+    const int64_t R = (int64_t)LB * mv.V, RE = (int64_t)LB * mv.E;
+    net.Dh.reserve(8 * R + 8);
+    net.w.reserve(4 * RE + 4);
+    net.X0.reserve(4 * R * F_IN + 4);
+    net.M0.reserve(4 * R * F_IN + 4);
+    for (DevBuf *b : {&net.H1, &net.M1, &net.H2, &net.M2, &net.H3}) b->reserve(4 * R * HID + 4);
+    net.zd.reserve(4 * R + 4);
+    net.gam.reserve(4 * R + 4);
+    for (DevBuf *b : {&net.zt, &net.zh, &net.zr, &net.eta}) b->reserve(4 * RE + 4);
+    net.Pd.reserve(8 * R + 8);
+    net.Qd.reserve(8 * R + 8);
+    net.Pq.reserve(8 * RE + 8);
+    net.Qe.reserve(8 * RE + 8);
+}
+
+void learned_copy_grad(grf_learned &net, float *host, hipStream_t st) {
+    GRF_HIP(hipMemcpyAsync(host, net.grad.ptr, 4 * P_COUNT, hipMemcpyDeviceToHost, st));
+    GRF_HIP(hipStreamSynchronize(st));
+}
+
+// Forward of the network over LB shifts of a mesh: fills net.{Dh, Pd, Pq, Qd, Qe} (and the activations).
+void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, const double *sd, const double *so,
+                     int32_t LB, hipStream_t st) {
+    const int64_t R = (int64_t)LB * mv.V, RE = (int64_t)LB * mv.E;
+    GRF_REQUIRE(net.Dh.bytes >= (size_t)(8 * R) && net.Qe.bytes >= (size_t)(8 * RE),
+                "internal: learned workspace not reserved");
+    const uint16_t *wb = net.wbf.as<uint16_t>();
+    const float *w32 = net.w32.as<float>();
+    hipLaunchKernelGGL(k_lrn_scale, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, sd, so, LB,
+                       net.Dh.as<double>());
+    if (RE > 0)
+        hipLaunchKernelGGL(k_lrn_edgew, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv, so, net.Dh.as<double>(),
+                           LB, net.w.as<float>());
+    hipLaunchKernelGGL(k_lrn_features, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, shift, net.w.as<float>(),
+                       LB, net.X0.as<float>());
+    GRF_LAUNCH_CHECK();
+    const unsigned gblocks = (unsigned)std::max<int64_t>(1, (R + 63) / 64);
+    // layer 1 (8 -> 64), 2, 3 (64 -> 64)
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * F_IN)), dim3(256), 0, st, mv, net.w.as<float>(),
+                       net.X0.as<float>(), LB, F_IN, net.M0.as<float>());
+    hipLaunchKernelGGL((k_lrn_gemm_fwd<F_IN>), dim3(gblocks), dim3(256), 0, st, net.X0.as<float>(), net.M0.as<float>(),
+                       wb + P_W1S, wb + P_W1N, w32 + P_B1, R, net.H1.as<float>());
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, mv, net.w.as<float>(),
+                       net.H1.as<float>(), LB, HID, net.M1.as<float>());
+    hipLaunchKernelGGL((k_lrn_gemm_fwd<HID>), dim3(gblocks), dim3(256), 0, st, net.H1.as<float>(), net.M1.as<float>(),
+                       wb + P_W2S, wb + P_W2N, w32 + P_B2, R, net.H2.as<float>());
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, mv, net.w.as<float>(),
+                       net.H2.as<float>(), LB, HID, net.M2.as<float>());
+    hipLaunchKernelGGL((k_lrn_gemm_fwd<HID>), dim3(gblocks), dim3(256), 0, st, net.H2.as<float>(), net.M2.as<float>(),
+                       wb + P_W3S, wb + P_W3N, w32 + P_B3, R, net.H3.as<float>());
+    GRF_LAUNCH_CHECK();
+    Heads hd{net.zd.as<float>(), net.gam.as<float>(), net.zt.as<float>(), net.zh.as<float>(), net.zr.as<float>(),
+             net.eta.as<float>(), net.Pd.as<double>(), net.Pq.as<double>(), net.Qd.as<double>(),
+             net.Qe.as<double>()};
+    if (RE > 0)
+        hipLaunchKernelGGL(k_lrn_ehead, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv, net.H3.as<float>(), wb,
+                           w32, LB, hd);
+    hipLaunchKernelGGL(k_lrn_vhead, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, net.H3.as<float>(), wb, w32,
+                       LB, hd);
+    GRF_LAUNCH_CHECK();
+}
+
+LearnedOps learned_ops(grf_learned &net) {
+    return LearnedOps{net.Dh.as<double>(), net.Pd.as<double>(), net.Pq.as<double>(), net.Qd.as<double>(),
+                      net.Qe.as<double>()};
+}
+
+// Loss and gradient (into net.grad) for systems S_l x = g, l < LB, S samples each:
+// g, x: device [LB][S][V].  Requires learned_forward on the same shifts.  Returns the loss.
+double learned_backward(grf_learned &net, const MeshView &mv, const double *g, const double *x, int32_t LB, int64_t S,
+                        hipStream_t st) {
+    const int64_t R = (int64_t)LB * mv.V, RE = (int64_t)LB * mv.E, NS = (int64_t)LB * S;
+    const int64_t nel = NS * mv.V;
+    net.eP.reserve(8 * nel + 8);
+    net.eQ.reserve(8 * nel + 8);
+    net.n2.reserve(8 * NS + 8);
+    net.lsys.reserve(8 * NS + 8);
+    net.gPd.reserve(8 * R + 8);
+    net.gQd.reserve(8 * R + 8);
+    net.gq.reserve(8 * RE + 8);
+    net.geta.reserve(8 * RE + 8);
+    net.dz.reserve(16 * RE + 16);
+    net.dzv.reserve(8 * R + 8);
+    for (DevBuf *b : {&net.dH, &net.dZ, &net.T0, &net.T1}) b->reserve(4 * R * HID + 4);
+    const int64_t CH = std::max<int64_t>(1, std::min<int64_t>(4096, (R + 255) / 256));
+    const int64_t CHE = std::max<int64_t>(1, std::min<int64_t>(4096, (RE + 255) / 256));
+    net.part.reserve(4 * (size_t)std::max(CH, CHE) * HID * HID + 4096);
+    const uint16_t *wb = net.wbf.as<uint16_t>();
+    float *grad = net.grad.as<float>();
+    Heads hd{net.zd.as<float>(), net.gam.as<float>(), net.zt.as<float>(), net.zh.as<float>(), net.zr.as<float>(),
+             net.eta.as<float>(), net.Pd.as<double>(), net.Pq.as<double>(), net.Qd.as<double>(),
+             net.Qe.as<double>()};
+    hipLaunchKernelGGL(k_lrn_resid, dim3((unsigned)blocks_for(nel)), dim3(256), 0, st, mv, net.Dh.as<double>(), g, x,
+                       LB, S, hd, net.eP.as<double>(), net.eQ.as<double>());
+    GRF_REQUIRE(NS < (int64_t(1) << 31), "too many training systems in one step");
+    hipLaunchKernelGGL(k_lrn_sysnorm, dim3((unsigned)NS), dim3(64), 0, st, mv, net.Dh.as<double>(), x,
+                       net.eP.as<double>(), net.eQ.as<double>(), S, net.n2.as<double>(), net.lsys.as<double>());
+    const double inv_ns = 1.0 / (double)NS;
+    hipLaunchKernelGGL(k_lrn_gdiag, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, net.Dh.as<double>(), g,
+                       net.eP.as<double>(), net.eQ.as<double>(), net.n2.as<double>(), LB, S, inv_ns,
+                       net.gPd.as<double>(), net.gQd.as<double>());
+    if (RE > 0) {
+        hipLaunchKernelGGL(k_lrn_gedge, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv, net.Dh.as<double>(), g,
+                           net.eP.as<double>(), net.eQ.as<double>(), net.n2.as<double>(), net.gPd.as<double>(),
+                           net.gQd.as<double>(), LB, S, inv_ns, net.gq.as<double>(), net.geta.as<double>());
+        hipLaunchKernelGGL(k_lrn_ehead_bwd, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv,
+                           net.gPd.as<double>(), net.gq.as<double>(), net.geta.as<double>(), LB, hd,
+                           net.dz.as<float>());
+    }
+    hipLaunchKernelGGL(k_lrn_vhead_bwd, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, net.gPd.as<double>(),
+                       net.gQd.as<double>(), net.dz.as<float>(), wb, LB, hd, net.dzv.as<float>(), net.dH.as<float>());
+    GRF_LAUNCH_CHECK();
+    float *part = net.part.as<float>();
+    // head parameters
+    {
+        const int64_t per = (R + CH - 1) / CH;
+        hipLaunchKernelGGL(k_lrn_vhead_wgrad, dim3((unsigned)CH), dim3(64), 0, st, net.H3.as<float>(),
+                           net.dzv.as<float>(), R, per, part);
+        // part[ch] = [a_d (64), c_d, a_g (64), c_g] matches the layout from P_AD
+        hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(2 * (HID + 1))), dim3(256), 0, st, part, CH,
+                           (int64_t)2 * (HID + 1), grad + P_AD, 0);
+    }
+    if (RE > 0) {
+        const int64_t per = (RE + CHE - 1) / CHE;
+        hipLaunchKernelGGL(k_lrn_ehead_wgrad, dim3((unsigned)CHE), dim3(64), 0, st, mv, net.H3.as<float>(),
+                           net.dz.as<float>(), LB, per, part);
+        // part[ch] = [a_p1 (64), c_p, a_p2 (64), 0, a_r (64), c_r, a_e (64), c_e]
+        // parameter layout from P_AP1: a_p1 (64), a_p2 (64), c_p, a_r (64), c_r, a_e (64), c_e
+        float *tmp = part + CHE * 4 * (HID + 1);
+        hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(4 * (HID + 1))), dim3(256), 0, st, part, CHE,
+                           (int64_t)4 * (HID + 1), tmp, 0);
+        GRF_LAUNCH_CHECK();
+        GRF_HIP(hipMemcpyAsync(grad + P_AP1, tmp, 4 * HID, hipMemcpyDeviceToDevice, st));
+        GRF_HIP(hipMemcpyAsync(grad + P_AP2, tmp + (HID + 1), 4 * HID, hipMemcpyDeviceToDevice, st));
+        GRF_HIP(hipMemcpyAsync(grad + P_CP, tmp + HID, 4, hipMemcpyDeviceToDevice, st));
+        GRF_HIP(hipMemcpyAsync(grad + P_AR, tmp + 2 * (HID + 1), 4 * (HID + 1), hipMemcpyDeviceToDevice, st));
+        GRF_HIP(hipMemcpyAsync(grad + P_AE, tmp + 3 * (HID + 1), 4 * (HID + 1), hipMemcpyDeviceToDevice, st));
+    } else {
+        std::vector<float> z(P_COUNT - P_AP1, 0.0f);
+        GRF_HIP(hipMemcpyAsync(grad + P_AP1, z.data(), 4 * z.size(), hipMemcpyHostToDevice, st));
+    }
+    // layers 3, 2, 1
+    const int64_t per = (R + CH - 1) / CH;
+    const unsigned gblocks = (unsigned)std::max<int64_t>(1, (R + 63) / 64);
+    float *dZ = net.dH.as<float>();  // dH of layer k, turned into dZ in place
+    struct Lay {
+        int ws, wn, b;
+        const float *Hin, *Min, *Hout;
+        int K;
+    };
+    const Lay lays[3] = {{P_W3S, P_W3N, P_B3, net.H2.as<float>(), net.M2.as<float>(), net.H3.as<float>(), HID},
+                         {P_W2S, P_W2N, P_B2, net.H1.as<float>(), net.M1.as<float>(), net.H2.as<float>(), HID},
+                         {P_W1S, P_W1N, P_B1, net.X0.as<float>(), net.M0.as<float>(), net.H1.as<float>(), F_IN}};
+    for (int li = 0; li < 3; ++li) {
+        const Lay &y = lays[li];
+        hipLaunchKernelGGL(k_lrn_relu_bwd, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, y.Hout, dZ,
+                           R * HID);
+        // dW_s, dW_n, db
+        if (y.K == HID) {
+            hipLaunchKernelGGL((k_lrn_gemm_wgrad<HID>), dim3((unsigned)CH), dim3(64), 0, st, dZ, y.Hin, R, per, part);
+            hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(HID * HID)), dim3(256), 0, st, part, CH,
+                               (int64_t)HID * HID, grad + y.ws, 0);
+            hipLaunchKernelGGL((k_lrn_gemm_wgrad<HID>), dim3((unsigned)CH), dim3(64), 0, st, dZ, y.Min, R, per, part);
+            hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(HID * HID)), dim3(256), 0, st, part, CH,
+                               (int64_t)HID * HID, grad + y.wn, 0);
+        } else {
+            hipLaunchKernelGGL((k_lrn_gemm_wgrad<F_IN>), dim3((unsigned)CH), dim3(64), 0, st, dZ, y.Hin, R, per, part);
+            hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(HID * F_IN)), dim3(256), 0, st, part, CH,
+                               (int64_t)HID * F_IN, grad + y.ws, 0);
+            hipLaunchKernelGGL((k_lrn_gemm_wgrad<F_IN>), dim3((unsigned)CH), dim3(64), 0, st, dZ, y.Min, R, per, part);
+            hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(HID * F_IN)), dim3(256), 0, st, part, CH,
+                               (int64_t)HID * F_IN, grad + y.wn, 0);
+        }
+        hipLaunchKernelGGL(k_lrn_colsum, dim3((unsigned)CH), dim3(64), 0, st, dZ, R, per, part);
+        hipLaunchKernelGGL(k_lrn_reduce, dim3(1), dim3(256), 0, st, part, CH, (int64_t)HID, grad + y.b, 0);
+        GRF_LAUNCH_CHECK();
+        if (li == 2) break;
+        // dH_in = dZ W_s + agg(dZ W_n)
+        float *T0 = net.T0.as<float>(), *T1 = net.T1.as<float>();
+        hipLaunchKernelGGL((k_lrn_gemm_bwd<HID>), dim3(gblocks), dim3(256), 0, st, dZ, wb + y.ws, R, T0);
+        hipLaunchKernelGGL((k_lrn_gemm_bwd<HID>), dim3(gblocks), dim3(256), 0, st, dZ, wb + y.wn, R, T1);
+        float *dHin = net.dZ.as<float>();
+        hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, mv, net.w.as<float>(), T1,
+                           LB, HID, dHin);
+        // dHin += T0
+        hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, T0, (int64_t)1,
+                           R * HID, dHin, 1);
+        GRF_LAUNCH_CHECK();
+        std::swap(net.dH.ptr, net.dZ.ptr);
+        std::swap(net.dH.bytes, net.dZ.bytes);
+        dZ = net.dH.as<float>();
+    }
+    // loss = mean of the per-system terms
+    std::vector<double> ls(NS);
+    GRF_HIP(hipMemcpyAsync(ls.data(), net.lsys.ptr, 8 * NS, hipMemcpyDeviceToHost, st));
+    GRF_HIP(hipStreamSynchronize(st));
+    double L = 0.0;
+    for (double v : ls) L += v;
+    return L / (double)NS;
+}
+
+void learned_adam(grf_learned &net, double lr, hipStream_t st) {
+    net.adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)net.adam_t), c2 = 1.0f - std::pow(b2, (float)net.adam_t);
+    hipLaunchKernelGGL(k_adam, dim3((P_COUNT + 255) / 256), dim3(256), 0, st, net.w32.as<float>(),
+                       net.grad.as<float>(), net.m1.as<float>(), net.m2.as<float>(), (int)P_COUNT, (float)lr, b1, b2,
+                       1e-8f, c1, c2);
+    hipLaunchKernelGGL(k_refresh_bf16, dim3((P_COUNT + 255) / 256), dim3(256), 0, st, net.w32.as<float>(),
+                       net.wbf.as<uint16_t>(), (int)P_COUNT);
+    GRF_LAUNCH_CHECK();
+}
+
+int64_t learned_param_count() { return P_COUNT; }
+
+}  // namespace grf
+
+using namespace grf;
+
+#define GRF_API_BEGIN try {
+#define GRF_API_END                                       \
+    }                                                     \
+    catch (const ::grf::Error &err) { return err.code; }  \
+    catch (const std::bad_alloc &) {                      \
+        ::grf::set_error("host allocation failed");        \
+        return GRF_ENOMEM;                                \
+    }                                                     \
+    catch (...) {                                         \
+        ::grf::set_error("unexpected internal error");     \
+        return GRF_EDEVICE;                               \
+    }                                                     \
+    return GRF_OK;
+
+extern "C" {
+
+int grf_learned_param_count(int64_t *n) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(n, "n is NULL");
+    *n = P_COUNT;
+    GRF_API_END
+}
+
+int grf_learned_create(const float *params, int64_t n_params, grf_learned **out) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    GRF_REQUIRE(params, "params is NULL");
+    GRF_REQUIRE(n_params == P_COUNT, "expected %d parameters, got %lld", (int)P_COUNT, (long long)n_params);
+    for (int64_t i = 0; i < n_params; ++i) GRF_REQUIRE(std::isfinite(params[i]), "parameter %lld is not finite", (long long)i);
+    grf_learned *net = new grf_learned();
+    try {
+        GRF_HIP(hipGetDevice(&net->device));
+        net->host.assign(params, params + n_params);
+        upload(net->w32, net->host, nullptr);
+        std::vector<uint16_t> b(P_COUNT);
+        for (int i = 0; i < P_COUNT; ++i) b[i] = is_bias(i) ? 0 : to_bf16(params[i]);
+        upload(net->wbf, b, nullptr);
+        std::vector<float> z(P_COUNT, 0.0f);
+        upload(net->m1, z, nullptr);
+        upload(net->m2, z, nullptr);
+        upload(net->grad, z, nullptr);
+        GRF_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        delete net;
+        throw;
+    }
+    *out = net;
+    GRF_API_END
+}
+
+int grf_learned_params(const grf_learned *net, float *out, int64_t n_params) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(net && out, "net/out is NULL");
+    GRF_REQUIRE(n_params == P_COUNT, "expected %d parameters", (int)P_COUNT);
+    GRF_HIP(hipMemcpy(out, net->w32.ptr, 4 * P_COUNT, hipMemcpyDeviceToHost));
+    GRF_API_END
+}
+
+int grf_learned_destroy(grf_learned *net) {
+    GRF_API_BEGIN
+    delete net;
+    GRF_API_END
+}
+
+}  // extern "C"

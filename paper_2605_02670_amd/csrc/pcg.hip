@@ -190,6 +190,154 @@ __global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restri
     }
 }
 
+// Same algorithm with the learned preconditioner and initial guess (global
+// memory, one workgroup per (graph, shift, sample) system):
+//   x0 = Dh Q_hat Dh g,  z = Dh P_hat Dh r  (Dh = D^{-1/2}),
+// P_hat SPD by construction.  If it has not converged after maxit/2
+// iterations the system restarts from its current iterate with the Jacobi
+// preconditioner (the fallback); the recomputed true residual decides
+// convergence either way.
+__device__ __forceinline__ double lrn_apply(const MeshView &mv, const double *__restrict__ dg,
+                                            const double *__restrict__ off, const double *__restrict__ dh,
+                                            const double *y, int u, int u0) {
+    // (Dh Op Dh y)_u, Op = diag(dg) + couplings off[e] between the two ends of e (no self-loops:
+    // a self-loop's coupling is inside dg)
+    double acc = dg[u] * dh[u] * y[u - u0];
+    for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
+        const int o = mv.adj_o[k];
+        if (o != u) acc += off[mv.adj_e[k]] * dh[o] * y[o - u0];
+    }
+    return dh[u] * acc;
+}
+
+__global__ void __launch_bounds__(256) k_pcg_learned(MeshView mv, const double *__restrict__ sd,
+                                                     const double *__restrict__ so, const double *__restrict__ gT,
+                                                     double *__restrict__ xT, double *__restrict__ scr,
+                                                     int32_t *__restrict__ its, double *__restrict__ res, int32_t LB,
+                                                     int64_t S, double tol, int32_t maxit, LearnedOps lo) {
+    __shared__ double red[64];
+    const int64_t E = mv.E;
+    const int nw = blockDim.x >> 6;
+    double *x = scr + (int64_t)blockIdx.x * 5 * mv.maxVg;
+    double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg, *jac = q + mv.maxVg;
+    const int64_t nsys = (int64_t)mv.ng * LB * S;
+    const int switch_at = max(1, maxit / 2);
+    for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
+        const int64_t tl = sys / S;
+        const int64_t smp = sys - tl * S;
+        const int l = (int)(tl % LB);
+        const int gi = (int)(tl / LB);
+        const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
+        const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
+        const double *sdl = sd + (int64_t)l * E;
+        const double *sol = so + (int64_t)l * E;
+        const double *dh = lo.Dh + (int64_t)l * mv.V;
+        const double *Pd = lo.Pd + (int64_t)l * mv.V, *Pq = lo.Pq + (int64_t)l * E;
+        const double *Qd = lo.Qd + (int64_t)l * mv.V, *Qe = lo.Qe + (int64_t)l * E;
+        // x0 = Dh Q Dh g  (g is read where it lives: shift its base to graph-local indexing)
+        double gg_[1] = {0.0};
+        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            const int u = u0 + v;
+            double d = 0.0;
+            for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
+                const int e = mv.adj_e[k];
+                d += sdl[e] + (mv.adj_o[k] == u ? sol[e] : 0.0);
+            }
+            jac[v] = d;
+            x[v] = lrn_apply(mv, Qd, Qe, dh, g, u, u0);
+            gg_[0] += g[v] * g[v];
+        }
+        block_sum<1>(gg_, red, nw);
+        const double gg = gg_[0];
+        const double tol2 = tol * tol * gg;
+        bool learned = true;
+        int it = 0;
+        double rel = 0.0;
+        auto restart = [&](double &rz_out, double &rr_out) {  // r = g - S x, z = M r, p = z
+            __syncthreads();  // x complete
+            double t[1] = {0.0};
+            for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                const double rv = g[v] - schur_apply(mv, sdl, sol, x, u0 + v, u0);
+                r[v] = rv;
+                t[0] += rv * rv;
+            }
+            block_sum<1>(t, red, nw);
+            rr_out = t[0];
+            double t2[1] = {0.0};
+            for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                const double zv = learned ? lrn_apply(mv, Pd, Pq, dh, r, u0 + v, u0) : r[v] / jac[v];
+                p[v] = zv;
+                t2[0] += r[v] * zv;
+            }
+            block_sum<1>(t2, red, nw);
+            rz_out = t2[0];
+        };
+        if (gg > 0.0) {
+            double rz, rr;
+            restart(rz, rr);
+            rel = sqrt(rr / gg);
+            if (rr > tol2) {
+                for (it = 1; it <= maxit; ++it) {
+                    if (learned && it == switch_at) {  // fallback: Jacobi from the current iterate
+                        learned = false;
+                        restart(rz, rr);
+                    }
+                    __syncthreads();  // p complete
+                    double t1[1] = {0.0};
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                        const double qv = schur_apply(mv, sdl, sol, p, u0 + v, u0);
+                        q[v] = qv;
+                        t1[0] += p[v] * qv;
+                    }
+                    block_sum<1>(t1, red, nw);
+                    const double alpha = rz / t1[0];
+                    double t3[1] = {0.0};
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                        x[v] += alpha * p[v];
+                        const double rv = r[v] - alpha * q[v];
+                        r[v] = rv;
+                        t3[0] += rv * rv;
+                    }
+                    block_sum<1>(t3, red, nw);
+                    double beta;
+                    double rz_new;
+                    if (t3[0] <= tol2) {
+                        double rzt, rrt;
+                        restart(rzt, rrt);  // true residual (and a fresh direction if it fails)
+                        rel = sqrt(rrt / gg);
+                        if (rrt <= tol2) break;
+                        rz = rzt;
+                        continue;
+                    }
+                    rel = sqrt(t3[0] / gg);
+                    __syncthreads();  // r complete (the preconditioner reads neighbours)
+                    double t4[1] = {0.0};
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                        const double zv = learned ? lrn_apply(mv, Pd, Pq, dh, r, u0 + v, u0) : r[v] / jac[v];
+                        q[v] = zv;  // q is free until the next product
+                        t4[0] += r[v] * zv;
+                    }
+                    block_sum<1>(t4, red, nw);
+                    rz_new = t4[0];
+                    beta = rz_new / rz;
+                    rz = rz_new;
+                    __syncthreads();
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) p[v] = q[v] + beta * p[v];
+                }
+                if (it > maxit) it = maxit + 1;
+            }
+        }
+        __syncthreads();
+        double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? x[v] : 0.0;
+        if (threadIdx.x == 0) {
+            its[sys] = it;
+            res[sys] = rel;
+        }
+        __syncthreads();
+    }
+}
+
 // Same algorithm with the vectors on chip, for graphs of at most TPB K
 // vertices of degree <= D, fewer than 2^16 vertices and edges, and (2 V + E)
 // doubles of LDS.  A workgroup takes a contiguous range of systems (mostly of
@@ -497,6 +645,14 @@ void prepare_pcg(const MeshView &mv) { (void)pcg_onchip(mv, nullptr, nullptr); }
 
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
+    if (a.learned) {
+        const int64_t nsys = (int64_t)mv.ng * a.LB * a.S;
+        const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
+        hipLaunchKernelGGL(k_pcg_learned, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr,
+                           a.its, a.res, a.LB, a.S, a.tol, a.maxit, *a.learned);
+        GRF_LAUNCH_CHECK();
+        return;
+    }
     if (!pcg_onchip(mv, &a, st)) pcg_global(mv, a, st);
 }
 

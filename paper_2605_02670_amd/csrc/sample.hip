@@ -146,6 +146,7 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     w.res.reserve(8 * (size_t)ps.ng * ps.L * S);
     w.pcg_scr.reserve(pcg_scratch_bytes(mv, ps.p.pcg_blocks));
     prepare_pcg(mv);
+    if (o.precond == GRF_PRECOND_LEARNED) learned_reserve(*const_cast<grf_learned *>(o.learned), mv, LBp);
     GRF_HIP(hipStreamSynchronize(st));  // uploads from host memory complete
     return ps;
 }
@@ -258,6 +259,15 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.tol = o.tol;
         sc.maxit = o.maxit;
         sc.pcg_blocks = p.pcg_blocks;
+        LearnedOps lops{};
+        if (o.precond == GRF_PRECOND_LEARNED) {
+            grf_learned &net = *const_cast<grf_learned *>(o.learned);
+            T.begin(GRF_K_LEARNED);
+            learned_forward(net, mv, ca.shift, ca.sd, ca.so, lb, st);
+            T.end();
+            lops = learned_ops(net);
+            sc.learned = &lops;
+        }
         T.begin(GRF_K_CONDENSE);
         launch_condense(mv, sc, st);
         T.end();
@@ -498,7 +508,6 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
     GRF_REQUIRE(out, "out is NULL");
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
-    GRF_REQUIRE(o.precond == GRF_PRECOND_JACOBI, "learned preconditioner is not available in this build");
     hipStream_t st = (hipStream_t)o.stream;
     set_kappa2(*g, kappa, st);
     grf_graph::Work &w = work(*g);
@@ -540,7 +549,6 @@ int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_
     GRF_REQUIRE(rhs != out, "rhs and out may not alias");
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
-    GRF_REQUIRE(o.precond == GRF_PRECOND_JACOBI, "learned preconditioner is not available in this build");
     hipStream_t st = (hipStream_t)o.stream;
     set_kappa2(*g, kappa, st);
     grf_graph::Work &w = work(*g);
@@ -643,7 +651,6 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     for (int32_t k = 0; k < n_graphs; ++k) GRF_REQUIRE(outs[k], "outs[%d] is NULL", k);
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
-    GRF_REQUIRE(o.precond == GRF_PRECOND_JACOBI, "learned preconditioner is not available in this build");
     hipStream_t st = (hipStream_t)o.stream;
     Batch &B = *get_batch(graphs, n_graphs);
     grf_graph &U = B.U;
@@ -761,6 +768,137 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     launch_from_interleaved_seg(mv, w.U.as<double>(), n_samples, B.d_outs.as<double *>(), st);
     GRF_HIP(hipStreamSynchronize(st));
     return code;
+    GRF_API_END
+}
+
+int grf_learned_loss_grad(grf_learned *net, grf_graph *g, double kappa, double c_I, double c_L, int64_t n_rhs,
+                          const double *rhs, const double *sol, double *loss, float *grad, const grf_opts *opts) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(net && g, "net/graph is NULL");
+    GRF_REQUIRE(std::isfinite(kappa) && kappa > 0, "kappa must be finite and > 0");
+    GRF_REQUIRE(std::isfinite(c_I) && c_I > 0 && std::isfinite(c_L) && c_L > 0, "c_I and c_L must be finite and > 0");
+    GRF_REQUIRE(n_rhs > 0 && rhs && sol && loss && grad, "need n_rhs > 0 and rhs, sol, loss, grad");
+    grf_opts o = resolve_opts(opts);
+    hipStream_t st = (hipStream_t)o.stream;
+    set_kappa2(*g, kappa, st);
+    grf_graph::Work &w = work(*g);
+    const MeshView mv = g->view();
+    std::vector<double> sh = {c_I, c_L};
+    upload(w.shift, sh, st);
+    w.babs.reserve(8 * (size_t)g->E + 8);
+    w.rhom.reserve(8 * (size_t)g->E + 8);
+    w.sd.reserve(8 * (size_t)g->E + 8);
+    w.so.reserve(8 * (size_t)g->E + 8);
+    CoeffArgs ca{};
+    ca.shift = w.shift.as<double>();
+    ca.LB = 1;
+    ca.LBp = 1;
+    ca.babs = w.babs.as<double>();
+    ca.rhom = w.rhom.as<double>();
+    ca.sd = w.sd.as<double>();
+    ca.so = w.so.as<double>();
+    launch_edge_coeff(mv, ca, st);
+    learned_reserve(*net, mv, 1);
+    learned_forward(*net, mv, ca.shift, ca.sd, ca.so, 1, st);
+    *loss = learned_backward(*net, mv, rhs, sol, 1, n_rhs, st);
+    learned_copy_grad(*net, grad, st);
+    GRF_API_END
+}
+
+int grf_learned_train(grf_learned *net, grf_graph *const *graphs, int32_t n_graphs, const double *kappas,
+                      double beta, double quad_step, int64_t n_samples, uint64_t seed, int32_t n_steps,
+                      int32_t shifts_per_step, double lr, double *losses, const grf_opts *opts) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(net && graphs && kappas && n_graphs > 0, "need a network, graphs and kappas");
+    GRF_REQUIRE(n_samples > 0 && n_steps >= 0 && shifts_per_step > 0, "need n_samples > 0, n_steps >= 0, "
+                "shifts_per_step > 0");
+    GRF_REQUIRE(std::isfinite(lr) && lr > 0, "lr must be > 0");
+    for (int32_t k = 0; k < n_graphs; ++k) {
+        GRF_REQUIRE(graphs[k], "graphs[%d] is NULL", k);
+        GRF_REQUIRE(std::isfinite(kappas[k]) && kappas[k] > 0, "kappas[%d] must be finite and > 0", k);
+    }
+    grf_opts o = resolve_opts(opts);
+    hipStream_t st = (hipStream_t)o.stream;
+    // training data: the method's own condensed right-hand sides and FP64 Jacobi-PCG solutions
+    grf_opts gen = o;
+    gen.precond = GRF_PRECOND_JACOBI;
+    gen.precision = GRF_PREC_FP64;
+    gen.stats = nullptr;
+    gen.sample_offset = 0;
+    struct Data {
+        Shifts sh;
+        DevBuf G, X;
+    };
+    std::vector<std::unique_ptr<Data>> data;
+    for (int32_t k = 0; k < n_graphs; ++k) {
+        grf_graph &g = *graphs[k];
+        auto d = std::make_unique<Data>();
+        d->sh = make_shifts(beta, quad_step, g.h, o);
+        const int32_t L = (int32_t)d->sh.cI.size();
+        const size_t per_shift = (size_t)n_samples * g.V;
+        d->G.reserve(8 * per_shift * L);
+        d->X.reserve(8 * per_shift * L);
+        set_kappa2(g, kappas[k], st);
+        grf_graph::Work &w = work(g);
+        const int64_t nb = (n_samples + 63) / 64;
+        w.X.reserve(8 * (size_t)nb * g.N * 64);
+        w.U.reserve(8 * (size_t)nb * g.N * 64);
+        const MeshView mv = g.view();
+        launch_noise(mv, n_samples, 0, seed + (uint64_t)k, w.X.as<double>(), st);
+        KTimer T(false, st);
+        for (int32_t l0 = 0; l0 < L; l0 += 64) {
+            const int32_t lb = std::min(64, L - l0);
+            std::vector<double> cI(d->sh.cI.begin() + l0, d->sh.cI.begin() + l0 + lb);
+            std::vector<double> cL(d->sh.cL.begin() + l0, d->sh.cL.begin() + l0 + lb);
+            gen.shift_block = lb;
+            run_shifts(g, cI, cL, n_samples, gen, st, nullptr, T);
+            GRF_HIP(hipMemcpyAsync(d->G.as<double>() + per_shift * l0, w.gT.ptr, 8 * per_shift * lb,
+                                   hipMemcpyDeviceToDevice, st));
+            GRF_HIP(hipMemcpyAsync(d->X.as<double>() + per_shift * l0, w.xT.ptr, 8 * per_shift * lb,
+                                   hipMemcpyDeviceToDevice, st));
+        }
+        GRF_HIP(hipStreamSynchronize(st));
+        data.push_back(std::move(d));
+    }
+    // Adam steps: graph t mod n_graphs, a window of consecutive shifts cycling through the schedule
+    for (int32_t t = 0; t < n_steps; ++t) {
+        const int32_t k = t % n_graphs;
+        grf_graph &g = *graphs[k];
+        Data &d = *data[k];
+        const int32_t L = (int32_t)d.sh.cI.size();
+        const int32_t lw = std::min(shifts_per_step, L);
+        const int32_t ws = (int32_t)(((int64_t)(t / n_graphs) * lw) % L);
+        const int32_t l1 = std::min(L, ws + lw), nl = l1 - ws;
+        set_kappa2(g, kappas[k], st);
+        grf_graph::Work &w = work(g);
+        const MeshView mv = g.view();
+        std::vector<double> sh(2 * (size_t)nl);
+        for (int32_t i = 0; i < nl; ++i) {
+            sh[2 * i] = d.sh.cI[ws + i];
+            sh[2 * i + 1] = d.sh.cL[ws + i];
+        }
+        upload(w.shift, sh, st);
+        w.babs.reserve(8 * (size_t)g.E * nl + 8);
+        w.rhom.reserve(8 * (size_t)g.E * nl + 8);
+        w.sd.reserve(8 * (size_t)g.E * nl + 8);
+        w.so.reserve(8 * (size_t)g.E * nl + 8);
+        CoeffArgs ca{};
+        ca.shift = w.shift.as<double>();
+        ca.LB = nl;
+        ca.LBp = nl;
+        ca.babs = w.babs.as<double>();
+        ca.rhom = w.rhom.as<double>();
+        ca.sd = w.sd.as<double>();
+        ca.so = w.so.as<double>();
+        launch_edge_coeff(mv, ca, st);
+        learned_reserve(*net, mv, nl);
+        learned_forward(*net, mv, ca.shift, ca.sd, ca.so, nl, st);
+        const size_t off = (size_t)ws * n_samples * g.V;
+        const double L_t = learned_backward(*net, mv, d.G.as<double>() + off, d.X.as<double>() + off, nl, n_samples, st);
+        learned_adam(*net, lr, st);
+        if (losses) losses[t] = L_t;
+    }
+    GRF_HIP(hipStreamSynchronize(st));
     GRF_API_END
 }
 

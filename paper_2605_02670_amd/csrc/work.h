@@ -103,6 +103,21 @@ void launch_axpy1(const double *X, double *Y, int64_t n, hipStream_t st);
 int64_t colnorm_chunks(int64_t N);
 void launch_colnorm2(const double *X, int64_t N, int32_t nb, double *P, hipStream_t st);
 
+// learned preconditioner (learned.hip): per shift of a block, D^{-1/2} [LB][V], the
+// scale-free preconditioner (diagonal [LB][V], edge couplings [LB][E]) and
+// initial-guess operator (same shapes)
+struct LearnedOps {
+    const double *Dh, *Pd, *Pq, *Qd, *Qe;
+};
+void learned_reserve(grf_learned &net, const MeshView &mv, int32_t LB);
+void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, const double *sd, const double *so,
+                     int32_t LB, hipStream_t st);
+LearnedOps learned_ops(grf_learned &net);
+double learned_backward(grf_learned &net, const MeshView &mv, const double *g, const double *x, int32_t LB, int64_t S,
+                        hipStream_t st);
+void learned_adam(grf_learned &net, double lr, hipStream_t st);
+void learned_copy_grad(grf_learned &net, float *host, hipStream_t st);
+
 // vertex Schur complement: condensed rhs, PCG, layout changes, accumulation
 struct SchurArgs {
     const double *X;      // [nb][N][64] noise (vertex part used)
@@ -119,7 +134,7 @@ struct SchurArgs {
     double tol;
     int32_t maxit;
     int32_t pcg_blocks;   // resident workgroups for the global-memory PCG
-    const float *learned_P;  // learned preconditioner operator (optional): [LB][V + 2E]... see learned.hip
+    const LearnedOps *learned;  // learned preconditioner and initial guess of this block, or null (Jacobi)
 };
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);

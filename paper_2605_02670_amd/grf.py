@@ -68,6 +68,15 @@ _SIGS = [
                                     C.c_void_p, C.POINTER(Opts)]),
     ("grf_sample_batched", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_int64,
                                      C.c_uint64, C.c_void_p, C.POINTER(Opts)]),
+    ("grf_learned_param_count", C.c_int, [C.POINTER(C.c_int64)]),
+    ("grf_learned_create", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]),
+    ("grf_learned_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    ("grf_learned_destroy", C.c_int, [C.c_void_p]),
+    ("grf_learned_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64,
+                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.POINTER(Opts)]),
+    ("grf_learned_train", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double,
+                                    C.c_int64, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
+                                    C.POINTER(Opts)]),
     ("grf_last_error", C.c_char_p, []),
 ]
 
@@ -119,6 +128,8 @@ def make_opts(tol=1e-12, maxit=10000, precision="fp64", precond="jacobi", k_minu
     o.sample_offset = sample_offset
     o.stream = C.c_void_p(_stream_handle(stream)) if stream is not False else None
     o.learned = C.c_void_p(learned.handle) if learned is not None else None
+    if learned is not None and precond == "jacobi":
+        o.precond = PRECOND["learned"]
     if stats is not None:
         o.stats = C.pointer(stats)
     return o
@@ -219,3 +230,58 @@ def sample_batched(graphs, kappas, beta: float, quad_step: float, n_samples: int
     o = make_opts(stats=st, **kw)
     _check(load().grf_sample_batched(harr, n, karr, beta, quad_step, n_samples, seed, oarr, C.byref(o)))
     return outs, st.as_dict()
+
+
+class Learned:
+    """The learned vertex preconditioner (network parameters on the device)."""
+
+    def __init__(self, params):
+        lib = load()
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        handle = C.c_void_p()
+        _check(lib.grf_learned_create(p.ctypes.data, p.size, C.byref(handle)))
+        self.handle = handle.value
+        self.n_params = p.size
+
+    @staticmethod
+    def param_count() -> int:
+        n = C.c_int64()
+        _check(load().grf_learned_param_count(C.byref(n)))
+        return n.value
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().grf_learned_params(self.handle, out.ctypes.data, out.size))
+        return out
+
+    def loss_grad(self, graph, kappa: float, c_I: float, c_L: float, rhs, sol, **kw):
+        """rhs, sol: device float64 tensors [n_rhs][V]; returns (loss, grad numpy float32)."""
+        loss = C.c_double()
+        grad = np.zeros(self.n_params, dtype=np.float32)
+        o = make_opts(**kw)
+        _check(load().grf_learned_loss_grad(self.handle, graph.handle, kappa, c_I, c_L, rhs.shape[0],
+                                            rhs.data_ptr(), sol.data_ptr(), C.byref(loss), grad.ctypes.data,
+                                            C.byref(o)))
+        return loss.value, grad
+
+    def train(self, graphs, kappas, beta: float, quad_step: float, n_samples: int, seed: int, n_steps: int,
+              shifts_per_step: int = 16, lr: float = 1e-3, **kw) -> np.ndarray:
+        n = len(graphs)
+        harr = (C.c_void_p * n)(*[g.handle for g in graphs])
+        karr = (C.c_double * n)(*[float(k) for k in kappas])
+        losses = np.zeros(max(1, n_steps), dtype=np.float64)
+        o = make_opts(**kw)
+        _check(load().grf_learned_train(self.handle, harr, n, karr, beta, quad_step, n_samples, seed, n_steps,
+                                        shifts_per_step, lr, losses.ctypes.data, C.byref(o)))
+        return losses[:n_steps]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().grf_learned_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
