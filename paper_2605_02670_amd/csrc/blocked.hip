@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                                                        int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
                                                        const double *__restrict__ tab, const double *__restrict__ X,
                                                        double *__restrict__ U, const double *__restrict__ rhom,
-                                                       double *__restrict__ ends, int32_t first) {
+                                                       double *__restrict__ ends, int32_t first, int64_t S) {
     constexpr int TS = 528 * NT + 256;  // doubles per buffer
     constexpr int N1 = 512 * NT;        // first contiguous range
     __shared__ double sbuf[2 * TS];
@@ -381,6 +381,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int b = (int)(wg - (int64_t)e * nb);
     const int g = 4 * b + wv;
     const int s0 = 16 * g;
+    const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
     const int side = FWD ? 1 : 0;
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int p = 4 * c + kq;
-        R[c] = (p < m) ? xb[inpos(p) * 64] : 0.0;
+        R[c] = (live && p < m) ? xb[inpos(p) * 64] : 0.0;
     }
     stage_store<double, TS>(stg, sbuf);
     __syncthreads();
@@ -431,11 +432,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 16 * (beta + 1) + 4 * c + kq;
-                if (p < m) Rn[c] = xb[inpos(p) * 64];
+                if (live && p < m) Rn[c] = xb[inpos(p) * 64];
             }
         }
         double uo[4] = {0.0, 0.0, 0.0, 0.0};
-        if (!store_only) {
+        if (!store_only && live) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int p = 16 * beta + 4 * r + kq;
@@ -443,35 +444,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                 if (p < m && op >= 0) uo[r] = ub[(int64_t)op * 64];
             }
         }
+        if (live) {
         const double *G = sb + (FWD ? 512 * NT : 528 * NT);
-        const double *H = sb + (FWD ? 0 : 256 * NT);
-        const double *C = sb + (FWD ? 256 * NT : 0);
-        const double *D = sb + (FWD ? 512 * NT + 256 : 512 * NT);
-        d4 F[4];
+            const double *H = sb + (FWD ? 0 : 256 * NT);
+            const double *C = sb + (FWD ? 256 * NT : 0);
+            const double *D = sb + (FWD ? 512 * NT + 256 : 512 * NT);
+            d4 F[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[c] = mfma(G[c * 64 + L], R[c], d4{0.0, 0.0, 0.0, 0.0});
-        if (beta > 0) {
+            for (int c = 0; c < 4; ++c) F[c] = mfma(G[c * 64 + L], R[c], d4{0.0, 0.0, 0.0, 0.0});
+            if (beta > 0) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) F[r] = mfma(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
+            }
+            // carry: Y <- d .* Y + C R
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) F[r] = mfma(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
-        }
-        // carry: Y <- d .* Y + C R
+                for (int r = 0; r < 4; ++r) Y[t][r] *= D[16 * t + 4 * r + kq];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Y[t][r] *= D[16 * t + 4 * r + kq];
+                for (int t = 0; t < NT; ++t) Y[t] = mfma(C[(t * 4 + c) * 64 + L], R[c], Y[t]);
+            // the block's output rows 4r + kq
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) Y[t] = mfma(C[(t * 4 + c) * 64 + L], R[c], Y[t]);
-        // the block's output rows 4r + kq
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int p = 16 * beta + 4 * r + kq;
-            const int op = outpos(p);
-            const double f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
-            if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + f;
+            for (int r = 0; r < 4; ++r) {
+                const int p = 16 * beta + 4 * r + kq;
+                const int op = outpos(p);
+                const double f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
+                if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + f;
+            }
         }
         if (more) stage_store<double, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
         __syncthreads();
@@ -485,7 +488,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int sh = 16 * t + 4 * r + kq;
-            if (sh < LB) endp[sh * endstride] = rm[sh] * Y[t][r];
+            if (live && sh < LB) endp[sh * endstride] = rm[sh] * Y[t][r];
         }
 }
 
@@ -501,7 +504,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                                                       int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
                                                       const double *__restrict__ ztab,
                                                       const double *__restrict__ babs,
-                                                      const double *__restrict__ ug, double *__restrict__ U) {
+                                                      const double *__restrict__ ug, double *__restrict__ U,
+                                                      int64_t S) {
     constexpr int TS = 512 * NT;
     __shared__ double sbuf[2 * TS];
     const int L = threadIdx.x & 63;
@@ -511,6 +515,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int b = (int)(wg - (int64_t)e * nb);
     const int g = 4 * b + wv;
     const int s0 = 16 * g;
+    const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
     if (m == 0) return;  // uniform over the workgroup
@@ -527,9 +532,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int r = 0; r < 4; ++r) {
             const int sh = 16 * t + 4 * r + kq;
             const int shc = min(sh, LB - 1);
-            const double bb = (sh < LB) ? babs[(int64_t)e * LBp + sh] : 0.0;
-            ct[t][r] = bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n];
-            ch[t][r] = bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n];
+            const double bb = (live && sh < LB) ? babs[(int64_t)e * LBp + sh] : 0.0;
+            ct[t][r] = live ? bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n] : 0.0;
+            ch[t][r] = live ? bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n] : 0.0;
         }
     stage_store<double, TS>(stg, sbuf);
     __syncthreads();
@@ -539,26 +544,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         const double *Z = sbuf + (beta & 1) * TS;
         const bool more = beta + 1 < nblk;
         if (more) stage_load<double, TS>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        if (live) {
         double uo[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pp = 16 * beta + 4 * r + kq;
-            uo[r] = (pp < m) ? ub[(int64_t)pp * 64] : 0.0;
-        }
-        d4 F[4];
+            for (int r = 0; r < 4; ++r) {
+                const int pp = 16 * beta + 4 * r + kq;
+                uo[r] = (pp < m) ? ub[(int64_t)pp * 64] : 0.0;
+            }
+            d4 F[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[c] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int c = 0; c < 4; ++c) F[c] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    F[r & 1] = mfma(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
+                    F[2 + (r & 1)] = mfma(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+                }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                F[r & 1] = mfma(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
-                F[2 + (r & 1)] = mfma(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+                const int pp = 16 * beta + 4 * r + kq;
+                if (pp < m) ub[(int64_t)pp * 64] = uo[r] + ((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
             }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pp = 16 * beta + 4 * r + kq;
-            if (pp < m) ub[(int64_t)pp * 64] = uo[r] + ((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
         }
         if (more) stage_store<double, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
         __syncthreads();
@@ -574,7 +581,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
                   int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
                   const float *__restrict__ tab, const double *__restrict__ X, double *__restrict__ U,
-                  const double *__restrict__ rhom, double *__restrict__ ends, int32_t first) {
+                  const double *__restrict__ rhom, double *__restrict__ ends, int32_t first, int64_t S) {
     constexpr int TS = 528 * NT + 256;  // floats per buffer
     constexpr int N1 = 512 * NT;
     __shared__ float sbuf[2 * TS];
@@ -585,6 +592,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
     const int b = (int)(wg - (int64_t)e * nb);
     const int g = 4 * b + wv;
     const int s0 = 16 * g;
+    const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
     const int side = FWD ? 1 : 0;
@@ -616,7 +624,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int p = 4 * c + kq;
-        R[c] = (p < m) ? (float)xb[inpos(p) * 64] : 0.0f;
+        R[c] = (live && p < m) ? (float)xb[inpos(p) * 64] : 0.0f;
     }
     stage_store<float, TS>(stg, sbuf);
     __syncthreads();
@@ -634,11 +642,11 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 16 * (beta + 1) + 4 * c + kq;
-                if (p < m) Rn[c] = (float)xb[inpos(p) * 64];
+                if (live && p < m) Rn[c] = (float)xb[inpos(p) * 64];
             }
         }
         double uo[4] = {0.0, 0.0, 0.0, 0.0};
-        if (!store_only) {
+        if (!store_only && live) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int p = 16 * beta + 4 * kq + r;
@@ -646,33 +654,35 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
                 if (p < m && op >= 0) uo[r] = ub[(int64_t)op * 64];
             }
         }
+        if (live) {
         const float *G = sb + (FWD ? 512 * NT : 528 * NT);
-        const float *H = sb + (FWD ? 0 : 256 * NT);
-        const float *C = sb + (FWD ? 256 * NT : 0);
-        const float *D = sb + (FWD ? 512 * NT + 256 : 512 * NT);
-        f4 F[4];
+            const float *H = sb + (FWD ? 0 : 256 * NT);
+            const float *C = sb + (FWD ? 256 * NT : 0);
+            const float *D = sb + (FWD ? 512 * NT + 256 : 512 * NT);
+            f4 F[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[c] = mfma32(G[c * 64 + L], R[c], f4{0.0f, 0.0f, 0.0f, 0.0f});
-        if (beta > 0) {
+            for (int c = 0; c < 4; ++c) F[c] = mfma32(G[c * 64 + L], R[c], f4{0.0f, 0.0f, 0.0f, 0.0f});
+            if (beta > 0) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) F[r] = mfma32(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
+            }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) F[r] = mfma32(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
-        }
+                for (int r = 0; r < 4; ++r) Y[t][r] *= D[16 * t + 4 * kq + r];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) Y[t][r] *= D[16 * t + 4 * kq + r];
+                for (int t = 0; t < NT; ++t) Y[t] = mfma32(C[(t * 4 + c) * 64 + L], R[c], Y[t]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) Y[t] = mfma32(C[(t * 4 + c) * 64 + L], R[c], Y[t]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int p = 16 * beta + 4 * kq + r;
-            const int op = outpos(p);
-            const float f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
-            if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + (double)f;
+            for (int r = 0; r < 4; ++r) {
+                const int p = 16 * beta + 4 * kq + r;
+                const int op = outpos(p);
+                const float f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
+                if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + (double)f;
+            }
         }
         if (more) stage_store<float, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
         __syncthreads();
@@ -685,7 +695,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int sh = 16 * t + 4 * kq + r;
-            if (sh < LB) endp[sh * endstride] = rm[sh] * (double)Y[t][r];
+            if (live && sh < LB) endp[sh * endstride] = rm[sh] * (double)Y[t][r];
         }
 }
 
@@ -694,7 +704,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ eu_,
                  const int32_t *__restrict__ ev_, const int32_t *__restrict__ boff, int32_t E, int32_t V, int64_t N,
                  int32_t nb, int32_t Sp, int32_t LB, int32_t LBp, const float *__restrict__ ztab,
-                 const double *__restrict__ babs, const double *__restrict__ ug, double *__restrict__ U) {
+                 const double *__restrict__ babs, const double *__restrict__ ug, double *__restrict__ U,
+                 int64_t S) {
     constexpr int TS = 512 * NT;
     __shared__ float sbuf[2 * TS];
     const int L = threadIdx.x & 63;
@@ -704,6 +715,7 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
     const int b = (int)(wg - (int64_t)e * nb);
     const int g = 4 * b + wv;
     const int s0 = 16 * g;
+    const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
     if (m == 0) return;
@@ -720,9 +732,9 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
         for (int r = 0; r < 4; ++r) {
             const int sh = 16 * t + 4 * kq + r;
             const int shc = min(sh, LB - 1);
-            const double bb = (sh < LB) ? babs[(int64_t)e * LBp + sh] : 0.0;
-            ct[t][r] = (float)(bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n]);
-            ch[t][r] = (float)(bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n]);
+            const double bb = (live && sh < LB) ? babs[(int64_t)e * LBp + sh] : 0.0;
+            ct[t][r] = live ? (float)(bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n]) : 0.0f;
+            ch[t][r] = live ? (float)(bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n]) : 0.0f;
         }
     stage_store<float, TS>(stg, sbuf);
     __syncthreads();
@@ -732,26 +744,28 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
         const float *Z = sbuf + (beta & 1) * TS;
         const bool more = beta + 1 < nblk;
         if (more) stage_load<float, TS>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        if (live) {
         double uo[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pp = 16 * beta + 4 * kq + r;
-            uo[r] = (pp < m) ? ub[(int64_t)pp * 64] : 0.0;
-        }
-        f4 F[4];
+            for (int r = 0; r < 4; ++r) {
+                const int pp = 16 * beta + 4 * kq + r;
+                uo[r] = (pp < m) ? ub[(int64_t)pp * 64] : 0.0;
+            }
+            f4 F[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) F[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int c = 0; c < 4; ++c) F[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    F[r & 1] = mfma32(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
+                    F[2 + (r & 1)] = mfma32(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+                }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                F[r & 1] = mfma32(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
-                F[2 + (r & 1)] = mfma32(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+                const int pp = 16 * beta + 4 * kq + r;
+                if (pp < m) ub[(int64_t)pp * 64] = uo[r] + (double)((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
             }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pp = 16 * beta + 4 * kq + r;
-            if (pp < m) ub[(int64_t)pp * 64] = uo[r] + (double)((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
         }
         if (more) stage_store<float, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
         __syncthreads();
@@ -764,19 +778,19 @@ void sweep_nt(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) 
     if (a.mixed) {
         if (fwd)
             hipLaunchKernelGGL((k_sweep_blocked32<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                               a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first);
+                               a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first, a.S);
         else
             hipLaunchKernelGGL((k_sweep_blocked32<NT, false>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E,
-                               mv.N, a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, 0);
+                               mv.N, a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, 0, a.S);
         GRF_LAUNCH_CHECK();
         return;
     }
     if (fwd)
         hipLaunchKernelGGL((k_sweep_blocked<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first);
+                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);
     else
         hipLaunchKernelGGL((k_sweep_blocked<NT, false>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, 0);
+                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, 0, a.S);
     GRF_LAUNCH_CHECK();
 }
 
@@ -785,12 +799,12 @@ void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
     if (a.mixed) {
         hipLaunchKernelGGL((k_corr_blocked32<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E,
-                           mv.V, mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug, a.U);
+                           mv.V, mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug, a.U, a.S);
         GRF_LAUNCH_CHECK();
         return;
     }
     hipLaunchKernelGGL((k_corr_blocked<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E, mv.V,
-                       mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U);
+                       mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U, a.S);
     GRF_LAUNCH_CHECK();
 }
 

@@ -85,6 +85,9 @@ struct MeshView {
     const int64_t *segs;
     int32_t maxVg, maxEg;  // largest graph of the batch (host-side dispatch)
     int64_t maxNg;
+    // first four edge ends of every vertex (column-major [4][V]: the other vertex, or the
+    // vertex itself past its degree) and the degree
+    const int32_t *ell, *deg;
 };
 
 }  // namespace grf
@@ -109,7 +112,7 @@ struct grf_graph {
     std::vector<int64_t> segs;
     int32_t max_deg = 0, maxVg = 0, maxEg = 0;
     int64_t maxNg = 0;
-    grf::DevBuf d_gv0, d_ge0, d_segs;
+    grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_deg;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;

@@ -192,6 +192,14 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     g.max_deg = 0;
     for (int64_t u = 0; u < g.V; ++u) g.max_deg = std::max<int32_t>(g.max_deg, (int32_t)(g.vptr[u + 1] - g.vptr[u]));
+    std::vector<int32_t> ell(4 * (size_t)g.V), deg(g.V);
+    for (int64_t u = 0; u < g.V; ++u) {
+        deg[u] = (int32_t)(g.vptr[u + 1] - g.vptr[u]);
+        for (int j = 0; j < 4; ++j)
+            ell[(size_t)j * g.V + u] = j < deg[u] ? g.adj_o[g.vptr[u] + j] : (int32_t)u;
+    }
+    upload(g.d_ell, ell, s);
+    upload(g.d_deg, deg, s);
     upload(g.d_gv0, g.gv0, s);
     upload(g.d_ge0, g.ge0, s);
     upload(g.d_segs, g.segs, s);
@@ -266,6 +274,8 @@ grf::MeshView grf_graph::view() const {
     v.maxVg = maxVg;
     v.maxEg = maxEg;
     v.maxNg = maxNg;
+    v.ell = d_ell.as<int32_t>();
+    v.deg = d_deg.as<int32_t>();
     return v;
 }
 

@@ -85,142 +85,128 @@ __device__ __forceinline__ double schur_apply(const MeshView &mv, const double *
     return acc;
 }
 
-// One workgroup per (graph, shift, sample) system, vectors in global scratch
-// (x, r, p, q, jac: 5 maxVg doubles per resident workgroup).  Systems are
-// numbered ((graph * LB) + shift) * S + sample; the vectors of system (g, l, s)
-// are the graph's vertex range of gT / xT[l][s].
-__global__ void __launch_bounds__(256) k_pcg(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so,
-                                             const double *__restrict__ gT, double *__restrict__ xT,
-                                             double *__restrict__ scr, int32_t *__restrict__ its,
-                                             double *__restrict__ res, int32_t LB, int64_t S, double tol,
-                                             int32_t maxit) {
-    __shared__ double red[64];
-    const int64_t E = mv.E;
-    const int nw = blockDim.x >> 6;
-    double *x = scr + (int64_t)blockIdx.x * 5 * mv.maxVg;
-    double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg, *jac = q + mv.maxVg;
-    const int64_t nsys = (int64_t)mv.ng * LB * S;
-    for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
-        const int64_t tl = sys / S;
-        const int64_t smp = sys - tl * S;
-        const int l = (int)(tl % LB);
-        const int gi = (int)(tl / LB);
-        const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
-        const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
-        const double *sdl = sd + (int64_t)l * E;
-        const double *sol = so + (int64_t)l * E;
-        double t2[2] = {0.0, 0.0};  // r.z, g.g
-        for (int v = threadIdx.x; v < V; v += blockDim.x) {
-            const int u = u0 + v;
-            double d = 0.0;
-            for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
-                const int e = mv.adj_e[k];
-                d += sdl[e] + (mv.adj_o[k] == u ? sol[e] : 0.0);
+// Vertex operators of a shift block in ELL-4 form, for the global-memory PCG:
+// (Op y)_u = diag[l][u] y_u + sum_{j<4} coef[l][j][u] y_{ell[j][u]} + sum over the
+// CSR slots k >= vptr[u] + 4 of ovf[l][k] y_{adj_o[k]}  (a self-loop's coupling is
+// in the diagonal; its slots carry 0).  S is the Schur complement; with the
+// learned preconditioner, P = Dh P_hat Dh and Q = Dh Q_hat Dh.
+struct EllOp {
+    double *diag, *coef, *ovf;  // [LB][V], [LB][4][V], [LB][2E]
+};
+
+__global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
+                          EllOp S, int32_t lrn, LearnedOps lo, EllOp P, EllOp Q) {
+    const int64_t n = (int64_t)LB * mv.V;
+    const int64_t E2 = 2 * (int64_t)mv.E;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), u = (int)(i - (int64_t)l * mv.V);
+        const double *sdl = sd + (int64_t)l * mv.E, *sol = so + (int64_t)l * mv.E;
+        const int64_t k0 = mv.vptr[u], k1 = mv.vptr[u + 1];
+        const double dhu = lrn ? lo.Dh[i] : 0.0;
+        double d = 0.0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const int e = mv.adj_e[k];
+            const int o = mv.adj_o[k];
+            d += sdl[e] + (o == u ? sol[e] : 0.0);
+            const double c = (o == u) ? 0.0 : sol[e];
+            const int j = (int)(k - k0);
+            double cp = 0.0, cq = 0.0;
+            if (lrn && o != u) {
+                const double dho = lo.Dh[(int64_t)l * mv.V + o];
+                cp = dhu * dho * lo.Pq[(int64_t)l * mv.E + e];
+                cq = dhu * dho * lo.Qe[(int64_t)l * mv.E + e];
             }
-            const double gv = g[v];
-            jac[v] = d;
-            x[v] = 0.0;
-            r[v] = gv;
-            const double z = gv / d;
-            p[v] = z;
-            t2[0] += gv * z;
-            t2[1] += gv * gv;
-        }
-        block_sum<2>(t2, red, nw);
-        double rz = t2[0];
-        const double gg = t2[1];
-        const double tol2 = tol * tol * gg;
-        int it = 0;
-        double rel = 0.0;
-        if (gg > 0.0) {
-            rel = 1.0;
-            for (it = 1; it <= maxit; ++it) {
-                __syncthreads();  // p complete
-                double t1[1] = {0.0};
-                for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                    const double qv = schur_apply(mv, sdl, sol, p, u0 + v, u0);
-                    q[v] = qv;
-                    t1[0] += p[v] * qv;
+            if (j < 4) {
+                S.coef[((int64_t)l * 4 + j) * mv.V + u] = c;
+                if (lrn) {
+                    P.coef[((int64_t)l * 4 + j) * mv.V + u] = cp;
+                    Q.coef[((int64_t)l * 4 + j) * mv.V + u] = cq;
                 }
-                block_sum<1>(t1, red, nw);
-                const double alpha = rz / t1[0];
-                double t3[2] = {0.0, 0.0};  // r.z, r.r
-                for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                    x[v] += alpha * p[v];
-                    const double rv = r[v] - alpha * q[v];
-                    r[v] = rv;
-                    t3[0] += rv * (rv / jac[v]);
-                    t3[1] += rv * rv;
+            } else {
+                S.ovf[(int64_t)l * E2 + k] = c;
+                if (lrn) {
+                    P.ovf[(int64_t)l * E2 + k] = cp;
+                    Q.ovf[(int64_t)l * E2 + k] = cq;
                 }
-                block_sum<2>(t3, red, nw);
-                double rz_new = t3[0];
-                double beta;
-                if (t3[1] <= tol2) {
-                    __syncthreads();  // x complete
-                    double tt[2] = {0.0, 0.0};  // true r.r, r.z
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                        const double rv = g[v] - schur_apply(mv, sdl, sol, x, u0 + v, u0);
-                        r[v] = rv;
-                        tt[0] += rv * rv;
-                        tt[1] += rv * (rv / jac[v]);
-                    }
-                    block_sum<2>(tt, red, nw);
-                    rel = sqrt(tt[0] / gg);
-                    if (tt[0] <= tol2) break;
-                    rz_new = tt[1];  // restart from the true residual
-                    beta = 0.0;
-                } else {
-                    rel = sqrt(t3[1] / gg);
-                    beta = rz_new / rz;
-                }
-                rz = rz_new;
-                __syncthreads();  // all reads of p (schur_apply on x aside) done
-                for (int v = threadIdx.x; v < V; v += blockDim.x) p[v] = r[v] / jac[v] + beta * p[v];
             }
-            if (it > maxit) it = maxit + 1;  // flags non-convergence
         }
-        __syncthreads();
-        double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
-        for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? x[v] : 0.0;
-        if (threadIdx.x == 0) {
-            its[sys] = it;
-            res[sys] = rel;
+        for (int j = (int)(k1 - k0); j < 4; ++j) {
+            S.coef[((int64_t)l * 4 + j) * mv.V + u] = 0.0;
+            if (lrn) {
+                P.coef[((int64_t)l * 4 + j) * mv.V + u] = 0.0;
+                Q.coef[((int64_t)l * 4 + j) * mv.V + u] = 0.0;
+            }
         }
-        __syncthreads();
+        S.diag[i] = d;
+        if (lrn) {
+            P.diag[i] = dhu * dhu * lo.Pd[i];
+            Q.diag[i] = dhu * dhu * lo.Qd[i];
+        }
     }
 }
 
-// Same algorithm with the learned preconditioner and initial guess (global
-// memory, one workgroup per (graph, shift, sample) system):
-//   x0 = Dh Q_hat Dh g,  z = Dh P_hat Dh r  (Dh = D^{-1/2}),
-// P_hat SPD by construction.  If it has not converged after maxit/2
-// iterations the system restarts from its current iterate with the Jacobi
-// preconditioner (the fallback); the recomputed true residual decides
-// convergence either way.
-__device__ __forceinline__ double lrn_apply(const MeshView &mv, const double *__restrict__ dg,
-                                            const double *__restrict__ off, const double *__restrict__ dh,
+// (Op y)_u for the graph-local vector y (vertex u = u0 + local index)
+__device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__restrict__ dg,
+                                            const double *__restrict__ cf, const double *__restrict__ of,
                                             const double *y, int u, int u0) {
-    // (Dh Op Dh y)_u, Op = diag(dg) + couplings off[e] between the two ends of e (no self-loops:
-    // a self-loop's coupling is inside dg)
-    double acc = dg[u] * dh[u] * y[u - u0];
-    for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
-        const int o = mv.adj_o[k];
-        if (o != u) acc += off[mv.adj_e[k]] * dh[o] * y[o - u0];
+    double acc = dg[u] * y[u - u0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc += cf[(int64_t)j * mv.V + u] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
+    const int d = mv.deg[u];
+    if (d > 4) {
+        const int64_t k0 = mv.vptr[u];
+        for (int64_t k = k0 + 4; k < k0 + d; ++k) acc += of[k] * y[mv.adj_o[k] - u0];
     }
-    return dh[u] * acc;
+    return acc;
 }
 
-__global__ void __launch_bounds__(256) k_pcg_learned(MeshView mv, const double *__restrict__ sd,
-                                                     const double *__restrict__ so, const double *__restrict__ gT,
-                                                     double *__restrict__ xT, double *__restrict__ scr,
-                                                     int32_t *__restrict__ its, double *__restrict__ res, int32_t LB,
-                                                     int64_t S, double tol, int32_t maxit, LearnedOps lo) {
+// (Op y) for the four graph-local vertices v0 + i * stride (i < 4) of this thread:
+// the ELL loads of all four are issued before any is consumed (indices past the
+// graph are clamped to its last vertex and their results ignored).
+__device__ __forceinline__ void ell_apply4(const MeshView &mv, const double *__restrict__ dg,
+                                           const double *__restrict__ cf, const double *__restrict__ of,
+                                           const double *y, int v0, int stride, int V, int u0, double (&out)[4]) {
+    int uu[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) uu[i] = u0 + min(v0 + i * stride, V - 1);
+    double acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = dg[uu[i]] * y[uu[i] - u0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc[i] += cf[(int64_t)j * mv.V + uu[i]] * y[mv.ell[(int64_t)j * mv.V + uu[i]] - u0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int d = mv.deg[uu[i]];
+        if (d > 4) {
+            const int64_t k0 = mv.vptr[uu[i]];
+            for (int64_t k = k0 + 4; k < k0 + d; ++k) acc[i] += of[k] * y[mv.adj_o[k] - u0];
+        }
+        out[i] = acc[i];
+    }
+}
+
+// One workgroup per (graph, shift, sample) system, vectors in global scratch
+// (x, r, p, q: 4 maxVg doubles per resident workgroup).  Systems are numbered
+// ((graph * LB) + shift) * S + sample; the vectors of system (g, l, s) are the
+// graph's vertex range of gT / xT[l][s].  LRN: the learned preconditioner
+// z = P r and initial guess x0 = Q g, with the Jacobi fallback after maxit / 2
+// iterations (restart from the current iterate); otherwise Jacobi from x0 = 0.
+// Either way the residual recomputed from x decides convergence.
+template <bool LRN>
+__global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
+                                                 const double *__restrict__ gT, double *__restrict__ xT,
+                                                 double *__restrict__ scr, int32_t *__restrict__ its,
+                                                 double *__restrict__ res, int32_t LB, int64_t S, double tol,
+                                                 int32_t maxit) {
     __shared__ double red[64];
-    const int64_t E = mv.E;
     const int nw = blockDim.x >> 6;
-    double *x = scr + (int64_t)blockIdx.x * 5 * mv.maxVg;
-    double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg, *jac = q + mv.maxVg;
+    double *x = scr + (int64_t)blockIdx.x * 4 * mv.maxVg;
+    double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg;
     const int64_t nsys = (int64_t)mv.ng * LB * S;
+    const int64_t E2 = 2 * (int64_t)mv.E;
     const int switch_at = max(1, maxit / 2);
     for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
         const int64_t tl = sys / S;
@@ -229,48 +215,50 @@ __global__ void __launch_bounds__(256) k_pcg_learned(MeshView mv, const double *
         const int gi = (int)(tl / LB);
         const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
         const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
-        const double *sdl = sd + (int64_t)l * E;
-        const double *sol = so + (int64_t)l * E;
-        const double *dh = lo.Dh + (int64_t)l * mv.V;
-        const double *Pd = lo.Pd + (int64_t)l * mv.V, *Pq = lo.Pq + (int64_t)l * E;
-        const double *Qd = lo.Qd + (int64_t)l * mv.V, *Qe = lo.Qe + (int64_t)l * E;
-        // x0 = Dh Q Dh g  (g is read where it lives: shift its base to graph-local indexing)
-        double gg_[1] = {0.0};
+        const double *Sd = Sop.diag + (int64_t)l * mv.V, *Sc = Sop.coef + (int64_t)l * 4 * mv.V,
+                     *So = Sop.ovf + (int64_t)l * E2;
+        const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
+        const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
+        const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
+        bool learned = LRN;
+        double t0[1] = {0.0};
         for (int v = threadIdx.x; v < V; v += blockDim.x) {
             const int u = u0 + v;
-            double d = 0.0;
-            for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
-                const int e = mv.adj_e[k];
-                d += sdl[e] + (mv.adj_o[k] == u ? sol[e] : 0.0);
-            }
-            jac[v] = d;
-            x[v] = lrn_apply(mv, Qd, Qe, dh, g, u, u0);
-            gg_[0] += g[v] * g[v];
+            x[v] = LRN ? ell_apply(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
+                                   Qop.ovf + (int64_t)l * E2, g, u, u0)
+                       : 0.0;
+            t0[0] += g[v] * g[v];
         }
-        block_sum<1>(gg_, red, nw);
-        const double gg = gg_[0];
+        block_sum<1>(t0, red, nw);
+        const double gg = t0[0];
         const double tol2 = tol * tol * gg;
-        bool learned = true;
         int it = 0;
         double rel = 0.0;
-        auto restart = [&](double &rz_out, double &rr_out) {  // r = g - S x, z = M r, p = z
+        // r = g - S x and z = M r into p; returns (r.z, r.r)
+        auto restart = [&](double &rz, double &rr) {
             __syncthreads();  // x complete
-            double t[1] = {0.0};
+            double t[2] = {0.0, 0.0};
             for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                const double rv = g[v] - schur_apply(mv, sdl, sol, x, u0 + v, u0);
+                const double rv = g[v] - ell_apply(mv, Sd, Sc, So, x, u0 + v, u0);
                 r[v] = rv;
-                t[0] += rv * rv;
+                t[1] += rv * rv;
+                if (!learned) {
+                    const double zv = rv / Sd[u0 + v];
+                    p[v] = zv;
+                    t[0] += rv * zv;
+                }
             }
-            block_sum<1>(t, red, nw);
-            rr_out = t[0];
-            double t2[1] = {0.0};
-            for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                const double zv = learned ? lrn_apply(mv, Pd, Pq, dh, r, u0 + v, u0) : r[v] / jac[v];
-                p[v] = zv;
-                t2[0] += r[v] * zv;
+            if (learned) {
+                __syncthreads();  // r complete
+                for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                    const double zv = ell_apply(mv, Pd, Pc, Po, r, u0 + v, u0);
+                    p[v] = zv;
+                    t[0] += r[v] * zv;
+                }
             }
-            block_sum<1>(t2, red, nw);
-            rz_out = t2[0];
+            block_sum<2>(t, red, nw);
+            rz = t[0];
+            rr = t[1];
         };
         if (gg > 0.0) {
             double rz, rr;
@@ -284,47 +272,64 @@ __global__ void __launch_bounds__(256) k_pcg_learned(MeshView mv, const double *
                     }
                     __syncthreads();  // p complete
                     double t1[1] = {0.0};
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                        const double qv = schur_apply(mv, sdl, sol, p, u0 + v, u0);
-                        q[v] = qv;
-                        t1[0] += p[v] * qv;
+                    for (int v0 = threadIdx.x; v0 < V; v0 += 4 * blockDim.x) {
+                        double qv[4];
+                        ell_apply4(mv, Sd, Sc, So, p, v0, blockDim.x, V, u0, qv);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int v = v0 + i * (int)blockDim.x;
+                            if (v < V) {
+                                q[v] = qv[i];
+                                t1[0] += p[v] * qv[i];
+                            }
+                        }
                     }
                     block_sum<1>(t1, red, nw);
                     const double alpha = rz / t1[0];
-                    double t3[1] = {0.0};
+                    double t3[2] = {0.0, 0.0};  // r.z (Jacobi), r.r
                     for (int v = threadIdx.x; v < V; v += blockDim.x) {
                         x[v] += alpha * p[v];
                         const double rv = r[v] - alpha * q[v];
                         r[v] = rv;
-                        t3[0] += rv * rv;
+                        t3[1] += rv * rv;
+                        if (!learned) t3[0] += rv * (rv / Sd[u0 + v]);
                     }
-                    block_sum<1>(t3, red, nw);
-                    double beta;
-                    double rz_new;
-                    if (t3[0] <= tol2) {
+                    block_sum<2>(t3, red, nw);
+                    if (t3[1] <= tol2) {
                         double rzt, rrt;
-                        restart(rzt, rrt);  // true residual (and a fresh direction if it fails)
+                        restart(rzt, rrt);  // true residual, and a fresh direction if it fails
                         rel = sqrt(rrt / gg);
                         if (rrt <= tol2) break;
                         rz = rzt;
                         continue;
                     }
-                    rel = sqrt(t3[0] / gg);
-                    __syncthreads();  // r complete (the preconditioner reads neighbours)
-                    double t4[1] = {0.0};
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                        const double zv = learned ? lrn_apply(mv, Pd, Pq, dh, r, u0 + v, u0) : r[v] / jac[v];
-                        q[v] = zv;  // q is free until the next product
-                        t4[0] += r[v] * zv;
+                    rel = sqrt(t3[1] / gg);
+                    double rz_new = t3[0];
+                    if (learned) {
+                        __syncthreads();  // r complete: the preconditioner reads neighbours
+                        double t4[1] = {0.0};
+                        for (int v0 = threadIdx.x; v0 < V; v0 += 4 * blockDim.x) {
+                            double zv[4];
+                            ell_apply4(mv, Pd, Pc, Po, r, v0, blockDim.x, V, u0, zv);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const int v = v0 + i * (int)blockDim.x;
+                                if (v < V) {
+                                    q[v] = zv[i];  // q is free until the next product
+                                    t4[0] += r[v] * zv[i];
+                                }
+                            }
+                        }
+                        block_sum<1>(t4, red, nw);
+                        rz_new = t4[0];
                     }
-                    block_sum<1>(t4, red, nw);
-                    rz_new = t4[0];
-                    beta = rz_new / rz;
+                    const double beta = rz_new / rz;
                     rz = rz_new;
-                    __syncthreads();
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) p[v] = q[v] + beta * p[v];
+                    __syncthreads();  // all reads of p and q done
+                    for (int v = threadIdx.x; v < V; v += blockDim.x)
+                        p[v] = (learned ? q[v] : r[v] / Sd[u0 + v]) + beta * p[v];
                 }
-                if (it > maxit) it = maxit + 1;
+                if (it > maxit) it = maxit + 1;  // flags non-convergence
             }
         }
         __syncthreads();
@@ -568,7 +573,11 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
 }  // namespace
 
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
-    return (size_t)blocks * 5 * mv.maxVg * sizeof(double);
+    return (size_t)blocks * 4 * mv.maxVg * sizeof(double);
+}
+
+size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, bool learned) {
+    return (learned ? 3 : 1) * (size_t)LB * (5 * (size_t)mv.V + 2 * (size_t)mv.E) * sizeof(double) + 64;
 }
 
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
@@ -634,10 +643,26 @@ static bool pcg_onchip(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
 }
 
 static void pcg_global(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    const bool lrn = a.learned != nullptr;
+    const size_t per = (size_t)a.LB * (5 * (size_t)mv.V + 2 * (size_t)mv.E);
+    EllOp ops[3];
+    for (int i = 0; i < 3; ++i) {
+        double *base = a.ops + (lrn ? i : 0) * per;
+        ops[i] = EllOp{base, base + (size_t)a.LB * mv.V, base + (size_t)a.LB * 5 * mv.V};
+    }
+    const LearnedOps lo = lrn ? *a.learned : LearnedOps{};
+    const int64_t n = (int64_t)a.LB * mv.V;
+    hipLaunchKernelGGL(k_ell_ops, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
+                       dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0], lrn ? 1 : 0, lo, ops[1], ops[2]);
+    GRF_LAUNCH_CHECK();
     const int64_t nsys = (int64_t)mv.ng * a.LB * a.S;
     const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
-    hipLaunchKernelGGL(k_pcg, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr, a.its,
-                       a.res, a.LB, a.S, a.tol, a.maxit);
+    if (lrn)
+        hipLaunchKernelGGL(k_pcg_ell<true>, dim3((unsigned)blocks), dim3(256), 0, st, mv, ops[0], ops[1], ops[2],
+                           a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+    else
+        hipLaunchKernelGGL(k_pcg_ell<false>, dim3((unsigned)blocks), dim3(256), 0, st, mv, ops[0], ops[1], ops[2],
+                           a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
 }
 
@@ -645,15 +670,7 @@ void prepare_pcg(const MeshView &mv) { (void)pcg_onchip(mv, nullptr, nullptr); }
 
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
-    if (a.learned) {
-        const int64_t nsys = (int64_t)mv.ng * a.LB * a.S;
-        const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
-        hipLaunchKernelGGL(k_pcg_learned, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.sd, a.so, a.gT, a.xT, a.scr,
-                           a.its, a.res, a.LB, a.S, a.tol, a.maxit, *a.learned);
-        GRF_LAUNCH_CHECK();
-        return;
-    }
-    if (!pcg_onchip(mv, &a, st)) pcg_global(mv, a, st);
+    if (a.learned || !pcg_onchip(mv, &a, st)) pcg_global(mv, a, st);
 }
 
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st) {

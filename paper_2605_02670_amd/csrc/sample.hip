@@ -70,8 +70,8 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     if (lb < L) lb = std::max<int64_t>(p.BL, (lb / p.BL) * p.BL);
     lb = std::max<int64_t>(1, std::min<int64_t>(lb, L));
     p.LB = (int32_t)lb;
-    const double vbytes = 40.0 * std::max<int32_t>(g.maxVg, 1);
-    int64_t blocks = (int64_t)std::min(2048.0, std::max(1.0, std::floor((2.0 * (1 << 30)) / vbytes)));
+    const double vbytes = 32.0 * std::max<int32_t>(g.maxVg, 1);  // 4 vectors per resident system
+    int64_t blocks = (int64_t)std::min(4096.0, std::max(1.0, std::floor((4.0 * (1 << 30)) / vbytes)));
     p.pcg_blocks = (int32_t)blocks;
     return p;
 }
@@ -145,6 +145,7 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     w.its.reserve(4 * (size_t)ps.ng * ps.L * S);
     w.res.reserve(8 * (size_t)ps.ng * ps.L * S);
     w.pcg_scr.reserve(pcg_scratch_bytes(mv, ps.p.pcg_blocks));
+    w.pcg_ops.reserve(pcg_ops_bytes(mv, lb, o.precond == GRF_PRECOND_LEARNED));
     prepare_pcg(mv);
     if (o.precond == GRF_PRECOND_LEARNED) learned_reserve(*const_cast<grf_learned *>(o.learned), mv, LBp);
     GRF_HIP(hipStreamSynchronize(st));  // uploads from host memory complete
@@ -218,6 +219,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
             ba.nb = nb;
             ba.Sp = Sp;
             ba.first = (l0 == 0) ? 1 : 0;
+            ba.S = S;
             ba.mixed = (o.precision == GRF_PREC_MIXED) ? 1 : 0;
             ba.tab32 = w.btab.as<float>();
             ba.ztab32 = w.ztab.as<float>();
@@ -249,6 +251,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.ug = w.ug.as<double>();
         sc.U = sa.U;
         sc.scr = w.pcg_scr.as<double>();
+        sc.ops = w.pcg_ops.as<double>();
         sc.its = w.its.as<int32_t>() + (size_t)ps.ng * l0 * S;  // [ng][lb][S] per shift block
         sc.res = w.res.as<double>() + (size_t)ps.ng * l0 * S;
         sc.LB = lb;

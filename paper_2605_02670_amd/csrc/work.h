@@ -17,6 +17,7 @@ struct grf_graph::Work {
     grf::DevBuf gT, xT;           // [LB][S][V]: condensed right-hand sides / vertex solutions
     grf::DevBuf ug;               // [LB][V][Sp]: vertex solutions, sample-interleaved
     grf::DevBuf pcg_scr;          // PCG vectors in global memory (large graphs)
+    grf::DevBuf pcg_ops;          // per-shift-block vertex operators of the global-memory PCG
     grf::DevBuf its, res;         // [LB][S] int32 iterations, double relative residual
     grf::DevBuf Bm, Xacc, nrm;    // mixed-precision refinement: right-hand sides, iterate, norm partials
     std::vector<int32_t> h_its;
@@ -88,6 +89,7 @@ struct BlockArgs {
     int32_t nb, Sp;
     int32_t first;          // first shift block: the forward pass writes (not updates) the interior accumulator
     int32_t mixed;          // FP32 operand tables and matrix-core products (mixed precision)
+    int64_t S;              // real samples (wavefronts of padding samples skip the products)
     float *tab32, *ztab32;  // the FP32 tables (same layout sizes as tab / ztab)
 };
 int64_t block_tab_doubles(int32_t NT);
@@ -127,6 +129,7 @@ struct SchurArgs {
     double *ug;           // [LB][V][Sp]
     double *U;            // [nb][N][64]
     double *scr;          // PCG scratch (large graphs)
+    double *ops;          // vertex operators of the block for the global-memory PCG (pcg_ops_bytes)
     int32_t *its;         // [LB][S]
     double *res;          // [LB][S]
     int32_t LB, LBp, nb, Sp;
@@ -141,5 +144,6 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void prepare_pcg(const MeshView &mv);  // one-time kernel attributes, before any graph capture
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);
+size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, bool learned);
 
 }  // namespace grf
