@@ -8,8 +8,14 @@ shift's condensed solve, accumulation and the output layout, with the inputs
 seconds per step.
 
 Prints one JSON line (rank 0).  Also reports the roofline of the dominant
-kernel (HIP-event durations recorded inside the timed steps) and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+kernel (HIP-event durations recorded inside the timed steps), the FP64 CPU
+oracle timed on a bounded sample of the same workload, and (unless
+--no-forms) the other forms of the method measured in the same run:
+  mixed            the same lattice with FP32 edge sweeps (error vs FP64 reported),
+  batched_plain    64 uneven graphs in one batched call, FP64, Jacobi PCG,
+  batched_learned  the same batch with the learned preconditioner (trained on
+                   the GPU in this run on small graphs of the same kinds) and
+                   mixed precision; its error vs batched_plain is reported.
 """
 
 from __future__ import annotations
@@ -74,10 +80,50 @@ def _traffic(dom: str, mode: str):
     return 1024.0 * (FETCH_FACTOR * fetch + WRITE_FACTOR * write)
 
 
-def bench_batched(args) -> int:
-    """64 uneven graphs (preferential-attachment trees and lattices, 100..20000
-    edges, h = 1/128), one kappa per graph, all 176 shifts x 32 samples in one
-    grf_sample_batched call (captured HIP graph replayed each step)."""
+def cpu_baseline(cfg, L: int, S: int, n_shift_sample: int = 3, n_samp: int = 4) -> dict:
+    """Time the FP64 oracle (numpy Philox noise, one sparse LU per shift) on a
+    bounded sample and extrapolate the whole job linearly:
+        t_job = S t_noise + L (t_factor + S t_rhs),
+    with t_factor and t_rhs fitted from solves with 1 and n_samp right-hand sides."""
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(cfg, L, S, n_shift_sample, n_samp)
+
+
+def _cpu_baseline(cfg, L: int, S: int, n_shift_sample: int, n_samp: int) -> dict:
+    import numpy as np
+
+    from oracle import mesh as omesh
+    from oracle import noise as onoise
+    from oracle import quadrature as oquad
+    from oracle import solve as osolve
+
+    g = cfg["graph"]
+    m = omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    ML = omesh.lumped_mass(m)
+    t0 = time.perf_counter()
+    W = onoise.white_noise(ML, cfg["seed"], n_samp)
+    t_noise = (time.perf_counter() - t0) / n_samp
+    _, cI, cL = oquad.shifts(cfg["beta"], cfg["quad_step"])
+    idx = np.linspace(0, len(cI) - 1, n_shift_sample).round().astype(int)
+    times = {}
+    for ns in (1, n_samp):
+        t0 = time.perf_counter()
+        for i in idx:
+            osolve.solve_shifted(m, cfg["kappa"], float(cI[i]), float(cL[i]), W[:ns])
+        times[ns] = (time.perf_counter() - t0) / n_shift_sample
+    t_rhs = max(0.0, (times[n_samp] - times[1]) / (n_samp - 1))
+    t_factor = max(0.0, times[1] - t_rhs)
+    t_job = S * t_noise + L * (t_factor + S * t_rhs)
+    return {"value": m.n_dof * L * S / t_job, "unit": "DOF-shift-solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (numpy Philox noise, scipy splu per shift, 1 thread) on the same graph: noise for "
+                      f"{n_samp} samples ({t_noise:.2f} s/sample) and {n_shift_sample} shifts solved with 1 and "
+                      f"{n_samp} right-hand sides (factor+assemble {t_factor:.2f} s/shift, {t_rhs:.3f} s/rhs); "
+                      f"whole job ({S} samples x {L} shifts) extrapolated as S*t_noise + L*(t_factor + S*t_rhs)"}
+
+
+def _batch_setup():
     import torch
 
     from paper_2605_02670_amd import grf
@@ -85,35 +131,94 @@ def bench_batched(args) -> int:
 
     cfg = config_c3()
     Gs = [grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"]) for g in cfg["graphs"]]
+    outs = [torch.empty((cfg["n_samples"], G.n_dof), dtype=torch.float64, device="cuda") for G in Gs]
+    return cfg, Gs, outs
+
+
+def run_batched(cfg, Gs, outs, steps: int, warmup: int, **kw) -> dict:
+    """Times grf_sample_batched over the 64-graph batch (the first call tunes and captures)."""
+    import torch
+
+    from paper_2605_02670_amd import grf
+
     S = cfg["n_samples"]
-    outs = [torch.empty((S, G.n_dof), dtype=torch.float64, device="cuda") for G in Gs]
-    kw = dict(tol=cfg["tol"], precision=args.precision, sweep_block=args.sweep_block, shift_block=args.shift_block)
     t0 = time.perf_counter()
-    _, st0 = grf.sample_batched(Gs, cfg["kappas"], cfg["beta"], 0.0, S, cfg["seed"], outs=outs, **kw)
+    grf.sample_batched(Gs, cfg["kappas"], cfg["beta"], 0.0, S, cfg["seed"], outs=outs, **kw)
     first = time.perf_counter() - t0
-    for _ in range(max(0, args.warmup - 1)):
+    for _ in range(max(0, warmup - 1)):
         grf.sample_batched(Gs, cfg["kappas"], cfg["beta"], 0.0, S, cfg["seed"], outs=outs, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = [grf.sample_batched(Gs, cfg["kappas"], cfg["beta"], 0.0, S, cfg["seed"], outs=outs, timing=True,
-                                **kw)[1] for _ in range(args.steps)]
+                                **kw)[1] for _ in range(steps)]
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     L = stats[0]["n_shifts"]
     ndof = sum(G.n_dof for G in Gs)
-    value = ndof * L * S / dt
+    return {"value": ndof * L * S / dt, "ms_per_step": dt * 1e3, "first_call_s": first, "n_dof": ndof,
+            "shifts": L, "samples": S, "graphs": len(Gs),
+            "pcg": {"max_iterations": max(s_["max_iterations"] for s_ in stats),
+                    "mean_iterations": stats[0]["total_iterations"] / max(1, stats[0]["n_systems"])}}
+
+
+def train_network(seed: int = 0):
+    """Trains the learned preconditioner on the GPU on small graphs of the batch's kinds
+    (preferential-attachment trees and lattices, 100..2000 edges, h = 1/128)."""
+    import numpy as np
+
+    from paper_2605_02670_amd import grf
+    from workloads import lattice, preferential_attachment
+    from workloads.learned_init import init_params
+
+    rng = np.random.default_rng(1000 + seed)
+    graphs, kappas = [], []
+    for i in range(8):
+        n_e = int(np.exp(rng.uniform(np.log(100), np.log(2000))))
+        if i % 2 == 0:
+            g = preferential_attachment(n_e + 1, 1, lengths=(0.1, 2.0), seed=int(rng.integers(1 << 30)))
+        else:
+            nx = max(2, int(round(np.sqrt(n_e / 2.0))))
+            g = lattice(nx, max(2, int(round(n_e / (2.0 * nx)))), lengths=(0.1, 2.0), seed=int(rng.integers(1 << 30)))
+        graphs.append(grf.Graph(g.n_vertices, g.edges, g.lengths, 1.0 / 128, "round"))
+        kappas.append(float(rng.uniform(2.0, 20.0)))
+    net = grf.Learned(init_params(seed))
+    t0 = time.perf_counter()
+    losses = net.train(graphs, kappas, 0.75, 0.0, n_samples=4, seed=seed + 11, n_steps=400, shifts_per_step=16,
+                       lr=2e-3)
+    return net, time.perf_counter() - t0, float(losses[:40].mean()), float(losses[-40:].mean())
+
+
+def _batch_rel_err(Gs, cfg, outs, ref):
+    """max over graphs and samples of ||u - ref||_{M_L} / ||ref||_{M_L}."""
+    import numpy as np
+
+    from oracle import mesh as omesh
+
+    worst = 0.0
+    for g, a, b in zip(cfg["graphs"], outs, ref):
+        ML = omesh.lumped_mass(omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"]))
+        d = (a - b).cpu().numpy()
+        r = b.cpu().numpy()
+        worst = max(worst, float(np.max(np.sqrt((d * d * ML).sum(1) / (r * r * ML).sum(1)))))
+    return worst
+
+
+def bench_batched(args) -> int:
+    """64 uneven graphs (preferential-attachment trees and lattices, 100..20000
+    edges, h = 1/128), one kappa per graph, all 176 shifts x 32 samples in one
+    grf_sample_batched call (captured HIP graph replayed each step)."""
+    cfg, Gs, outs = _batch_setup()
+    kw = dict(tol=cfg["tol"], precision=args.precision, sweep_block=args.sweep_block, shift_block=args.shift_block)
+    r = run_batched(cfg, Gs, outs, args.steps, args.warmup, **kw)
     line = {
-        "metric": METRIC, "value": value, "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": r["value"], "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"64 uneven graphs (trees + lattices, 100..20000 edges) h=1/128 beta=0.75 "
-                               f"S={S} batched-{args.precision}-jacobi",
-                   "n_dof": ndof, "shifts": L, "samples": S, "graphs": len(Gs), "parallelism": "1 GPU"},
-        "roofline": None, "cpu_baseline": None,
-        "first_call_s": first,
-        "graph_replay_ms": stats[0]["kernel_ms"]["ends_fwd"],
-        "pcg": {"max_iterations": max(s_["max_iterations"] for s_ in stats),
-                "mean_iterations": stats[0]["total_iterations"] / max(1, stats[0]["n_systems"])},
+                               f"S={r['samples']} batched-{args.precision}-jacobi",
+                   "n_dof": r["n_dof"], "shifts": r["shifts"], "samples": r["samples"], "graphs": r["graphs"],
+                   "parallelism": "1 GPU"},
+        "roofline": None, "cpu_baseline": None, "first_call_s": r["first_call_s"], "pcg": r["pcg"],
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -131,6 +236,7 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="mixed: FP32 edge sweeps, FP64 noise/Schur/PCG/accumulation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the mixed / batched / learned forms")
     ap.add_argument("--workload", choices=["lattice64", "batched64"], default="lattice64",
                     help="lattice64: one 64x64 lattice (default); batched64: 64 uneven graphs in one batched call")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -220,6 +326,38 @@ def main() -> int:
         check["rel_err_vs_fp64"] = float(np.max(np.sqrt((d * d * ML).sum(1) / (r * r * ML).sum(1))))
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, L, S)
+    forms = None
+    if not args.no_forms and args.precision == "fp64":
+        forms = {"plain": {"value": value, "ms_per_step": dt * 1e3}}
+        # mixed precision on the same lattice
+        kwm = dict(kw, precision="mixed")
+        outm = torch.empty_like(out)
+        for _ in range(args.warmup):
+            G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=outm, **kwm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=outm, **kwm)
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - t0) / args.steps
+        d = (outm - out).cpu().numpy()
+        r_ = out.cpu().numpy()
+        errm = float(np.max(np.sqrt((d * d * ML).sum(1) / (r_ * r_ * ML).sum(1))))
+        forms["mixed"] = {"value": G.n_dof * L * S / dtm, "ms_per_step": dtm * 1e3, "rel_err_vs_fp64": errm}
+        del outm
+        # the 64-graph batch: plain, then learned + mixed
+        bcfg, Gs, bouts = _batch_setup()
+        bsteps = max(1, min(args.steps, 2))
+        bp = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=bcfg["tol"])
+        forms["batched_plain"] = dict(bp, workload="64 uneven graphs (trees + lattices, 100..20000 edges) h=1/128 "
+                                                   "beta=0.75 S=32, FP64, Jacobi")
+        ref = [o.clone() for o in bouts]
+        net, t_train, l0, l1 = train_network()
+        bl = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=bcfg["tol"], learned=net, precision="mixed")
+        bl["rel_err_vs_batched_plain"] = _batch_rel_err(Gs, bcfg, bouts, ref)
+        bl["training"] = {"seconds": t_train, "steps": 400, "loss_first": l0, "loss_last": l1,
+                          "graphs": "8 trees/lattices, 100..2000 edges"}
+        forms["batched_learned"] = dict(bl, workload="same batch, learned preconditioner + FP32 edge sweeps")
     line = {
         "metric": METRIC, "value": value, "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -235,6 +373,7 @@ def main() -> int:
         "pcg": {"max_iterations": max(s["max_iterations"] for s in stats),
                 "mean_iterations": stats[0]["total_iterations"] / max(1, stats[0]["n_systems"])},
         "check": check,
+        "forms": forms,
     }
     print(json.dumps(line), flush=True)
     return 0
