@@ -209,13 +209,17 @@ def bench_batched(args) -> int:
     grf_sample_batched call (captured HIP graph replayed each step)."""
     cfg, Gs, outs = _batch_setup()
     kw = dict(tol=cfg["tol"], precision=args.precision, sweep_block=args.sweep_block, shift_block=args.shift_block)
+    net = None
+    if args.precond == "learned":
+        net = train_network()[0]
+        kw["learned"] = net
     r = run_batched(cfg, Gs, outs, args.steps, args.warmup, **kw)
     line = {
         "metric": METRIC, "value": r["value"], "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"64 uneven graphs (trees + lattices, 100..20000 edges) h=1/128 beta=0.75 "
-                               f"S={r['samples']} batched-{args.precision}-jacobi",
+                               f"S={r['samples']} batched-{args.precision}-{args.precond}",
                    "n_dof": r["n_dof"], "shifts": r["shifts"], "samples": r["samples"], "graphs": r["graphs"],
                    "parallelism": "1 GPU"},
         "roofline": None, "cpu_baseline": None, "first_call_s": r["first_call_s"], "pcg": r["pcg"],
@@ -235,6 +239,8 @@ def main() -> int:
     ap.add_argument("--shift-block", type=int, default=0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="mixed: FP32 edge sweeps, FP64 noise/Schur/PCG/accumulation")
+    ap.add_argument("--precond", choices=["jacobi", "learned"], default="jacobi",
+                    help="vertex PCG preconditioner of the batched64 workload (learned: trained first, on the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed / batched / learned forms")
     ap.add_argument("--workload", choices=["lattice64", "batched64"], default="lattice64",

@@ -62,6 +62,11 @@ void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 }
 
 // ---- mesh as seen by kernels (plain device pointers, passed by value) ------
+// vertex capacity of the on-chip PCG size classes (a graph goes to the first
+// class that holds it)
+constexpr int kPcgClasses = 6;
+constexpr int32_t kPcgCap[kPcgClasses] = {64, 256, 1024, 4096, 10176, 20352};
+
 struct MeshView {
     int32_t V, E;
     int32_t max_deg;      // largest vertex degree (edge ends)
@@ -88,6 +93,11 @@ struct MeshView {
     // first four edge ends of every vertex (column-major [4][V]: the other vertex, or the
     // vertex itself past its degree) and the degree
     const int32_t *ell, *deg;
+    // graphs ordered by PCG size class (kPcgCap), largest first within a class:
+    // class c is gord[cls_off[c] .. cls_off[c+1]-1]; class kPcgClasses holds the
+    // graphs too large for every on-chip class
+    const int32_t *gord;
+    int32_t cls_off[kPcgClasses + 2];
 };
 
 }  // namespace grf
@@ -113,6 +123,9 @@ struct grf_graph {
     int32_t max_deg = 0, maxVg = 0, maxEg = 0;
     int64_t maxNg = 0;
     grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_deg;
+    std::vector<int32_t> gord;
+    int32_t cls_off[grf::kPcgClasses + 2] = {};
+    grf::DevBuf d_gord;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;

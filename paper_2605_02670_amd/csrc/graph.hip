@@ -200,6 +200,26 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     upload(g.d_ell, ell, s);
     upload(g.d_deg, deg, s);
+    // PCG size classes, each ordered largest graph first
+    std::vector<int32_t> cls(ng);
+    for (int64_t k = 0; k < ng; ++k) {
+        const int32_t vk = g.gv0[k + 1] - g.gv0[k];
+        int c = 0;
+        while (c < kPcgClasses && vk > kPcgCap[c]) ++c;
+        cls[k] = c;
+    }
+    g.gord.resize(ng);
+    for (int64_t k = 0; k < ng; ++k) g.gord[k] = (int32_t)k;
+    std::stable_sort(g.gord.begin(), g.gord.end(), [&](int32_t a, int32_t b) {
+        if (cls[a] != cls[b]) return cls[a] < cls[b];
+        return g.gv0[a + 1] - g.gv0[a] > g.gv0[b + 1] - g.gv0[b];
+    });
+    for (int c = 0; c <= kPcgClasses + 1; ++c) {
+        int32_t n = 0;
+        for (int64_t k = 0; k < ng; ++k) n += cls[k] < c ? 1 : 0;
+        g.cls_off[c] = n;
+    }
+    upload(g.d_gord, g.gord, s);
     upload(g.d_gv0, g.gv0, s);
     upload(g.d_ge0, g.ge0, s);
     upload(g.d_segs, g.segs, s);
@@ -276,6 +296,8 @@ grf::MeshView grf_graph::view() const {
     v.maxNg = maxNg;
     v.ell = d_ell.as<int32_t>();
     v.deg = d_deg.as<int32_t>();
+    v.gord = d_gord.as<int32_t>();
+    for (int c = 0; c <= grf::kPcgClasses + 1; ++c) v.cls_off[c] = cls_off[c];
     return v;
 }
 

@@ -73,25 +73,14 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     }
 }
 
-// (S p)_u over the edge ends at vertex u; p holds the graph's vertices from u0
-__device__ __forceinline__ double schur_apply(const MeshView &mv, const double *__restrict__ sdl,
-                                              const double *__restrict__ sol, const double *p, int u, int u0) {
-    const double pv = p[u - u0];
-    double acc = 0.0;
-    for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
-        const int e = mv.adj_e[k];
-        acc += sdl[e] * pv + sol[e] * p[mv.adj_o[k] - u0];
-    }
-    return acc;
-}
-
 // Vertex operators of a shift block in ELL-4 form, for the global-memory PCG:
 // (Op y)_u = diag[l][u] y_u + sum_{j<4} coef[l][j][u] y_{ell[j][u]} + sum over the
 // CSR slots k >= vptr[u] + 4 of ovf[l][k] y_{adj_o[k]}  (a self-loop's coupling is
-// in the diagonal; its slots carry 0).  S is the Schur complement; with the
-// learned preconditioner, P = Dh P_hat Dh and Q = Dh Q_hat Dh.
+// in the diagonal; its slots carry 0).  S is the Schur complement (with jinv =
+// 1 / diag, the Jacobi preconditioner); with the learned preconditioner,
+// P = Dh P_hat Dh and Q = Dh Q_hat Dh.
 struct EllOp {
-    double *diag, *coef, *ovf;  // [LB][V], [LB][4][V], [LB][2E]
+    double *diag, *jinv, *coef, *ovf;  // [LB][V], [LB][V], [LB][4][V], [LB][2E]
 };
 
 __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
@@ -138,6 +127,7 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
             }
         }
         S.diag[i] = d;
+        S.jinv[i] = 1.0 / d;
         if (lrn) {
             P.diag[i] = dhu * dhu * lo.Pd[i];
             Q.diag[i] = dhu * dhu * lo.Qd[i];
@@ -188,15 +178,17 @@ __device__ __forceinline__ void ell_apply4(const MeshView &mv, const double *__r
     }
 }
 
-// One workgroup per (graph, shift, sample) system, vectors in global scratch
-// (x, r, p, q: 4 maxVg doubles per resident workgroup).  Systems are numbered
-// ((graph * LB) + shift) * S + sample; the vectors of system (g, l, s) are the
-// graph's vertex range of gT / xT[l][s].  LRN: the learned preconditioner
+// One workgroup per (graph, shift, sample) system of the graphs glist[0 .. ngl-1],
+// vectors in global scratch (x, r, p, q: 4 maxVg doubles per resident
+// workgroup), for graphs too large for the on-chip kernel.  The vectors of
+// system (g, l, s) are the graph's vertex range of gT / xT[l][s]; its
+// statistics go to its / res[(g * LB + l) * S + s].  LRN: the learned preconditioner
 // z = P r and initial guess x0 = Q g, with the Jacobi fallback after maxit / 2
 // iterations (restart from the current iterate); otherwise Jacobi from x0 = 0.
 // Either way the residual recomputed from x decides convergence.
 template <bool LRN>
 __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
+                                                 const int32_t *__restrict__ glist, int32_t ngl,
                                                  const double *__restrict__ gT, double *__restrict__ xT,
                                                  double *__restrict__ scr, int32_t *__restrict__ its,
                                                  double *__restrict__ res, int32_t LB, int64_t S, double tol,
@@ -205,18 +197,19 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
     const int nw = blockDim.x >> 6;
     double *x = scr + (int64_t)blockIdx.x * 4 * mv.maxVg;
     double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg;
-    const int64_t nsys = (int64_t)mv.ng * LB * S;
+    const int64_t nsys = (int64_t)ngl * LB * S;
     const int64_t E2 = 2 * (int64_t)mv.E;
     const int switch_at = max(1, maxit / 2);
-    for (int64_t sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
-        const int64_t tl = sys / S;
-        const int64_t smp = sys - tl * S;
+    for (int64_t lsys = blockIdx.x; lsys < nsys; lsys += gridDim.x) {
+        const int64_t tl = lsys / S;
+        const int64_t smp = lsys - tl * S;
         const int l = (int)(tl % LB);
-        const int gi = (int)(tl / LB);
+        const int gi = glist[tl / LB];
+        const int64_t sys = ((int64_t)gi * LB + l) * S + smp;
         const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
         const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
         const double *Sd = Sop.diag + (int64_t)l * mv.V, *Sc = Sop.coef + (int64_t)l * 4 * mv.V,
-                     *So = Sop.ovf + (int64_t)l * E2;
+                     *So = Sop.ovf + (int64_t)l * E2, *Sj = Sop.jinv + (int64_t)l * mv.V;
         const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
         const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
         const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
@@ -243,7 +236,7 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
                 r[v] = rv;
                 t[1] += rv * rv;
                 if (!learned) {
-                    const double zv = rv / Sd[u0 + v];
+                    const double zv = rv * Sj[u0 + v];
                     p[v] = zv;
                     t[0] += rv * zv;
                 }
@@ -292,7 +285,7 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
                         const double rv = r[v] - alpha * q[v];
                         r[v] = rv;
                         t3[1] += rv * rv;
-                        if (!learned) t3[0] += rv * (rv / Sd[u0 + v]);
+                        if (!learned) t3[0] += rv * (rv * Sj[u0 + v]);
                     }
                     block_sum<2>(t3, red, nw);
                     if (t3[1] <= tol2) {
@@ -327,7 +320,7 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
                     rz = rz_new;
                     __syncthreads();  // all reads of p and q done
                     for (int v = threadIdx.x; v < V; v += blockDim.x)
-                        p[v] = (learned ? q[v] : r[v] / Sd[u0 + v]) + beta * p[v];
+                        p[v] = (learned ? q[v] : r[v] * Sj[u0 + v]) + beta * p[v];
                 }
                 if (it > maxit) it = maxit + 1;  // flags non-convergence
             }
@@ -343,194 +336,383 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
     }
 }
 
-// Same algorithm with the vectors on chip, for graphs of at most TPB K
-// vertices of degree <= D, fewer than 2^16 vertices and edges, and (2 V + E)
-// doubles of LDS.  A workgroup takes a contiguous range of systems (mostly of
-// one graph and shift).  LDS holds p, x and the shift's edge coefficients s_o
-// of the graph (reloaded when the shift or the graph changes); each thread
-// keeps, for its K vertices, the graph-local (neighbour, edge) pairs in CSR
-// order packed in 16-bit halves, the Schur diagonal, the Jacobi inverse, r and
-// q = S p in registers.  Only g is read and x written in HBM.
-template <int K, int TPB, int D>
-__global__ void __launch_bounds__(TPB) k_pcg_lds(MeshView mv, const double *__restrict__ sd,
-                                                 const double *__restrict__ so, const double *__restrict__ gT,
-                                                 double *__restrict__ xT, int32_t *__restrict__ its,
-                                                 double *__restrict__ res, int32_t LB, int64_t S, double tol,
-                                                 int32_t maxit) {
-    extern __shared__ double sv[];  // p [maxVg], x [maxVg], s_o [maxEg]
+// Sum of NV <= 2 values over a workgroup of TPB threads, every thread getting
+// the result (combined in a fixed order: deterministic).  Two LDS buffers taken
+// in turn: a buffer is written again only two sums later, after every thread
+// has passed the barrier of the sum in between, so each sum needs one barrier.
+// A single wavefront sums with shuffles alone.
+template <int TPB>
+struct GroupSum {
+    double *lds;  // [2][2][16]
+    int buf;
+    template <int NV>
+    __device__ __forceinline__ void operator()(double (&v)[NV]) {
+        static_assert(NV <= 2, "two values per sum");
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+        if constexpr (TPB > 64) {
+            // every block of NW lanes takes the NW wavefront partials (lane w
+            // of a block: wavefront w's), then a butterfly within the block:
+            // every lane ends with the same total, two registers per value
+            constexpr int NW = TPB / 64;
+            double *r = lds + buf * 32;
+            const int lane = threadIdx.x & 63;
+            if (lane == 0)
+#pragma unroll
+                for (int i = 0; i < NV; ++i) r[i * 16 + (threadIdx.x >> 6)] = v[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                double t = r[i * 16 + (lane & (NW - 1))];
+#pragma unroll
+                for (int o = NW / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+                v[i] = t;
+            }
+            buf ^= 1;
+        }
+    }
+};
+
+#ifndef GRF_PCG_GROUP
+#define GRF_PCG_GROUP 1
+#endif
+#ifndef GRF_PCG_OPAQUE_K
+#define GRF_PCG_OPAQUE_K 4
+#endif
+
+// A group of G items of this thread: graph-local vertices t + TPB i (i0 <= i <
+// i0 + G).  The items of a group are processed without control flow between
+// them (indices past the graph are clamped to its last vertex for the loads,
+// their results masked and their stores skipped), so that their loads are in
+// flight together.  With K >= 8 items per thread the index is made opaque, so
+// that the compiler reads the operator rows again in every iteration (from L2)
+// instead of holding K rows in registers, which would spill.
+template <int TPB, int K, int G>
+struct ItemGroup {
+    int v[G], vc[G];
+    bool ok[G];
+    __device__ __forceinline__ ItemGroup(int i0, int nv) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            int t = (int)threadIdx.x + TPB * (i0 + g);
+            if constexpr (K >= GRF_PCG_OPAQUE_K) asm volatile("" : "+v"(t));
+            v[g] = t;
+            ok[g] = t < nv;
+            vc[g] = min(t, nv - 1);
+        }
+    }
+};
+
+// Whether the wavefront owns any vertex of item group i0 (uniform over the
+// wavefront: a scalar branch skips the groups past the graph).
+template <int TPB>
+__device__ __forceinline__ bool group_live(int i0, int nv) {
+    const int w0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+    return w0 + TPB * i0 < nv;
+}
+
+// (Op y) at the G items of a group (y graph-local; 0 at masked items).  The
+// CSR slots past the first four (vertices of degree > 4) are summed after the
+// ELL part of every item of the group has been issued.
+template <int G>
+__device__ __forceinline__ void ell_group(const MeshView &mv, const double *__restrict__ dg,
+                                          const double *__restrict__ cf, const double *__restrict__ of,
+                                          const double *y, const int (&vc)[G], const bool (&ok)[G], int u0,
+                                          double (&out)[G]) {
+    double acc[G];
+    int dd[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int u = u0 + vc[g];
+        dd[g] = mv.deg[u];
+        acc[g] = dg[u] * y[vc[g]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g] += cf[(int64_t)j * mv.V + u] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (dd[g] > 4) {
+            const int64_t k0 = mv.vptr[u0 + vc[g]];
+            for (int64_t k = k0 + 4; k < k0 + dd[g]; ++k) acc[g] += of[k] * y[mv.adj_o[k] - u0];
+        }
+        out[g] = ok[g] ? acc[g] : 0.0;
+    }
+}
+
+// The same PCG with the search direction p in LDS, for the graphs glist[0 ..
+// ngl-1] of at most cap <= TPB K vertices: one workgroup per (graph, shift,
+// sample) system, thread t owning the graph-local vertices t + TPB i (i < K),
+// whose r and q = S p (and x unless XG) stay in registers.  XG keeps x in its
+// output row of xT instead (the large classes, where K doubles fewer registers
+// decide whether the kernel spills).  LRN: the learned preconditioner reads the
+// neighbours' residuals, so r is also kept in LDS (2 cap doubles).  The
+// operator rows (EllOp) are read from global memory; the workgroups of one
+// (graph, shift) are sent to one XCD (block b goes to XCD b mod 8), so its L2
+// serves the rows to all of that shift's samples.  Three barriers per Jacobi
+// iteration (four with the learned preconditioner).
+template <int TPB, int K, bool LRN, bool XG>
+__global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
+                                                  const int32_t *__restrict__ glist, int32_t ngl, int32_t cap,
+                                                  const double *__restrict__ gT, double *__restrict__ xT,
+                                                  int32_t *__restrict__ its, double *__restrict__ res, int32_t LB,
+                                                  int64_t S, double tol, int32_t maxit) {
+    constexpr int G = K >= GRF_PCG_OPAQUE_K ? GRF_PCG_GROUP : K;
+    static_assert(K % G == 0, "items per thread: a multiple of the group size");
+    using IG = ItemGroup<TPB, K, G>;
+    extern __shared__ double sv[];  // p [cap], r [cap] (LRN)
     __shared__ double red[64];
-    const int E = mv.E;
-    double *ps = sv, *xs = sv + mv.maxVg, *sos = sv + 2 * mv.maxVg;
-    const int nw = blockDim.x >> 6;
-    const int64_t nsys = (int64_t)mv.ng * LB * S;
-    const int64_t per = (nsys + gridDim.x - 1) / gridDim.x;
-    const int64_t sys0 = (int64_t)blockIdx.x * per;
-    const int64_t sys1 = min(nsys, sys0 + per);
-    uint32_t nbr[K][D];  // local other vertex | local edge << 16
-    int nd[K];
-    double ds[K], ji[K];
-    int gcur = -1, lcur = -1, u0 = 0, V = 0, e0 = 0, Eg = 0;
-    for (int64_t sys = sys0; sys < sys1; ++sys) {
-        const int64_t tl = sys / S;
-        const int64_t smp = sys - tl * S;
-        const int l = (int)(tl % LB);
-        const int gi = (int)(tl / LB);
-        if (gi != gcur) {  // uniform over the workgroup: the graph's adjacency, local ids
-            gcur = gi;
-            lcur = -1;
-            u0 = mv.gv0[gi];
-            V = mv.gv0[gi + 1] - u0;
-            e0 = mv.ge0[gi];
-            Eg = mv.ge0[gi + 1] - e0;
+    // block -> (group = (graph, shift), sample): the S blocks of a group share b mod 8
+    const int64_t b = blockIdx.x;
+    const int64_t grp = (b / (8 * S)) * 8 + (b & 7);
+    const int64_t smp = (b % (8 * S)) >> 3;
+    if (grp >= (int64_t)ngl * LB) return;  // padding group (whole workgroup)
+    const int c = (int)(grp / LB), l = (int)(grp - (int64_t)c * LB);
+    const int gi = glist[c];
+    const int u0 = mv.gv0[gi], nv = mv.gv0[gi + 1] - u0;
+    const int64_t E2 = 2 * (int64_t)mv.E;
+    const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
+    double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
+    const double *Sd = Sop.diag + (int64_t)l * mv.V, *Sc = Sop.coef + (int64_t)l * 4 * mv.V,
+                 *So = Sop.ovf + (int64_t)l * E2, *Sj = Sop.jinv + (int64_t)l * mv.V + u0;
+    const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
+    const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
+    const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
+    double *ps = sv, *rs = sv + cap;
+    GroupSum<TPB> gsum{red, 0};
+    double x[XG ? 1 : K], r[K], q[K];
+
+    // r = g - S x, z = M r (M = P if lz, else Jacobi) and p = z; returns (r.z, r.r).
+    // Every earlier read of p and r in LDS is behind the barrier of an earlier sum.
+    auto restart = [&](bool lz, double &rz, double &rr) {
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int v = threadIdx.x + TPB * i;
-                nd[i] = 0;
+        for (int i0 = 0; i0 < K; i0 += G) {
+            if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
 #pragma unroll
-                for (int d = 0; d < D; ++d) nbr[i][d] = 0;
-                if (v < V) {
-                    const int k0 = (int)mv.vptr[u0 + v], k1 = (int)mv.vptr[u0 + v + 1];
-                    nd[i] = k1 - k0;
+            for (int e = 0; e < G; ++e) {
+                double xv;
+                if constexpr (XG)
+                    xv = xo[it.vc[e]];
+                else
+                    xv = x[i0 + e];
+                if (it.ok[e]) ps[it.v[e]] = xv;
+            }
+        }
+        __syncthreads();  // x in LDS
+        double t[2] = {0.0, 0.0};
 #pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        if (k0 + d < k1)
-                            nbr[i][d] = (uint32_t)(mv.adj_o[k0 + d] - u0) | ((uint32_t)(mv.adj_e[k0 + d] - e0) << 16);
+        for (int i0 = 0; i0 < K; i0 += G) {
+            if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+            double sx[G];
+            ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, sx);
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const double rv = it.ok[e] ? g[it.vc[e]] - sx[e] : 0.0;
+                r[i0 + e] = rv;
+                t[1] += rv * rv;
+                if (!lz) {
+                    q[i0 + e] = rv * Sj[it.vc[e]];
+                    t[0] += rv * q[i0 + e];
                 }
             }
         }
-        if (l != lcur) {  // uniform over the workgroup
-            lcur = l;
-            __syncthreads();  // previous coefficients no longer read
-            const double *sdl = sd + (int64_t)l * E + e0;
-            const double *sol = so + (int64_t)l * E + e0;
-            for (int e = threadIdx.x; e < Eg; e += TPB) sos[e] = sol[e];
+        if (LRN && lz) {
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int v = threadIdx.x + TPB * i;
-                double dsum = 0.0, dj = 0.0;
+            for (int i0 = 0; i0 < K; i0 += G) {
+                if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    if (d < nd[i]) {
-                        const int e = (int)(nbr[i][d] >> 16), o = (int)(nbr[i][d] & 0xffff);
-                        dsum += sdl[e];
-                        dj += (o == v) ? sol[e] : 0.0;
-                    }
+                for (int e = 0; e < G; ++e)
+                    if (it.ok[e]) rs[it.v[e]] = r[i0 + e];
+            }
+            __syncthreads();  // r in LDS
+#pragma unroll
+            for (int i0 = 0; i0 < K; i0 += G) {
+                if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+                double z[G];
+                ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, z);
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    q[i0 + e] = z[e];
+                    t[0] += r[i0 + e] * z[e];
                 }
-                ds[i] = dsum;
-                ji[i] = (v < V) ? 1.0 / (dsum + dj) : 0.0;
-            }
-            __syncthreads();  // s_o in LDS
-        }
-        // (S y)_v, y = sv[yo ..] in LDS, summed in CSR order.  The packed ids are
-        // decoded at each use (the empty asm keeps the compiler from hoisting the
-        // decoded ids and their LDS addresses out of the loop into registers).
-        auto apply = [&](int yo, int i, int v) -> double {
-            double acc = ds[i] * sv[yo + v];
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                uint32_t pk = nbr[i][d];
-                asm volatile("" : "+v"(pk));
-                if (d < nd[i]) acc += sos[pk >> 16] * sv[yo + (int)(pk & 0xffff)];
-            }
-            return acc;
-        };
-        const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
-        double r[K], q[K];
-        double t2[2] = {0.0, 0.0};
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int v = threadIdx.x + TPB * i;
-            r[i] = 0.0;
-            q[i] = 0.0;
-            if (v < V) {
-                const double gv = g[v];
-                r[i] = gv;
-                const double z = gv * ji[i];
-                ps[v] = z;
-                xs[v] = 0.0;
-                t2[0] += gv * z;
-                t2[1] += gv * gv;
             }
         }
-        block_sum<2>(t2, red, nw);
-        double rz = t2[0];
-        const double gg = t2[1];
-        const double tol2 = tol * tol * gg;
-        int it = 0;
-        double rel = 0.0;
-        if (gg > 0.0) {
-            rel = 1.0;
-            for (it = 1; it <= maxit; ++it) {
-                __syncthreads();  // p complete
-                double t1[1] = {0.0};
+        gsum(t);  // also: every read of x in LDS done
 #pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    const int v = threadIdx.x + TPB * i;
-                    if (v < V) {
-                        q[i] = apply(0, i, v);
-                        t1[0] += ps[v] * q[i];
-                    }
-                }
-                block_sum<1>(t1, red, nw);
-                const double alpha = rz / t1[0];
-                double t3[2] = {0.0, 0.0};
+        for (int i0 = 0; i0 < K; i0 += G) {
+            if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
 #pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    const int v = threadIdx.x + TPB * i;
-                    if (v < V) {
-                        xs[v] += alpha * ps[v];
-                        r[i] -= alpha * q[i];
-                        t3[0] += r[i] * r[i] * ji[i];
-                        t3[1] += r[i] * r[i];
-                    }
-                }
-                block_sum<2>(t3, red, nw);
-                double rz_new = t3[0];
-                double beta;
-                if (t3[1] <= tol2) {
-                    __syncthreads();  // x complete
-                    double tt[2] = {0.0, 0.0};
+            for (int e = 0; e < G; ++e)
+                if (it.ok[e]) ps[it.v[e]] = q[i0 + e];
+        }
+        rz = t[0];
+        rr = t[1];
+    };
+
+    // ||g||^2; Jacobi: x0 = 0, r = g, p = J g; learned: x0 = Q g
+    double rz, rr, gg;
+    {
+        double t[2] = {0.0, 0.0};
 #pragma unroll
-                    for (int i = 0; i < K; ++i) {
-                        const int v = threadIdx.x + TPB * i;
-                        if (v < V) {
-                            const double rv = g[v] - apply(mv.maxVg, i, v);
-                            r[i] = rv;
-                            tt[0] += rv * rv;
-                            tt[1] += rv * rv * ji[i];
-                        }
+        for (int i0 = 0; i0 < K; i0 += G) {
+            if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+            double xq[G];
+            if constexpr (LRN)
+                ell_group<G>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
+                             Qop.ovf + (int64_t)l * E2, g, it.vc, it.ok, u0, xq);
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const int i = i0 + e;
+                const double gv = it.ok[e] ? g[it.vc[e]] : 0.0;
+                t[1] += gv * gv;
+                q[i] = 0.0;
+                if constexpr (LRN) {
+                    r[i] = 0.0;
+                    if constexpr (XG) {
+                        if (it.ok[e]) xo[it.v[e]] = xq[e];
+                    } else {
+                        x[i] = xq[e];
                     }
-                    block_sum<2>(tt, red, nw);
-                    rel = sqrt(tt[0] / gg);
-                    if (tt[0] <= tol2) break;
-                    rz_new = tt[1];
-                    beta = 0.0;
                 } else {
-                    rel = sqrt(t3[1] / gg);
-                    beta = rz_new / rz;
-                }
-                rz = rz_new;
-                __syncthreads();  // every read of p done
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    const int v = threadIdx.x + TPB * i;
-                    if (v < V) ps[v] = r[i] * ji[i] + beta * ps[v];
+                    r[i] = gv;
+                    const double z = gv * Sj[it.vc[e]];
+                    t[0] += gv * z;
+                    if (it.ok[e]) ps[it.v[e]] = z;
+                    if constexpr (XG) {
+                        if (it.ok[e]) xo[it.v[e]] = 0.0;
+                    } else {
+                        x[i] = 0.0;
+                    }
                 }
             }
-            if (it > maxit) it = maxit + 1;
         }
-        __syncthreads();  // x complete
-        double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
+        gsum(t);
+        rz = t[0];
+        gg = t[1];
+        rr = gg;
+    }
+    const double tol2 = tol * tol * gg;
+    int it_n = 0;
+    double rel = 1.0;
+    bool lz = LRN;      // the learned preconditioner is in use
+    bool fresh = LRN;   // r, z and p are to be recomputed from x
+    const int switch_at = max(1, maxit / 2);
+    if (gg > 0.0) {
+        for (;;) {
+            if (fresh) {  // the only convergence test: the residual recomputed from x
+                restart(lz, rz, rr);
+                fresh = false;
+                rel = sqrt(rr / gg);
+                if (rr <= tol2) break;
+            }
+            if (it_n == maxit) {  // flags non-convergence
+                it_n = maxit + 1;
+                break;
+            }
+            if (LRN && lz && it_n + 1 == switch_at) {  // fallback: Jacobi from the current iterate
+                lz = false;
+                fresh = true;
+                continue;
+            }
+            ++it_n;
+            __syncthreads();  // p complete
+            double t1[1] = {0.0};
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int v = threadIdx.x + TPB * i;
-            if (v < V) xo[v] = (gg > 0.0) ? xs[v] : 0.0;
+            for (int i0 = 0; i0 < K; i0 += G) {
+                if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+                double sp[G];
+                ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, sp);
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    q[i0 + e] = sp[e];
+                    t1[0] += ps[it.vc[e]] * sp[e];
+                }
+            }
+            gsum(t1);
+            const double alpha = rz / t1[0];
+            double t3[2] = {0.0, 0.0};  // r.z (Jacobi), r.r
+#pragma unroll
+            for (int i0 = 0; i0 < K; i0 += G) {
+                if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    const int i = i0 + e;
+                    const double pv = ps[it.vc[e]];
+                    const double sj = Sj[it.vc[e]];
+                    if constexpr (XG) {
+                        const double xv = xo[it.vc[e]];
+                        if (it.ok[e]) xo[it.v[e]] = xv + alpha * pv;
+                    } else {
+                        x[i] += alpha * pv;
+                    }
+                    r[i] -= alpha * q[i];  // 0 at masked items
+                    t3[1] += r[i] * r[i];
+                    if (!lz) t3[0] += r[i] * (r[i] * sj);
+                    if (LRN && lz && it.ok[e]) rs[it.v[e]] = r[i];
+                }
+            }
+            gsum(t3);
+            if (t3[1] <= tol2) {  // verify with the true residual (and restart if it fails)
+                fresh = true;
+                continue;
+            }
+            rel = sqrt(t3[1] / gg);
+            double rz_new = t3[0];
+            if (LRN && lz) {
+                double t4[1] = {0.0};
+#pragma unroll
+                for (int i0 = 0; i0 < K; i0 += G) {
+                    if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+                    double z[G];
+                    ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, z);
+#pragma unroll
+                    for (int e = 0; e < G; ++e) {
+                        q[i0 + e] = z[e];
+                        t4[0] += r[i0 + e] * z[e];
+                    }
+                }
+                gsum(t4);
+                rz_new = t4[0];
+            }
+            const double beta = rz_new / rz;
+            rz = rz_new;
+#pragma unroll
+            for (int i0 = 0; i0 < K; i0 += G) {
+                if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    const double z = (LRN && lz) ? q[i0 + e] : r[i0 + e] * Sj[it.vc[e]];
+                    const double pn = z + beta * ps[it.vc[e]];
+                    if (it.ok[e]) ps[it.v[e]] = pn;
+                }
+            }
         }
-        if (threadIdx.x == 0) {
-            its[sys] = it;
-            res[sys] = rel;
+    } else {
+        rel = 0.0;
+    }
+    if constexpr (!XG) {
+#pragma unroll
+        for (int i0 = 0; i0 < K; i0 += G) {
+            if (!group_live<TPB>(i0, nv)) continue;
+            const IG it(i0, nv);
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                if (it.ok[e]) xo[it.v[e]] = x[i0 + e];
         }
-        __syncthreads();  // LDS reused by the next system
+    }
+    if (threadIdx.x == 0) {
+        const int64_t sys = ((int64_t)gi * LB + l) * S + smp;
+        its[sys] = it_n;
+        res[sys] = rel;
     }
 }
 
@@ -576,8 +758,13 @@ size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
     return (size_t)blocks * 4 * mv.maxVg * sizeof(double);
 }
 
+// diag, jinv, coef [4], ovf of each shift, for S (and P, Q with the learned preconditioner)
+static size_t ell_op_doubles(const MeshView &mv, int32_t LB) {
+    return (size_t)LB * (6 * (size_t)mv.V + 2 * (size_t)mv.E);
+}
+
 size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, bool learned) {
-    return (learned ? 3 : 1) * (size_t)LB * (5 * (size_t)mv.V + 2 * (size_t)mv.E) * sizeof(double) + 64;
+    return (learned ? 3 : 1) * ell_op_doubles(mv, LB) * sizeof(double) + 64;
 }
 
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
@@ -588,89 +775,88 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
-constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+// launch shape of the on-chip size classes: TPB threads, K vertices per thread
+// (TPB K >= kPcgCap[c]); the learned variant keeps two vectors in LDS and runs
+// on classes 0 .. kChipLearned - 1 only
+constexpr int kChipTpb[kPcgClasses] = {64, 64, 256, 512, 1024, 1024};
+constexpr int kChipK[kPcgClasses] = {1, 4, 4, 8, 10, 20};
+constexpr int kChipLearned = 5;
 
-// Dynamic LDS needed by the on-chip kernel for this mesh, 0 if it does not fit.
-size_t pcg_lds_bytes(const MeshView &mv) {
-    const size_t lds = sizeof(double) * (2 * (size_t)mv.maxVg + (size_t)mv.maxEg);
-    return lds > kMaxLds - 1024 ? 0 : lds;
-}
+static size_t chip_lds(int c, bool lrn) { return (size_t)kPcgCap[c] * sizeof(double) * (lrn ? 2 : 1); }
 
-// Grants the on-chip kernel variant its dynamic LDS (before any graph capture:
-// the attribute call is not a stream operation).  Returns false if refused.
-template <int K, int TPB, int D>
-bool pcg_lds_attr(size_t lds) {
-    static size_t granted = 0;  // largest dynamic LDS size granted so far
-    if (lds <= granted) return true;
-    if (hipFuncSetAttribute((const void *)k_pcg_lds<K, TPB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
+template <int C, bool LRN>
+static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st) {
+    constexpr int TPB = kChipTpb[C], K = kChipK[C];
+    static_assert(TPB * K >= kPcgCap[C], "class capacity");
+    constexpr bool XG = K >= 10;
+    const size_t lds = chip_lds(C, LRN);
+    if (!a) {  // preparation: the dynamic LDS of the variant (not a stream operation)
+        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        return;
     }
-    granted = lds;
-    return true;
-}
-
-template <int K, int TPB, int D>
-static bool pcg_lds_d(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
-    const size_t lds = pcg_lds_bytes(mv);
-    if (lds == 0 || !pcg_lds_attr<K, TPB, D>(lds)) return false;
-    if (!a) return true;  // preparation only
-    const int64_t nsys = (int64_t)mv.ng * a->LB * a->S;
-    const int64_t blocks = std::min<int64_t>(nsys, 256 * (2048 / TPB));
-    hipLaunchKernelGGL((k_pcg_lds<K, TPB, D>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, a->sd, a->so, a->gT,
-                       a->xT, a->its, a->res, a->LB, a->S, a->tol, a->maxit);
+    const int32_t n = mv.cls_off[C + 1] - mv.cls_off[C];
+    if (n == 0) return;
+    const int64_t groups = (int64_t)n * a->LB;
+    const int64_t blocks = (groups + 7) / 8 * 8 * a->S;
+    GRF_REQUIRE(blocks < ((int64_t)1 << 31), "too many systems in one shift block");
+    hipLaunchKernelGGL((k_pcg_chip<TPB, K, LRN, XG>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, ops[0], ops[1],
+                       ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], a->gT, a->xT, a->its, a->res, a->LB, a->S,
+                       a->tol, a->maxit);
     GRF_LAUNCH_CHECK();
-    return true;
 }
 
-template <int K, int TPB>
-static bool pcg_lds(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
-    if (mv.max_deg <= 4) return pcg_lds_d<K, TPB, 4>(mv, a, st);
-    return pcg_lds_d<K, TPB, 8>(mv, a, st);
+template <bool LRN>
+static void chip_all(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st) {
+    chip_class<0, LRN>(mv, a, ops, st);
+    chip_class<1, LRN>(mv, a, ops, st);
+    chip_class<2, LRN>(mv, a, ops, st);
+    chip_class<3, LRN>(mv, a, ops, st);
+    chip_class<4, LRN>(mv, a, ops, st);
+    if constexpr (!LRN) chip_class<5, LRN>(mv, a, ops, st);
 }
 
-// the on-chip variant for this mesh (a = null: only grant its LDS); false if none applies
-static bool pcg_onchip(const MeshView &mv, const SchurArgs *a, hipStream_t st) {
-    // every neighbour of a vertex in registers, 16-bit graph-local vertex and edge ids
-    if (!(mv.max_deg <= 8 && mv.maxVg < 65536 && mv.maxEg < 65536)) return false;
-    if (mv.maxVg <= 256) return pcg_lds<1, 256>(mv, a, st);
-    if (mv.maxVg <= 512) return pcg_lds<2, 256>(mv, a, st);
-    if (mv.maxVg <= 1024) return pcg_lds<2, 512>(mv, a, st);
-    if (mv.maxVg <= 2048) return pcg_lds<2, 1024>(mv, a, st);
-    if (mv.maxVg <= 4096) return pcg_lds<4, 1024>(mv, a, st);
-    return false;
+void prepare_pcg(const MeshView &mv) {
+    static bool done = false;  // the attributes hold for the process (every device)
+    if (done) return;
+    chip_all<false>(mv, nullptr, nullptr, nullptr);
+    chip_all<true>(mv, nullptr, nullptr, nullptr);
+    done = true;
 }
 
-static void pcg_global(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
+    if (a.LB == 0 || a.S == 0) return;
     const bool lrn = a.learned != nullptr;
-    const size_t per = (size_t)a.LB * (5 * (size_t)mv.V + 2 * (size_t)mv.E);
+    const size_t per = ell_op_doubles(mv, a.LB);
     EllOp ops[3];
     for (int i = 0; i < 3; ++i) {
         double *base = a.ops + (lrn ? i : 0) * per;
-        ops[i] = EllOp{base, base + (size_t)a.LB * mv.V, base + (size_t)a.LB * 5 * mv.V};
+        ops[i] = EllOp{base, base + (size_t)a.LB * mv.V, base + 2 * (size_t)a.LB * mv.V,
+                       base + 6 * (size_t)a.LB * mv.V};
     }
     const LearnedOps lo = lrn ? *a.learned : LearnedOps{};
     const int64_t n = (int64_t)a.LB * mv.V;
     hipLaunchKernelGGL(k_ell_ops, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
                        dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0], lrn ? 1 : 0, lo, ops[1], ops[2]);
     GRF_LAUNCH_CHECK();
-    const int64_t nsys = (int64_t)mv.ng * a.LB * a.S;
+    if (lrn)
+        chip_all<true>(mv, &a, ops, st);
+    else
+        chip_all<false>(mv, &a, ops, st);
+    // graphs beyond the on-chip classes
+    const int c0 = lrn ? kChipLearned : kPcgClasses;
+    const int32_t ngl = mv.cls_off[kPcgClasses + 1] - mv.cls_off[c0];
+    if (ngl == 0) return;
+    const int64_t nsys = (int64_t)ngl * a.LB * a.S;
     const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
+    const int32_t *glist = mv.gord + mv.cls_off[c0];
     if (lrn)
         hipLaunchKernelGGL(k_pcg_ell<true>, dim3((unsigned)blocks), dim3(256), 0, st, mv, ops[0], ops[1], ops[2],
-                           a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+                           glist, ngl, a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
     else
         hipLaunchKernelGGL(k_pcg_ell<false>, dim3((unsigned)blocks), dim3(256), 0, st, mv, ops[0], ops[1], ops[2],
-                           a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+                           glist, ngl, a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
-}
-
-void prepare_pcg(const MeshView &mv) { (void)pcg_onchip(mv, nullptr, nullptr); }
-
-void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
-    if (a.LB == 0 || a.S == 0) return;
-    if (a.learned || !pcg_onchip(mv, &a, st)) pcg_global(mv, a, st);
 }
 
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st) {

@@ -1,0 +1,61 @@
+"""Vertex PCG size classes: a batch whose graphs sit on both sides of every
+class capacity (64, 256, 1024, 4096, 10176 and 20352 vertices; the last
+graph is beyond every on-chip class and takes the global-memory kernel), so
+every on-chip variant and the fallback solve systems of the same call.
+
+Bars: each graph's batched sample equals the FP64 oracle to 1e-10 relative
+in the lumped-mass norm, with the Jacobi and with the learned
+preconditioner (an untrained network: its Jacobi fallback and the true
+residual still decide convergence); every system converges.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh
+from oracle import noise as onoise
+from oracle import solve as osolve
+from workloads import preferential_attachment
+from workloads.learned_init import init_params
+
+pytestmark = pytest.mark.gpu
+H, RULE = 0.5, "round"          # lengths U[0.5, 1.5]: 0 to 2 interior DOFs per edge
+BETA, K, S, SEED = 0.7, 1.0, 3, 13
+SIZES = [64, 65, 256, 257, 1024, 1025, 4096, 4097, 10176, 10177, 20352, 20353]
+
+
+def _rel_ml(u, ref, ML):
+    num = np.sqrt(((u - ref) ** 2 * ML).sum(axis=-1))
+    den = np.sqrt((ref ** 2 * ML).sum(axis=-1))
+    return float(np.max(num / den))
+
+
+@pytest.fixture(scope="module")
+def batch(grf):
+    trees = [preferential_attachment(n, 1, lengths=(0.5, 1.5), seed=100 + i) for i, n in enumerate(SIZES)]
+    assert [t.n_vertices for t in trees] == SIZES
+    Gs = [grf.Graph(t.n_vertices, t.edges, t.lengths, H, RULE) for t in trees]
+    kappas = np.linspace(4.0, 12.0, len(Gs))
+    refs = []
+    for t, kap in zip(trees, kappas):
+        m = omesh.build_mesh(t.n_vertices, t.edges, t.lengths, H, RULE)
+        ML = omesh.lumped_mass(m)
+        W = onoise.white_noise(ML, SEED, S)
+        refs.append((ML, osolve.sample(m, float(kap), BETA, K, W)))
+    return Gs, kappas, refs
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "learned"])
+def test_every_class_matches_oracle(grf, batch, precond):
+    Gs, kappas, refs = batch
+    net = grf.Learned(init_params(7, head_scale=0.5)) if precond == "learned" else None
+    try:
+        outs, st = grf.sample_batched(Gs, kappas, BETA, K, S, SEED, learned=net)
+    finally:
+        if net is not None:
+            net.close()
+    assert st["n_unconverged"] == 0
+    for n, u, (ML, ref) in zip(SIZES, outs, refs):
+        err = _rel_ml(u.cpu().numpy(), ref, ML)
+        print(f"{precond} V={n}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-10, (n, err)
