@@ -66,6 +66,10 @@ void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 // class that holds it)
 constexpr int kPcgClasses = 6;
 constexpr int32_t kPcgCap[kPcgClasses] = {64, 256, 1024, 4096, 10176, 20352};
+// launch shape of each class: TPB threads, K vertices per thread (TPB K >= cap),
+// thread t owning the graph-local vertices t + TPB i
+constexpr int kChipTpb[kPcgClasses] = {64, 64, 256, 512, 1024, 1024};
+constexpr int kChipK[kPcgClasses] = {1, 4, 4, 8, 10, 20};
 
 struct MeshView {
     int32_t V, E;
@@ -98,6 +102,12 @@ struct MeshView {
     // graphs too large for every on-chip class
     const int32_t *gord;
     int32_t cls_off[kPcgClasses + 2];
+    // graph-local ids of the first four edge ends of every vertex ([V], 16 bits
+    // each, the vertex itself past its degree; graphs of an on-chip class only)
+    const uint2 *ell16;
+    // per graph and wavefront of its class shape: bit i set if item i of some
+    // lane of the wavefront has degree > 4 ([ng][16])
+    const uint32_t *ovfm;
 };
 
 }  // namespace grf
@@ -125,7 +135,7 @@ struct grf_graph {
     grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_deg;
     std::vector<int32_t> gord;
     int32_t cls_off[grf::kPcgClasses + 2] = {};
-    grf::DevBuf d_gord;
+    grf::DevBuf d_gord, d_ell16, d_ovfm;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;

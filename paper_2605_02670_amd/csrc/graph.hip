@@ -220,6 +220,27 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
         g.cls_off[c] = n;
     }
     upload(g.d_gord, g.gord, s);
+    // 16-bit local neighbour ids and overflow masks for the graphs of an on-chip class
+    std::vector<uint32_t> e16(2 * (size_t)g.V, 0), om(16 * (size_t)ng, 0);
+    for (int64_t k = 0; k < ng; ++k) {
+        const int c = cls[k];
+        if (c >= kPcgClasses) continue;
+        const int32_t u0 = g.gv0[k], nv = g.gv0[k + 1] - u0;
+        for (int32_t v = 0; v < nv; ++v) {
+            const int64_t u = u0 + v;
+            uint32_t id[4];
+            for (int j = 0; j < 4; ++j) id[j] = (uint32_t)(ell[(size_t)j * g.V + u] - u0);
+            e16[2 * u] = id[0] | (id[1] << 16);
+            e16[2 * u + 1] = id[2] | (id[3] << 16);
+            if (deg[u] > 4) {
+                const int tpb = kChipTpb[c];
+                const int t = v % tpb, i = v / tpb;
+                om[16 * k + t / 64] |= 1u << i;
+            }
+        }
+    }
+    upload(g.d_ell16, e16, s);
+    upload(g.d_ovfm, om, s);
     upload(g.d_gv0, g.gv0, s);
     upload(g.d_ge0, g.ge0, s);
     upload(g.d_segs, g.segs, s);
@@ -297,6 +318,8 @@ grf::MeshView grf_graph::view() const {
     v.ell = d_ell.as<int32_t>();
     v.deg = d_deg.as<int32_t>();
     v.gord = d_gord.as<int32_t>();
+    v.ell16 = d_ell16.as<uint2>();
+    v.ovfm = d_ovfm.as<uint32_t>();
     for (int c = 0; c <= grf::kPcgClasses + 1; ++c) v.cls_off[c] = cls_off[c];
     return v;
 }

@@ -624,6 +624,22 @@ void learned_reserve(grf_learned &net, const MeshView &mv, int32_t LB) {
     net.Qe.reserve(8 * RE + 8);
 }
 
+// Identifies the device buffers a forward uses (weights and activations): a
+// captured graph that ran the forward stays valid while this is unchanged.
+uint64_t learned_signature(const grf_learned &net) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the buffer addresses
+    for (const DevBuf *b : {&net.w32, &net.wbf, &net.Dh, &net.w, &net.X0, &net.M0, &net.H1, &net.M1, &net.H2,
+                            &net.M2, &net.H3, &net.zd, &net.gam, &net.zt, &net.zh, &net.zr, &net.eta, &net.Pd,
+                            &net.Qd, &net.Pq, &net.Qe}) {
+        uint64_t v = (uint64_t)(uintptr_t)b->ptr;
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    }
+    return h;
+}
+
 void learned_copy_grad(grf_learned &net, float *host, hipStream_t st) {
     GRF_HIP(hipMemcpyAsync(host, net.grad.ptr, 4 * P_COUNT, hipMemcpyDeviceToHost, st));
     GRF_HIP(hipStreamSynchronize(st));

@@ -74,13 +74,13 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
 }
 
 // Vertex operators of a shift block in ELL-4 form, for the global-memory PCG:
-// (Op y)_u = diag[l][u] y_u + sum_{j<4} coef[l][j][u] y_{ell[j][u]} + sum over the
+// (Op y)_u = diag[l][u] y_u + sum_{j<4} coef[l][u][j] y_{ell[j][u]} + sum over the
 // CSR slots k >= vptr[u] + 4 of ovf[l][k] y_{adj_o[k]}  (a self-loop's coupling is
 // in the diagonal; its slots carry 0).  S is the Schur complement (with jinv =
 // 1 / diag, the Jacobi preconditioner); with the learned preconditioner,
 // P = Dh P_hat Dh and Q = Dh Q_hat Dh.
 struct EllOp {
-    double *diag, *jinv, *coef, *ovf;  // [LB][V], [LB][V], [LB][4][V], [LB][2E]
+    double *diag, *jinv, *coef, *ovf;  // [LB][V], [LB][V], [LB][V][4], [LB][2E]
 };
 
 __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
@@ -106,10 +106,10 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
                 cq = dhu * dho * lo.Qe[(int64_t)l * mv.E + e];
             }
             if (j < 4) {
-                S.coef[((int64_t)l * 4 + j) * mv.V + u] = c;
+                S.coef[((int64_t)l * mv.V + u) * 4 + j] = c;
                 if (lrn) {
-                    P.coef[((int64_t)l * 4 + j) * mv.V + u] = cp;
-                    Q.coef[((int64_t)l * 4 + j) * mv.V + u] = cq;
+                    P.coef[((int64_t)l * mv.V + u) * 4 + j] = cp;
+                    Q.coef[((int64_t)l * mv.V + u) * 4 + j] = cq;
                 }
             } else {
                 S.ovf[(int64_t)l * E2 + k] = c;
@@ -120,10 +120,10 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
             }
         }
         for (int j = (int)(k1 - k0); j < 4; ++j) {
-            S.coef[((int64_t)l * 4 + j) * mv.V + u] = 0.0;
+            S.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
             if (lrn) {
-                P.coef[((int64_t)l * 4 + j) * mv.V + u] = 0.0;
-                Q.coef[((int64_t)l * 4 + j) * mv.V + u] = 0.0;
+                P.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
+                Q.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
             }
         }
         S.diag[i] = d;
@@ -141,7 +141,7 @@ __device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__
                                             const double *y, int u, int u0) {
     double acc = dg[u] * y[u - u0];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc += cf[(int64_t)j * mv.V + u] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
+    for (int j = 0; j < 4; ++j) acc += cf[4 * (int64_t)u + j] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
     const int d = mv.deg[u];
     if (d > 4) {
         const int64_t k0 = mv.vptr[u];
@@ -166,7 +166,7 @@ __device__ __forceinline__ void ell_apply4(const MeshView &mv, const double *__r
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            acc[i] += cf[(int64_t)j * mv.V + uu[i]] * y[mv.ell[(int64_t)j * mv.V + uu[i]] - u0];
+            acc[i] += cf[4 * (int64_t)uu[i] + j] * y[mv.ell[(int64_t)j * mv.V + uu[i]] - u0];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int d = mv.deg[uu[i]];
@@ -411,29 +411,37 @@ __device__ __forceinline__ bool group_live(int i0, int nv) {
     return w0 + TPB * i0 < nv;
 }
 
-// (Op y) at the G items of a group (y graph-local; 0 at masked items).  The
-// CSR slots past the first four (vertices of degree > 4) are summed after the
-// ELL part of every item of the group has been issued.
+// (Op y) at the G items i0 .. i0+G-1 of a group (y graph-local; 0 at masked
+// items): the row is one 8-byte load of 16-bit local neighbour ids and two
+// 16-byte coefficient loads.  The CSR slots past the first four (degree > 4)
+// are added only for the items whose bit is set in the wavefront's overflow
+// mask om (a scalar test: no branch waits on a vector load).
 template <int G>
 __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__restrict__ dg,
                                           const double *__restrict__ cf, const double *__restrict__ of,
                                           const double *y, const int (&vc)[G], const bool (&ok)[G], int u0,
-                                          double (&out)[G]) {
+                                          uint32_t om, int i0, double (&out)[G]) {
     double acc[G];
-    int dd[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int u = u0 + vc[g];
-        dd[g] = mv.deg[u];
-        acc[g] = dg[u] * y[vc[g]];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[g] += cf[(int64_t)j * mv.V + u] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
+        const uint2 nb = mv.ell16[u];
+        const double2 c01 = *reinterpret_cast<const double2 *>(cf + 4 * (int64_t)u);
+        const double2 c23 = *reinterpret_cast<const double2 *>(cf + 4 * (int64_t)u + 2);
+        double a = dg[u] * y[vc[g]];
+        a += c01.x * y[nb.x & 0xffffu];
+        a += c01.y * y[nb.x >> 16];
+        a += c23.x * y[nb.y & 0xffffu];
+        a += c23.y * y[nb.y >> 16];
+        acc[g] = a;
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        if (dd[g] > 4) {
-            const int64_t k0 = mv.vptr[u0 + vc[g]];
-            for (int64_t k = k0 + 4; k < k0 + dd[g]; ++k) acc[g] += of[k] * y[mv.adj_o[k] - u0];
+        if ((om >> (i0 + g)) & 1u) {
+            const int u = u0 + vc[g];
+            const int d = mv.deg[u];
+            const int64_t k0 = mv.vptr[u];
+            for (int64_t k = k0 + 4; k < k0 + d; ++k) acc[g] += of[k] * y[mv.adj_o[k] - u0];
         }
         out[g] = ok[g] ? acc[g] : 0.0;
     }
@@ -444,16 +452,21 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
 // sample) system, thread t owning the graph-local vertices t + TPB i (i < K),
 // whose r and q = S p (and x unless XG) stay in registers.  XG keeps x in its
 // output row of xT instead (the large classes, where K doubles fewer registers
-// decide whether the kernel spills).  LRN: the learned preconditioner reads the
-// neighbours' residuals, so r is also kept in LDS (2 cap doubles).  The
+// decide whether the kernel spills), updated by FP64 atomic adds that return
+// nothing, so no wavefront waits on the row (x has one writer per entry, its
+// owner thread, so the sum is the same as in registers).  LRN: the learned
+// preconditioner reads the neighbours' residuals, so r is also kept in LDS (2
+// cap doubles), or with RG (the largest class, whose p fills the LDS) in a row
+// of rrow, [LB][S][V] like xT, read back after a barrier.  The
 // operator rows (EllOp) are read from global memory; the workgroups of one
 // (graph, shift) are sent to one XCD (block b goes to XCD b mod 8), so its L2
 // serves the rows to all of that shift's samples.  Three barriers per Jacobi
 // iteration (four with the learned preconditioner).
-template <int TPB, int K, bool LRN, bool XG>
+template <int TPB, int K, bool LRN, bool XG, bool RG>
 __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
                                                   const int32_t *__restrict__ glist, int32_t ngl, int32_t cap,
                                                   const double *__restrict__ gT, double *__restrict__ xT,
+                                                  double *__restrict__ rrow,
                                                   int32_t *__restrict__ its, double *__restrict__ res, int32_t LB,
                                                   int64_t S, double tol, int32_t maxit) {
     constexpr int G = K >= GRF_PCG_OPAQUE_K ? GRF_PCG_GROUP : K;
@@ -461,6 +474,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     using IG = ItemGroup<TPB, K, G>;
     extern __shared__ double sv[];  // p [cap], r [cap] (LRN)
     __shared__ double red[64];
+    __shared__ double dump;  // target of the stores of masked items (no branch per store)
     // block -> (group = (graph, shift), sample): the S blocks of a group share b mod 8
     const int64_t b = blockIdx.x;
     const int64_t grp = (b / (8 * S)) * 8 + (b & 7);
@@ -477,7 +491,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
     const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
     const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
-    double *ps = sv, *rs = sv + cap;
+    static_assert(!RG || LRN, "r rows in global memory only for the learned preconditioner");
+    double *ps = sv;
+    double *rs = RG ? rrow + ((int64_t)l * S + smp) * mv.V + u0 : sv + cap;
+    const uint32_t om = mv.ovfm[16 * (int64_t)gi + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
     GroupSum<TPB> gsum{red, 0};
     double x[XG ? 1 : K], r[K], q[K];
 
@@ -492,10 +509,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             for (int e = 0; e < G; ++e) {
                 double xv;
                 if constexpr (XG)
-                    xv = xo[it.vc[e]];
+                    xv = unsafeAtomicAdd(&xo[it.vc[e]], 0.0);  // ordered after this thread's updates
                 else
                     xv = x[i0 + e];
-                if (it.ok[e]) ps[it.v[e]] = xv;
+                *(it.ok[e] ? &ps[it.v[e]] : &dump) = xv;
             }
         }
         __syncthreads();  // x in LDS
@@ -505,7 +522,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
             double sx[G];
-            ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, sx);
+            ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, om, i0, sx);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const double rv = it.ok[e] ? g[it.vc[e]] - sx[e] : 0.0;
@@ -524,7 +541,11 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             const IG it(i0, nv);
 #pragma unroll
                 for (int e = 0; e < G; ++e)
-                    if (it.ok[e]) rs[it.v[e]] = r[i0 + e];
+                    if constexpr (RG) {
+                        if (it.ok[e]) rs[it.v[e]] = r[i0 + e];
+                    } else {
+                        *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i0 + e];
+                    }
             }
             __syncthreads();  // r in LDS
 #pragma unroll
@@ -532,7 +553,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
                 double z[G];
-                ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, z);
+                ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     q[i0 + e] = z[e];
@@ -547,7 +568,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             const IG it(i0, nv);
 #pragma unroll
             for (int e = 0; e < G; ++e)
-                if (it.ok[e]) ps[it.v[e]] = q[i0 + e];
+                *(it.ok[e] ? &ps[it.v[e]] : &dump) = q[i0 + e];
         }
         rz = t[0];
         rr = t[1];
@@ -564,7 +585,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             double xq[G];
             if constexpr (LRN)
                 ell_group<G>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
-                             Qop.ovf + (int64_t)l * E2, g, it.vc, it.ok, u0, xq);
+                             Qop.ovf + (int64_t)l * E2, g, it.vc, it.ok, u0, om, i0, xq);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const int i = i0 + e;
@@ -582,7 +603,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                     r[i] = gv;
                     const double z = gv * Sj[it.vc[e]];
                     t[0] += gv * z;
-                    if (it.ok[e]) ps[it.v[e]] = z;
+                    *(it.ok[e] ? &ps[it.v[e]] : &dump) = z;
                     if constexpr (XG) {
                         if (it.ok[e]) xo[it.v[e]] = 0.0;
                     } else {
@@ -627,7 +648,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
                 double sp[G];
-                ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, sp);
+                ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, om, i0, sp);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     q[i0 + e] = sp[e];
@@ -645,17 +666,24 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 for (int e = 0; e < G; ++e) {
                     const int i = i0 + e;
                     const double pv = ps[it.vc[e]];
-                    const double sj = Sj[it.vc[e]];
-                    if constexpr (XG) {
-                        const double xv = xo[it.vc[e]];
-                        if (it.ok[e]) xo[it.v[e]] = xv + alpha * pv;
+                    if constexpr (XG) {  // no return value: the wavefront does not wait (+0 at masked items)
+                        unsafeAtomicAdd(&xo[it.vc[e]], it.ok[e] ? alpha * pv : 0.0);
                     } else {
                         x[i] += alpha * pv;
                     }
                     r[i] -= alpha * q[i];  // 0 at masked items
                     t3[1] += r[i] * r[i];
-                    if (!lz) t3[0] += r[i] * (r[i] * sj);
-                    if (LRN && lz && it.ok[e]) rs[it.v[e]] = r[i];
+                    if (!lz) {  // z = J r, kept in q for the direction update
+                        q[i] = r[i] * Sj[it.vc[e]];
+                        t3[0] += r[i] * q[i];
+                    }
+                    if (LRN && lz) {
+                        if constexpr (RG) {
+                            if (it.ok[e]) rs[it.v[e]] = r[i];
+                        } else {
+                            *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i];
+                        }
+                    }
                 }
             }
             gsum(t3);
@@ -672,7 +700,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                     if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
                     double z[G];
-                    ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, z);
+                    ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
 #pragma unroll
                     for (int e = 0; e < G; ++e) {
                         q[i0 + e] = z[e];
@@ -690,9 +718,8 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             const IG it(i0, nv);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
-                    const double z = (LRN && lz) ? q[i0 + e] : r[i0 + e] * Sj[it.vc[e]];
-                    const double pn = z + beta * ps[it.vc[e]];
-                    if (it.ok[e]) ps[it.v[e]] = pn;
+                    const double pn = q[i0 + e] + beta * ps[it.vc[e]];  // q = z
+                    *(it.ok[e] ? &ps[it.v[e]] : &dump) = pn;
                 }
             }
         }
@@ -775,23 +802,25 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
-// launch shape of the on-chip size classes: TPB threads, K vertices per thread
-// (TPB K >= kPcgCap[c]); the learned variant keeps two vectors in LDS and runs
-// on classes 0 .. kChipLearned - 1 only
-constexpr int kChipTpb[kPcgClasses] = {64, 64, 256, 512, 1024, 1024};
-constexpr int kChipK[kPcgClasses] = {1, 4, 4, 8, 10, 20};
-constexpr int kChipLearned = 5;
+// the learned variant keeps two vectors in LDS and runs on the size classes
+// 0 .. kChipLearned - 1 only
+constexpr int kChipLearned = 6;
 
-static size_t chip_lds(int c, bool lrn) { return (size_t)kPcgCap[c] * sizeof(double) * (lrn ? 2 : 1); }
+// the learned variant of the largest class keeps r in global memory (RG)
+constexpr bool chip_rg(int c, bool lrn) { return lrn && kChipK[c] > 10; }
+static size_t chip_lds(int c, bool lrn) {
+    return (size_t)kPcgCap[c] * sizeof(double) * (lrn && !chip_rg(c, lrn) ? 2 : 1);
+}
 
 template <int C, bool LRN>
 static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st) {
     constexpr int TPB = kChipTpb[C], K = kChipK[C];
     static_assert(TPB * K >= kPcgCap[C], "class capacity");
-    constexpr bool XG = K >= 10;
+    constexpr bool XG = K > 10;
+    constexpr bool RG = chip_rg(C, LRN);
     const size_t lds = chip_lds(C, LRN);
     if (!a) {  // preparation: the dynamic LDS of the variant (not a stream operation)
-        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG>,
+        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG, RG>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         return;
     }
@@ -800,9 +829,9 @@ static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops,
     const int64_t groups = (int64_t)n * a->LB;
     const int64_t blocks = (groups + 7) / 8 * 8 * a->S;
     GRF_REQUIRE(blocks < ((int64_t)1 << 31), "too many systems in one shift block");
-    hipLaunchKernelGGL((k_pcg_chip<TPB, K, LRN, XG>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, ops[0], ops[1],
-                       ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], a->gT, a->xT, a->its, a->res, a->LB, a->S,
-                       a->tol, a->maxit);
+    hipLaunchKernelGGL((k_pcg_chip<TPB, K, LRN, XG, RG>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, ops[0],
+                       ops[1], ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], a->gT, a->xT, a->ug, a->its, a->res,
+                       a->LB, a->S, a->tol, a->maxit);
     GRF_LAUNCH_CHECK();
 }
 
@@ -813,7 +842,7 @@ static void chip_all(const MeshView &mv, const SchurArgs *a, const EllOp *ops, h
     chip_class<2, LRN>(mv, a, ops, st);
     chip_class<3, LRN>(mv, a, ops, st);
     chip_class<4, LRN>(mv, a, ops, st);
-    if constexpr (!LRN) chip_class<5, LRN>(mv, a, ops, st);
+    chip_class<5, LRN>(mv, a, ops, st);
 }
 
 void prepare_pcg(const MeshView &mv) {

@@ -362,6 +362,7 @@ struct Batch {
     grf_graph U;
     std::vector<double> kap2;     // per-edge kappa^2 on the device
     bool tuned = false;
+    std::vector<double> tuned_key;  // (precision, preconditioner) the tuning was done for
     int32_t sweep_block = 0, shift_block = 0;
     hipStream_t stream = nullptr;  // capture and replay stream (default priority)
     hipGraphExec_t exec = nullptr;
@@ -677,7 +678,8 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     grf_opts run = o;
     run.timing = 0;
     if (o.sweep_block == 0 && o.shift_block == 0) {
-        if (!B.tuned) {
+        const std::vector<double> tk = {(double)o.precision, (double)o.precond};
+        if (!B.tuned || tk != B.tuned_key) {
             std::vector<std::pair<int32_t, int32_t>> cand = {{0, 0}, {0, 64}};
             if (o.precision == GRF_PREC_FP64) {
                 cand.push_back({32, 0});
@@ -697,6 +699,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
                 }
             }
             B.tuned = true;
+            B.tuned_key = tk;
             if (B.exec) {
                 (void)hipGraphExecDestroy(B.exec);
                 B.exec = nullptr;
@@ -705,11 +708,20 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
         run.sweep_block = B.sweep_block;
         run.shift_block = B.shift_block;
     }
-    std::vector<double> key = {beta, sh.k, (double)sh.kminus, (double)sh.kplus, (double)n_samples,
-                               (double)(seed >> 32), (double)(seed & 0xffffffffu), (double)run.sample_offset,
-                               run.tol, (double)run.maxit, (double)run.precision, (double)run.sweep_block,
-                               (double)run.shift_block};
-    key.insert(key.end(), kappas, kappas + n_graphs);
+    // everything the captured graph depends on; with the learned preconditioner also
+    // the network's buffers (taken again after the capture: the preparation may grow them)
+    auto make_key = [&]() {
+        std::vector<double> k = {beta, sh.k, (double)sh.kminus, (double)sh.kplus, (double)n_samples,
+                                 (double)(seed >> 32), (double)(seed & 0xffffffffu), (double)run.sample_offset,
+                                 run.tol, (double)run.maxit, (double)run.precision, (double)run.sweep_block,
+                                 (double)run.shift_block, (double)run.precond, (double)run.refine};
+        const uint64_t ls = run.precond == GRF_PRECOND_LEARNED ? learned_signature(*run.learned) : 0;
+        k.push_back((double)(ls >> 32));
+        k.push_back((double)(ls & 0xffffffffu));
+        k.insert(k.end(), kappas, kappas + n_graphs);
+        return k;
+    };
+    const std::vector<double> key = make_key();
     hipStream_t cs = B.stream;
     if (!B.exec || key != B.exec_key) {
         if (B.exec) {
@@ -737,7 +749,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
             set_error("HIP graph instantiation failed: %s", hipGetErrorString(ie));
             throw Error{GRF_EDEVICE};
         }
-        B.exec_key = key;
+        B.exec_key = make_key();
     }
     hipEvent_t ea = nullptr, eb = nullptr;
     if (o.timing) {

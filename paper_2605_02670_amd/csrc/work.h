@@ -119,6 +119,7 @@ double learned_backward(grf_learned &net, const MeshView &mv, const double *g, c
                         hipStream_t st);
 void learned_adam(grf_learned &net, double lr, hipStream_t st);
 void learned_copy_grad(grf_learned &net, float *host, hipStream_t st);
+uint64_t learned_signature(const grf_learned &net);
 
 // vertex Schur complement: condensed rhs, PCG, layout changes, accumulation
 struct SchurArgs {
@@ -126,7 +127,7 @@ struct SchurArgs {
     const double *ends;   // [LB][E][2][Sp]
     const double *sd, *so;  // [LBp][E]
     double *gT, *xT;      // [LB][S][V]
-    double *ug;           // [LB][V][Sp]
+    double *ug;           // [LB][V][Sp]; during the PCG also the learned preconditioner's residual rows [LB][S][V]
     double *U;            // [nb][N][64]
     double *scr;          // PCG scratch (large graphs)
     double *ops;          // vertex operators of the block for the global-memory PCG (pcg_ops_bytes)

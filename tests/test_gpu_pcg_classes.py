@@ -48,13 +48,20 @@ def batch(grf):
 @pytest.mark.parametrize("precond", ["jacobi", "learned"])
 def test_every_class_matches_oracle(grf, batch, precond):
     Gs, kappas, refs = batch
-    net = grf.Learned(init_params(7, head_scale=0.5)) if precond == "learned" else None
+    net = None
+    if precond == "learned":
+        # the same handles were just run with Jacobi: the learned call must not replay
+        # that captured graph (its iteration total differs)
+        _, st_j = grf.sample_batched(Gs, kappas, BETA, K, S, SEED)
+        net = grf.Learned(init_params(7, head_scale=0.5))
     try:
         outs, st = grf.sample_batched(Gs, kappas, BETA, K, S, SEED, learned=net)
     finally:
         if net is not None:
             net.close()
     assert st["n_unconverged"] == 0
+    if precond == "learned":
+        assert st["total_iterations"] != st_j["total_iterations"]
     for n, u, (ML, ref) in zip(SIZES, outs, refs):
         err = _rel_ml(u.cpu().numpy(), ref, ML)
         print(f"{precond} V={n}: rel err {err:.2e}", flush=True)
