@@ -248,7 +248,8 @@ def bench_batched(args) -> int:
     edges, h = 1/128), one kappa per graph, all 176 shifts x 32 samples in one
     grf_sample_batched call (captured HIP graph replayed each step)."""
     cfg, Gs, outs = _batch_setup()
-    kw = dict(tol=cfg["tol"], precision=args.precision, sweep_block=args.sweep_block, shift_block=args.shift_block)
+    kw = dict(tol=args.tol if args.tol else cfg["tol"], precision=args.precision, sweep_block=args.sweep_block,
+              shift_block=args.shift_block)
     net = None
     if args.precond == "learned":
         net = train_network()[0]
@@ -259,7 +260,7 @@ def bench_batched(args) -> int:
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"64 uneven graphs (trees + lattices, 100..20000 edges) h=1/128 beta=0.75 "
-                               f"S={r['samples']} batched-{args.precision}-{args.precond}",
+                               f"S={r['samples']} PCG tol {kw['tol']:g} batched-{args.precision}-{args.precond}",
                    "n_dof": r["n_dof"], "shifts": r["shifts"], "samples": r["samples"], "graphs": r["graphs"],
                    "parallelism": "1 GPU"},
         "roofline": None, "cpu_baseline": None, "first_call_s": r["first_call_s"], "pcg": r["pcg"],
@@ -279,6 +280,8 @@ def main() -> int:
     ap.add_argument("--shift-block", type=int, default=0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="mixed: FP32 edge sweeps, FP64 noise/Schur/PCG/accumulation")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="PCG tolerance of the batched64 workload (0: the configuration's, 1e-12)")
     ap.add_argument("--precond", choices=["jacobi", "learned"], default="jacobi",
                     help="vertex PCG preconditioner of the batched64 workload (learned: trained first, on the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -157,30 +157,41 @@ __device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk
 }
 
 constexpr int kTabThreads = 128;          // one thread per (padded) shift, LBp <= 128
-constexpr int kSPad = kTabThreads + 4;    // LDS row stride of the Ghat operands
 constexpr double kThetaSplit = 40.0;      // see k_blocktab
 
-// Writes the 16 per-position values v[i] of every shift of this wave as 16
-// contiguous 64-lane operand vectors, in one of three layouts:
+// 16-byte vectors of the table element type
+template <typename ET> struct V16;
+template <> struct V16<double> { typedef d2 type; };
+template <> struct V16<float> { typedef f4 type; };
+
+// Writes thread (shift) l's 16 per-position values v[p] into the operand
+// vectors, in one of three layouts:
 //   C layout: lane n + 16 q of vector (t, c) <- shift 16t + n, position 4c + q;
 //   H/Z layout, FP64 (F32L false): lane i + 16 k of vector (t, r) <- shift 16t + 4r + k, position i;
 //   H/Z layout, FP32 (F32L true):  lane i + 16 k of vector (t, r) <- shift 16t + 4k + r, position i
-// (the shift order of the accumulator registers used as B operands).
+// (the shift order of the accumulator registers used as B operands).  In the
+// H/Z layouts a shift's 16 values are 16 contiguous elements (16-byte vector
+// stores); in the C layout a store instruction writes 16-element runs.
 template <bool CLAYOUT, bool F32L, typename OT>
-__device__ __forceinline__ void emit16(double (*tile)[17], const double (&v)[16], OT *dst, int wv, int NT) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void put16(const double (&v)[16], OT *__restrict__ dst, int l) {
+    if constexpr (CLAYOUT) {
+        const int t = l >> 4, n = l & 15;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) tile[lane][i] = v[i];
-    __syncthreads();
+        for (int p = 0; p < 16; ++p) dst[(int64_t)(4 * t + (p >> 2)) * 64 + n + 16 * (p & 3)] = (OT)v[p];
+    } else {
+        const int64_t at = F32L ? (int64_t)(4 * (l >> 4) + (l & 3)) * 64 + 16 * ((l & 15) >> 2)
+                                : (int64_t)(l >> 2) * 64 + 16 * (l & 3);
+        typedef typename V16<OT>::type VT;
+        constexpr int NV = 16 / sizeof(OT);  // elements per 16-byte vector
+        VT *d = reinterpret_cast<VT *>(dst + at);
 #pragma unroll
-    for (int o = 0; o < 16; ++o) {
-        if (4 * wv + (o >> 2) >= NT) break;
-        const double x = CLAYOUT ? tile[16 * (o >> 2) + (lane & 15)][4 * (o & 3) + (lane >> 4)]
-                         : F32L  ? tile[16 * (o >> 2) + 4 * (lane >> 4) + (o & 3)][lane & 15]
-                                 : tile[4 * o + (lane >> 4)][lane & 15];
-        dst[(int64_t)(16 * wv + o) * 64 + lane] = (OT)x;
+        for (int c = 0; c < 16 / NV; ++c) {
+            VT x;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) x[k] = (OT)v[NV * c + k];
+            d[c] = x;
+        }
     }
-    __syncthreads();
 }
 
 // One workgroup per 16-position edge block, thread = shift l (base = 16 beta,
@@ -203,10 +214,11 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
                                                           const double *__restrict__ shift, int32_t LB, int32_t LBp,
                                                           int32_t NT, OT *__restrict__ tab, OT *__restrict__ ztab) {
     constexpr bool F32L = sizeof(OT) == 4;  // FP32 operand tables for the mixed-precision sweeps
-    __shared__ double sAf[17][kSPad];   // dg / (w^i E(base+i+1)) split factor, rows 0..16
-    __shared__ double sBm[16][kSPad];   // E(base+j+1) split factor
-    __shared__ double srw[kSPad];       // w / w_split
-    __shared__ double tile[2][64][17];
+    // Ghat split factors, rows of ld = LBp + 4 doubles: Af rows 0..16 (dg / (w^i E(base+i+1))),
+    // Bm rows 0..15 (E(base+j+1)), then w / w_split
+    extern __shared__ double sfac[];
+    const int ld = LBp + 4;
+    double *sAf = sfac, *sBm = sfac + 17 * ld, *srw = sfac + 33 * ld;
     const int tid = threadIdx.x, wv = tid >> 6;
     const int64_t blk = blockIdx.x;
     const int e = find_edge(boff, (int)mv.E, blk);
@@ -219,67 +231,78 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     OT *Z = ztab + blk * (int64_t)(512 * NT);
     const int l = tid;
     const bool live = l < LB;
-    double th = 0.0, w = 0.0, E1 = 0.0, K = 0.0, ascale = 0.0;
+    double th = 0.0, w = 0.0, E1 = 0.0, bab = 1.0, sh2 = 1.0;
     if (live) {
         const EdgeShift s = edge_shift(shift[2 * l], shift[2 * l + 1], mv.kap2[e], mv.he[e]);
         th = s.th;
         w = s.w;
         E1 = s.E1;
-        K = 1.0 / (s.bab * Ek(th, m + 1));
-        ascale = K / s.sh2;
+        bab = s.bab;
+        sh2 = s.sh2;
     }
-    // Ef[k] = E(base + k), k = 0..16 (E(k+1) = E(k) + (1 - E(k)) E(1): positive terms only)
+    // E values from two evaluations and the addition rule E(a + b) = E(a) + (1 - E(a)) E(b)
+    // (positive terms only, no cancellation): Ef[k] = E(base + k), k = 0..16
     double Ef[17];
     Ef[0] = live ? Ek(th, base) : 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) Ef[k + 1] = Ef[k] + (1.0 - Ef[k]) * E1;
-    // Q[i] = E(m - base - i), i = 0..16 (rows past the edge are never used unmasked)
+    // Q[i] = E(max(m - base - i, 0)), i = 0..16, upwards from Q[16] (rows past the edge
+    // are never used unmasked)
+    const int nr = m - base;  // >= 1: positions of the edge from this block on
     double Q[17];
+    Q[16] = live ? Ek(th, max(nr - 16, 0)) : 0.0;
 #pragma unroll
-    for (int i = 0; i < 17; ++i) Q[i] = live ? Ek(th, max(m - base - i, 0)) : 0.0;
-    double wp[18];
-    wp[0] = 1.0;
-#pragma unroll
-    for (int d = 0; d < 17; ++d) wp[d + 1] = wp[d] * w;
+    for (int i = 15; i >= 0; --i) Q[i] = (nr - i > 0) ? Q[i + 1] + (1.0 - Q[i + 1]) * E1 : 0.0;
+    // E(m + 1) = E(base) + (1 - E(base)) E(nr + 1), E(nr + 1) = Q[0] + (1 - Q[0]) E(1)
+    const double En1 = Q[0] + (1.0 - Q[0]) * E1;
+    const double Em1 = Ef[0] + (1.0 - Ef[0]) * En1;
+    const double K = live ? 1.0 / (bab * Em1) : 0.0;
+    const double ascale = live ? K / sh2 : 0.0;
     const double lam0 = Ef[0] * ascale;  // E(base) / (2 sinh(theta) |b| E(m+1))
 
     double v[16];
     // H_fwd[i] = dg_i lam_i = w^{i+1} E(base) E(m-base-i) / (2 sinh |b| E(m+1))
+    {
+        double pw = w;  // w^{i+1}
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wp[i + 1] * lam0 * Q[i] : 0.0;
-    emit16<false, F32L>(tile[wv], v, T + TL.HF(), wv, NT);
+        for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? pw * lam0 * Q[i] : 0.0;
+    }
+    if (l < LBp) put16<false, F32L>(v, T + TL.HF(), l);
     // H_bwd[i] = of_i lam_i = w^{i+2} E(base) E(m-base-i-1) / (...)
+    {
+        double pw = w * w;  // w^{i+2}
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wp[i + 2] * lam0 * Q[i + 1] : 0.0;
-    emit16<false, F32L>(tile[wv], v, T + TL.HB(), wv, NT);
+        for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? pw * lam0 * Q[i + 1] : 0.0;
+    }
+    if (l < LBp) put16<false, F32L>(v, T + TL.HB(), l);
     // Z_tail[i] = w^{base+1+i} E(m-base-i) K
     {
         const double wb = live ? exp(-(double)(base + 1) * th) * K : 0.0;
+        double pw = 1.0;  // w^i
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = (live && i <= istar) ? wb * wp[i] * Q[i] : 0.0;
+        for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? wb * pw * Q[i] : 0.0;
     }
-    emit16<false, F32L>(tile[wv], v, Z, wv, NT);
+    if (l < LBp) put16<false, F32L>(v, Z, l);
     // C[j] = w^{i*-j} E(base+j+1) / E(base+i*+1), d = w^{i*+1} E(base) / E(base+i*+1), and
     // Z_head[i] = w^{m-base-i} E(base+i+1) K: descending chains from i*
     double dval = 0.0;
-    {
+    {  // one chain at a time (fewer live registers)
         double pw = 1.0, inv = 0.0;
-        double zh = live ? exp(-(double)(m - base - istar) * th) * K : 0.0;
-        double vz[16];
 #pragma unroll
         for (int j = 15; j >= 0; --j) {
             if (j == istar) inv = 1.0 / Ef[j + 1];
-            const bool ok = live && j <= istar;
-            v[j] = ok ? pw * Ef[j + 1] * inv : 0.0;
-            vz[j] = ok ? zh * Ef[j + 1] : 0.0;
-            if (j <= istar) {
-                pw *= w;
-                zh *= w;
-            }
+            v[j] = (live && j <= istar) ? pw * Ef[j + 1] * inv : 0.0;
+            if (j <= istar) pw *= w;
         }
         dval = live ? pw * Ef[0] * inv : 0.0;  // pw = w^{i*+1}
-        emit16<true, F32L>(tile[wv], v, T + TL.CT(), wv, NT);
-        emit16<false, F32L>(tile[wv], vz, Z + 256 * NT, wv, NT);
+        if (l < LBp) put16<true, F32L>(v, T + TL.CT(), l);
+        double zh = live ? exp(-(double)(m - base - istar) * th) * K : 0.0;
+#pragma unroll
+        for (int j = 15; j >= 0; --j) {
+            v[j] = (live && j <= istar) ? zh * Ef[j + 1] : 0.0;
+            if (j <= istar) zh *= w;
+        }
+        if (l < LBp) put16<false, F32L>(v, Z + 256 * NT, l);
     }
     if (l < LBp) T[TL.DT() + l] = (OT)dval;
     // Ghat operands (split factors); rows past i*+1 (Af) / i* (Bm) are zero
@@ -291,12 +314,14 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
         const double iwc = live ? exp(thc) : 0.0;
 #pragma unroll
         for (int i = 0; i < 17; ++i) {
-            sAf[i][l] = (live && i <= istar + 1) ? Q[i] * ascale * fa : 0.0;
-            if (i < 16) sBm[i][l] = (live && i <= istar) ? Ef[i + 1] * fb : 0.0;
+            if (l < ld) {
+                sAf[i * ld + l] = (live && i <= istar + 1) ? Q[i] * ascale * fa : 0.0;
+                if (i < 16) sBm[i * ld + l] = (live && i <= istar) ? Ef[i + 1] * fb : 0.0;
+            }
             fa *= wc;
             fb *= iwc;
         }
-        srw[l] = live ? exp(thc - th) : 0.0;  // w / w_c
+        if (l < ld) srw[l] = live ? exp(thc - th) : 0.0;  // w / w_c
     }
     __syncthreads();
     // Ghat^T = B^T A^T (D layout of the transpose = the A-operand table layout):
@@ -307,8 +332,8 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
         d4 acc = d4{0.0, 0.0, 0.0, 0.0};
         for (int c = 0; c < LBp / 4; ++c) {
             const int ll = 4 * c + q;
-            const double a = sBm[n][ll];
-            const double b = (wv == 0) ? sAf[n][ll] : sAf[n + 1][ll] * srw[ll];
+            const double a = sBm[n * ld + ll];
+            const double b = (wv == 0) ? sAf[n * ld + ll] : sAf[(n + 1) * ld + ll] * srw[ll];
             acc = mfma(a, b, acc);
         }
         OT *G = T + (wv == 0 ? TL.GF() : TL.GB());
@@ -324,10 +349,6 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
 // workgroup (one edge, 64 samples): every thread loads its share of the next
 // block into registers while the current block is computed, then writes it to
 // the other LDS buffer.
-// 16-byte vectors of the table element type
-template <typename ET> struct V16;
-template <> struct V16<double> { typedef d2 type; };
-template <> struct V16<float> { typedef f4 type; };
 
 template <typename ET, int NE>
 constexpr int stage_per() { return (NE * (int)sizeof(ET) / 16 + 255) / 256; }
@@ -822,16 +843,18 @@ void launch_edge_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
+static size_t blocktab_lds(int32_t LBp) { return sizeof(double) * 34 * (size_t)(LBp + 4); }
+
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return;
     GRF_REQUIRE(a.LBp == 16 * a.NT && a.NT >= 1 && a.NT <= 8, "internal: blocked sweeps need 16..128 padded shifts");
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
     if (a.mixed)
-        hipLaunchKernelGGL(k_blocktab<float>, dim3((unsigned)a.nblocks), dim3(kTabThreads), 0, st, mv, a.boff, a.shift,
-                           a.LB, a.LBp, a.NT, a.tab32, a.ztab32);
+        hipLaunchKernelGGL(k_blocktab<float>, dim3((unsigned)a.nblocks), dim3(kTabThreads), blocktab_lds(a.LBp), st, mv,
+                           a.boff, a.shift, a.LB, a.LBp, a.NT, a.tab32, a.ztab32);
     else
-        hipLaunchKernelGGL(k_blocktab<double>, dim3((unsigned)a.nblocks), dim3(kTabThreads), 0, st, mv, a.boff,
-                           a.shift, a.LB, a.LBp, a.NT, a.tab, a.ztab);
+        hipLaunchKernelGGL(k_blocktab<double>, dim3((unsigned)a.nblocks), dim3(kTabThreads), blocktab_lds(a.LBp), st, mv,
+                           a.boff, a.shift, a.LB, a.LBp, a.NT, a.tab, a.ztab);
     GRF_LAUNCH_CHECK();
 }
 
