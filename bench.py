@@ -67,11 +67,11 @@ HIP_KERNEL = {
 # FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0 KiB: the factors a 1 GiB plain copy
 # reads on these counters), valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = "paper_2605_02670_amd/csrc/blocked.hip"
-TRAFFIC_SHA256 = "1c107201bf45fe8f95f0a18ee4548d0a91db706cc49fd55366341437ad9fbd24"
+TRAFFIC_SHA256 = "b15bf4daa88be39378d78990fdb99715f354e87543e20dc5d77f2799ae370518"
 TRAFFIC = {  # kernel id: (fetch KiB, write KiB) per launch
-    "ends_fwd": (4471735.5, 5996584.0),
-    "ends_bwd": (6674479.1875, 5980456.0),
-    "acc_fwd": (5630185.3125, 4125736.0),
+    "ends_fwd": (4573967.9375, 5996584.0),
+    "ends_bwd": (6639972.4375, 5980456.0),
+    "acc_fwd": (6000674.625, 4125736.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 

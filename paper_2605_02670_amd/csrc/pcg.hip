@@ -52,10 +52,11 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     const int b = blockIdx.y;
     const int l = blockIdx.z;
     const int64_t E = mv.E;
+    const bool real = (int64_t)b * 64 + lane < S;  // padding samples load nothing
     for (int vi = wv; vi < 64; vi += 4) {
         const int v = v0 + vi;
         double g = 0.0;
-        if (v < mv.V) {
+        if (v < mv.V && real) {
             g = X[((int64_t)b * mv.N + mv.NI + v) * 64 + lane];
             for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
                 const int e = mv.adj_e[k];
