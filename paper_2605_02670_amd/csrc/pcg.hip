@@ -74,38 +74,55 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     }
 }
 
-// Vertex operators of a shift block in ELL-4 form, for the global-memory PCG:
+// The vertex systems are solved on their Jacobi-scaled form: with d = diag(S)
+// and h = d^{-1/2}, S^ = H S H has unit diagonal, g^ = H g and x = H x^.  CG on
+// S^ from x^ = 0 takes exactly the iterates of Jacobi-PCG on S, and needs no
+// diagonal in the product and no preconditioner in the update.  The learned
+// operators are defined on S^ already: z^ = P^ r^, x0^ = Q^ g^.
+//
+// Vertex operators of a shift block in ELL-4 form:
 // (Op y)_u = diag[l][u] y_u + sum_{j<4} coef[l][u][j] y_{ell[j][u]} + sum over the
 // CSR slots k >= vptr[u] + 4 of ovf[l][k] y_{adj_o[k]}  (a self-loop's coupling is
-// in the diagonal; its slots carry 0).  S is the Schur complement (with jinv =
-// 1 / diag, the Jacobi preconditioner); with the learned preconditioner,
-// P = Dh P_hat Dh and Q = Dh Q_hat Dh.
+// in the diagonal; its slots carry 0).  For S^ the diagonal is 1 (not stored) and
+// dh holds h; for P^ and Q^ diag holds their diagonal.
 struct EllOp {
-    double *diag, *jinv, *coef, *ovf;  // [LB][V], [LB][V], [LB][V][4], [LB][2E]
+    double *diag, *dh, *coef, *ovf;  // [LB][V], [LB][V], [LB][V][4], [LB][2E]
 };
 
-__global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
-                          EllOp S, int32_t lrn, LearnedOps lo, EllOp P, EllOp Q) {
+// h = diag(S)^{-1/2} per (shift, vertex)
+__global__ void k_ell_diag(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
+                           double *__restrict__ dh) {
+    const int64_t n = (int64_t)LB * mv.V;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / mv.V), u = (int)(i - (int64_t)l * mv.V);
+        const double *sdl = sd + (int64_t)l * mv.E, *sol = so + (int64_t)l * mv.E;
+        double d = 0.0;
+        for (int64_t k = mv.vptr[u]; k < mv.vptr[u + 1]; ++k) {
+            const int e = mv.adj_e[k];
+            d += sdl[e] + (mv.adj_o[k] == u ? sol[e] : 0.0);
+        }
+        dh[i] = 1.0 / sqrt(d);
+    }
+}
+
+// ELL rows of S^ = H S H (and of P^, Q^ with the learned preconditioner)
+__global__ void k_ell_ops(MeshView mv, const double *__restrict__ so, int32_t LB, EllOp S, int32_t lrn,
+                          LearnedOps lo, EllOp P, EllOp Q) {
     const int64_t n = (int64_t)LB * mv.V;
     const int64_t E2 = 2 * (int64_t)mv.E;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(i / mv.V), u = (int)(i - (int64_t)l * mv.V);
-        const double *sdl = sd + (int64_t)l * mv.E, *sol = so + (int64_t)l * mv.E;
+        const double *sol = so + (int64_t)l * mv.E;
+        const double *hl = S.dh + (int64_t)l * mv.V;
+        const double hu = hl[u];
         const int64_t k0 = mv.vptr[u], k1 = mv.vptr[u + 1];
-        const double dhu = lrn ? lo.Dh[i] : 0.0;
-        double d = 0.0;
         for (int64_t k = k0; k < k1; ++k) {
             const int e = mv.adj_e[k];
             const int o = mv.adj_o[k];
-            d += sdl[e] + (o == u ? sol[e] : 0.0);
-            const double c = (o == u) ? 0.0 : sol[e];
+            const double c = (o == u) ? 0.0 : hu * sol[e] * hl[o];
+            const double cp = (lrn && o != u) ? lo.Pq[(int64_t)l * mv.E + e] : 0.0;
+            const double cq = (lrn && o != u) ? lo.Qe[(int64_t)l * mv.E + e] : 0.0;
             const int j = (int)(k - k0);
-            double cp = 0.0, cq = 0.0;
-            if (lrn && o != u) {
-                const double dho = lo.Dh[(int64_t)l * mv.V + o];
-                cp = dhu * dho * lo.Pq[(int64_t)l * mv.E + e];
-                cq = dhu * dho * lo.Qe[(int64_t)l * mv.E + e];
-            }
             if (j < 4) {
                 S.coef[((int64_t)l * mv.V + u) * 4 + j] = c;
                 if (lrn) {
@@ -127,20 +144,20 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
                 Q.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
             }
         }
-        S.diag[i] = d;
-        S.jinv[i] = 1.0 / d;
         if (lrn) {
-            P.diag[i] = dhu * dhu * lo.Pd[i];
-            Q.diag[i] = dhu * dhu * lo.Qd[i];
+            P.diag[i] = lo.Pd[i];
+            Q.diag[i] = lo.Qd[i];
         }
     }
 }
 
-// (Op y)_u for the graph-local vector y (vertex u = u0 + local index)
+// (Op y)_u for the graph-local vector y (vertex u = u0 + local index); UNIT: the
+// diagonal is 1
+template <bool UNIT>
 __device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__restrict__ dg,
                                             const double *__restrict__ cf, const double *__restrict__ of,
                                             const double *y, int u, int u0) {
-    double acc = dg[u] * y[u - u0];
+    double acc = UNIT ? y[u - u0] : dg[u] * y[u - u0];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc += cf[4 * (int64_t)u + j] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
     const int d = mv.deg[u];
@@ -151,42 +168,17 @@ __device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__
     return acc;
 }
 
-// (Op y) for the four graph-local vertices v0 + i * stride (i < 4) of this thread:
-// the ELL loads of all four are issued before any is consumed (indices past the
-// graph are clamped to its last vertex and their results ignored).
-__device__ __forceinline__ void ell_apply4(const MeshView &mv, const double *__restrict__ dg,
-                                           const double *__restrict__ cf, const double *__restrict__ of,
-                                           const double *y, int v0, int stride, int V, int u0, double (&out)[4]) {
-    int uu[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) uu[i] = u0 + min(v0 + i * stride, V - 1);
-    double acc[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = dg[uu[i]] * y[uu[i] - u0];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            acc[i] += cf[4 * (int64_t)uu[i] + j] * y[mv.ell[(int64_t)j * mv.V + uu[i]] - u0];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int d = mv.deg[uu[i]];
-        if (d > 4) {
-            const int64_t k0 = mv.vptr[uu[i]];
-            for (int64_t k = k0 + 4; k < k0 + d; ++k) acc[i] += of[k] * y[mv.adj_o[k] - u0];
-        }
-        out[i] = acc[i];
-    }
-}
-
 // One workgroup per (graph, shift, sample) system of the graphs glist[0 .. ngl-1],
-// vectors in global scratch (x, r, p, q: 4 maxVg doubles per resident
+// vectors in global scratch (x^, r^, p, q: 4 maxVg doubles per resident
 // workgroup), for graphs too large for the on-chip kernel.  The vectors of
 // system (g, l, s) are the graph's vertex range of gT / xT[l][s]; its
-// statistics go to its / res[(g * LB + l) * S + s].  LRN: the learned preconditioner
-// z = P r and initial guess x0 = Q g, with the Jacobi fallback after maxit / 2
-// iterations (restart from the current iterate); otherwise Jacobi from x0 = 0.
-// Either way the residual recomputed from x decides convergence.
+// statistics go to its / res[(g * LB + l) * S + s].  LRN: the learned
+// preconditioner z^ = P^ r^ and initial guess x0^ = Q^ g^, with the Jacobi
+// fallback after maxit / 2 iterations (restart from the current iterate);
+// otherwise CG on S^ (Jacobi) from x^ = 0.  Either way the residual g - S x
+// recomputed from x decides convergence; the scaled recursive residual only
+// triggers that test, at a threshold corrected by the ratio of the true to the
+// scaled residual norm measured at the last test.
 template <bool LRN>
 __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
                                                  const int32_t *__restrict__ glist, int32_t ngl,
@@ -209,110 +201,104 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
         const int64_t sys = ((int64_t)gi * LB + l) * S + smp;
         const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
         const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
-        const double *Sd = Sop.diag + (int64_t)l * mv.V, *Sc = Sop.coef + (int64_t)l * 4 * mv.V,
-                     *So = Sop.ovf + (int64_t)l * E2, *Sj = Sop.jinv + (int64_t)l * mv.V;
+        const double *Sc = Sop.coef + (int64_t)l * 4 * mv.V, *So = Sop.ovf + (int64_t)l * E2,
+                     *H = Sop.dh + (int64_t)l * mv.V + u0;
         const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
         const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
         const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
         bool learned = LRN;
-        double t0[1] = {0.0};
+        // g^ into r, ||g||^2, ||g^||^2
+        double t0[2] = {0.0, 0.0};
         for (int v = threadIdx.x; v < V; v += blockDim.x) {
-            const int u = u0 + v;
-            x[v] = LRN ? ell_apply(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
-                                   Qop.ovf + (int64_t)l * E2, g, u, u0)
-                       : 0.0;
+            const double gh = H[v] * g[v];
+            r[v] = gh;
             t0[0] += g[v] * g[v];
+            t0[1] += gh * gh;
         }
-        block_sum<1>(t0, red, nw);
+        block_sum<2>(t0, red, nw);
         const double gg = t0[0];
         const double tol2 = tol * tol * gg;
+        double thr = tol * tol * t0[1];  // trigger on ||r^||^2
+        for (int v = threadIdx.x; v < V; v += blockDim.x)
+            x[v] = LRN ? ell_apply<false>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
+                                          Qop.ovf + (int64_t)l * E2, r, u0 + v, u0)
+                       : 0.0;
         int it = 0;
         double rel = 0.0;
-        // r = g - S x and z = M r into p; returns (r.z, r.r)
-        auto restart = [&](double &rz, double &rr) {
-            __syncthreads();  // x complete
-            double t[2] = {0.0, 0.0};
+        // r^ = g^ - S^ x^ and z^ = M r^ into p; returns (r^.z^, ||r||^2, ||r^||^2)
+        auto restart = [&](double &rz, double &rr, double &rh) {
+            __syncthreads();  // x^ complete, every read of r done
+            double t[3] = {0.0, 0.0, 0.0};
             for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                const double rv = g[v] - ell_apply(mv, Sd, Sc, So, x, u0 + v, u0);
+                const double rv = H[v] * g[v] - ell_apply<true>(mv, nullptr, Sc, So, x, u0 + v, u0);
                 r[v] = rv;
-                t[1] += rv * rv;
+                const double ru = rv / H[v];
+                t[1] += ru * ru;
+                t[2] += rv * rv;
                 if (!learned) {
-                    const double zv = rv * Sj[u0 + v];
-                    p[v] = zv;
-                    t[0] += rv * zv;
+                    p[v] = rv;
+                    t[0] += rv * rv;
                 }
             }
             if (learned) {
                 __syncthreads();  // r complete
                 for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                    const double zv = ell_apply(mv, Pd, Pc, Po, r, u0 + v, u0);
+                    const double zv = ell_apply<false>(mv, Pd, Pc, Po, r, u0 + v, u0);
                     p[v] = zv;
                     t[0] += r[v] * zv;
                 }
             }
-            block_sum<2>(t, red, nw);
+            block_sum<3>(t, red, nw);
             rz = t[0];
             rr = t[1];
+            rh = t[2];
         };
         if (gg > 0.0) {
-            double rz, rr;
-            restart(rz, rr);
+            double rz, rr, rh;
+            restart(rz, rr, rh);
             rel = sqrt(rr / gg);
+            if (rh > 0.0) thr = tol2 * rh / rr;
             if (rr > tol2) {
                 for (it = 1; it <= maxit; ++it) {
                     if (learned && it == switch_at) {  // fallback: Jacobi from the current iterate
                         learned = false;
-                        restart(rz, rr);
+                        restart(rz, rr, rh);
                     }
                     __syncthreads();  // p complete
                     double t1[1] = {0.0};
-                    for (int v0 = threadIdx.x; v0 < V; v0 += 4 * blockDim.x) {
-                        double qv[4];
-                        ell_apply4(mv, Sd, Sc, So, p, v0, blockDim.x, V, u0, qv);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int v = v0 + i * (int)blockDim.x;
-                            if (v < V) {
-                                q[v] = qv[i];
-                                t1[0] += p[v] * qv[i];
-                            }
-                        }
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                        const double qv = ell_apply<true>(mv, nullptr, Sc, So, p, u0 + v, u0);
+                        q[v] = qv;
+                        t1[0] += p[v] * qv;
                     }
                     block_sum<1>(t1, red, nw);
                     const double alpha = rz / t1[0];
-                    double t3[2] = {0.0, 0.0};  // r.z (Jacobi), r.r
+                    double t3[1] = {0.0};  // ||r^||^2 (= r^.z^ for Jacobi)
                     for (int v = threadIdx.x; v < V; v += blockDim.x) {
                         x[v] += alpha * p[v];
                         const double rv = r[v] - alpha * q[v];
                         r[v] = rv;
-                        t3[1] += rv * rv;
-                        if (!learned) t3[0] += rv * (rv * Sj[u0 + v]);
+                        t3[0] += rv * rv;
                     }
-                    block_sum<2>(t3, red, nw);
-                    if (t3[1] <= tol2) {
-                        double rzt, rrt;
-                        restart(rzt, rrt);  // true residual, and a fresh direction if it fails
+                    block_sum<1>(t3, red, nw);
+                    if (t3[0] <= thr) {
+                        double rzt, rrt, rht;
+                        restart(rzt, rrt, rht);  // true residual, and a fresh direction if it fails
                         rel = sqrt(rrt / gg);
                         if (rrt <= tol2) break;
+                        if (rht > 0.0) thr = tol2 * rht / rrt;
                         rz = rzt;
                         continue;
                     }
-                    rel = sqrt(t3[1] / gg);
+                    rel = sqrt(t3[0] * rr / (rh > 0.0 ? rh : 1.0) / gg);
                     double rz_new = t3[0];
                     if (learned) {
                         __syncthreads();  // r complete: the preconditioner reads neighbours
                         double t4[1] = {0.0};
-                        for (int v0 = threadIdx.x; v0 < V; v0 += 4 * blockDim.x) {
-                            double zv[4];
-                            ell_apply4(mv, Pd, Pc, Po, r, v0, blockDim.x, V, u0, zv);
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                const int v = v0 + i * (int)blockDim.x;
-                                if (v < V) {
-                                    q[v] = zv[i];  // q is free until the next product
-                                    t4[0] += r[v] * zv[i];
-                                }
-                            }
+                        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+                            const double zv = ell_apply<false>(mv, Pd, Pc, Po, r, u0 + v, u0);
+                            q[v] = zv;  // q is free until the next product
+                            t4[0] += r[v] * zv;
                         }
                         block_sum<1>(t4, red, nw);
                         rz_new = t4[0];
@@ -320,15 +306,14 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
                     const double beta = rz_new / rz;
                     rz = rz_new;
                     __syncthreads();  // all reads of p and q done
-                    for (int v = threadIdx.x; v < V; v += blockDim.x)
-                        p[v] = (learned ? q[v] : r[v] * Sj[u0 + v]) + beta * p[v];
+                    for (int v = threadIdx.x; v < V; v += blockDim.x) p[v] = (learned ? q[v] : r[v]) + beta * p[v];
                 }
                 if (it > maxit) it = maxit + 1;  // flags non-convergence
             }
         }
         __syncthreads();
         double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
-        for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? x[v] : 0.0;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? H[v] * x[v] : 0.0;
         if (threadIdx.x == 0) {
             its[sys] = it;
             res[sys] = rel;
@@ -337,18 +322,18 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
     }
 }
 
-// Sum of NV <= 2 values over a workgroup of TPB threads, every thread getting
+// Sum of NV <= 3 values over a workgroup of TPB threads, every thread getting
 // the result (combined in a fixed order: deterministic).  Two LDS buffers taken
 // in turn: a buffer is written again only two sums later, after every thread
 // has passed the barrier of the sum in between, so each sum needs one barrier.
 // A single wavefront sums with shuffles alone.
 template <int TPB>
 struct GroupSum {
-    double *lds;  // [2][2][16]
+    double *lds;  // [2][3][16]
     int buf;
     template <int NV>
     __device__ __forceinline__ void operator()(double (&v)[NV]) {
-        static_assert(NV <= 2, "two values per sum");
+        static_assert(NV <= 3, "three values per sum");
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
         if constexpr (TPB > 64) {
@@ -356,7 +341,7 @@ struct GroupSum {
             // of a block: wavefront w's), then a butterfly within the block:
             // every lane ends with the same total, two registers per value
             constexpr int NW = TPB / 64;
-            double *r = lds + buf * 32;
+            double *r = lds + buf * 48;
             const int lane = threadIdx.x & 63;
             if (lane == 0)
 #pragma unroll
@@ -385,9 +370,9 @@ struct GroupSum {
 // i0 + G).  The items of a group are processed without control flow between
 // them (indices past the graph are clamped to its last vertex for the loads,
 // their results masked and their stores skipped), so that their loads are in
-// flight together.  With K >= 8 items per thread the index is made opaque, so
-// that the compiler reads the operator rows again in every iteration (from L2)
-// instead of holding K rows in registers, which would spill.
+// flight together.  With K >= GRF_PCG_OPAQUE_K items per thread the index is
+// made opaque, so that the compiler reads the operator rows again in every
+// iteration (from L2) instead of holding K rows in registers, which would spill.
 template <int TPB, int K, int G>
 struct ItemGroup {
     int v[G], vc[G];
@@ -396,7 +381,10 @@ struct ItemGroup {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             int t = (int)threadIdx.x + TPB * (i0 + g);
-            if constexpr (K >= GRF_PCG_OPAQUE_K) asm volatile("" : "+v"(t));
+            if constexpr (K >= GRF_PCG_OPAQUE_K) {
+                if (g % GRF_PCG_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                asm volatile("" : "+v"(t));
+            }
             v[g] = t;
             ok[g] = t < nv;
             vc[g] = min(t, nv - 1);
@@ -414,10 +402,11 @@ __device__ __forceinline__ bool group_live(int i0, int nv) {
 
 // (Op y) at the G items i0 .. i0+G-1 of a group (y graph-local; 0 at masked
 // items): the row is one 8-byte load of 16-bit local neighbour ids and two
-// 16-byte coefficient loads.  The CSR slots past the first four (degree > 4)
-// are added only for the items whose bit is set in the wavefront's overflow
-// mask om (a scalar test: no branch waits on a vector load).
-template <int G>
+// 16-byte coefficient loads (UNIT: unit diagonal, no diagonal load).  The CSR
+// slots past the first four (degree > 4) are added only for the items whose
+// bit is set in the wavefront's overflow mask om (a scalar test: no branch
+// waits on a vector load).
+template <int G, bool UNIT>
 __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__restrict__ dg,
                                           const double *__restrict__ cf, const double *__restrict__ of,
                                           const double *y, const int (&vc)[G], const bool (&ok)[G], int u0,
@@ -429,7 +418,7 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
         const uint2 nb = mv.ell16[u];
         const double2 c01 = *reinterpret_cast<const double2 *>(cf + 4 * (int64_t)u);
         const double2 c23 = *reinterpret_cast<const double2 *>(cf + 4 * (int64_t)u + 2);
-        double a = dg[u] * y[vc[g]];
+        double a = UNIT ? y[vc[g]] : dg[u] * y[vc[g]];
         a += c01.x * y[nb.x & 0xffffu];
         a += c01.y * y[nb.x >> 16];
         a += c23.x * y[nb.y & 0xffffu];
@@ -448,33 +437,34 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
     }
 }
 
-// The same PCG with the search direction p in LDS, for the graphs glist[0 ..
+// The same solve with the search direction p in LDS, for the graphs glist[0 ..
 // ngl-1] of at most cap <= TPB K vertices: one workgroup per (graph, shift,
 // sample) system, thread t owning the graph-local vertices t + TPB i (i < K),
-// whose r and q = S p (and x unless XG) stay in registers.  XG keeps x in its
-// output row of xT instead (the large classes, where K doubles fewer registers
-// decide whether the kernel spills), updated by FP64 atomic adds that return
-// nothing, so no wavefront waits on the row (x has one writer per entry, its
-// owner thread, so the sum is the same as in registers).  LRN: the learned
-// preconditioner reads the neighbours' residuals, so r is also kept in LDS (2
-// cap doubles), or with RG (the largest class, whose p fills the LDS) in a row
-// of rrow, [LB][S][V] like xT, read back after a barrier.  The
-// operator rows (EllOp) are read from global memory; the workgroups of one
-// (graph, shift) are sent to one XCD (block b goes to XCD b mod 8), so its L2
-// serves the rows to all of that shift's samples.  Three barriers per Jacobi
-// iteration (four with the learned preconditioner).
+// whose r^ and q = S^ p (and x^ unless XG) stay in registers.  XG keeps x^ in
+// its output row of xT instead (the largest class, where K doubles fewer
+// registers decide whether the kernel spills), updated by FP64 atomic adds
+// that return nothing, so no wavefront waits on the row (x^ has one writer per
+// entry, its owner thread, so the sum is the same as in registers).  LRN: the
+// learned preconditioner reads the neighbours' residuals, so r^ is also kept in
+// LDS (2 cap doubles), or with RG (the largest class, whose p fills the LDS) in
+// a row of rrow, [LB][S][V] like xT, read back after a barrier.  The operator
+// rows (EllOp) are read from global memory; the workgroups of one (graph,
+// shift) are sent to one XCD (block b goes to XCD b mod 8), so its L2 serves the
+// rows to all of that shift's samples.  Three barriers per Jacobi iteration
+// (four with the learned preconditioner); the update reads nothing from HBM.
 template <int TPB, int K, bool LRN, bool XG, bool RG>
 __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
                                                   const int32_t *__restrict__ glist, int32_t ngl, int32_t cap,
                                                   const double *__restrict__ gT, double *__restrict__ xT,
-                                                  double *__restrict__ rrow,
-                                                  int32_t *__restrict__ its, double *__restrict__ res, int32_t LB,
-                                                  int64_t S, double tol, int32_t maxit) {
+                                                  double *__restrict__ rrow, int32_t *__restrict__ its,
+                                                  double *__restrict__ res, int32_t LB, int64_t S, double tol,
+                                                  int32_t maxit) {
     constexpr int G = K >= GRF_PCG_OPAQUE_K ? GRF_PCG_GROUP : K;
     static_assert(K % G == 0, "items per thread: a multiple of the group size");
+    static_assert(!RG || LRN, "r rows in global memory only for the learned preconditioner");
     using IG = ItemGroup<TPB, K, G>;
-    extern __shared__ double sv[];  // p [cap], r [cap] (LRN)
-    __shared__ double red[64];
+    extern __shared__ double sv[];  // p [cap], r [cap] (LRN && !RG)
+    __shared__ double red[96];
     __shared__ double dump;  // target of the stores of masked items (no branch per store)
     // block -> (group = (graph, shift), sample): the S blocks of a group share b mod 8
     const int64_t b = blockIdx.x;
@@ -487,21 +477,21 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     const int64_t E2 = 2 * (int64_t)mv.E;
     const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
     double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
-    const double *Sd = Sop.diag + (int64_t)l * mv.V, *Sc = Sop.coef + (int64_t)l * 4 * mv.V,
-                 *So = Sop.ovf + (int64_t)l * E2, *Sj = Sop.jinv + (int64_t)l * mv.V + u0;
+    const double *Sc = Sop.coef + (int64_t)l * 4 * mv.V, *So = Sop.ovf + (int64_t)l * E2,
+                 *H = Sop.dh + (int64_t)l * mv.V + u0;
     const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
     const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
     const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
-    static_assert(!RG || LRN, "r rows in global memory only for the learned preconditioner");
     double *ps = sv;
     double *rs = RG ? rrow + ((int64_t)l * S + smp) * mv.V + u0 : sv + cap;
     const uint32_t om = mv.ovfm[16 * (int64_t)gi + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
     GroupSum<TPB> gsum{red, 0};
     double x[XG ? 1 : K], r[K], q[K];
 
-    // r = g - S x, z = M r (M = P if lz, else Jacobi) and p = z; returns (r.z, r.r).
-    // Every earlier read of p and r in LDS is behind the barrier of an earlier sum.
-    auto restart = [&](bool lz, double &rz, double &rr) {
+    // r^ = g^ - S^ x^, z^ = M r^ (M = P^ if lz, else the identity: Jacobi on S) and
+    // p = z^; returns (r^.z^, ||g - S x||^2, ||r^||^2).  Every earlier read of p and r
+    // in LDS is behind the barrier of an earlier sum.
+    auto restart = [&](bool lz, double &rz, double &rr, double &rh) {
 #pragma unroll
         for (int i0 = 0; i0 < K; i0 += G) {
             if (!group_live<TPB>(i0, nv)) continue;
@@ -516,22 +506,25 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 *(it.ok[e] ? &ps[it.v[e]] : &dump) = xv;
             }
         }
-        __syncthreads();  // x in LDS
-        double t[2] = {0.0, 0.0};
+        __syncthreads();  // x^ in LDS
+        double t[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i0 = 0; i0 < K; i0 += G) {
             if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
             double sx[G];
-            ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, om, i0, sx);
+            ell_group<G, true>(mv, nullptr, Sc, So, ps, it.vc, it.ok, u0, om, i0, sx);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
-                const double rv = it.ok[e] ? g[it.vc[e]] - sx[e] : 0.0;
+                const double h = H[it.vc[e]];
+                const double rv = it.ok[e] ? h * g[it.vc[e]] - sx[e] : 0.0;
+                const double ru = rv / h;
                 r[i0 + e] = rv;
-                t[1] += rv * rv;
+                t[1] += ru * ru;
+                t[2] += rv * rv;
                 if (!lz) {
-                    q[i0 + e] = rv * Sj[it.vc[e]];
-                    t[0] += rv * q[i0 + e];
+                    q[i0 + e] = rv;
+                    t[0] += rv * rv;
                 }
             }
         }
@@ -539,22 +532,23 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+                const IG it(i0, nv);
 #pragma unroll
-                for (int e = 0; e < G; ++e)
+                for (int e = 0; e < G; ++e) {
                     if constexpr (RG) {
                         if (it.ok[e]) rs[it.v[e]] = r[i0 + e];
                     } else {
                         *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i0 + e];
                     }
+                }
             }
-            __syncthreads();  // r in LDS
+            __syncthreads();  // r^ in LDS (or its row)
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+                const IG it(i0, nv);
                 double z[G];
-                ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
+                ell_group<G, false>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     q[i0 + e] = z[e];
@@ -562,75 +556,84 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 }
             }
         }
-        gsum(t);  // also: every read of x in LDS done
+        gsum(t);  // also: every read of x^ in LDS done
 #pragma unroll
         for (int i0 = 0; i0 < K; i0 += G) {
             if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
 #pragma unroll
-            for (int e = 0; e < G; ++e)
-                *(it.ok[e] ? &ps[it.v[e]] : &dump) = q[i0 + e];
+            for (int e = 0; e < G; ++e) *(it.ok[e] ? &ps[it.v[e]] : &dump) = q[i0 + e];
         }
         rz = t[0];
         rr = t[1];
+        rh = t[2];
     };
 
-    // ||g||^2; Jacobi: x0 = 0, r = g, p = J g; learned: x0 = Q g
-    double rz, rr, gg;
+    // ||g||^2 and ||g^||^2; Jacobi: x^0 = 0, r^ = p = g^; learned: x^0 = Q^ g^ (g^ staged in LDS)
+    double rz, rr, rh, gg;
     {
         double t[2] = {0.0, 0.0};
 #pragma unroll
         for (int i0 = 0; i0 < K; i0 += G) {
             if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
-            double xq[G];
-            if constexpr (LRN)
-                ell_group<G>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
-                             Qop.ovf + (int64_t)l * E2, g, it.vc, it.ok, u0, om, i0, xq);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const int i = i0 + e;
                 const double gv = it.ok[e] ? g[it.vc[e]] : 0.0;
-                t[1] += gv * gv;
+                const double gh = H[it.vc[e]] * gv;
+                t[0] += gv * gv;
+                t[1] += gh * gh;
                 q[i] = 0.0;
-                if constexpr (LRN) {
-                    r[i] = 0.0;
+                r[i] = LRN ? 0.0 : gh;
+                *(it.ok[e] ? &ps[it.v[e]] : &dump) = gh;
+                if constexpr (XG) {
+                    if (it.ok[e]) xo[it.v[e]] = 0.0;
+                } else {
+                    x[i] = 0.0;
+                }
+            }
+        }
+        if constexpr (LRN) {
+            __syncthreads();  // g^ in LDS
+#pragma unroll
+            for (int i0 = 0; i0 < K; i0 += G) {
+                if (!group_live<TPB>(i0, nv)) continue;
+                const IG it(i0, nv);
+                double xq[G];
+                ell_group<G, false>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
+                                    Qop.ovf + (int64_t)l * E2, ps, it.vc, it.ok, u0, om, i0, xq);
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
                     if constexpr (XG) {
                         if (it.ok[e]) xo[it.v[e]] = xq[e];
                     } else {
-                        x[i] = xq[e];
-                    }
-                } else {
-                    r[i] = gv;
-                    const double z = gv * Sj[it.vc[e]];
-                    t[0] += gv * z;
-                    *(it.ok[e] ? &ps[it.v[e]] : &dump) = z;
-                    if constexpr (XG) {
-                        if (it.ok[e]) xo[it.v[e]] = 0.0;
-                    } else {
-                        x[i] = 0.0;
+                        x[i0 + e] = xq[e];
                     }
                 }
             }
         }
-        gsum(t);
-        rz = t[0];
-        gg = t[1];
+        gsum(t);  // also: every read of g^ in LDS done
+        gg = t[0];
         rr = gg;
+        rh = t[1];
+        rz = t[1];
     }
     const double tol2 = tol * tol * gg;
+    double thr = tol * tol * rh;  // trigger on the scaled residual, corrected at each test
     int it_n = 0;
     double rel = 1.0;
     bool lz = LRN;      // the learned preconditioner is in use
-    bool fresh = LRN;   // r, z and p are to be recomputed from x
+    bool fresh = LRN;   // r^, z^ and p are to be recomputed from x^
     const int switch_at = max(1, maxit / 2);
     if (gg > 0.0) {
         for (;;) {
             if (fresh) {  // the only convergence test: the residual recomputed from x
-                restart(lz, rz, rr);
+                restart(lz, rz, rr, rh);
                 fresh = false;
                 rel = sqrt(rr / gg);
                 if (rr <= tol2) break;
+                if (rh > 0.0) thr = tol2 * rh / rr;
             }
             if (it_n == maxit) {  // flags non-convergence
                 it_n = maxit + 1;
@@ -647,9 +650,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+                const IG it(i0, nv);
                 double sp[G];
-                ell_group<G>(mv, Sd, Sc, So, ps, it.vc, it.ok, u0, om, i0, sp);
+                ell_group<G, true>(mv, nullptr, Sc, So, ps, it.vc, it.ok, u0, om, i0, sp);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     q[i0 + e] = sp[e];
@@ -658,11 +661,11 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             }
             gsum(t1);
             const double alpha = rz / t1[0];
-            double t3[2] = {0.0, 0.0};  // r.z (Jacobi), r.r
+            double t3[1] = {0.0};  // ||r^||^2 (= r^.z^ for Jacobi)
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+                const IG it(i0, nv);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     const int i = i0 + e;
@@ -673,11 +676,8 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                         x[i] += alpha * pv;
                     }
                     r[i] -= alpha * q[i];  // 0 at masked items
-                    t3[1] += r[i] * r[i];
-                    if (!lz) {  // z = J r, kept in q for the direction update
-                        q[i] = r[i] * Sj[it.vc[e]];
-                        t3[0] += r[i] * q[i];
-                    }
+                    t3[0] += r[i] * r[i];
+                    if (!lz) q[i] = r[i];  // z^ = r^, kept in q for the direction update
                     if (LRN && lz) {
                         if constexpr (RG) {
                             if (it.ok[e]) rs[it.v[e]] = r[i];
@@ -688,20 +688,20 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 }
             }
             gsum(t3);
-            if (t3[1] <= tol2) {  // verify with the true residual (and restart if it fails)
+            if (t3[0] <= thr) {  // test with the true residual (and restart if it fails)
                 fresh = true;
                 continue;
             }
-            rel = sqrt(t3[1] / gg);
+            rel = sqrt(t3[0] * rr / (rh > 0.0 ? rh : 1.0) / gg);  // estimate
             double rz_new = t3[0];
             if (LRN && lz) {
                 double t4[1] = {0.0};
 #pragma unroll
                 for (int i0 = 0; i0 < K; i0 += G) {
                     if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+                    const IG it(i0, nv);
                     double z[G];
-                    ell_group<G>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
+                    ell_group<G, false>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
 #pragma unroll
                     for (int e = 0; e < G; ++e) {
                         q[i0 + e] = z[e];
@@ -716,10 +716,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+                const IG it(i0, nv);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
-                    const double pn = q[i0 + e] + beta * ps[it.vc[e]];  // q = z
+                    const double pn = q[i0 + e] + beta * ps[it.vc[e]];  // q = z^
                     *(it.ok[e] ? &ps[it.v[e]] : &dump) = pn;
                 }
             }
@@ -727,14 +727,21 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     } else {
         rel = 0.0;
     }
-    if constexpr (!XG) {
+    // x = H x^
+    if constexpr (XG) __syncthreads();  // the atomic updates of the row are complete
 #pragma unroll
-        for (int i0 = 0; i0 < K; i0 += G) {
-            if (!group_live<TPB>(i0, nv)) continue;
-            const IG it(i0, nv);
+    for (int i0 = 0; i0 < K; i0 += G) {
+        if (!group_live<TPB>(i0, nv)) continue;
+        const IG it(i0, nv);
 #pragma unroll
-            for (int e = 0; e < G; ++e)
-                if (it.ok[e]) xo[it.v[e]] = x[i0 + e];
+        for (int e = 0; e < G; ++e) {
+            double xv;
+            if constexpr (XG)
+                xv = unsafeAtomicAdd(&xo[it.vc[e]], 0.0);
+            else
+                xv = x[i0 + e];
+            const double xs = H[it.vc[e]] * xv;
+            if (it.ok[e]) xo[it.v[e]] = xs;
         }
     }
     if (threadIdx.x == 0) {
@@ -786,7 +793,7 @@ size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
     return (size_t)blocks * 4 * mv.maxVg * sizeof(double);
 }
 
-// diag, jinv, coef [4], ovf of each shift, for S (and P, Q with the learned preconditioner)
+// diag, dh, coef [4], ovf of each shift, for S^ (and P^, Q^ with the learned preconditioner)
 static size_t ell_op_doubles(const MeshView &mv, int32_t LB) {
     return (size_t)LB * (6 * (size_t)mv.V + 2 * (size_t)mv.E);
 }
@@ -866,8 +873,9 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     }
     const LearnedOps lo = lrn ? *a.learned : LearnedOps{};
     const int64_t n = (int64_t)a.LB * mv.V;
-    hipLaunchKernelGGL(k_ell_ops, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536))),
-                       dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0], lrn ? 1 : 0, lo, ops[1], ops[2]);
+    const dim3 eg((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)));
+    hipLaunchKernelGGL(k_ell_diag, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0].dh);
+    hipLaunchKernelGGL(k_ell_ops, eg, dim3(256), 0, st, mv, a.so, a.LB, ops[0], lrn ? 1 : 0, lo, ops[1], ops[2]);
     GRF_LAUNCH_CHECK();
     if (lrn)
         chip_all<true>(mv, &a, ops, st);
