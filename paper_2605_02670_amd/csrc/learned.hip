@@ -158,42 +158,53 @@ __global__ void k_lrn_agg(MeshView mv, const float *__restrict__ w, const float 
 }
 
 // ---- layer products on the FP32 matrix cores ------------------------------------
-// Out[r][n] = relu?( sum_k A[r][k] Ws[n][k] + sum_k B[r][k] Wn[n][k] + bias[n] ), n < 64,
-// K in {8, 64}.  One wavefront per 16 rows; accumulator item j of lane L is
-// row 4 (L/16) + j, column L%16 of its 16x16 tile.
+// Out[r][n] = relu( sum_k A[r][k] Ws[n][k] + sum_k B[r][k] Wn[n][k] + bias[n] ), n < 64,
+// K in {8, 64}.  The workgroup stages both weight matrices in LDS once (bf16 to
+// FP32 is exact), transposed so that the sixteen lanes of a B operand read
+// consecutive words; each wavefront then loops over 16-row tiles.  Accumulator
+// item j of lane L is row 4 (L/16) + j, column L%16 of its 16x16 tile.
 template <int K>
 __global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ A, const float *__restrict__ B,
                                                       const uint16_t *__restrict__ Ws, const uint16_t *__restrict__ Wn,
                                                       const float *__restrict__ bias, int64_t R,
                                                       float *__restrict__ Out) {
-    const int L = threadIdx.x & 63;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (r0 >= R) return;
-    const int64_t ra = r0 + (L & 15);
-    const bool rok = ra < R;
-    f4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + (L >> 4);
-        const float a = rok ? A[ra * K + k] : 0.0f;
-        const float b = rok ? B[ra * K + k] : 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int n = 16 * t + (L & 15);
-            acc[t] = mfma32(a, bf(Ws, n * K + k), acc[t]);
-            acc[t] = mfma32(b, bf(Wn, n * K + k), acc[t]);
-        }
+    __shared__ float sW[2][K][HID];  // sW[m][k][n] = W_m[n][k]
+    for (int i = threadIdx.x; i < 2 * K * HID; i += blockDim.x) {
+        const int m = i / (K * HID), rem = i - m * (K * HID);
+        const int k = rem / HID, n = rem - k * HID;
+        sW[m][k][n] = bf(m ? Wn : Ws, n * K + k);
     }
+    __syncthreads();
+    const int L = threadIdx.x & 63;
+    const int64_t ntiles = (R + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t r0 = tile * 16;
+        const int64_t ra = r0 + (L & 15);
+        const bool rok = ra < R;
+        f4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t r = r0 + 4 * (L >> 4) + j;
-            const int n = 16 * t + (L & 15);
-            if (r < R) Out[r * HID + n] = fmaxf(acc[t][j] + bias[n], 0.0f);
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + (L >> 4);
+            const float a = rok ? A[ra * K + k] : 0.0f;
+            const float b = rok ? B[ra * K + k] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int n = 16 * t + (L & 15);
+                acc[t] = mfma32(a, sW[0][k][n], acc[t]);
+                acc[t] = mfma32(b, sW[1][k][n], acc[t]);
+            }
         }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = r0 + 4 * (L >> 4) + j;
+                const int n = 16 * t + (L & 15);
+                if (r < R) Out[r * HID + n] = fmaxf(acc[t][j] + bias[n], 0.0f);
+            }
+    }
 }
 
 // Out[r][k] = sum_n G[r][n] W[n][k]  (input gradient of a layer, K in {8, 64})
@@ -661,7 +672,8 @@ void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, 
     hipLaunchKernelGGL(k_lrn_features, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, shift, net.w.as<float>(),
                        LB, net.X0.as<float>());
     GRF_LAUNCH_CHECK();
-    const unsigned gblocks = (unsigned)std::max<int64_t>(1, (R + 63) / 64);
+    // 64 rows per workgroup pass, at most 8 workgroups per compute unit (the weights are staged once each)
+    const unsigned gblocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((R + 63) / 64, 2048));
     // layer 1 (8 -> 64), 2, 3 (64 -> 64)
     hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * F_IN)), dim3(256), 0, st, mv, net.w.as<float>(),
                        net.X0.as<float>(), LB, F_IN, net.M0.as<float>());
@@ -768,7 +780,7 @@ double learned_backward(grf_learned &net, const MeshView &mv, const double *g, c
     }
     // layers 3, 2, 1
     const int64_t per = (R + CH - 1) / CH;
-    const unsigned gblocks = (unsigned)std::max<int64_t>(1, (R + 63) / 64);
+    const unsigned gblocks = (unsigned)std::max<int64_t>(1, (R + 63) / 64);  // one 64-row pass per workgroup
     float *dZ = net.dH.as<float>();  // dH of layer k, turned into dZ in place
     struct Lay {
         int ws, wn, b;

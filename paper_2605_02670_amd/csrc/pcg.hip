@@ -445,25 +445,27 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
 // registers decide whether the kernel spills), updated by FP64 atomic adds
 // that return nothing, so no wavefront waits on the row (x^ has one writer per
 // entry, its owner thread, so the sum is the same as in registers).  LRN: the
-// learned preconditioner reads the neighbours' residuals, so r^ is also kept in
-// LDS (2 cap doubles), or with RG (the largest class, whose p fills the LDS) in
-// a row of rrow, [LB][S][V] like xT, read back after a barrier.  The operator
+// learned initial guess x^0 = Q^ g^ and preconditioner z^ = P^ r^; P^ reads the
+// neighbours' residuals, so r^ is also kept in LDS (2 cap doubles).  XP (the
+// largest class, whose p fills the LDS): the learned initial guess only, with
+// the Jacobi preconditioner.  The operator
 // rows (EllOp) are read from global memory; the workgroups of one (graph,
 // shift) are sent to one XCD (block b goes to XCD b mod 8), so its L2 serves the
 // rows to all of that shift's samples.  Three barriers per Jacobi iteration
 // (four with the learned preconditioner); the update reads nothing from HBM.
-template <int TPB, int K, bool LRN, bool XG, bool RG>
+template <int TPB, int K, bool LRN, bool XG, bool XP>
 __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
                                                   const int32_t *__restrict__ glist, int32_t ngl, int32_t cap,
                                                   const double *__restrict__ gT, double *__restrict__ xT,
-                                                  double *__restrict__ rrow, int32_t *__restrict__ its,
+                                                  int32_t *__restrict__ its,
                                                   double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                                   int32_t maxit) {
     constexpr int G = K >= GRF_PCG_OPAQUE_K ? GRF_PCG_GROUP : K;
     static_assert(K % G == 0, "items per thread: a multiple of the group size");
-    static_assert(!RG || LRN, "r rows in global memory only for the learned preconditioner");
+    static_assert(!XP || LRN, "initial guess only: a learned variant");
+    constexpr bool LP = LRN && !XP;  // the learned preconditioner is applied
     using IG = ItemGroup<TPB, K, G>;
-    extern __shared__ double sv[];  // p [cap], r [cap] (LRN && !RG)
+    extern __shared__ double sv[];  // p [cap], r [cap] (LP)
     __shared__ double red[96];
     __shared__ double dump;  // target of the stores of masked items (no branch per store)
     // block -> (group = (graph, shift), sample): the S blocks of a group share b mod 8
@@ -482,8 +484,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
     const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
     const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
-    double *ps = sv;
-    double *rs = RG ? rrow + ((int64_t)l * S + smp) * mv.V + u0 : sv + cap;
+    double *ps = sv, *rs = sv + cap;
     const uint32_t om = mv.ovfm[16 * (int64_t)gi + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
     GroupSum<TPB> gsum{red, 0};
     double x[XG ? 1 : K], r[K], q[K];
@@ -528,21 +529,15 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 }
             }
         }
-        if (LRN && lz) {
+        if (LP && lz) {
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
                 const IG it(i0, nv);
 #pragma unroll
-                for (int e = 0; e < G; ++e) {
-                    if constexpr (RG) {
-                        if (it.ok[e]) rs[it.v[e]] = r[i0 + e];
-                    } else {
-                        *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i0 + e];
-                    }
-                }
+                for (int e = 0; e < G; ++e) *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i0 + e];
             }
-            __syncthreads();  // r^ in LDS (or its row)
+            __syncthreads();  // r^ in LDS
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
@@ -623,7 +618,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     double thr = tol * tol * rh;  // trigger on the scaled residual, corrected at each test
     int it_n = 0;
     double rel = 1.0;
-    bool lz = LRN;      // the learned preconditioner is in use
+    bool lz = LP;       // the learned preconditioner is in use
     bool fresh = LRN;   // r^, z^ and p are to be recomputed from x^
     const int switch_at = max(1, maxit / 2);
     if (gg > 0.0) {
@@ -639,7 +634,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 it_n = maxit + 1;
                 break;
             }
-            if (LRN && lz && it_n + 1 == switch_at) {  // fallback: Jacobi from the current iterate
+            if (LP && lz && it_n + 1 == switch_at) {  // fallback: Jacobi from the current iterate
                 lz = false;
                 fresh = true;
                 continue;
@@ -678,13 +673,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                     r[i] -= alpha * q[i];  // 0 at masked items
                     t3[0] += r[i] * r[i];
                     if (!lz) q[i] = r[i];  // z^ = r^, kept in q for the direction update
-                    if (LRN && lz) {
-                        if constexpr (RG) {
-                            if (it.ok[e]) rs[it.v[e]] = r[i];
-                        } else {
-                            *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i];
-                        }
-                    }
+                    if (LP && lz) *(it.ok[e] ? &rs[it.v[e]] : &dump) = r[i];
                 }
             }
             gsum(t3);
@@ -694,7 +683,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             }
             rel = sqrt(t3[0] * rr / (rh > 0.0 ? rh : 1.0) / gg);  // estimate
             double rz_new = t3[0];
-            if (LRN && lz) {
+            if (LP && lz) {
                 double t4[1] = {0.0};
 #pragma unroll
                 for (int i0 = 0; i0 < K; i0 += G) {
@@ -814,10 +803,10 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
 // 0 .. kChipLearned - 1 only
 constexpr int kChipLearned = 6;
 
-// the learned variant of the largest class keeps r in global memory (RG)
-constexpr bool chip_rg(int c, bool lrn) { return lrn && kChipK[c] > 10; }
+// the learned variant of the largest class applies the learned initial guess only (XP)
+constexpr bool chip_xp(int c, bool lrn) { return lrn && kChipK[c] > 10; }
 static size_t chip_lds(int c, bool lrn) {
-    return (size_t)kPcgCap[c] * sizeof(double) * (lrn && !chip_rg(c, lrn) ? 2 : 1);
+    return (size_t)kPcgCap[c] * sizeof(double) * (lrn && !chip_xp(c, lrn) ? 2 : 1);
 }
 
 template <int C, bool LRN>
@@ -825,10 +814,10 @@ static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops,
     constexpr int TPB = kChipTpb[C], K = kChipK[C];
     static_assert(TPB * K >= kPcgCap[C], "class capacity");
     constexpr bool XG = K > 10;
-    constexpr bool RG = chip_rg(C, LRN);
+    constexpr bool XP = chip_xp(C, LRN);
     const size_t lds = chip_lds(C, LRN);
     if (!a) {  // preparation: the dynamic LDS of the variant (not a stream operation)
-        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG, RG>,
+        GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG, XP>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         return;
     }
@@ -837,9 +826,9 @@ static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops,
     const int64_t groups = (int64_t)n * a->LB;
     const int64_t blocks = (groups + 7) / 8 * 8 * a->S;
     GRF_REQUIRE(blocks < ((int64_t)1 << 31), "too many systems in one shift block");
-    hipLaunchKernelGGL((k_pcg_chip<TPB, K, LRN, XG, RG>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, ops[0],
-                       ops[1], ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], a->gT, a->xT, a->ug, a->its, a->res,
-                       a->LB, a->S, a->tol, a->maxit);
+    hipLaunchKernelGGL((k_pcg_chip<TPB, K, LRN, XG, XP>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, ops[0],
+                       ops[1], ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], a->gT, a->xT, a->its, a->res, a->LB,
+                       a->S, a->tol, a->maxit);
     GRF_LAUNCH_CHECK();
 }
 

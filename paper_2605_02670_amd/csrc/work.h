@@ -127,7 +127,7 @@ struct SchurArgs {
     const double *ends;   // [LB][E][2][Sp]
     const double *sd, *so;  // [LBp][E]
     double *gT, *xT;      // [LB][S][V]
-    double *ug;           // [LB][V][Sp]; during the PCG also the learned preconditioner's residual rows [LB][S][V]
+    double *ug;           // [LB][V][Sp]
     double *U;            // [nb][N][64]
     double *scr;          // PCG scratch (large graphs)
     double *ops;          // vertex operators of the block for the global-memory PCG (pcg_ops_bytes)
