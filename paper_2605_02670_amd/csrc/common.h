@@ -95,8 +95,8 @@ struct MeshView {
     int32_t maxVg, maxEg;  // largest graph of the batch (host-side dispatch)
     int64_t maxNg;
     // first four edge ends of every vertex (column-major [4][V]: the other vertex, or the
-    // vertex itself past its degree) and the degree
-    const int32_t *ell, *deg;
+    // vertex itself past its degree; eend: 2 edge + side, or -1 past the degree) and the degree
+    const int32_t *ell, *eend, *deg;
     // graphs ordered by PCG size class (kPcgCap), largest first within a class:
     // class c is gord[cls_off[c] .. cls_off[c+1]-1]; class kPcgClasses holds the
     // graphs too large for every on-chip class
@@ -132,7 +132,7 @@ struct grf_graph {
     std::vector<int64_t> segs;
     int32_t max_deg = 0, maxVg = 0, maxEg = 0;
     int64_t maxNg = 0;
-    grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_deg;
+    grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_eend, d_deg;
     std::vector<int32_t> gord;
     int32_t cls_off[grf::kPcgClasses + 2] = {};
     grf::DevBuf d_gord, d_ell16, d_ovfm;

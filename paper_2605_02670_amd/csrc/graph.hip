@@ -192,13 +192,17 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     g.max_deg = 0;
     for (int64_t u = 0; u < g.V; ++u) g.max_deg = std::max<int32_t>(g.max_deg, (int32_t)(g.vptr[u + 1] - g.vptr[u]));
-    std::vector<int32_t> ell(4 * (size_t)g.V), deg(g.V);
+    std::vector<int32_t> ell(4 * (size_t)g.V), eend(4 * (size_t)g.V), deg(g.V);
     for (int64_t u = 0; u < g.V; ++u) {
         deg[u] = (int32_t)(g.vptr[u + 1] - g.vptr[u]);
-        for (int j = 0; j < 4; ++j)
-            ell[(size_t)j * g.V + u] = j < deg[u] ? g.adj_o[g.vptr[u] + j] : (int32_t)u;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = g.vptr[u] + j;
+            ell[(size_t)j * g.V + u] = j < deg[u] ? g.adj_o[k] : (int32_t)u;
+            eend[(size_t)j * g.V + u] = j < deg[u] ? 2 * g.adj_e[k] + g.adj_s[k] : -1;
+        }
     }
     upload(g.d_ell, ell, s);
+    upload(g.d_eend, eend, s);
     upload(g.d_deg, deg, s);
     // PCG size classes, each ordered largest graph first
     std::vector<int32_t> cls(ng);
@@ -316,6 +320,7 @@ grf::MeshView grf_graph::view() const {
     v.maxEg = maxEg;
     v.maxNg = maxNg;
     v.ell = d_ell.as<int32_t>();
+    v.eend = d_eend.as<int32_t>();
     v.deg = d_deg.as<int32_t>();
     v.gord = d_gord.as<int32_t>();
     v.ell16 = d_ell16.as<uint2>();

@@ -141,19 +141,29 @@ __global__ void k_lrn_features(MeshView mv, const double *__restrict__ shift, co
     }
 }
 
-// M[l][v][c] = sum over the edge ends at v of w_e H[l][other][c]   (C channels)
+// M[l][v][c] = sum over the edge ends at v of w_e H[l][other][c]   (C channels, C % 4 == 0):
+// a thread takes four channels of a row (16-byte loads of the neighbours' rows,
+// every channel summed in CSR order)
 __global__ void k_lrn_agg(MeshView mv, const float *__restrict__ w, const float *__restrict__ H, int32_t LB, int C,
                           float *__restrict__ M) {
-    const int64_t n = (int64_t)LB * mv.V * C;
+    const int C4 = C >> 2;
+    const int64_t n = (int64_t)LB * mv.V * C4;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = i / C;
-        const int c = (int)(i - row * C);
+        const int64_t row = i / C4;
+        const int c4 = (int)(i - row * C4);
         const int l = (int)(row / mv.V), v = (int)(row - (int64_t)l * mv.V);
-        const float *Hl = H + (int64_t)l * mv.V * C;
-        float acc = 0.0f;
-        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k)
-            acc += w[(int64_t)l * mv.E + mv.adj_e[k]] * Hl[(int64_t)mv.adj_o[k] * C + c];
-        M[i] = acc;
+        const float4 *Hl = reinterpret_cast<const float4 *>(H + (int64_t)l * mv.V * C);
+        const float *wl = w + (int64_t)l * mv.E;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            const float we = wl[mv.adj_e[k]];
+            const float4 h = Hl[(int64_t)mv.adj_o[k] * C4 + c4];
+            acc.x += we * h.x;
+            acc.y += we * h.y;
+            acc.z += we * h.z;
+            acc.w += we * h.w;
+        }
+        reinterpret_cast<float4 *>(M)[i] = acc;
     }
 }
 
@@ -675,15 +685,15 @@ void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, 
     // 64 rows per workgroup pass, at most 8 workgroups per compute unit (the weights are staged once each)
     const unsigned gblocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((R + 63) / 64, 2048));
     // layer 1 (8 -> 64), 2, 3 (64 -> 64)
-    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * F_IN)), dim3(256), 0, st, mv, net.w.as<float>(),
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * F_IN / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
                        net.X0.as<float>(), LB, F_IN, net.M0.as<float>());
     hipLaunchKernelGGL((k_lrn_gemm_fwd<F_IN>), dim3(gblocks), dim3(256), 0, st, net.X0.as<float>(), net.M0.as<float>(),
                        wb + P_W1S, wb + P_W1N, w32 + P_B1, R, net.H1.as<float>());
-    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, mv, net.w.as<float>(),
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
                        net.H1.as<float>(), LB, HID, net.M1.as<float>());
     hipLaunchKernelGGL((k_lrn_gemm_fwd<HID>), dim3(gblocks), dim3(256), 0, st, net.H1.as<float>(), net.M1.as<float>(),
                        wb + P_W2S, wb + P_W2N, w32 + P_B2, R, net.H2.as<float>());
-    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, mv, net.w.as<float>(),
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
                        net.H2.as<float>(), LB, HID, net.M2.as<float>());
     hipLaunchKernelGGL((k_lrn_gemm_fwd<HID>), dim3(gblocks), dim3(256), 0, st, net.H2.as<float>(), net.M2.as<float>(),
                        wb + P_W3S, wb + P_W3N, w32 + P_B3, R, net.H3.as<float>());
@@ -819,7 +829,7 @@ double learned_backward(grf_learned &net, const MeshView &mv, const double *g, c
         hipLaunchKernelGGL((k_lrn_gemm_bwd<HID>), dim3(gblocks), dim3(256), 0, st, dZ, wb + y.ws, R, T0);
         hipLaunchKernelGGL((k_lrn_gemm_bwd<HID>), dim3(gblocks), dim3(256), 0, st, dZ, wb + y.wn, R, T1);
         float *dHin = net.dZ.as<float>();
-        hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, mv, net.w.as<float>(), T1,
+        hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(), T1,
                            LB, HID, dHin);
         // dHin += T0
         hipLaunchKernelGGL(k_lrn_reduce, dim3((unsigned)blocks_for(R * HID)), dim3(256), 0, st, T0, (int64_t)1,

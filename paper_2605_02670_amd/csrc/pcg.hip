@@ -42,7 +42,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds, int nwav
 }
 
 // g[l][s][v] = W_v + sum over edge ends at v of |b| w_end; tiles of 64 vertices
-// x 64 samples are transposed through LDS so both sides are contiguous.
+// x 64 samples are transposed through LDS so both sides are contiguous.  A
+// wavefront takes four vertices at a time with their first four edge ends from
+// the ELL table (all loads of a step in flight together); vertices of degree
+// > 4 add their remaining ends from the CSR lists.
 __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__restrict__ X,
                                                   const double *__restrict__ ends, int32_t Sp, int64_t S,
                                                   double *__restrict__ gT) {
@@ -51,20 +54,31 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     const int v0 = blockIdx.x * 64;
     const int b = blockIdx.y;
     const int l = blockIdx.z;
-    const int64_t E = mv.E;
     const bool real = (int64_t)b * 64 + lane < S;  // padding samples load nothing
-    for (int vi = wv; vi < 64; vi += 4) {
-        const int v = v0 + vi;
-        double g = 0.0;
-        if (v < mv.V && real) {
-            g = X[((int64_t)b * mv.N + mv.NI + v) * 64 + lane];
-            for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
-                const int e = mv.adj_e[k];
-                const int side = mv.adj_s[k];
-                g += ends[(((int64_t)l * E + e) * 2 + side) * Sp + (int64_t)b * 64 + lane];
-            }
+    const double *el = ends + (int64_t)l * 2 * mv.E * Sp + (int64_t)b * 64 + lane;  // row 2 e + side
+    for (int vb = wv; vb < 64; vb += 16) {
+        double g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int v = v0 + vb + 4 * q;
+            g[q] = (v < mv.V && real) ? X[((int64_t)b * mv.N + mv.NI + v) * 64 + lane] : 0.0;
         }
-        tile[vi][lane] = g;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int v = v0 + vb + 4 * q;
+                const int id = v < mv.V ? mv.eend[(int64_t)j * mv.V + v] : -1;
+                if (id >= 0 && real) g[q] += el[(int64_t)id * Sp];
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int v = v0 + vb + 4 * q;
+            if (v < mv.V && real && mv.deg[v] > 4)
+                for (int64_t k = mv.vptr[v] + 4; k < mv.vptr[v + 1]; ++k)
+                    g[q] += el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
+            tile[vb + 4 * q][lane] = g[q];
+        }
     }
     __syncthreads();
     for (int si = wv; si < 64; si += 4) {
