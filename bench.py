@@ -39,6 +39,9 @@ METRIC = "sample-shift DOF-solves/sec at 1e-6 rel err: learned+batched vs plain,
 # PCG tolerance of the batch forms: their samples stay within 1e-6 of the FP64
 # result at tolerance 1e-12 (reported with each form)
 METRIC_TOL = 1e-8
+# Adam phases (steps, learning rate) of the learned preconditioner's training, 16 shifts x 4 samples per step
+TRAIN_PHASES = ((3000, 5e-3), (3000, 2e-3), (1000, 5e-4))
+TRAIN_STEPS = sum(n for n, _ in TRAIN_PHASES)
 BATCH_WORKLOAD = "64 uneven graphs (trees + lattices, 100..20000 edges) h=1/128 beta=0.75 S=32, PCG tol 1e-8"
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64, matrix cores (dense) and vector units alike; FMA = 2 flops
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 matrix cores, dense
@@ -223,9 +226,9 @@ def train_network(seed: int = 0):
         kappas.append(float(rng.uniform(2.0, 20.0)))
     net = grf.Learned(init_params(seed))
     t0 = time.perf_counter()
-    losses = net.train(graphs, kappas, 0.75, 0.0, n_samples=4, seed=seed + 11, n_steps=400, shifts_per_step=16,
-                       lr=2e-3)
-    return net, time.perf_counter() - t0, float(losses[:40].mean()), float(losses[-40:].mean())
+    losses = np.concatenate([net.train(graphs, kappas, 0.75, 0.0, n_samples=4, seed=seed + 11 + 7 * k, n_steps=n,
+                                       shifts_per_step=16, lr=lr) for k, (n, lr) in enumerate(TRAIN_PHASES)])
+    return net, time.perf_counter() - t0, float(losses[:400].mean()), float(losses[-400:].mean())
 
 
 def _batch_rel_err(Gs, cfg, outs, ref):
@@ -415,7 +418,8 @@ def main() -> int:
         net, t_train, l0, l1 = train_network()
         bl = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=METRIC_TOL, learned=net, precision="mixed")
         bl["rel_err_vs_fp64_tol1e-12"] = _batch_rel_err(Gs, bcfg, bouts, ref)
-        bl["training"] = {"seconds": t_train, "steps": 400, "loss_first": l0, "loss_last": l1,
+        bl["training"] = {"seconds": t_train, "steps": TRAIN_STEPS, "phases": TRAIN_PHASES, "loss_first400": l0,
+                          "loss_last400": l1,
                           "graphs": "8 trees/lattices, 100..2000 edges"}
         forms["batch_learned_mixed"] = dict(bl, workload=BATCH_WORKLOAD + "; one batched call, FP32 edge sweeps, "
                                                                           "learned preconditioner")

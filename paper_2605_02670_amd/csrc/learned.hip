@@ -171,13 +171,20 @@ __global__ void k_lrn_agg(MeshView mv, const float *__restrict__ w, const float 
 // Out[r][n] = relu( sum_k A[r][k] Ws[n][k] + sum_k B[r][k] Wn[n][k] + bias[n] ), n < 64,
 // K in {8, 64}.  The workgroup stages both weight matrices in LDS once (bf16 to
 // FP32 is exact), transposed so that the sixteen lanes of a B operand read
-// consecutive words; each wavefront then loops over 16-row tiles.  Accumulator
-// item j of lane L is row 4 (L/16) + j, column L%16 of its 16x16 tile.
+// consecutive words; each wavefront then loops over 16-row tiles.  The
+// contraction runs over k in the order that makes the A loads 16-byte chunks:
+// lane L reads row L%16, columns 16 m + 4 (L/16) + j (j < 4) as one chunk per m,
+// and supplies column 16 m + 4 (L/16) + j in matrix-core step (m, j); the B
+// operand takes the same k from LDS.  Accumulator item j of lane L is row
+// 4 (L/16) + j, column L%16 of its 16x16 tile.
 template <int K>
 __global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ A, const float *__restrict__ B,
                                                       const uint16_t *__restrict__ Ws, const uint16_t *__restrict__ Wn,
                                                       const float *__restrict__ bias, int64_t R,
                                                       float *__restrict__ Out) {
+    static_assert(K % 4 == 0, "16-byte chunks");
+    constexpr int NC = K / 4;             // chunks per row
+    constexpr int CPL = NC >= 4 ? NC / 4 : 1;  // chunks per lane
     __shared__ float sW[2][K][HID];  // sW[m][k][n] = W_m[n][k]
     for (int i = threadIdx.x; i < 2 * K * HID; i += blockDim.x) {
         const int m = i / (K * HID), rem = i - m * (K * HID);
@@ -186,6 +193,7 @@ __global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ 
     }
     __syncthreads();
     const int L = threadIdx.x & 63;
+    const int q = L >> 4;  // lane group
     const int64_t ntiles = (R + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += (int64_t)gridDim.x * 4) {
         const int64_t r0 = tile * 16;
@@ -195,15 +203,22 @@ __global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ 
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            const int k = k0 + (L >> 4);
-            const float a = rok ? A[ra * K + k] : 0.0f;
-            const float b = rok ? B[ra * K + k] : 0.0f;
+        for (int m = 0; m < CPL; ++m) {
+            // chunk c = 4 m + q of the row (K = 8: chunks 0, 1 for lane groups 0, 1; groups 2, 3 add zeros)
+            const int c = 4 * m + q;
+            const bool cok = rok && c < NC;
+            const float4 a4 = cok ? reinterpret_cast<const float4 *>(A + ra * K)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 b4 = cok ? reinterpret_cast<const float4 *>(B + ra * K)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float av[4] = {a4.x, a4.y, a4.z, a4.w}, bv[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int n = 16 * t + (L & 15);
-                acc[t] = mfma32(a, sW[0][k][n], acc[t]);
-                acc[t] = mfma32(b, sW[1][k][n], acc[t]);
+            for (int j = 0; j < 4; ++j) {
+                const int k = min(4 * c + j, K - 1);  // clamped for the zero lanes of K = 8
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int n = 16 * t + (L & 15);
+                    acc[t] = mfma32(av[j], sW[0][k][n], acc[t]);
+                    acc[t] = mfma32(bv[j], sW[1][k][n], acc[t]);
+                }
             }
         }
 #pragma unroll
