@@ -72,9 +72,9 @@ HIP_KERNEL = {
 TRAFFIC_SOURCE = "paper_2605_02670_amd/csrc/blocked.hip"
 TRAFFIC_SHA256 = "b15bf4daa88be39378d78990fdb99715f354e87543e20dc5d77f2799ae370518"
 TRAFFIC = {  # kernel id: (fetch KiB, write KiB) per launch
-    "ends_fwd": (4573967.9375, 5996584.0),
-    "ends_bwd": (6639972.4375, 5980456.0),
-    "acc_fwd": (6000674.625, 4125736.0),
+    "ends_fwd": (4579871.125, 5996584.0),
+    "ends_bwd": (6625983.75, 5980456.0),
+    "acc_fwd": (5998387.8125, 4125736.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
