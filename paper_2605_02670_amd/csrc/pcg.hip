@@ -57,28 +57,35 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     const bool real = (int64_t)b * 64 + lane < S;  // padding samples load nothing
     const double *el = ends + (int64_t)l * 2 * mv.E * Sp + (int64_t)b * 64 + lane;  // row 2 e + side
     for (int vb = wv; vb < 64; vb += 16) {
-        double g[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int v = v0 + vb + 4 * q;
-            g[q] = (v < mv.V && real) ? X[((int64_t)b * mv.N + mv.NI + v) * 64 + lane] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
+        double g[4] = {0.0, 0.0, 0.0, 0.0};
+        if (real) {  // one lane mask per step; inside it no branch until the loads are issued
+            int vc[4], id[4][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int v = v0 + vb + 4 * q;
-                const int id = v < mv.V ? mv.eend[(int64_t)j * mv.V + v] : -1;
-                if (id >= 0 && real) g[q] += el[(int64_t)id * Sp];
+                vc[q] = min(v, mv.V - 1);
+                const double x = X[((int64_t)b * mv.N + mv.NI + vc[q]) * 64 + lane];
+                g[q] = v < mv.V ? x : 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) id[q][j] = v < mv.V ? mv.eend[(int64_t)j * mv.V + vc[q]] : -1;
             }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int v = v0 + vb + 4 * q;
-            if (v < mv.V && real && mv.deg[v] > 4)
-                for (int64_t k = mv.vptr[v] + 4; k < mv.vptr[v + 1]; ++k)
-                    g[q] += el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
-            tile[vb + 4 * q][lane] = g[q];
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double e = el[(int64_t)max(id[q][j], 0) * Sp];  // a valid row even past the degree
+                    g[q] += id[q][j] >= 0 ? e : 0.0;
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int v = v0 + vb + 4 * q;
+                if (v < mv.V && mv.deg[vc[q]] > 4)
+                    for (int64_t k = mv.vptr[v] + 4; k < mv.vptr[v + 1]; ++k)
+                        g[q] += el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
+            }
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tile[vb + 4 * q][lane] = g[q];
     }
     __syncthreads();
     for (int si = wv; si < 64; si += 4) {
@@ -376,6 +383,9 @@ struct GroupSum {
 #ifndef GRF_PCG_GROUP
 #define GRF_PCG_GROUP 1
 #endif
+#ifndef GRF_PCG_GROUP20
+#define GRF_PCG_GROUP20 GRF_PCG_GROUP
+#endif
 #ifndef GRF_PCG_OPAQUE_K
 #define GRF_PCG_OPAQUE_K 4
 #endif
@@ -396,7 +406,7 @@ struct ItemGroup {
         for (int g = 0; g < G; ++g) {
             int t = (int)threadIdx.x + TPB * (i0 + g);
             if constexpr (K >= GRF_PCG_OPAQUE_K) {
-                if (g % GRF_PCG_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                if (g == 0) __builtin_amdgcn_sched_barrier(0);
                 asm volatile("" : "+v"(t));
             }
             v[g] = t;
@@ -474,7 +484,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                                                   int32_t *__restrict__ its,
                                                   double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                                   int32_t maxit) {
-    constexpr int G = K >= GRF_PCG_OPAQUE_K ? GRF_PCG_GROUP : K;
+    constexpr int G = K < GRF_PCG_OPAQUE_K ? K : (K >= 20 ? GRF_PCG_GROUP20 : GRF_PCG_GROUP);
     static_assert(K % G == 0, "items per thread: a multiple of the group size");
     static_assert(!XP || LRN, "initial guess only: a learned variant");
     constexpr bool LP = LRN && !XP;  // the learned preconditioner is applied
