@@ -12,12 +12,14 @@ kernel (HIP-event durations recorded inside the timed steps), the FP64 CPU
 oracle timed on a bounded sample of the same workload, and (unless
 --no-forms) the other forms of the method measured in the same run:
   mixed                  the same lattice with FP32 edge sweeps (error vs FP64 reported);
+  nn                     the same lattice with the paper's Neumann-Neumann preconditioner;
   and on a batch of 64 uneven graphs (trees and lattices, 100..20000 edges),
   every form with its PCG at tolerance 1e-8 and its error against the FP64
   batch at tolerance 1e-12 reported (the metric counts results within 1e-6):
   batch_plain_per_graph  the plain method: one grf_sample call per graph, FP64, Jacobi,
   batch_plain            one batched call (captured graph replayed), FP64, Jacobi,
   batch_mixed            one batched call, FP32 edge sweeps, Jacobi,
+  batch_nn               one batched call, FP64, Neumann-Neumann preconditioner,
   batch_learned_mixed    one batched call, FP32 edge sweeps, learned preconditioner
                          (trained on the GPU in this run on small graphs of the same kinds).
 """
@@ -257,6 +259,8 @@ def bench_batched(args) -> int:
     if args.precond == "learned":
         net = train_network()[0]
         kw["learned"] = net
+    elif args.precond == "nn":
+        kw["precond"] = "nn"
     r = run_batched(cfg, Gs, outs, args.steps, args.warmup, **kw)
     line = {
         "metric": METRIC, "value": r["value"], "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
@@ -285,7 +289,7 @@ def main() -> int:
                     help="mixed: FP32 edge sweeps, FP64 noise/Schur/PCG/accumulation")
     ap.add_argument("--tol", type=float, default=0.0,
                     help="PCG tolerance of the batched64 workload (0: the configuration's, 1e-12)")
-    ap.add_argument("--precond", choices=["jacobi", "learned"], default="jacobi",
+    ap.add_argument("--precond", choices=["jacobi", "learned", "nn"], default="jacobi",
                     help="vertex PCG preconditioner of the batched64 workload (learned: trained first, on the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed / batched / learned forms")
@@ -396,6 +400,21 @@ def main() -> int:
         r_ = out.cpu().numpy()
         errm = float(np.max(np.sqrt((d * d * ML).sum(1) / (r_ * r_ * ML).sum(1))))
         forms["mixed"] = {"value": G.n_dof * L * S / dtm, "ms_per_step": dtm * 1e3, "rel_err_vs_fp64": errm}
+        # the paper's Neumann-Neumann preconditioner on the same lattice (FP64)
+        kwn = dict(kw, precond="nn")
+        for _ in range(args.warmup):
+            G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=outm, **kwn)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stn = [G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=outm, **kwn)[1]
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dtn = (time.perf_counter() - t0) / args.steps
+        d = (outm - out).cpu().numpy()
+        forms["nn"] = {"value": G.n_dof * L * S / dtn, "ms_per_step": dtn * 1e3,
+                       "rel_err_vs_jacobi": float(np.max(np.sqrt((d * d * ML).sum(1) / (r_ * r_ * ML).sum(1)))),
+                       "pcg": {"max_iterations": max(s_["max_iterations"] for s_ in stn),
+                               "mean_iterations": stn[0]["total_iterations"] / max(1, stn[0]["n_systems"])}}
         del outm
         # the 64-graph batch, every form at the metric's accuracy: PCG tolerance
         # METRIC_TOL, error against the FP64 batch at tol 1e-12 reported
@@ -410,11 +429,12 @@ def main() -> int:
         del pg_outs
         forms["batch_plain_per_graph"] = dict(pg, workload=BATCH_WORKLOAD + "; plain method: one grf_sample per "
                                                                             "graph, FP64, Jacobi")
-        for name, kwb in (("batch_plain", {}), ("batch_mixed", {"precision": "mixed"})):
+        for name, kwb, what in (("batch_plain", {}, "FP64, Jacobi"),
+                                ("batch_mixed", {"precision": "mixed"}, "FP32 edge sweeps, Jacobi"),
+                                ("batch_nn", {"precond": "nn"}, "FP64, Neumann-Neumann preconditioner")):
             r_ = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=METRIC_TOL, **kwb)
             r_["rel_err_vs_fp64_tol1e-12"] = _batch_rel_err(Gs, bcfg, bouts, ref)
-            forms[name] = dict(r_, workload=BATCH_WORKLOAD + "; one batched call, "
-                               + ("FP32 edge sweeps" if kwb else "FP64") + ", Jacobi")
+            forms[name] = dict(r_, workload=BATCH_WORKLOAD + "; one batched call, " + what)
         net, t_train, l0, l1 = train_network()
         bl = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=METRIC_TOL, learned=net, precision="mixed")
         bl["rel_err_vs_fp64_tol1e-12"] = _batch_rel_err(Gs, bcfg, bouts, ref)
@@ -425,7 +445,8 @@ def main() -> int:
                                                                           "learned preconditioner")
         base = forms["batch_plain_per_graph"]["value"]
         forms["batch_speedup_vs_plain_per_graph"] = {k: forms[k]["value"] / base for k in
-                                                     ("batch_plain", "batch_mixed", "batch_learned_mixed")}
+                                                     ("batch_plain", "batch_mixed", "batch_nn",
+                                                      "batch_learned_mixed")}
     line = {
         "metric": METRIC, "value": value, "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",

@@ -63,6 +63,8 @@ typedef enum grf_status {
 /* grf_opts.precond */
 #define GRF_PRECOND_JACOBI 0  /* diagonal of the vertex Schur complement */
 #define GRF_PRECOND_LEARNED 1 /* learned diagonal-plus-neighbour operator (opts->learned) */
+#define GRF_PRECOND_NN 2      /* Neumann-Neumann: D^{-1} (sum_e S_e^{-1}) D^{-1}, D = diag(edge ends at v),
+                                 S_e the edge's 2x2 Schur block (Phase 4, "The Neumann Step"); x0 = 0 */
 
 typedef struct grf_graph grf_graph;
 typedef struct grf_learned grf_learned;

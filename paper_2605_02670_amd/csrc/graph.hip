@@ -282,7 +282,8 @@ grf_opts resolve_opts(const grf_opts *o) {
     GRF_REQUIRE(std::isfinite(r.tol) && r.tol > 0, "tol must be > 0");
     GRF_REQUIRE(r.maxit >= 1, "maxit must be >= 1");
     GRF_REQUIRE(r.precision == GRF_PREC_FP64 || r.precision == GRF_PREC_MIXED, "unknown precision");
-    GRF_REQUIRE(r.precond == GRF_PRECOND_JACOBI || r.precond == GRF_PRECOND_LEARNED, "unknown precond");
+    GRF_REQUIRE(r.precond == GRF_PRECOND_JACOBI || r.precond == GRF_PRECOND_LEARNED || r.precond == GRF_PRECOND_NN,
+                "unknown precond");
     GRF_REQUIRE(r.precond != GRF_PRECOND_LEARNED || r.learned, "learned preconditioner needs opts->learned");
     GRF_REQUIRE(r.sample_offset >= 0, "sample_offset must be >= 0");
     GRF_REQUIRE(r.sweep_block == 0 || r.sweep_block == 8 || r.sweep_block == 16 || r.sweep_block == 32 ||

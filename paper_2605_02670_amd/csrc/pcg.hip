@@ -126,48 +126,70 @@ __global__ void k_ell_diag(MeshView mv, const double *__restrict__ sd, const dou
     }
 }
 
-// ELL rows of S^ = H S H (and of P^, Q^ with the learned preconditioner)
-__global__ void k_ell_ops(MeshView mv, const double *__restrict__ so, int32_t LB, EllOp S, int32_t lrn,
-                          LearnedOps lo, EllOp P, EllOp Q) {
+// ELL rows of S^ = H S H, and of the operator preconditioner of the mode:
+// learned (PM_LEARNED): P^ and Q^ from the network's per-vertex and per-edge
+// outputs, already on the scaled system; Neumann-Neumann (PM_NN): P^ = H^{-1}
+// D^{-1} (sum_e S_e^{-1}) D^{-1} H^{-1} (Phase 4, the Neumann step, in its closed
+// form), D = diag(d_u) with d_u the edge ends at u, S_e^{-1} =
+// [[sd, -so], [-so, sd]] / ((sd - so)(sd + so)) for the edge's 2x2 Schur block
+// (eq. local_reduced_schur); a self-loop slot adds its whole block row to the
+// diagonal.  Q is not written for PM_NN (initial guess 0).
+enum { PM_JACOBI = 0, PM_LEARNED = 1, PM_NN = 2 };
+
+__global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
+                          EllOp S, int32_t pm, LearnedOps lo, EllOp P, EllOp Q) {
     const int64_t n = (int64_t)LB * mv.V;
     const int64_t E2 = 2 * (int64_t)mv.E;
+    const bool lrn = pm == PM_LEARNED, opP = pm != PM_JACOBI;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(i / mv.V), u = (int)(i - (int64_t)l * mv.V);
-        const double *sol = so + (int64_t)l * mv.E;
+        const double *sdl = sd + (int64_t)l * mv.E, *sol = so + (int64_t)l * mv.E;
         const double *hl = S.dh + (int64_t)l * mv.V;
         const double hu = hl[u];
         const int64_t k0 = mv.vptr[u], k1 = mv.vptr[u + 1];
+        const double du = (double)(k1 - k0);
+        double pdiag = 0.0;  // PM_NN: sum over the slots of (D^-1 S_e^-1 D^-1)_uu
         for (int64_t k = k0; k < k1; ++k) {
             const int e = mv.adj_e[k];
             const int o = mv.adj_o[k];
             const double c = (o == u) ? 0.0 : hu * sol[e] * hl[o];
-            const double cp = (lrn && o != u) ? lo.Pq[(int64_t)l * mv.E + e] : 0.0;
-            const double cq = (lrn && o != u) ? lo.Qe[(int64_t)l * mv.E + e] : 0.0;
+            double cp = 0.0, cq = 0.0;
+            if (lrn && o != u) {
+                cp = lo.Pq[(int64_t)l * mv.E + e];
+                cq = lo.Qe[(int64_t)l * mv.E + e];
+            } else if (pm == PM_NN) {
+                const double sde = sdl[e], soe = sol[e];
+                const double det = (sde - soe) * (sde + soe);
+                const double isd = sde / det, iso = -soe / det;
+                if (o == u) {
+                    pdiag += (isd + iso) / (du * du);
+                } else {
+                    pdiag += isd / (du * du);
+                    const double dov = (double)(mv.vptr[o + 1] - mv.vptr[o]);
+                    cp = iso / (du * dov * hu * hl[o]);
+                }
+            }
             const int j = (int)(k - k0);
             if (j < 4) {
                 S.coef[((int64_t)l * mv.V + u) * 4 + j] = c;
-                if (lrn) {
-                    P.coef[((int64_t)l * mv.V + u) * 4 + j] = cp;
-                    Q.coef[((int64_t)l * mv.V + u) * 4 + j] = cq;
-                }
+                if (opP) P.coef[((int64_t)l * mv.V + u) * 4 + j] = cp;
+                if (lrn) Q.coef[((int64_t)l * mv.V + u) * 4 + j] = cq;
             } else {
                 S.ovf[(int64_t)l * E2 + k] = c;
-                if (lrn) {
-                    P.ovf[(int64_t)l * E2 + k] = cp;
-                    Q.ovf[(int64_t)l * E2 + k] = cq;
-                }
+                if (opP) P.ovf[(int64_t)l * E2 + k] = cp;
+                if (lrn) Q.ovf[(int64_t)l * E2 + k] = cq;
             }
         }
         for (int j = (int)(k1 - k0); j < 4; ++j) {
             S.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
-            if (lrn) {
-                P.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
-                Q.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
-            }
+            if (opP) P.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
+            if (lrn) Q.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
         }
         if (lrn) {
             P.diag[i] = lo.Pd[i];
             Q.diag[i] = lo.Qd[i];
+        } else if (pm == PM_NN) {
+            P.diag[i] = pdiag / (hu * hu);
         }
     }
 }
@@ -193,8 +215,9 @@ __device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__
 // vectors in global scratch (x^, r^, p, q: 4 maxVg doubles per resident
 // workgroup), for graphs too large for the on-chip kernel.  The vectors of
 // system (g, l, s) are the graph's vertex range of gT / xT[l][s]; its
-// statistics go to its / res[(g * LB + l) * S + s].  LRN: the learned
-// preconditioner z^ = P^ r^ and initial guess x0^ = Q^ g^, with the Jacobi
+// statistics go to its / res[(g * LB + l) * S + s].  LRN: an operator
+// preconditioner z^ = P^ r^ (learned or Neumann-Neumann) and the initial guess
+// x0^ = Q^ g^ (learned; x0^ = 0 when Qop.diag is null), with the Jacobi
 // fallback after maxit / 2 iterations (restart from the current iterate);
 // otherwise CG on S^ (Jacobi) from x^ = 0.  Either way the residual g - S x
 // recomputed from x decides convergence; the scaled recursive residual only
@@ -240,10 +263,11 @@ __global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp P
         const double gg = t0[0];
         const double tol2 = tol * tol * gg;
         double thr = tol * tol * t0[1];  // trigger on ||r^||^2
+        const bool hq = LRN && Qop.diag != nullptr;
         for (int v = threadIdx.x; v < V; v += blockDim.x)
-            x[v] = LRN ? ell_apply<false>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
-                                          Qop.ovf + (int64_t)l * E2, r, u0 + v, u0)
-                       : 0.0;
+            x[v] = hq ? ell_apply<false>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
+                                         Qop.ovf + (int64_t)l * E2, r, u0 + v, u0)
+                      : 0.0;
         int it = 0;
         double rel = 0.0;
         // r^ = g^ - S^ x^ and z^ = M r^ into p; returns (r^.z^, ||r||^2, ||r^||^2)
@@ -468,8 +492,9 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
 // its output row of xT instead (the largest class, where K doubles fewer
 // registers decide whether the kernel spills), updated by FP64 atomic adds
 // that return nothing, so no wavefront waits on the row (x^ has one writer per
-// entry, its owner thread, so the sum is the same as in registers).  LRN: the
-// learned initial guess x^0 = Q^ g^ and preconditioner z^ = P^ r^; P^ reads the
+// entry, its owner thread, so the sum is the same as in registers).  LRN: an
+// operator preconditioner z^ = P^ r^ (learned or Neumann-Neumann) and the
+// initial guess x^0 = Q^ g^ (learned; 0 when Qop.diag is null); P^ reads the
 // neighbours' residuals, so r^ is also kept in LDS (2 cap doubles).  XP (the
 // largest class, whose p fills the LDS): the learned initial guess only, with
 // the Jacobi preconditioner.  The operator
@@ -487,7 +512,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     constexpr int G = K < GRF_PCG_OPAQUE_K ? K : (K >= 20 ? GRF_PCG_GROUP20 : GRF_PCG_GROUP);
     static_assert(K % G == 0, "items per thread: a multiple of the group size");
     static_assert(!XP || LRN, "initial guess only: a learned variant");
-    constexpr bool LP = LRN && !XP;  // the learned preconditioner is applied
+    constexpr bool LP = LRN && !XP;  // the operator preconditioner is applied
     using IG = ItemGroup<TPB, K, G>;
     extern __shared__ double sv[];  // p [cap], r [cap] (LP)
     __shared__ double red[96];
@@ -588,7 +613,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
         rh = t[2];
     };
 
-    // ||g||^2 and ||g^||^2; Jacobi: x^0 = 0, r^ = p = g^; learned: x^0 = Q^ g^ (g^ staged in LDS)
+    // ||g||^2 and ||g^||^2; Jacobi: x^0 = 0, r^ = p = g^; LRN: x^0 = Q^ g^ (g^ staged in LDS) or 0
     double rz, rr, rh, gg;
     {
         double t[2] = {0.0, 0.0};
@@ -613,7 +638,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 }
             }
         }
-        if constexpr (LRN) {
+        if (LRN && Qop.diag != nullptr) {
             __syncthreads();  // g^ in LDS
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
@@ -642,7 +667,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     double thr = tol * tol * rh;  // trigger on the scaled residual, corrected at each test
     int it_n = 0;
     double rel = 1.0;
-    bool lz = LP;       // the learned preconditioner is in use
+    bool lz = LP;       // the operator preconditioner is in use
     bool fresh = LRN;   // r^, z^ and p are to be recomputed from x^
     const int switch_at = max(1, maxit / 2);
     if (gg > 0.0) {
@@ -811,8 +836,9 @@ static size_t ell_op_doubles(const MeshView &mv, int32_t LB) {
     return (size_t)LB * (6 * (size_t)mv.V + 2 * (size_t)mv.E);
 }
 
-size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, bool learned) {
-    return (learned ? 3 : 1) * ell_op_doubles(mv, LB) * sizeof(double) + 64;
+size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, int32_t precond) {
+    const int n = precond == GRF_PRECOND_LEARNED ? 3 : precond == GRF_PRECOND_NN ? 2 : 1;  // S^, P^, Q^
+    return n * ell_op_doubles(mv, LB) * sizeof(double) + 64;
 }
 
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
@@ -824,8 +850,11 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
 }
 
 // the learned variant keeps two vectors in LDS and runs on the size classes
-// 0 .. kChipLearned - 1 only
+// 0 .. kChipLearned - 1 only; the Neumann-Neumann preconditioner needs both
+// vectors in every class, so its graphs beyond class kChipNN - 1 take the
+// global-memory kernel
 constexpr int kChipLearned = 6;
+constexpr int kChipNN = 5;
 
 // the learned variant of the largest class applies the learned initial guess only (XP)
 constexpr bool chip_xp(int c, bool lrn) { return lrn && kChipK[c] > 10; }
@@ -856,14 +885,15 @@ static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops,
     GRF_LAUNCH_CHECK();
 }
 
+// the classes 0 .. nc - 1
 template <bool LRN>
-static void chip_all(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st) {
-    chip_class<0, LRN>(mv, a, ops, st);
-    chip_class<1, LRN>(mv, a, ops, st);
-    chip_class<2, LRN>(mv, a, ops, st);
-    chip_class<3, LRN>(mv, a, ops, st);
-    chip_class<4, LRN>(mv, a, ops, st);
-    chip_class<5, LRN>(mv, a, ops, st);
+static void chip_all(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st, int nc = kPcgClasses) {
+    if (nc > 0) chip_class<0, LRN>(mv, a, ops, st);
+    if (nc > 1) chip_class<1, LRN>(mv, a, ops, st);
+    if (nc > 2) chip_class<2, LRN>(mv, a, ops, st);
+    if (nc > 3) chip_class<3, LRN>(mv, a, ops, st);
+    if (nc > 4) chip_class<4, LRN>(mv, a, ops, st);
+    if (nc > 5) chip_class<5, LRN>(mv, a, ops, st);
 }
 
 void prepare_pcg(const MeshView &mv) {
@@ -876,7 +906,9 @@ void prepare_pcg(const MeshView &mv) {
 
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
-    const bool lrn = a.learned != nullptr;
+    const int32_t pm = a.precond == GRF_PRECOND_LEARNED ? PM_LEARNED : a.precond == GRF_PRECOND_NN ? PM_NN : PM_JACOBI;
+    GRF_REQUIRE(pm != PM_LEARNED || a.learned, "internal: learned operators missing");
+    const bool lrn = pm != PM_JACOBI;  // an operator preconditioner (the LRN kernels)
     const size_t per = ell_op_doubles(mv, a.LB);
     EllOp ops[3];
     for (int i = 0; i < 3; ++i) {
@@ -884,18 +916,19 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
         ops[i] = EllOp{base, base + (size_t)a.LB * mv.V, base + 2 * (size_t)a.LB * mv.V,
                        base + 6 * (size_t)a.LB * mv.V};
     }
-    const LearnedOps lo = lrn ? *a.learned : LearnedOps{};
+    if (pm == PM_NN) ops[2] = EllOp{nullptr, nullptr, nullptr, nullptr};  // no initial-guess operator
+    const LearnedOps lo = pm == PM_LEARNED ? *a.learned : LearnedOps{};
     const int64_t n = (int64_t)a.LB * mv.V;
     const dim3 eg((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)));
     hipLaunchKernelGGL(k_ell_diag, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0].dh);
-    hipLaunchKernelGGL(k_ell_ops, eg, dim3(256), 0, st, mv, a.so, a.LB, ops[0], lrn ? 1 : 0, lo, ops[1], ops[2]);
+    hipLaunchKernelGGL(k_ell_ops, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0], pm, lo, ops[1], ops[2]);
     GRF_LAUNCH_CHECK();
+    const int c0 = pm == PM_LEARNED ? kChipLearned : pm == PM_NN ? kChipNN : kPcgClasses;
     if (lrn)
-        chip_all<true>(mv, &a, ops, st);
+        chip_all<true>(mv, &a, ops, st, c0);
     else
         chip_all<false>(mv, &a, ops, st);
     // graphs beyond the on-chip classes
-    const int c0 = lrn ? kChipLearned : kPcgClasses;
     const int32_t ngl = mv.cls_off[kPcgClasses + 1] - mv.cls_off[c0];
     if (ngl == 0) return;
     const int64_t nsys = (int64_t)ngl * a.LB * a.S;

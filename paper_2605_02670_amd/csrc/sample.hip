@@ -145,7 +145,7 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     w.its.reserve(4 * (size_t)ps.ng * ps.L * S);
     w.res.reserve(8 * (size_t)ps.ng * ps.L * S);
     w.pcg_scr.reserve(pcg_scratch_bytes(mv, ps.p.pcg_blocks));
-    w.pcg_ops.reserve(pcg_ops_bytes(mv, lb, o.precond == GRF_PRECOND_LEARNED));
+    w.pcg_ops.reserve(pcg_ops_bytes(mv, lb, o.precond));
     prepare_pcg(mv);
     if (o.precond == GRF_PRECOND_LEARNED) learned_reserve(*const_cast<grf_learned *>(o.learned), mv, LBp);
     GRF_HIP(hipStreamSynchronize(st));  // uploads from host memory complete
@@ -262,6 +262,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.tol = o.tol;
         sc.maxit = o.maxit;
         sc.pcg_blocks = p.pcg_blocks;
+        sc.precond = o.precond;
         LearnedOps lops{};
         if (o.precond == GRF_PRECOND_LEARNED) {
             grf_learned &net = *const_cast<grf_learned *>(o.learned);

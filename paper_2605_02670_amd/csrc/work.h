@@ -138,13 +138,14 @@ struct SchurArgs {
     double tol;
     int32_t maxit;
     int32_t pcg_blocks;   // resident workgroups for the global-memory PCG
-    const LearnedOps *learned;  // learned preconditioner and initial guess of this block, or null (Jacobi)
+    int32_t precond;            // GRF_PRECOND_* of the solve
+    const LearnedOps *learned;  // learned preconditioner and initial guess of this block (GRF_PRECOND_LEARNED)
 };
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void prepare_pcg(const MeshView &mv);  // one-time kernel attributes, before any graph capture
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);
-size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, bool learned);
+size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, int32_t precond);
 
 }  // namespace grf

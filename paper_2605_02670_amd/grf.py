@@ -19,7 +19,7 @@ _lib = None
 GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP = 0, -1, -2, -3, -4, -5
 MESH = {"ceil": 0, "round": 1}
 PREC = {"fp64": 0, "mixed": 1}
-PRECOND = {"jacobi": 0, "learned": 1}
+PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
 KERNELS = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd",
            "layout", "mixed", "learned"]
 

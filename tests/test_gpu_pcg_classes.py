@@ -4,9 +4,10 @@ graph is beyond every on-chip class and takes the global-memory kernel), so
 every on-chip variant and the fallback solve systems of the same call.
 
 Bars: each graph's batched sample equals the FP64 oracle to 1e-10 relative
-in the lumped-mass norm, with the Jacobi and with the learned
-preconditioner (an untrained network: its Jacobi fallback and the true
-residual still decide convergence); every system converges.
+in the lumped-mass norm, with the Jacobi, the learned (an untrained network:
+its Jacobi fallback and the true residual still decide convergence) and the
+Neumann-Neumann preconditioner (on chip up to 10176 vertices, in the
+global-memory kernel beyond); every system converges.
 """
 
 import numpy as np
@@ -45,22 +46,27 @@ def batch(grf):
     return Gs, kappas, refs
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "learned"])
+@pytest.mark.parametrize("precond", ["jacobi", "learned", "nn"])
 def test_every_class_matches_oracle(grf, batch, precond):
     Gs, kappas, refs = batch
-    net = None
-    if precond == "learned":
-        # the same handles were just run with Jacobi: the learned call must not replay
+    net, kw, st_j = None, {}, None
+    if precond != "jacobi":
+        # the same handles were just run with Jacobi: this call must not replay
         # that captured graph (its iteration total differs)
         _, st_j = grf.sample_batched(Gs, kappas, BETA, K, S, SEED)
+    if precond == "learned":
         net = grf.Learned(init_params(7, head_scale=0.5))
+        kw = dict(learned=net)
+    elif precond == "nn":
+        kw = dict(precond="nn")
     try:
-        outs, st = grf.sample_batched(Gs, kappas, BETA, K, S, SEED, learned=net)
+        outs, st = grf.sample_batched(Gs, kappas, BETA, K, S, SEED, **kw)
     finally:
         if net is not None:
             net.close()
     assert st["n_unconverged"] == 0
-    if precond == "learned":
+    if st_j is not None:
+        print(f"{precond}: {st['total_iterations']} iterations, Jacobi {st_j['total_iterations']}", flush=True)
         assert st["total_iterations"] != st_j["total_iterations"]
     for n, u, (ML, ref) in zip(SIZES, outs, refs):
         err = _rel_ml(u.cpu().numpy(), ref, ML)
