@@ -171,7 +171,8 @@ def run_batched(cfg, Gs, outs, steps: int, warmup: int, **kw) -> dict:
     return {"value": ndof * L * S / dt, "ms_per_step": dt * 1e3, "first_call_s": first, "n_dof": ndof,
             "shifts": L, "samples": S, "graphs": len(Gs),
             "pcg": {"max_iterations": max(s_["max_iterations"] for s_ in stats),
-                    "mean_iterations": stats[0]["total_iterations"] / max(1, stats[0]["n_systems"])}}
+                    "mean_iterations": stats[0]["total_iterations"] / max(1, stats[0]["n_systems"]),
+                    "class_variants": grf.class_modes(stats[0]["pcg_class_modes"])}}
 
 
 def run_per_graph(cfg, steps: int, **kw):

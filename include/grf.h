@@ -60,6 +60,9 @@ typedef enum grf_status {
 #define GRF_PREC_FP64 0  /* every step in FP64 */
 #define GRF_PREC_MIXED 1 /* FP32 edge sweeps, FP64 Schur/PCG/residual/accumulation, refinement */
 
+/* grf_opts.pcg_class_modes: marks the per-class variants as given */
+#define GRF_PCG_MODES_SET (1 << 12)
+
 /* grf_opts.precond */
 #define GRF_PRECOND_JACOBI 0  /* diagonal of the vertex Schur complement */
 #define GRF_PRECOND_LEARNED 1 /* learned diagonal-plus-neighbour operator (opts->learned) */
@@ -97,7 +100,8 @@ typedef struct grf_stats {
     int32_t refine_steps;       /* mixed precision: refinement sweeps run */
     int32_t shift_block;        /* shifts processed per pass (as planned) */
     int32_t sweep_block;        /* shifts held per wavefront in the sweeps */
-    int32_t reserved;
+    int32_t pcg_class_modes;    /* grf_sample_batched: on-chip PCG variant of size class c in bits 2c..2c+1
+                                   (0 operator preconditioner, 1 learned initial guess only, 2 Jacobi) */
     double kernel_ms[12];       /* with opts.timing: summed HIP-event time per grf_kernel_id */
     int32_t kernel_launches[12];/* with opts.timing: launches per grf_kernel_id */
 } grf_stats;
@@ -114,7 +118,10 @@ typedef struct grf_opts {
     int32_t sweep_block;   /* shifts per wavefront in the sweeps: 0 (auto), 8, 16, 32, 64 */
     int32_t refine;        /* mixed precision: max refinement sweeps; < 0 = default (2) */
     int32_t timing;        /* 1: time every kernel with HIP events into stats->kernel_ms */
-    int32_t reserved0;
+    int32_t pcg_class_modes; /* learned preconditioner only: 0 = automatic (grf_sample_batched times the
+                                three on-chip PCG variants per size class once and keeps the fastest;
+                                elsewhere the default); or GRF_PCG_MODES_SET | (variant of class c)
+                                << 2c, variants as in grf_stats.pcg_class_modes (0 only for c < 5) */
     int64_t sample_offset; /* global index of the first sample (noise key) */
     void *stream;          /* hipStream_t; NULL = null stream */
     const grf_learned *learned; /* required when precond = GRF_PRECOND_LEARNED */
@@ -241,6 +248,9 @@ int grf_learned_loss_grad(grf_learned *net, grf_graph *g, double kappa, double c
  * schedule (beta, quad_step) to collect (g, x) pairs, then takes n_steps Adam
  * steps (learning rate lr), step t on graph t mod n_graphs and a window of
  * shifts_per_step consecutive shifts.  losses (host, [n_steps]) may be NULL.
+ * Each graph's sampling workspace is released once its pairs are collected (a
+ * later grf_sample on it allocates again); the pairs stay on the device until
+ * the call returns.
  */
 int grf_learned_train(grf_learned *net, grf_graph *const *graphs, int32_t n_graphs,
                       const double *kappas, double beta, double quad_step, int64_t n_samples,

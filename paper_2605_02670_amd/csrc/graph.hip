@@ -286,6 +286,14 @@ grf_opts resolve_opts(const grf_opts *o) {
                 "unknown precond");
     GRF_REQUIRE(r.precond != GRF_PRECOND_LEARNED || r.learned, "learned preconditioner needs opts->learned");
     GRF_REQUIRE(r.sample_offset >= 0, "sample_offset must be >= 0");
+    if (r.pcg_class_modes != 0) {
+        GRF_REQUIRE(r.precond == GRF_PRECOND_LEARNED, "pcg_class_modes is for the learned preconditioner");
+        GRF_REQUIRE((r.pcg_class_modes & ~(GRF_PCG_MODES_SET | 0xfff)) == 0 && (r.pcg_class_modes & GRF_PCG_MODES_SET),
+                    "pcg_class_modes: GRF_PCG_MODES_SET | 2-bit variants of the 6 size classes");
+        for (int c = 0; c < kPcgClasses; ++c)
+            GRF_REQUIRE(chip_mode_valid(c, (r.pcg_class_modes >> (2 * c)) & 3),
+                        "pcg_class_modes: variant %d is not available in size class %d", (r.pcg_class_modes >> (2 * c)) & 3, c);
+    }
     GRF_REQUIRE(r.sweep_block == 0 || r.sweep_block == 8 || r.sweep_block == 16 || r.sweep_block == 32 ||
                     r.sweep_block == 64,
                 "sweep_block must be 0, 8, 16, 32 or 64");

@@ -11,6 +11,7 @@
 // diagonal of S); stop when ||g - S x||_2 <= tol ||g||_2 on the residual
 // recomputed from x; g = 0 gives x = 0.
 #include <algorithm>
+#include <type_traits>
 
 #include "work.h"
 
@@ -211,159 +212,281 @@ __device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__
     return acc;
 }
 
-// One workgroup per (graph, shift, sample) system of the graphs glist[0 .. ngl-1],
-// vectors in global scratch (x^, r^, p, q: 4 maxVg doubles per resident
-// workgroup), for graphs too large for the on-chip kernel.  The vectors of
-// system (g, l, s) are the graph's vertex range of gT / xT[l][s]; its
-// statistics go to its / res[(g * LB + l) * S + s].  LRN: an operator
-// preconditioner z^ = P^ r^ (learned or Neumann-Neumann) and the initial guess
-// x0^ = Q^ g^ (learned; x0^ = 0 when Qop.diag is null), with the Jacobi
-// fallback after maxit / 2 iterations (restart from the current iterate);
-// otherwise CG on S^ (Jacobi) from x^ = 0.  Either way the residual g - S x
-// recomputed from x decides convergence; the scaled recursive residual only
-// triggers that test, at a threshold corrected by the ratio of the true to the
-// scaled residual norm measured at the last test.
-template <bool LRN>
-__global__ void __launch_bounds__(256) k_pcg_ell(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
-                                                 const int32_t *__restrict__ glist, int32_t ngl,
-                                                 const double *__restrict__ gT, double *__restrict__ xT,
-                                                 double *__restrict__ scr, int32_t *__restrict__ its,
-                                                 double *__restrict__ res, int32_t LB, int64_t S, double tol,
-                                                 int32_t maxit) {
-    __shared__ double red[64];
-    const int nw = blockDim.x >> 6;
-    double *x = scr + (int64_t)blockIdx.x * 4 * mv.maxVg;
-    double *r = x + mv.maxVg, *p = r + mv.maxVg, *q = p + mv.maxVg;
-    const int64_t nsys = (int64_t)ngl * LB * S;
+// Sums of NV per-system values over a workgroup whose thread t works for system
+// (sample) t % SB: every thread gets the sum of its own system.  Inside a
+// wavefront the lanes of one system are combined by an xor butterfly (every
+// lane ends with the same value); the wavefronts' partials are added through
+// LDS in a fixed order, so the result is deterministic.  Two LDS buffers taken
+// in turn (a buffer is written again only two sums later, after the barrier of
+// the sum in between), so one barrier per sum.
+template <int TPB, int SB>
+struct SampleSum {
+    static constexpr int NW = TPB / 64;
+    double *lds;  // [2][4][NW][SB]
+    int buf;
+    template <int NV>
+    __device__ __forceinline__ void operator()(double (&v)[NV]) {
+        static_assert(NV <= 4, "at most four values per sum");
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int o = SB; o < 64; o <<= 1) v[i] += __shfl_xor(v[i], o, 64);
+        double *b = lds + buf * 4 * NW * SB;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (lane < SB) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) b[(i * NW + w) * SB + lane] = v[i];
+        }
+        __syncthreads();
+        const int s = threadIdx.x % SB;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double t = 0.0;
+            for (int k = 0; k < NW; ++k) t += b[(i * NW + k) * SB + s];
+            v[i] = t;
+        }
+        buf ^= 1;
+    }
+};
+
+// Vertex PCG for the graphs glist[0 .. ngl-1] that no on-chip variant takes:
+// one workgroup per (graph, shift, block of SB samples), the SB systems of a
+// block solved side by side.  Thread t works for sample t % SB at the local
+// vertices t / SB + VS i (VS = TPB / SB).  The vectors g^, x^, r^, p and q of the
+// block live in global scratch as [vertex][SB] rows (5 maxVg SB doubles per
+// resident workgroup), so a neighbour gather reads one contiguous row of SB
+// values and each operator row is read once for SB systems.  The systems of
+// (g, l, s) are the graph's vertex range of gT / xT[l][s]; statistics go to
+// its / res[(g * LB + l) * S + s].
+//
+// Every system keeps its own scalars, stopping test and restarts, as in the
+// on-chip kernel: CG on S^ from x^ = 0 (Jacobi), or with LRN the operator
+// preconditioner z^ = P^ r^ and the initial guess x0^ = Q^ g^ (none when
+// Qop.diag is null), with the Jacobi fallback after maxit / 2 iterations.  The
+// residual g - S x recomputed from x decides convergence; the scaled
+// recursive residual only triggers that test.  A converged system stops
+// changing while the others go on.  Loop control: after each decision the
+// first thread of each system posts in LDS whether it is still active and
+// whether it asks for the true-residual step; the barrier at the top of the
+// loop makes the flags visible, and every thread reads all of them, so all
+// threads take the same branches.
+template <int SB, bool LRN>
+__global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
+                                                   const int32_t *__restrict__ glist, int32_t ngl,
+                                                   const double *__restrict__ gT, double *__restrict__ xT,
+                                                   double *__restrict__ scr, int32_t *__restrict__ its,
+                                                   double *__restrict__ res, int32_t LB, int64_t S, double tol,
+                                                   int32_t maxit) {
+    constexpr int TPB = 1024, VS = TPB / SB;
+    static_assert(SB >= 1 && SB <= 64 && (64 % SB) == 0, "samples per block divide a wavefront");
+    __shared__ double red[2 * 4 * (TPB / 64) * SB];
+    __shared__ int32_t flag[2][SB];  // [0][s]: system s active; [1][s]: it asks for the true-residual step
+    SampleSum<TPB, SB> ssum{red, 0};
+    const int s = threadIdx.x % SB, vs = threadIdx.x / SB;
     const int64_t E2 = 2 * (int64_t)mv.E;
+    const int64_t nsb = (S + SB - 1) / SB;
+    const int64_t nunits = (int64_t)ngl * LB * nsb;
+    const int64_t rowlen = (int64_t)mv.maxVg * SB;
+    double *Gh = scr + (int64_t)blockIdx.x * 5 * rowlen;
+    double *X = Gh + rowlen, *R = X + rowlen, *P = R + rowlen, *Q = P + rowlen;
     const int switch_at = max(1, maxit / 2);
-    for (int64_t lsys = blockIdx.x; lsys < nsys; lsys += gridDim.x) {
-        const int64_t tl = lsys / S;
-        const int64_t smp = lsys - tl * S;
+    for (int64_t unit = blockIdx.x; unit < nunits; unit += gridDim.x) {
+        const int64_t tl = unit / nsb;
+        const int64_t smp = (unit - tl * nsb) * SB + s;
+        const bool live = smp < S;
         const int l = (int)(tl % LB);
         const int gi = glist[tl / LB];
-        const int64_t sys = ((int64_t)gi * LB + l) * S + smp;
         const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
-        const double *g = gT + ((int64_t)l * S + smp) * mv.V + u0;
-        const double *Sc = Sop.coef + (int64_t)l * 4 * mv.V, *So = Sop.ovf + (int64_t)l * E2,
-                     *H = Sop.dh + (int64_t)l * mv.V + u0;
+        const double *H = Sop.dh + (int64_t)l * mv.V + u0;
+        const double *Sc = Sop.coef + (int64_t)l * 4 * mv.V, *So = Sop.ovf + (int64_t)l * E2;
         const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
         const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
         const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
-        bool learned = LRN;
-        // g^ into r, ||g||^2, ||g^||^2
+        // (Op y)_v of this thread's system, y in [vertex][SB] rows; UNIT: the diagonal is 1
+        auto apply = [&](auto unit_diag, const double *dg, const double *cf, const double *of, const double *y,
+                         int v) -> double {
+            const int u = u0 + v;
+            double acc = (decltype(unit_diag)::value ? 1.0 : dg[u]) * y[v * SB + s];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc += cf[4 * (int64_t)u + j] * y[(mv.ell[(int64_t)j * mv.V + u] - u0) * SB + s];
+            const int d = mv.deg[u];
+            if (d > 4) {
+                const int64_t k0 = mv.vptr[u];
+                for (int64_t k = k0 + 4; k < k0 + d; ++k) acc += of[k] * y[(mv.adj_o[k] - u0) * SB + s];
+            }
+            return acc;
+        };
+        auto applyS = [&](const double *y, int v) { return apply(std::true_type{}, nullptr, Sc, So, y, v); };
+        auto applyP = [&](const double *y, int v) { return apply(std::false_type{}, Pd, Pc, Po, y, v); };
+
+        // g^ and x^0; Jacobi also r^ = p = g^
         double t0[2] = {0.0, 0.0};
-        for (int v = threadIdx.x; v < V; v += blockDim.x) {
-            const double gh = H[v] * g[v];
-            r[v] = gh;
-            t0[0] += g[v] * g[v];
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+            const int i = v * SB + s;
+            const double gv = live ? gT[((int64_t)l * S + smp) * mv.V + u0 + v] : 0.0;
+            const double gh = H[v] * gv;
+            Gh[i] = gh;
+            X[i] = 0.0;
+            if (!LRN) {
+                R[i] = gh;
+                P[i] = gh;
+            }
+            t0[0] += gv * gv;
             t0[1] += gh * gh;
         }
-        block_sum<2>(t0, red, nw);
+        ssum(t0);
         const double gg = t0[0];
         const double tol2 = tol * tol * gg;
-        double thr = tol * tol * t0[1];  // trigger on ||r^||^2
-        const bool hq = LRN && Qop.diag != nullptr;
-        for (int v = threadIdx.x; v < V; v += blockDim.x)
-            x[v] = hq ? ell_apply<false>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
-                                         Qop.ovf + (int64_t)l * E2, r, u0 + v, u0)
-                      : 0.0;
-        int it = 0;
-        double rel = 0.0;
-        // r^ = g^ - S^ x^ and z^ = M r^ into p; returns (r^.z^, ||r||^2, ||r^||^2)
-        auto restart = [&](double &rz, double &rr, double &rh) {
-            __syncthreads();  // x^ complete, every read of r done
-            double t[3] = {0.0, 0.0, 0.0};
-            for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                const double rv = H[v] * g[v] - ell_apply<true>(mv, nullptr, Sc, So, x, u0 + v, u0);
-                r[v] = rv;
-                const double ru = rv / H[v];
-                t[1] += ru * ru;
-                t[2] += rv * rv;
-                if (!learned) {
-                    p[v] = rv;
-                    t[0] += rv * rv;
+        double thr = tol * tol * t0[1];  // trigger on ||r^||^2, corrected at each test
+        if (LRN && Qop.diag != nullptr) {
+            __syncthreads();  // g^ complete: Q^ reads neighbours
+            const double *Qd = Qop.diag + (int64_t)l * mv.V, *Qc = Qop.coef + (int64_t)l * 4 * mv.V,
+                         *Qo = Qop.ovf + (int64_t)l * E2;
+            for (int v = vs; v < V; v += VS) X[v * SB + s] = apply(std::false_type{}, Qd, Qc, Qo, Gh, v);
+        }
+        bool done = !(gg > 0.0);  // a zero right-hand side (and a padding sample) keeps x = 0
+        bool fresh = LRN && !done;
+        bool lz = LRN;            // the operator preconditioner is in use
+        bool switched = !LRN;
+        double rz = t0[1], rr = gg, rh = t0[1], rel = done ? 0.0 : 1.0;
+        int it = 0, its_s = 0;
+        if (vs == 0) {
+            flag[0][s] = !done;
+            flag[1][s] = fresh;
+        }
+        for (;;) {
+            __syncthreads();  // p and x^ complete; the flags of the last decisions visible
+            bool any_act = false, any_fresh = false;
+#pragma unroll
+            for (int k = 0; k < SB; ++k) {
+                any_act |= flag[0][k] != 0;
+                any_fresh |= flag[1][k] != 0;
+            }
+            if (!any_act) break;
+            if (!switched && it + 1 == switch_at) {  // fallback: Jacobi from the current iterate
+                switched = true;
+                if (!done && lz) {
+                    lz = false;
+                    fresh = true;
+                }
+                any_fresh = true;
+            }
+            if (any_fresh) {
+                // r^ = g^ - S^ x^; the systems that asked test it and, if they go on,
+                // restart from it (z^ and p from the true residual)
+                double t[3] = {0.0, 0.0, 0.0};  // r^.z^, ||g - S x||^2, ||r^||^2
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+                    if (!fresh) break;
+                    const int i = v * SB + s;
+                    const double rv = Gh[i] - applyS(X, v);
+                    const double ru = rv / H[v];
+                    R[i] = rv;
+                    t[1] += ru * ru;
+                    t[2] += rv * rv;
+                    if (!lz) {
+                        P[i] = rv;
+                        t[0] += rv * rv;
+                    }
+                }
+                if (LRN) {
+                    __syncthreads();  // r^ complete: the preconditioner reads neighbours
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+                        if (!(fresh && lz)) break;
+                        const int i = v * SB + s;
+                        const double zv = applyP(R, v);
+                        P[i] = zv;
+                        t[0] += R[i] * zv;
+                    }
+                }
+                ssum(t);
+                if (fresh) {
+                    fresh = false;
+                    rel = sqrt(t[1] / gg);
+                    if (t[1] <= tol2) {
+                        done = true;
+                        its_s = it;
+                    } else {
+                        if (t[2] > 0.0) thr = tol2 * t[2] / t[1];
+                        rz = t[0];
+                        rr = t[1];
+                        rh = t[2];
+                    }
+                }
+                if (vs == 0) {
+                    flag[0][s] = !done;
+                    flag[1][s] = 0;
+                }
+                continue;
+            }
+            if (it == maxit) break;  // the systems still active did not converge
+            ++it;
+            double t1[1] = {0.0};  // p.q
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+                if (done) break;
+                const int i = v * SB + s;
+                const double qv = applyS(P, v);
+                Q[i] = qv;
+                t1[0] += P[i] * qv;
+            }
+            ssum(t1);
+            const double alpha = done ? 0.0 : rz / t1[0];
+            double t2[2] = {0.0, 0.0};  // ||r^||^2, r^.z^
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+                if (done) break;
+                const int i = v * SB + s;
+                X[i] += alpha * P[i];
+                const double rv = R[i] - alpha * Q[i];
+                R[i] = rv;
+                t2[0] += rv * rv;
+            }
+            if (LRN) {
+                __syncthreads();  // r^ complete: the preconditioner reads neighbours
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+                    if (done || !lz) break;
+                    const int i = v * SB + s;
+                    const double zv = applyP(R, v);
+                    Q[i] = zv;  // q is free until the next product
+                    t2[1] += R[i] * zv;
                 }
             }
-            if (learned) {
-                __syncthreads();  // r complete
-                for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                    const double zv = ell_apply<false>(mv, Pd, Pc, Po, r, u0 + v, u0);
-                    p[v] = zv;
-                    t[0] += r[v] * zv;
+            ssum(t2);
+            if (!done) {
+                if (t2[0] <= thr) {
+                    fresh = true;  // test with the true residual (and restart if it fails)
+                } else {
+                    rel = sqrt(t2[0] * rr / (rh > 0.0 ? rh : 1.0) / gg);  // estimate
+                    const double rzn = (LRN && lz) ? t2[1] : t2[0];
+                    const double beta = rzn / rz;
+                    rz = rzn;
+#pragma unroll 1
+        for (int v = vs; v < V; v += VS) {
+                        const int i = v * SB + s;
+                        P[i] = ((LRN && lz) ? Q[i] : R[i]) + beta * P[i];
+                    }
                 }
             }
-            block_sum<3>(t, red, nw);
-            rz = t[0];
-            rr = t[1];
-            rh = t[2];
-        };
-        if (gg > 0.0) {
-            double rz, rr, rh;
-            restart(rz, rr, rh);
-            rel = sqrt(rr / gg);
-            if (rh > 0.0) thr = tol2 * rh / rr;
-            if (rr > tol2) {
-                for (it = 1; it <= maxit; ++it) {
-                    if (learned && it == switch_at) {  // fallback: Jacobi from the current iterate
-                        learned = false;
-                        restart(rz, rr, rh);
-                    }
-                    __syncthreads();  // p complete
-                    double t1[1] = {0.0};
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                        const double qv = ell_apply<true>(mv, nullptr, Sc, So, p, u0 + v, u0);
-                        q[v] = qv;
-                        t1[0] += p[v] * qv;
-                    }
-                    block_sum<1>(t1, red, nw);
-                    const double alpha = rz / t1[0];
-                    double t3[1] = {0.0};  // ||r^||^2 (= r^.z^ for Jacobi)
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                        x[v] += alpha * p[v];
-                        const double rv = r[v] - alpha * q[v];
-                        r[v] = rv;
-                        t3[0] += rv * rv;
-                    }
-                    block_sum<1>(t3, red, nw);
-                    if (t3[0] <= thr) {
-                        double rzt, rrt, rht;
-                        restart(rzt, rrt, rht);  // true residual, and a fresh direction if it fails
-                        rel = sqrt(rrt / gg);
-                        if (rrt <= tol2) break;
-                        if (rht > 0.0) thr = tol2 * rht / rrt;
-                        rz = rzt;
-                        continue;
-                    }
-                    rel = sqrt(t3[0] * rr / (rh > 0.0 ? rh : 1.0) / gg);
-                    double rz_new = t3[0];
-                    if (learned) {
-                        __syncthreads();  // r complete: the preconditioner reads neighbours
-                        double t4[1] = {0.0};
-                        for (int v = threadIdx.x; v < V; v += blockDim.x) {
-                            const double zv = ell_apply<false>(mv, Pd, Pc, Po, r, u0 + v, u0);
-                            q[v] = zv;  // q is free until the next product
-                            t4[0] += r[v] * zv;
-                        }
-                        block_sum<1>(t4, red, nw);
-                        rz_new = t4[0];
-                    }
-                    const double beta = rz_new / rz;
-                    rz = rz_new;
-                    __syncthreads();  // all reads of p and q done
-                    for (int v = threadIdx.x; v < V; v += blockDim.x) p[v] = (learned ? q[v] : r[v]) + beta * p[v];
-                }
-                if (it > maxit) it = maxit + 1;  // flags non-convergence
+            if (vs == 0) {
+                flag[0][s] = !done;
+                flag[1][s] = fresh;
             }
         }
-        __syncthreads();
-        double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
-        for (int v = threadIdx.x; v < V; v += blockDim.x) xo[v] = (gg > 0.0) ? H[v] * x[v] : 0.0;
-        if (threadIdx.x == 0) {
-            its[sys] = it;
-            res[sys] = rel;
+        // x = H x^ (each entry read by the thread that wrote it)
+        if (live) {
+            double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
+            for (int v = vs; v < V; v += VS) xo[v] = (gg > 0.0) ? H[v] * X[v * SB + s] : 0.0;
+            if (vs == 0) {
+                const int64_t sys = ((int64_t)gi * LB + l) * S + smp;
+                its[sys] = done ? its_s : maxit + 1;
+                res[sys] = rel;
+            }
         }
-        __syncthreads();
     }
 }
 
@@ -828,7 +951,16 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
 }  // namespace
 
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
-    return (size_t)blocks * 4 * mv.maxVg * sizeof(double);
+    return (size_t)blocks * 5 * kMrhsMaxSB * (size_t)mv.maxVg * sizeof(double);
+}
+
+// samples per block of the multi-system kernel: the largest of 16, 8, 4 whose
+// blocks fill every compute unit once (wider rows gather better; more blocks keep
+// more compute units busy)
+static int mrhs_sb(int64_t ngl, int64_t LB, int64_t S) {
+    for (int sb = kMrhsMaxSB; sb > 4; sb /= 2)
+        if (S >= sb && ngl * LB * ((S + sb - 1) / sb) >= 256) return sb;
+    return 4;
 }
 
 // diag, dh, coef [4], ovf of each shift, for S^ (and P^, Q^ with the learned preconditioner)
@@ -849,33 +981,26 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
-// the learned variant keeps two vectors in LDS and runs on the size classes
-// 0 .. kChipLearned - 1 only; the Neumann-Neumann preconditioner needs both
-// vectors in every class, so its graphs beyond class kChipNN - 1 take the
-// global-memory kernel
-constexpr int kChipLearned = 6;
-constexpr int kChipNN = 5;
+// Variant of the on-chip kernel per size class (ChipMode, work.h): CM_OP applies
+// the operator preconditioner P^ (and the learned initial guess, if any) with r^
+// and p in LDS, which only the classes 0 .. kChipOpClasses - 1 can hold;
+// CM_GUESS applies the learned initial guess with the Jacobi preconditioner
+// (one vector in LDS); CM_JACOBI is plain Jacobi-PCG.
+static_assert(2 * kPcgCap[kChipOpClasses - 1] * 8 <= 160 * 1024 && 2 * kPcgCap[kChipOpClasses] * 8 > 160 * 1024,
+              "two FP64 vectors of the class capacity in 160 KiB of LDS");
 
-// the learned variant of the largest class applies the learned initial guess only (XP)
-constexpr bool chip_xp(int c, bool lrn) { return lrn && kChipK[c] > 10; }
-static size_t chip_lds(int c, bool lrn) {
-    return (size_t)kPcgCap[c] * sizeof(double) * (lrn && !chip_xp(c, lrn) ? 2 : 1);
-}
-
-template <int C, bool LRN>
-static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st) {
+template <int C, bool LRN, bool XP>
+static void chip_launch(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st) {
     constexpr int TPB = kChipTpb[C], K = kChipK[C];
     static_assert(TPB * K >= kPcgCap[C], "class capacity");
     constexpr bool XG = K > 10;
-    constexpr bool XP = chip_xp(C, LRN);
-    const size_t lds = chip_lds(C, LRN);
+    constexpr size_t lds = (size_t)kPcgCap[C] * sizeof(double) * (LRN && !XP ? 2 : 1);
     if (!a) {  // preparation: the dynamic LDS of the variant (not a stream operation)
         GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG, XP>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         return;
     }
     const int32_t n = mv.cls_off[C + 1] - mv.cls_off[C];
-    if (n == 0) return;
     const int64_t groups = (int64_t)n * a->LB;
     const int64_t blocks = (groups + 7) / 8 * 8 * a->S;
     GRF_REQUIRE(blocks < ((int64_t)1 << 31), "too many systems in one shift block");
@@ -885,23 +1010,52 @@ static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops,
     GRF_LAUNCH_CHECK();
 }
 
-// the classes 0 .. nc - 1
-template <bool LRN>
-static void chip_all(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st, int nc = kPcgClasses) {
-    if (nc > 0) chip_class<0, LRN>(mv, a, ops, st);
-    if (nc > 1) chip_class<1, LRN>(mv, a, ops, st);
-    if (nc > 2) chip_class<2, LRN>(mv, a, ops, st);
-    if (nc > 3) chip_class<3, LRN>(mv, a, ops, st);
-    if (nc > 4) chip_class<4, LRN>(mv, a, ops, st);
-    if (nc > 5) chip_class<5, LRN>(mv, a, ops, st);
+template <int C>
+static void chip_class(const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st, int mode) {
+    if (mode == CM_OP) {
+        if constexpr (C < kChipOpClasses)
+            chip_launch<C, true, false>(mv, a, ops, st);
+        else
+            GRF_REQUIRE(false, "internal: operator preconditioner in a class without room for it");
+    } else if (mode == CM_GUESS) {
+        chip_launch<C, true, true>(mv, a, ops, st);
+    } else {
+        chip_launch<C, false, false>(mv, a, ops, st);
+    }
 }
+
+static void chip_dispatch(int c, const MeshView &mv, const SchurArgs *a, const EllOp *ops, hipStream_t st,
+                          int mode) {
+    switch (c) {
+    case 0: chip_class<0>(mv, a, ops, st, mode); break;
+    case 1: chip_class<1>(mv, a, ops, st, mode); break;
+    case 2: chip_class<2>(mv, a, ops, st, mode); break;
+    case 3: chip_class<3>(mv, a, ops, st, mode); break;
+    case 4: chip_class<4>(mv, a, ops, st, mode); break;
+    case 5: chip_class<5>(mv, a, ops, st, mode); break;
+    default: GRF_REQUIRE(false, "internal: size class %d", c);
+    }
+}
+static_assert(kPcgClasses == 6, "chip_dispatch covers every class");
 
 void prepare_pcg(const MeshView &mv) {
     static bool done = false;  // the attributes hold for the process (every device)
     if (done) return;
-    chip_all<false>(mv, nullptr, nullptr, nullptr);
-    chip_all<true>(mv, nullptr, nullptr, nullptr);
+    for (int c = 0; c < kPcgClasses; ++c) {
+        chip_dispatch(c, mv, nullptr, nullptr, nullptr, CM_JACOBI);
+        chip_dispatch(c, mv, nullptr, nullptr, nullptr, CM_GUESS);
+        if (c < kChipOpClasses) chip_dispatch(c, mv, nullptr, nullptr, nullptr, CM_OP);
+    }
     done = true;
+}
+
+void default_chip_modes(int32_t precond, int8_t *mode) {
+    for (int c = 0; c < kPcgClasses; ++c)
+        mode[c] = precond == GRF_PRECOND_JACOBI ? CM_JACOBI : c < kChipOpClasses ? CM_OP : CM_GUESS;
+}
+
+bool chip_mode_valid(int c, int mode) {
+    return mode == CM_JACOBI || mode == CM_GUESS || (mode == CM_OP && c < kChipOpClasses);
 }
 
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
@@ -923,23 +1077,47 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_ell_diag, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0].dh);
     hipLaunchKernelGGL(k_ell_ops, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0], pm, lo, ops[1], ops[2]);
     GRF_LAUNCH_CHECK();
-    const int c0 = pm == PM_LEARNED ? kChipLearned : pm == PM_NN ? kChipNN : kPcgClasses;
-    if (lrn)
-        chip_all<true>(mv, &a, ops, st, c0);
-    else
-        chip_all<false>(mv, &a, ops, st);
+    // on-chip classes: Jacobi everywhere; Neumann-Neumann in the classes that hold both
+    // vectors (the others take the global-memory kernel); learned: per class as chosen
+    int8_t mode[kPcgClasses];
+    default_chip_modes(a.precond, mode);
+    if (pm == PM_LEARNED && a.cls_mode)
+        for (int c = 0; c < kPcgClasses; ++c) mode[c] = a.cls_mode[c];
+    const int c_end = pm == PM_NN ? kChipOpClasses : kPcgClasses;
+    for (int c = 0; c < c_end; ++c) {
+        if (mv.cls_off[c + 1] == mv.cls_off[c]) continue;
+        GRF_REQUIRE(chip_mode_valid(c, mode[c]), "internal: PCG variant %d in size class %d", mode[c], c);
+        if (a.ctimer) a.ctimer->begin(kClassTimerId + c);
+        chip_dispatch(c, mv, &a, ops, st, mode[c]);
+        if (a.ctimer) a.ctimer->end();
+    }
     // graphs beyond the on-chip classes
-    const int32_t ngl = mv.cls_off[kPcgClasses + 1] - mv.cls_off[c0];
+    const int32_t ngl = mv.cls_off[kPcgClasses + 1] - mv.cls_off[c_end];
     if (ngl == 0) return;
-    const int64_t nsys = (int64_t)ngl * a.LB * a.S;
-    const int64_t blocks = nsys < a.pcg_blocks ? nsys : a.pcg_blocks;
-    const int32_t *glist = mv.gord + mv.cls_off[c0];
-    if (lrn)
-        hipLaunchKernelGGL(k_pcg_ell<true>, dim3((unsigned)blocks), dim3(256), 0, st, mv, ops[0], ops[1], ops[2],
-                           glist, ngl, a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
-    else
-        hipLaunchKernelGGL(k_pcg_ell<false>, dim3((unsigned)blocks), dim3(256), 0, st, mv, ops[0], ops[1], ops[2],
-                           glist, ngl, a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+    const int sb = mrhs_sb(ngl, a.LB, a.S);
+    const int64_t units = (int64_t)ngl * a.LB * ((a.S + sb - 1) / sb);
+    const int64_t blocks = std::min<int64_t>(units, (int64_t)a.pcg_blocks * (kMrhsMaxSB / sb));
+    GRF_REQUIRE(blocks >= 1 && blocks < ((int64_t)1 << 31), "internal: no scratch for the multi-system PCG");
+    GRF_REQUIRE((int64_t)mv.maxVg * kMrhsMaxSB < ((int64_t)1 << 31), "a graph too large for the vertex PCG");
+    const int32_t *glist = mv.gord + mv.cls_off[c_end];
+    auto launch = [&](auto sbc, auto lrnc) {
+        hipLaunchKernelGGL((k_pcg_mrhs<decltype(sbc)::value, decltype(lrnc)::value>), dim3((unsigned)blocks),
+                           dim3(1024), 0, st, mv, ops[0], ops[1], ops[2], glist, ngl, a.gT, a.xT, a.scr, a.its,
+                           a.res, a.LB, a.S, a.tol, a.maxit);
+    };
+    using T4 = std::integral_constant<int, 4>;
+    using T8 = std::integral_constant<int, 8>;
+    using T16 = std::integral_constant<int, 16>;
+    static_assert(kMrhsMaxSB == 16, "the launch covers SB = 4, 8, 16");
+    if (lrn) {
+        if (sb == 16) launch(T16{}, std::true_type{});
+        else if (sb == 8) launch(T8{}, std::true_type{});
+        else launch(T4{}, std::true_type{});
+    } else {
+        if (sb == 16) launch(T16{}, std::false_type{});
+        else if (sb == 8) launch(T8{}, std::false_type{});
+        else launch(T4{}, std::false_type{});
+    }
     GRF_LAUNCH_CHECK();
 }
 

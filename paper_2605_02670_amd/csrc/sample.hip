@@ -70,9 +70,14 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     if (lb < L) lb = std::max<int64_t>(p.BL, (lb / p.BL) * p.BL);
     lb = std::max<int64_t>(1, std::min<int64_t>(lb, L));
     p.LB = (int32_t)lb;
-    const double vbytes = 32.0 * std::max<int32_t>(g.maxVg, 1);  // 4 vectors per resident system
-    int64_t blocks = (int64_t)std::min(4096.0, std::max(1.0, std::floor((4.0 * (1 << 30)) / vbytes)));
-    p.pcg_blocks = (int32_t)blocks;
+    // multi-system PCG (graphs no on-chip variant takes): resident blocks of
+    // kMrhsMaxSB samples, 5 vectors each, up to one per block of the pass and 16 GiB
+    const int c0 = o.precond == GRF_PRECOND_NN ? kChipOpClasses : kPcgClasses;
+    const int64_t nglob = g.cls_off[kPcgClasses + 1] - g.cls_off[c0];
+    const int64_t units = nglob * lb * ((S + kMrhsMaxSB - 1) / kMrhsMaxSB);
+    const double ubytes = 5.0 * kMrhsMaxSB * sizeof(double) * std::max<int32_t>(g.maxVg, 1);
+    const int64_t cap = (int64_t)std::max(1.0, std::floor(16.0 * (double)(1ull << 30) / ubytes));
+    p.pcg_blocks = (int32_t)std::min<int64_t>(std::min<int64_t>(units, cap), 4096);
     return p;
 }
 
@@ -152,7 +157,8 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     return ps;
 }
 
-static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStream_t st, KTimer &T) {
+static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStream_t st, KTimer &T,
+                         const int8_t *cls_mode = nullptr, KTimer *ct = nullptr) {
     grf_graph::Work &w = work(g);
     const MeshView mv = g.view();
     const Plan &p = ps.p;
@@ -263,6 +269,8 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.maxit = o.maxit;
         sc.pcg_blocks = p.pcg_blocks;
         sc.precond = o.precond;
+        sc.cls_mode = cls_mode;
+        sc.ctimer = ct;
         LearnedOps lops{};
         if (o.precond == GRF_PRECOND_LEARNED) {
             grf_learned &net = *const_cast<grf_learned *>(o.learned);
@@ -342,13 +350,21 @@ static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStre
     }
 }
 
+// the per-class PCG variants the caller fixed (grf_opts.pcg_class_modes), if any
+static bool given_modes(const grf_opts &o, int8_t *md) {
+    if (!(o.pcg_class_modes & GRF_PCG_MODES_SET)) return false;
+    for (int c = 0; c < kPcgClasses; ++c) md[c] = (int8_t)((o.pcg_class_modes >> (2 * c)) & 3);
+    return true;
+}
+
 // Runs shifts (cI[i], cL[i]) on the right-hand sides in w.X into w.U (zeroed
 // here: the blocked forward pass of the first shift block writes the interior
 // rows, so only the vertex rows are cleared).
 static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::vector<double> &cL, int64_t S,
                        const grf_opts &o, hipStream_t st, grf_stats *stats, KTimer &T) {
     const Pass ps = prepare_pass(g, cI, cL, S, o, st);
-    enqueue_pass(g, ps, o, st, T);
+    int8_t md[kPcgClasses];
+    enqueue_pass(g, ps, o, st, T, given_modes(o, md) ? md : nullptr);
     finish_pass(g, ps, o, st, stats);
 }
 
@@ -363,8 +379,11 @@ struct Batch {
     grf_graph U;
     std::vector<double> kap2;     // per-edge kappa^2 on the device
     bool tuned = false;
-    std::vector<double> tuned_key;  // (precision, preconditioner) the tuning was done for
+    std::vector<double> tuned_key;  // (precision, preconditioner, network) the tuning was done for
     int32_t sweep_block = 0, shift_block = 0;
+    int8_t tuned_mode[kPcgClasses] = {};  // learned: the tuner's PCG variant per size class (ChipMode)
+    bool modes_tuned = false;             // tuned_mode was measured (not the default)
+    int8_t cls_mode[kPcgClasses] = {};    // the variants of this call
     hipStream_t stream = nullptr;  // capture and replay stream (default priority)
     hipGraphExec_t exec = nullptr;
     std::vector<double> exec_key;  // parameters the captured graph was recorded with
@@ -429,7 +448,10 @@ Batch *get_batch(grf_graph *const *graphs, int32_t ng) {
 }
 
 // One uncaptured run of the batch with the given options; returns its device time in ms.
-double timed_run(Batch &B, const Shifts &sh, int64_t S, uint64_t seed, const grf_opts &o) {
+// One run of the batch on its stream; returns its time in ms.  With cls_ms, also the
+// PCG time of each size class (cls_ms[kPcgClasses], summed over the shift blocks).
+double timed_run(Batch &B, const Shifts &sh, int64_t S, uint64_t seed, const grf_opts &o,
+                 const int8_t *cls_mode = nullptr, double *cls_ms = nullptr) {
     grf_graph &U = B.U;
     grf_graph::Work &w = work(U);
     hipStream_t cs = B.stream;
@@ -438,11 +460,20 @@ double timed_run(Batch &B, const Shifts &sh, int64_t S, uint64_t seed, const grf
     GRF_HIP(hipEventCreate(&a));
     GRF_HIP(hipEventCreate(&b));
     KTimer T(false, cs);
+    KTimer CT(cls_ms != nullptr, cs);
     GRF_HIP(hipEventRecord(a, cs));
     launch_noise(U.view(), S, o.sample_offset, seed, w.X.as<double>(), cs);
-    enqueue_pass(U, ps, o, cs, T);
+    enqueue_pass(U, ps, o, cs, T, cls_mode, cls_ms ? &CT : nullptr);
     GRF_HIP(hipEventRecord(b, cs));
     GRF_HIP(hipEventSynchronize(b));
+    if (cls_ms) {
+        for (int c = 0; c < kPcgClasses; ++c) cls_ms[c] = 0.0;
+        for (const KTimer::Rec &r : CT.recs) {
+            float t = 0.0f;
+            GRF_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            cls_ms[r.id - kClassTimerId] += t;
+        }
+    }
     float ms = 0.0f;
     GRF_HIP(hipEventElapsedTime(&ms, a, b));
     (void)hipEventDestroy(a);
@@ -678,17 +709,24 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     // options: the autotuner picks the sweep form and shift block unless the caller fixed them
     grf_opts run = o;
     run.timing = 0;
+    auto tune_key = [&]() {
+        const uint64_t ls = o.precond == GRF_PRECOND_LEARNED ? learned_signature(*o.learned) : 0;
+        return std::vector<double>{(double)o.precision, (double)o.precond, (double)(ls >> 32),
+                                   (double)(ls & 0xffffffffu)};
+    };
+    int8_t given[kPcgClasses];
+    const bool has_given = given_modes(o, given);
     if (o.sweep_block == 0 && o.shift_block == 0) {
-        const std::vector<double> tk = {(double)o.precision, (double)o.precond};
-        if (!B.tuned || tk != B.tuned_key) {
+        if (!B.tuned || tune_key() != B.tuned_key) {
             std::vector<std::pair<int32_t, int32_t>> cand = {{0, 0}, {0, 64}};
             if (o.precision == GRF_PREC_FP64) {
                 cand.push_back({32, 0});
                 cand.push_back({64, 0});
             }
+            grf_opts t = run;
+            if (has_given) t.pcg_class_modes = 0;  // the sweeps are tuned with the default variants
             double best = 0.0;
             for (size_t c = 0; c < cand.size(); ++c) {
-                grf_opts t = run;
                 t.sweep_block = cand[c].first;
                 t.shift_block = cand[c].second;
                 if (c == 0) (void)timed_run(B, sh, n_samples, seed, t);  // first launches of the kernels
@@ -699,8 +737,10 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
                     B.shift_block = t.shift_block;
                 }
             }
+            default_chip_modes(o.precond, B.tuned_mode);
+            B.modes_tuned = false;
             B.tuned = true;
-            B.tuned_key = tk;
+            B.tuned_key = tune_key();  // after the runs: the preparation may grow the network's buffers
             if (B.exec) {
                 (void)hipGraphExecDestroy(B.exec);
                 B.exec = nullptr;
@@ -708,7 +748,31 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
         }
         run.sweep_block = B.sweep_block;
         run.shift_block = B.shift_block;
+        if (o.precond == GRF_PRECOND_LEARNED && !has_given && !B.modes_tuned) {
+            // per size class, the fastest PCG variant: the learned operator and initial
+            // guess, the initial guess only, or Jacobi.  Each class is its own launch,
+            // so one timed run per variant (after one that loads it) times every class.
+            double cms[3][kPcgClasses];
+            for (int m = 0; m < 3; ++m) {
+                int8_t md[kPcgClasses];
+                for (int c = 0; c < kPcgClasses; ++c) md[c] = (int8_t)(chip_mode_valid(c, m) ? m : CM_GUESS);
+                (void)timed_run(B, sh, n_samples, seed, run, md);
+                (void)timed_run(B, sh, n_samples, seed, run, md, cms[m]);
+            }
+            for (int c = 0; c < kPcgClasses; ++c) {
+                int bm = CM_JACOBI;
+                for (int m = 0; m < 3; ++m)
+                    if (chip_mode_valid(c, m) && cms[m][c] < cms[bm][c]) bm = m;
+                B.tuned_mode[c] = (int8_t)bm;
+            }
+            B.modes_tuned = true;
+            B.tuned_key = tune_key();
+        }
+        std::copy(B.tuned_mode, B.tuned_mode + kPcgClasses, B.cls_mode);
+    } else {
+        default_chip_modes(o.precond, B.cls_mode);
     }
+    if (has_given) std::copy(given, given + kPcgClasses, B.cls_mode);
     // everything the captured graph depends on; with the learned preconditioner also
     // the network's buffers (taken again after the capture: the preparation may grow them)
     auto make_key = [&]() {
@@ -720,6 +784,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
         k.push_back((double)(ls >> 32));
         k.push_back((double)(ls & 0xffffffffu));
         k.insert(k.end(), kappas, kappas + n_graphs);
+        k.insert(k.end(), B.cls_mode, B.cls_mode + kPcgClasses);
         return k;
     };
     const std::vector<double> key = make_key();
@@ -736,7 +801,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
         GRF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         try {
             launch_noise(mv, n_samples, run.sample_offset, seed, w.X.as<double>(), cs);
-            enqueue_pass(U, B.exec_pass, run, cs, T);
+            enqueue_pass(U, B.exec_pass, run, cs, T, B.cls_mode);
         } catch (...) {
             (void)hipStreamEndCapture(cs, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -767,6 +832,11 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     } catch (const Error &err) {
         if (err.code != GRF_ENOCONV) throw;
         code = GRF_ENOCONV;
+    }
+    if (o.stats) {
+        int32_t mw = 0;
+        for (int c = 0; c < kPcgClasses; ++c) mw |= (int32_t)B.cls_mode[c] << (2 * c);
+        o.stats->pcg_class_modes = mw;
     }
     if (o.timing) {
         float ms = 0.0f;
@@ -875,6 +945,7 @@ int grf_learned_train(grf_learned *net, grf_graph *const *graphs, int32_t n_grap
         }
         GRF_HIP(hipStreamSynchronize(st));
         data.push_back(std::move(d));
+        free_work(g);  // the sampling workspace (block tables of up to 64 shifts) is not needed for the steps
     }
     // Adam steps: graph t mod n_graphs, a window of consecutive shifts cycling through the schedule
     for (int32_t t = 0; t < n_steps; ++t) {

@@ -140,12 +140,23 @@ struct SchurArgs {
     int32_t pcg_blocks;   // resident workgroups for the global-memory PCG
     int32_t precond;            // GRF_PRECOND_* of the solve
     const LearnedOps *learned;  // learned preconditioner and initial guess of this block (GRF_PRECOND_LEARNED)
+    const int8_t *cls_mode;     // learned: ChipMode per size class, or null (default_chip_modes)
+    KTimer *ctimer;             // optional: times each size class's launch under kClassTimerId + class
 };
+
+// On-chip PCG variant of a size class: the operator preconditioner (with the
+// learned initial guess, if any), the learned initial guess with Jacobi, or Jacobi.
+enum ChipMode : int8_t { CM_OP = 0, CM_GUESS = 1, CM_JACOBI = 2 };
+constexpr int kChipOpClasses = 5;  // size classes whose LDS holds r^ and p (CM_OP)
+constexpr int kMrhsMaxSB = 16;     // most samples per block of the multi-system PCG kernel
+constexpr int kClassTimerId = 100;
+void default_chip_modes(int32_t precond, int8_t *mode);  // [kPcgClasses]
+bool chip_mode_valid(int c, int mode);
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void prepare_pcg(const MeshView &mv);  // one-time kernel attributes, before any graph capture
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st);
-size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);
+size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);  // blocks of kMrhsMaxSB samples
 size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, int32_t precond);
 
 }  // namespace grf

@@ -20,6 +20,8 @@ GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP = 0, -1, -2
 MESH = {"ceil": 0, "round": 1}
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
+PCG_MODES = {"op": 0, "guess": 1, "jacobi": 2}
+PCG_MODES_SET = 1 << 12
 KERNELS = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd",
            "layout", "mixed", "learned"]
 
@@ -34,11 +36,11 @@ class Stats(C.Structure):
     _fields_ = [("n_shifts", C.c_int32), ("n_systems", C.c_int32), ("n_unconverged", C.c_int32),
                 ("max_iterations", C.c_int32), ("total_iterations", C.c_int64),
                 ("max_rel_residual", C.c_double), ("refine_steps", C.c_int32),
-                ("shift_block", C.c_int32), ("sweep_block", C.c_int32), ("reserved", C.c_int32),
+                ("shift_block", C.c_int32), ("sweep_block", C.c_int32), ("pcg_class_modes", C.c_int32),
                 ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int32 * 12)]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "kernel_ms", "kernel_launches")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("kernel_ms", "kernel_launches")}
         d["kernel_ms"] = {KERNELS[i]: self.kernel_ms[i] for i in range(12)}
         d["kernel_launches"] = {KERNELS[i]: self.kernel_launches[i] for i in range(12)}
         return d
@@ -48,7 +50,7 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
                 ("k_minus", C.c_int32), ("k_plus", C.c_int32), ("shift_block", C.c_int32),
                 ("sweep_block", C.c_int32), ("refine", C.c_int32), ("timing", C.c_int32),
-                ("reserved0", C.c_int32), ("sample_offset", C.c_int64),
+                ("pcg_class_modes", C.c_int32), ("sample_offset", C.c_int64),
                 ("stream", C.c_void_p), ("learned", C.c_void_p), ("stats", C.POINTER(Stats))]
 
 
@@ -112,7 +114,9 @@ def _stream_handle(stream=None) -> int:
 
 def make_opts(tol=1e-12, maxit=10000, precision="fp64", precond="jacobi", k_minus=-1, k_plus=-1,
               shift_block=0, sweep_block=0, refine=-1, sample_offset=0, stream=None, learned=None,
-              stats: Stats | None = None, timing=False) -> Opts:
+              stats: Stats | None = None, timing=False, pcg_class_modes=None) -> Opts:
+    """pcg_class_modes: None (automatic) or, with the learned preconditioner, one
+    on-chip PCG variant per size class (PCG_MODES: "op", "guess", "jacobi")."""
     o = Opts()
     load().grf_opts_init(C.byref(o))
     o.tol = tol
@@ -130,9 +134,20 @@ def make_opts(tol=1e-12, maxit=10000, precision="fp64", precond="jacobi", k_minu
     o.learned = C.c_void_p(learned.handle) if learned is not None else None
     if learned is not None and precond == "jacobi":
         o.precond = PRECOND["learned"]
+    if pcg_class_modes is not None:
+        mw = PCG_MODES_SET
+        for c, m in enumerate(pcg_class_modes):
+            mw |= PCG_MODES[m] << (2 * c)
+        o.pcg_class_modes = mw
     if stats is not None:
         o.stats = C.pointer(stats)
     return o
+
+
+def class_modes(word: int) -> list[str]:
+    """The per-class PCG variants of grf_stats.pcg_class_modes."""
+    names = {v: k for k, v in PCG_MODES.items()}
+    return [names[(word >> (2 * c)) & 3] for c in range(6)]
 
 
 class Graph:

@@ -4,10 +4,12 @@ graph is beyond every on-chip class and takes the global-memory kernel), so
 every on-chip variant and the fallback solve systems of the same call.
 
 Bars: each graph's batched sample equals the FP64 oracle to 1e-10 relative
-in the lumped-mass norm, with the Jacobi, the learned (an untrained network:
-its Jacobi fallback and the true residual still decide convergence) and the
-Neumann-Neumann preconditioner (on chip up to 10176 vertices, in the
-global-memory kernel beyond); every system converges.
+in the lumped-mass norm, with the Jacobi, the Neumann-Neumann (on chip up to
+10176 vertices, in the global-memory kernel beyond) and the learned
+preconditioner (an untrained network: its Jacobi fallback and the true
+residual still decide convergence), the last with every on-chip variant
+forced in turn (operator, initial guess only, Jacobi) and as the autotuner
+picks them; every system converges.
 """
 
 import numpy as np
@@ -46,8 +48,13 @@ def batch(grf):
     return Gs, kappas, refs
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "learned", "nn"])
-def test_every_class_matches_oracle(grf, batch, precond):
+CASES = [("jacobi", None), ("nn", None), ("learned", None), ("learned", ["op"] * 5 + ["guess"]),
+         ("learned", ["guess"] * 6), ("learned", ["jacobi"] * 6)]
+
+
+@pytest.mark.parametrize("precond,modes", CASES, ids=["jacobi", "nn", "learned-auto", "learned-op",
+                                                       "learned-guess", "learned-jacobi"])
+def test_every_class_matches_oracle(grf, batch, precond, modes):
     Gs, kappas, refs = batch
     net, kw, st_j = None, {}, None
     if precond != "jacobi":
@@ -56,7 +63,7 @@ def test_every_class_matches_oracle(grf, batch, precond):
         _, st_j = grf.sample_batched(Gs, kappas, BETA, K, S, SEED)
     if precond == "learned":
         net = grf.Learned(init_params(7, head_scale=0.5))
-        kw = dict(learned=net)
+        kw = dict(learned=net, pcg_class_modes=modes)
     elif precond == "nn":
         kw = dict(precond="nn")
     try:
@@ -65,6 +72,13 @@ def test_every_class_matches_oracle(grf, batch, precond):
         if net is not None:
             net.close()
     assert st["n_unconverged"] == 0
+    if precond == "learned":
+        used = grf.class_modes(st["pcg_class_modes"])
+        print(f"PCG variants per size class: {used}", flush=True)
+        if modes is not None:
+            assert used == modes
+        else:
+            assert used[5] != "op"
     if st_j is not None:
         print(f"{precond}: {st['total_iterations']} iterations, Jacobi {st_j['total_iterations']}", flush=True)
         assert st["total_iterations"] != st_j["total_iterations"]
@@ -72,3 +86,19 @@ def test_every_class_matches_oracle(grf, batch, precond):
         err = _rel_ml(u.cpu().numpy(), ref, ML)
         print(f"{precond} V={n}: rel err {err:.2e}", flush=True)
         assert err <= 1e-10, (n, err)
+
+
+def test_class_modes_are_validated(grf):
+    g = preferential_attachment(40, 1, lengths=(0.5, 1.5), seed=3)
+    G = grf.Graph(g.n_vertices, g.edges, g.lengths, H, RULE)
+    net = grf.Learned(init_params(7, head_scale=0.5))
+    try:
+        with pytest.raises(grf.GrfError, match="not available in size class 5"):
+            G.sample(4.0, BETA, K, 2, SEED, learned=net, pcg_class_modes=["op"] * 6)
+        with pytest.raises(grf.GrfError, match="for the learned preconditioner"):
+            G.sample(4.0, BETA, K, 2, SEED, pcg_class_modes=["jacobi"] * 6)
+        u, st = G.sample(4.0, BETA, K, 2, SEED, learned=net, pcg_class_modes=["guess"] * 6)
+        assert st["n_unconverged"] == 0
+    finally:
+        net.close()
+        G.close()
