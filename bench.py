@@ -21,7 +21,10 @@ oracle timed on a bounded sample of the same workload, and (unless
   batch_mixed            one batched call, FP32 edge sweeps, Jacobi,
   batch_nn               one batched call, FP64, Neumann-Neumann preconditioner,
   batch_learned_mixed    one batched call, FP32 edge sweeps, learned preconditioner
-                         (trained on the GPU in this run on small graphs of the same kinds).
+                         (trained on the GPU in this run on small graphs of the same kinds),
+                         with the PCG variant of each size class picked by the autotuner;
+  batch_learned_mixed_op the same with the learned operator and initial guess in every class.
+--workload rgg100k times the learned preconditioner's held-out graph (98k vertices) instead.
 """
 
 from __future__ import annotations
@@ -249,6 +252,87 @@ def _batch_rel_err(Gs, cfg, outs, ref):
     return worst
 
 
+def train_network_rgg(seed: int = 0):
+    """Trains the learned preconditioner on the GPU on the held-out graph's kind: 16
+    random geometric graphs of 2k..20k points, h = 1/256, kappa ~ U[2, 20]."""
+    from paper_2605_02670_amd import grf
+    from workloads import config_c5_train
+    from workloads.learned_init import init_params
+
+    tr = config_c5_train()
+    Gs = [grf.Graph(d["graph"].n_vertices, d["graph"].edges, d["graph"].lengths, 1.0 / 256, "round") for d in tr]
+    net = grf.Learned(init_params(seed))
+    t0 = time.perf_counter()
+    for k, (n, lr) in enumerate(TRAIN_PHASES):
+        net.train(Gs, [d["kappa"] for d in tr], 0.75, 0.0, n_samples=4, seed=seed + 11 + 7 * k, n_steps=n,
+                  shifts_per_step=16, lr=lr)
+    t = time.perf_counter() - t0
+    for G in Gs:
+        G.close()
+    return net, t
+
+
+def bench_rgg(args) -> int:
+    """The held-out random geometric graph (98,129 vertices, 199,826 edges, h =
+    1/256, 38.4M DOFs), kappa = 2, beta = 0.75 (229 shifts), 64 samples, PCG
+    tol 1e-8: one grf_sample call per step with Jacobi, the learned
+    preconditioner (trained first, on the GPU, on 16 smaller graphs of the
+    same kind), the Neumann-Neumann preconditioner, and learned + FP32 edge
+    sweeps.  value: the learned form."""
+    import torch
+
+    from paper_2605_02670_amd import grf
+    from workloads import config_c5_eval
+
+    net, t_train = train_network_rgg()
+    torch.cuda.empty_cache()
+    cfg = config_c5_eval()
+    g = cfg["graph"]
+    G = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    S = cfg["n_samples"]
+    out = torch.empty((S, G.n_dof), dtype=torch.float64, device="cuda")
+    steps = max(1, min(args.steps, 2))
+    forms, ref = {}, None
+    for name, kw in (("jacobi", {}), ("learned", {"learned": net}), ("nn", {"precond": "nn"}),
+                     ("learned_mixed", {"learned": net, "precision": "mixed"})):
+        G.sample(cfg["kappa"], cfg["beta"], 0.0, S, cfg["seed"], out=out, tol=METRIC_TOL, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [G.sample(cfg["kappa"], cfg["beta"], 0.0, S, cfg["seed"], out=out, tol=METRIC_TOL, timing=True,
+                          **kw)[1] for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = stats[0]
+        f = {"value": G.n_dof * st["n_shifts"] * S / dt, "ms_per_step": dt * 1e3,
+             "pcg_ms": sum(s_["kernel_ms"]["pcg"] for s_ in stats) / steps,
+             "learned_ms": sum(s_["kernel_ms"]["learned"] for s_ in stats) / steps,
+             "pcg": {"max_iterations": st["max_iterations"],
+                     "mean_iterations": st["total_iterations"] / max(1, st["n_systems"])}}
+        if ref is None:
+            ref = out[:8].clone()
+        else:
+            f["rel_err_vs_jacobi_8_samples"] = float(((out[:8] - ref).norm(dim=1) / ref.norm(dim=1)).max())
+        forms[name] = f
+        print(f"# {name}: {dt * 1e3:.0f} ms, PCG {f['pcg_ms']:.0f} ms, mean iterations "
+              f"{f['pcg']['mean_iterations']:.2f}", file=sys.stderr, flush=True)
+    for k in ("learned", "nn", "learned_mixed"):
+        forms[k]["speedup_vs_jacobi"] = forms["jacobi"]["ms_per_step"] / forms[k]["ms_per_step"]
+    lf = forms["learned"]
+    line = {
+        "metric": METRIC, "value": lf["value"], "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": lf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"held-out random geometric graph {g.n_vertices} vertices {g.edges.shape[0]} edges "
+                               f"h=1/256 kappa=2 beta=0.75 S={S} PCG tol {METRIC_TOL:g} learned",
+                   "n_dof": G.n_dof, "shifts": stats[0]["n_shifts"], "samples": S, "parallelism": "1 GPU"},
+        "roofline": None, "cpu_baseline": None,
+        "training": {"seconds": t_train, "steps": TRAIN_STEPS, "graphs": "16 random geometric graphs, 2k..20k points"},
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_batched(args) -> int:
     """64 uneven graphs (preferential-attachment trees and lattices, 100..20000
     edges, h = 1/128), one kappa per graph, all 176 shifts x 32 samples in one
@@ -294,8 +378,9 @@ def main() -> int:
                     help="vertex PCG preconditioner of the batched64 workload (learned: trained first, on the GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed / batched / learned forms")
-    ap.add_argument("--workload", choices=["lattice64", "batched64"], default="lattice64",
-                    help="lattice64: one 64x64 lattice (default); batched64: 64 uneven graphs in one batched call")
+    ap.add_argument("--workload", choices=["lattice64", "batched64", "rgg100k"], default="lattice64",
+                    help="lattice64: one 64x64 lattice (default); batched64: 64 uneven graphs in one batched call; "
+                         "rgg100k: the learned preconditioner's held-out random geometric graph")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -314,6 +399,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == "batched64":
         return bench_batched(args)
+    if args.workload == "rgg100k":
+        return bench_rgg(args)
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -443,11 +530,18 @@ def main() -> int:
                           "loss_last400": l1,
                           "graphs": "8 trees/lattices, 100..2000 edges"}
         forms["batch_learned_mixed"] = dict(bl, workload=BATCH_WORKLOAD + "; one batched call, FP32 edge sweeps, "
-                                                                          "learned preconditioner")
+                                                                          "learned preconditioner, PCG variant per "
+                                                                          "size class as the autotuner picks it")
+        blo = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=METRIC_TOL, learned=net, precision="mixed",
+                          pcg_class_modes=["op"] * 5 + ["guess"])
+        blo["rel_err_vs_fp64_tol1e-12"] = _batch_rel_err(Gs, bcfg, bouts, ref)
+        forms["batch_learned_mixed_op"] = dict(blo, workload=BATCH_WORKLOAD + "; one batched call, FP32 edge "
+                                                                              "sweeps, learned operator and initial "
+                                                                              "guess forced in every size class")
         base = forms["batch_plain_per_graph"]["value"]
         forms["batch_speedup_vs_plain_per_graph"] = {k: forms[k]["value"] / base for k in
                                                      ("batch_plain", "batch_mixed", "batch_nn",
-                                                      "batch_learned_mixed")}
+                                                      "batch_learned_mixed", "batch_learned_mixed_op")}
     line = {
         "metric": METRIC, "value": value, "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",

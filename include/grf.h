@@ -101,7 +101,8 @@ typedef struct grf_stats {
     int32_t shift_block;        /* shifts processed per pass (as planned) */
     int32_t sweep_block;        /* shifts held per wavefront in the sweeps */
     int32_t pcg_class_modes;    /* grf_sample_batched: on-chip PCG variant of size class c in bits 2c..2c+1
-                                   (0 operator preconditioner, 1 learned initial guess only, 2 Jacobi) */
+                                   (0 operator preconditioner, 1 learned initial guess only, 2 Jacobi,
+                                   3 the class runs the global-memory kernel) */
     double kernel_ms[12];       /* with opts.timing: summed HIP-event time per grf_kernel_id */
     int32_t kernel_launches[12];/* with opts.timing: launches per grf_kernel_id */
 } grf_stats;

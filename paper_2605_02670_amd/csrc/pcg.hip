@@ -1051,7 +1051,10 @@ void prepare_pcg(const MeshView &mv) {
 
 void default_chip_modes(int32_t precond, int8_t *mode) {
     for (int c = 0; c < kPcgClasses; ++c)
-        mode[c] = precond == GRF_PRECOND_JACOBI ? CM_JACOBI : c < kChipOpClasses ? CM_OP : CM_GUESS;
+        mode[c] = precond == GRF_PRECOND_JACOBI    ? CM_JACOBI
+                  : c < kChipOpClasses             ? CM_OP
+                  : precond == GRF_PRECOND_NN      ? CM_GLOBAL
+                                                   : CM_GUESS;
 }
 
 bool chip_mode_valid(int c, int mode) {

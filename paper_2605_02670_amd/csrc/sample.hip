@@ -272,7 +272,19 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.cls_mode = cls_mode;
         sc.ctimer = ct;
         LearnedOps lops{};
+        // the network runs only where its outputs are read: a size class with a learned
+        // variant, or a graph beyond the on-chip classes
+        bool net_used = false;
         if (o.precond == GRF_PRECOND_LEARNED) {
+            int8_t md[kPcgClasses];
+            default_chip_modes(o.precond, md);
+            if (cls_mode) std::copy(cls_mode, cls_mode + kPcgClasses, md);
+            net_used = mv.cls_off[kPcgClasses + 1] > mv.cls_off[kPcgClasses];
+            for (int c = 0; c < kPcgClasses; ++c)
+                net_used |= md[c] != CM_JACOBI && mv.cls_off[c + 1] > mv.cls_off[c];
+            if (!net_used) sc.precond = GRF_PRECOND_JACOBI;
+        }
+        if (net_used) {
             grf_learned &net = *const_cast<grf_learned *>(o.learned);
             T.begin(GRF_K_LEARNED);
             learned_forward(net, mv, ca.shift, ca.sd, ca.so, lb, st);

@@ -146,7 +146,8 @@ struct SchurArgs {
 
 // On-chip PCG variant of a size class: the operator preconditioner (with the
 // learned initial guess, if any), the learned initial guess with Jacobi, or Jacobi.
-enum ChipMode : int8_t { CM_OP = 0, CM_GUESS = 1, CM_JACOBI = 2 };
+// CM_GLOBAL (reported only): the class runs the multi-system kernel instead.
+enum ChipMode : int8_t { CM_OP = 0, CM_GUESS = 1, CM_JACOBI = 2, CM_GLOBAL = 3 };
 constexpr int kChipOpClasses = 5;  // size classes whose LDS holds r^ and p (CM_OP)
 constexpr int kMrhsMaxSB = 16;     // most samples per block of the multi-system PCG kernel
 constexpr int kClassTimerId = 100;

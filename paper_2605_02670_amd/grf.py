@@ -20,7 +20,7 @@ GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP = 0, -1, -2
 MESH = {"ceil": 0, "round": 1}
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
-PCG_MODES = {"op": 0, "guess": 1, "jacobi": 2}
+PCG_MODES = {"op": 0, "guess": 1, "jacobi": 2}  # grf_stats also reports 3: "global"
 PCG_MODES_SET = 1 << 12
 KERNELS = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd",
            "layout", "mixed", "learned"]
@@ -147,6 +147,7 @@ def make_opts(tol=1e-12, maxit=10000, precision="fp64", precond="jacobi", k_minu
 def class_modes(word: int) -> list[str]:
     """The per-class PCG variants of grf_stats.pcg_class_modes."""
     names = {v: k for k, v in PCG_MODES.items()}
+    names[3] = "global"
     return [names[(word >> (2 * c)) & 3] for c in range(6)]
 
 

@@ -102,3 +102,29 @@ def test_class_modes_are_validated(grf):
     finally:
         net.close()
         G.close()
+
+
+def test_unused_network_is_skipped(grf):
+    """With Jacobi in every size class and no graph beyond them, the learned call runs
+    no network kernel and returns the Jacobi batch bit for bit."""
+    import torch
+
+    trees = [preferential_attachment(n, 1, lengths=(0.5, 1.5), seed=200 + n) for n in (50, 300, 2000)]
+    Gs = [grf.Graph(t.n_vertices, t.edges, t.lengths, H, RULE) for t in trees]
+    kap = [3.0, 6.0, 9.0]
+    net = grf.Learned(init_params(7, head_scale=0.5))
+    try:
+        uj, sj = grf.sample_batched(Gs, kap, BETA, K, S, SEED)
+        ul, sl = grf.sample_batched(Gs, kap, BETA, K, S, SEED, learned=net, pcg_class_modes=["jacobi"] * 6)
+        assert sl["total_iterations"] == sj["total_iterations"]
+        for a, b in zip(uj, ul):
+            assert torch.equal(a, b)
+        # per-kernel timing (single-graph calls): no network launch when no class reads it
+        _, s1 = Gs[2].sample(kap[2], BETA, K, S, SEED, learned=net, pcg_class_modes=["jacobi"] * 6, timing=True)
+        assert s1["kernel_launches"]["learned"] == 0
+        _, s2 = Gs[2].sample(kap[2], BETA, K, S, SEED, learned=net, timing=True)
+        assert s2["kernel_launches"]["learned"] > 0
+    finally:
+        net.close()
+        for G in Gs:
+            G.close()
