@@ -108,6 +108,12 @@ struct MeshView {
     // per graph and wavefront of its class shape: bit i set if item i of some
     // lane of the wavefront has degree > 4 ([ng][16])
     const uint32_t *ovfm;
+    // vertex PCG row order: the graphs beyond every on-chip class keep their operator
+    // rows (dh, coef, diag of S^, P^, Q^) in a Cuthill-McKee order of their vertices,
+    // every other graph in vertex order.  prow[u]: row of vertex u; pvtx[r]: vertex of
+    // row r; pell[j][r] ([4][V]): graph-local row of the j-th ELL neighbour of row r's
+    // vertex (its own past the degree); padj[k] ([2E]): graph-local row of adj_o[k]
+    const int32_t *prow, *pvtx, *pell, *padj;
 };
 
 }  // namespace grf
@@ -135,7 +141,7 @@ struct grf_graph {
     grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_eend, d_deg;
     std::vector<int32_t> gord;
     int32_t cls_off[grf::kPcgClasses + 2] = {};
-    grf::DevBuf d_gord, d_ell16, d_ovfm;
+    grf::DevBuf d_gord, d_ell16, d_ovfm, d_prow, d_pvtx, d_pell, d_padj;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;

@@ -245,6 +245,58 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     upload(g.d_ell16, e16, s);
     upload(g.d_ovfm, om, s);
+    // vertex PCG row order: reverse Cuthill-McKee for the graphs beyond every on-chip
+    // class (their neighbour gathers then stay close in memory), vertex order otherwise
+    std::vector<int32_t> prow(g.V), pvtx(g.V), pell(4 * (size_t)g.V), padj(g.adj_o.size());
+    for (int64_t u = 0; u < g.V; ++u) prow[u] = pvtx[u] = (int32_t)u;
+    for (int64_t k = 0; k < ng; ++k) {
+        if (cls[k] < kPcgClasses) continue;
+        const int32_t u0 = g.gv0[k], nv = g.gv0[k + 1] - u0;
+        std::vector<int32_t> byd(nv), order;
+        order.reserve(nv);
+        for (int32_t v = 0; v < nv; ++v) byd[v] = v;
+        std::stable_sort(byd.begin(), byd.end(), [&](int32_t a, int32_t b) { return deg[u0 + a] < deg[u0 + b]; });
+        std::vector<char> seen(nv, 0);
+        std::vector<int32_t> nb;
+        for (int32_t st0 : byd) {  // each component from its least-connected vertex, breadth first
+            if (seen[st0]) continue;
+            seen[st0] = 1;
+            size_t head = order.size();
+            order.push_back(st0);
+            while (head < order.size()) {
+                const int32_t v = order[head++];
+                nb.clear();
+                for (int64_t q = g.vptr[u0 + v]; q < g.vptr[u0 + v + 1]; ++q) {
+                    const int32_t w = g.adj_o[q] - u0;
+                    if (!seen[w]) {
+                        seen[w] = 1;
+                        nb.push_back(w);
+                    }
+                }
+                std::stable_sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg[u0 + a] < deg[u0 + b]; });
+                order.insert(order.end(), nb.begin(), nb.end());
+            }
+        }
+        GRF_REQUIRE((int32_t)order.size() == nv, "internal: vertex order incomplete");
+        for (int32_t r = 0; r < nv; ++r) {  // reversed
+            const int32_t v = order[nv - 1 - r];
+            pvtx[u0 + r] = u0 + v;
+            prow[u0 + v] = u0 + r;
+        }
+    }
+    for (int64_t k = 0; k < ng; ++k) {
+        const int32_t u0 = g.gv0[k];
+        for (int32_t r = u0; r < g.gv0[k + 1]; ++r) {
+            const int32_t u = pvtx[r];
+            for (int j = 0; j < 4; ++j) pell[(size_t)j * g.V + r] = prow[ell[(size_t)j * g.V + u]] - u0;
+        }
+        for (int32_t u = u0; u < g.gv0[k + 1]; ++u)
+            for (int64_t q = g.vptr[u]; q < g.vptr[u + 1]; ++q) padj[q] = prow[g.adj_o[q]] - u0;
+    }
+    upload(g.d_prow, prow, s);
+    upload(g.d_pvtx, pvtx, s);
+    upload(g.d_pell, pell, s);
+    upload(g.d_padj, padj, s);
     upload(g.d_gv0, g.gv0, s);
     upload(g.d_ge0, g.ge0, s);
     upload(g.d_segs, g.segs, s);
@@ -334,6 +386,10 @@ grf::MeshView grf_graph::view() const {
     v.gord = d_gord.as<int32_t>();
     v.ell16 = d_ell16.as<uint2>();
     v.ovfm = d_ovfm.as<uint32_t>();
+    v.prow = d_prow.as<int32_t>();
+    v.pvtx = d_pvtx.as<int32_t>();
+    v.pell = d_pell.as<int32_t>();
+    v.padj = d_padj.as<int32_t>();
     for (int c = 0; c <= grf::kPcgClasses + 1; ++c) v.cls_off[c] = cls_off[c];
     return v;
 }

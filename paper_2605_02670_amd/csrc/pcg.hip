@@ -102,16 +102,17 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
 // diagonal in the product and no preconditioner in the update.  The learned
 // operators are defined on S^ already: z^ = P^ r^, x0^ = Q^ g^.
 //
-// Vertex operators of a shift block in ELL-4 form:
-// (Op y)_u = diag[l][u] y_u + sum_{j<4} coef[l][u][j] y_{ell[j][u]} + sum over the
+// Vertex operators of a shift block in ELL-4 form, per row r = prow[u] of vertex u:
+// (Op y)_u = diag[l][r] y_u + sum_{j<4} coef[l][r][j] y_{ell[j][u]} + sum over the
 // CSR slots k >= vptr[u] + 4 of ovf[l][k] y_{adj_o[k]}  (a self-loop's coupling is
 // in the diagonal; its slots carry 0).  For S^ the diagonal is 1 (not stored) and
-// dh holds h; for P^ and Q^ diag holds their diagonal.
+// dh holds h; for P^ and Q^ diag holds their diagonal.  Rows follow the vertex
+// order except in the graphs beyond every on-chip class (MeshView::prow).
 struct EllOp {
     double *diag, *dh, *coef, *ovf;  // [LB][V], [LB][V], [LB][V][4], [LB][2E]
 };
 
-// h = diag(S)^{-1/2} per (shift, vertex)
+// h = diag(S)^{-1/2} per (shift, vertex), stored at the vertex's row (prow)
 __global__ void k_ell_diag(MeshView mv, const double *__restrict__ sd, const double *__restrict__ so, int32_t LB,
                            double *__restrict__ dh) {
     const int64_t n = (int64_t)LB * mv.V;
@@ -123,7 +124,7 @@ __global__ void k_ell_diag(MeshView mv, const double *__restrict__ sd, const dou
             const int e = mv.adj_e[k];
             d += sdl[e] + (mv.adj_o[k] == u ? sol[e] : 0.0);
         }
-        dh[i] = 1.0 / sqrt(d);
+        dh[(int64_t)l * mv.V + mv.prow[u]] = 1.0 / sqrt(d);
     }
 }
 
@@ -145,15 +146,16 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(i / mv.V), u = (int)(i - (int64_t)l * mv.V);
         const double *sdl = sd + (int64_t)l * mv.E, *sol = so + (int64_t)l * mv.E;
-        const double *hl = S.dh + (int64_t)l * mv.V;
-        const double hu = hl[u];
+        const double *hl = S.dh + (int64_t)l * mv.V;  // by row (prow)
+        const int64_t ru = (int64_t)l * mv.V + mv.prow[u];
+        const double hu = hl[mv.prow[u]];
         const int64_t k0 = mv.vptr[u], k1 = mv.vptr[u + 1];
         const double du = (double)(k1 - k0);
         double pdiag = 0.0;  // PM_NN: sum over the slots of (D^-1 S_e^-1 D^-1)_uu
         for (int64_t k = k0; k < k1; ++k) {
             const int e = mv.adj_e[k];
             const int o = mv.adj_o[k];
-            const double c = (o == u) ? 0.0 : hu * sol[e] * hl[o];
+            const double c = (o == u) ? 0.0 : hu * sol[e] * hl[mv.prow[o]];
             double cp = 0.0, cq = 0.0;
             if (lrn && o != u) {
                 cp = lo.Pq[(int64_t)l * mv.E + e];
@@ -167,14 +169,14 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
                 } else {
                     pdiag += isd / (du * du);
                     const double dov = (double)(mv.vptr[o + 1] - mv.vptr[o]);
-                    cp = iso / (du * dov * hu * hl[o]);
+                    cp = iso / (du * dov * hu * hl[mv.prow[o]]);
                 }
             }
             const int j = (int)(k - k0);
             if (j < 4) {
-                S.coef[((int64_t)l * mv.V + u) * 4 + j] = c;
-                if (opP) P.coef[((int64_t)l * mv.V + u) * 4 + j] = cp;
-                if (lrn) Q.coef[((int64_t)l * mv.V + u) * 4 + j] = cq;
+                S.coef[ru * 4 + j] = c;
+                if (opP) P.coef[ru * 4 + j] = cp;
+                if (lrn) Q.coef[ru * 4 + j] = cq;
             } else {
                 S.ovf[(int64_t)l * E2 + k] = c;
                 if (opP) P.ovf[(int64_t)l * E2 + k] = cp;
@@ -182,34 +184,17 @@ __global__ void k_ell_ops(MeshView mv, const double *__restrict__ sd, const doub
             }
         }
         for (int j = (int)(k1 - k0); j < 4; ++j) {
-            S.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
-            if (opP) P.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
-            if (lrn) Q.coef[((int64_t)l * mv.V + u) * 4 + j] = 0.0;
+            S.coef[ru * 4 + j] = 0.0;
+            if (opP) P.coef[ru * 4 + j] = 0.0;
+            if (lrn) Q.coef[ru * 4 + j] = 0.0;
         }
         if (lrn) {
-            P.diag[i] = lo.Pd[i];
-            Q.diag[i] = lo.Qd[i];
+            P.diag[ru] = lo.Pd[i];
+            Q.diag[ru] = lo.Qd[i];
         } else if (pm == PM_NN) {
-            P.diag[i] = pdiag / (hu * hu);
+            P.diag[ru] = pdiag / (hu * hu);
         }
     }
-}
-
-// (Op y)_u for the graph-local vector y (vertex u = u0 + local index); UNIT: the
-// diagonal is 1
-template <bool UNIT>
-__device__ __forceinline__ double ell_apply(const MeshView &mv, const double *__restrict__ dg,
-                                            const double *__restrict__ cf, const double *__restrict__ of,
-                                            const double *y, int u, int u0) {
-    double acc = UNIT ? y[u - u0] : dg[u] * y[u - u0];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc += cf[4 * (int64_t)u + j] * y[mv.ell[(int64_t)j * mv.V + u] - u0];
-    const int d = mv.deg[u];
-    if (d > 4) {
-        const int64_t k0 = mv.vptr[u];
-        for (int64_t k = k0 + 4; k < k0 + d; ++k) acc += of[k] * y[mv.adj_o[k] - u0];
-    }
-    return acc;
 }
 
 // Sums of NV per-system values over a workgroup whose thread t works for system
@@ -253,7 +238,8 @@ struct SampleSum {
 // one workgroup per (graph, shift, block of SB samples), the SB systems of a
 // block solved side by side.  Thread t works for sample t % SB at the local
 // vertices t / SB + VS i (VS = TPB / SB).  The vectors g^, x^, r^, p and q of the
-// block live in global scratch as [vertex][SB] rows (5 maxVg SB doubles per
+// block live in global scratch as [row][SB] rows, in the graph's row order
+// (prow / pvtx: Cuthill-McKee for these graphs), (5 maxVg SB doubles per
 // resident workgroup), so a neighbour gather reads one contiguous row of SB
 // values and each operator row is read once for SB systems.  The systems of
 // (g, l, s) are the graph's vertex range of gT / xT[l][s]; statistics go to
@@ -302,18 +288,19 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
         const double *Pd = LRN ? Pop.diag + (int64_t)l * mv.V : nullptr;
         const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
         const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
-        // (Op y)_v of this thread's system, y in [vertex][SB] rows; UNIT: the diagonal is 1
+        // (Op y)_v of this thread's system at graph-local row v (operator rows and y
+        // in the graph's row order), y in [row][SB]; UNIT: the diagonal is 1
         auto apply = [&](auto unit_diag, const double *dg, const double *cf, const double *of, const double *y,
                          int v) -> double {
-            const int u = u0 + v;
-            double acc = (decltype(unit_diag)::value ? 1.0 : dg[u]) * y[v * SB + s];
+            const int r = u0 + v;
+            double acc = (decltype(unit_diag)::value ? 1.0 : dg[r]) * y[v * SB + s];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc += cf[4 * (int64_t)u + j] * y[(mv.ell[(int64_t)j * mv.V + u] - u0) * SB + s];
+            for (int j = 0; j < 4; ++j) acc += cf[4 * (int64_t)r + j] * y[mv.pell[(int64_t)j * mv.V + r] * SB + s];
+            const int u = mv.pvtx[r];
             const int d = mv.deg[u];
             if (d > 4) {
                 const int64_t k0 = mv.vptr[u];
-                for (int64_t k = k0 + 4; k < k0 + d; ++k) acc += of[k] * y[(mv.adj_o[k] - u0) * SB + s];
+                for (int64_t k = k0 + 4; k < k0 + d; ++k) acc += of[k] * y[mv.padj[k] * SB + s];
             }
             return acc;
         };
@@ -325,7 +312,7 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
 #pragma unroll 1
         for (int v = vs; v < V; v += VS) {
             const int i = v * SB + s;
-            const double gv = live ? gT[((int64_t)l * S + smp) * mv.V + u0 + v] : 0.0;
+            const double gv = live ? gT[((int64_t)l * S + smp) * mv.V + mv.pvtx[u0 + v]] : 0.0;
             const double gh = H[v] * gv;
             Gh[i] = gh;
             X[i] = 0.0;
@@ -477,10 +464,10 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
                 flag[1][s] = fresh;
             }
         }
-        // x = H x^ (each entry read by the thread that wrote it)
+        // x = H x^ (each entry read by the thread that wrote it), back in vertex order
         if (live) {
-            double *xo = xT + ((int64_t)l * S + smp) * mv.V + u0;
-            for (int v = vs; v < V; v += VS) xo[v] = (gg > 0.0) ? H[v] * X[v * SB + s] : 0.0;
+            double *xo = xT + ((int64_t)l * S + smp) * mv.V;
+            for (int v = vs; v < V; v += VS) xo[mv.pvtx[u0 + v]] = (gg > 0.0) ? H[v] * X[v * SB + s] : 0.0;
             if (vs == 0) {
                 const int64_t sys = ((int64_t)gi * LB + l) * S + smp;
                 its[sys] = done ? its_s : maxit + 1;

@@ -114,8 +114,11 @@ def test_unused_network_is_skipped(grf):
     kap = [3.0, 6.0, 9.0]
     net = grf.Learned(init_params(7, head_scale=0.5))
     try:
-        uj, sj = grf.sample_batched(Gs, kap, BETA, K, S, SEED)
-        ul, sl = grf.sample_batched(Gs, kap, BETA, K, S, SEED, learned=net, pcg_class_modes=["jacobi"] * 6)
+        # a fixed shift block: both calls take the same plan (the autotuner would time
+        # each (precision, preconditioner) separately and may pick different sweeps)
+        uj, sj = grf.sample_batched(Gs, kap, BETA, K, S, SEED, shift_block=16)
+        ul, sl = grf.sample_batched(Gs, kap, BETA, K, S, SEED, learned=net, pcg_class_modes=["jacobi"] * 6,
+                                    shift_block=16)
         assert sl["total_iterations"] == sj["total_iterations"]
         for a, b in zip(uj, ul):
             assert torch.equal(a, b)
