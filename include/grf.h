@@ -189,6 +189,19 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
                uint64_t seed, double *out, const grf_opts *opts);
 
 /*
+ * The same sum for caller-supplied noise, W[s] = noise[s] (eq. spde_approx_fem
+ * with a given load): the path of grf_sample without the Philox draw, for noise
+ * coupled across meshes (convergence studies, multilevel estimators).
+ *   noise  device, float64 [n_samples][n_dof], canonical order (the layout
+ *          grf_noise writes); read only, may not alias out
+ *   out    device, float64 [n_samples][n_dof], canonical order
+ * With noise = grf_noise(g, n_samples, seed) the result equals grf_sample's bit
+ * for bit.  Returns GRF_ENOCONV (with out written) if a Schur system hit maxit.
+ */
+int grf_sample_from_noise(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples,
+                          const double *noise, double *out, const grf_opts *opts);
+
+/*
  * One shifted solve for n_rhs right-hand sides:
  *   out[r] = ((c_I + c_L kappa^2) M_L + c_L G)^{-1} rhs[r]
  * (paper: eq. spde_approx_fem for a single l, solved by eq. global_schur).

@@ -937,6 +937,46 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
 
 }  // namespace
 
+// Range of a right-hand side.  The stopping test compares squared norms,
+// ||g - S x||^2 <= tol^2 ||g||^2, which underflow when g is tiny.  A load far
+// inside an edge reaches the vertices damped like e^{-d theta}, 1e-170 and less
+// at strongly mass-dominated shifts.  Before the PCG every (graph, shift,
+// sample) system whose sum of |g| lies outside [2^-300, 2^300] has its row
+// scaled in place by the power of two 2^e that brings the sum into [1, 2)
+// (exact: the solve is unchanged but for the scale), and e is kept.  After the
+// PCG both g and x of such a system are scaled back by 2^-e.  Every other
+// system keeps e = 0 and is not touched again.  One workgroup per system.
+__global__ void __launch_bounds__(256) k_rhs_range(MeshView mv, double *__restrict__ gT, int32_t *__restrict__ gexp,
+                                                   int32_t LB, int64_t S) {
+    __shared__ double red[16];
+    const int64_t sys = blockIdx.x;  // (g * LB + l) * S + s
+    const int64_t s = sys % S, l = (sys / S) % LB, gi = sys / (S * LB);
+    const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
+    double *g = gT + (l * S + s) * mv.V + u0;
+    double t[1] = {0.0};
+    for (int v = threadIdx.x; v < V; v += blockDim.x) t[0] += fabs(g[v]);
+    block_sum<1>(t, red, blockDim.x >> 6);
+    const double a = t[0];
+    const int e = (a > 0.0 && (a < 0x1p-300 || a > 0x1p300)) ? -ilogb(a) : 0;
+    if (threadIdx.x == 0) gexp[sys] = e;
+    if (e != 0)
+        for (int v = threadIdx.x; v < V; v += blockDim.x) g[v] = ldexp(g[v], e);
+}
+
+__global__ void __launch_bounds__(256) k_rhs_unrange(MeshView mv, double *__restrict__ gT, double *__restrict__ xT,
+                                                     const int32_t *__restrict__ gexp, int32_t LB, int64_t S) {
+    const int64_t sys = blockIdx.x;
+    const int e = gexp[sys];
+    if (e == 0) return;
+    const int64_t s = sys % S, l = (sys / S) % LB, gi = sys / (S * LB);
+    const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
+    double *g = gT + (l * S + s) * mv.V + u0, *x = xT + (l * S + s) * mv.V + u0;
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        g[v] = ldexp(g[v], -e);
+        x[v] = ldexp(x[v], -e);
+    }
+}
+
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
     return (size_t)blocks * 5 * kMrhsMaxSB * (size_t)mv.maxVg * sizeof(double);
 }
@@ -1048,6 +1088,9 @@ bool chip_mode_valid(int c, int mode) {
     return mode == CM_JACOBI || mode == CM_GUESS || (mode == CM_OP && c < kChipOpClasses);
 }
 
+static void launch_mrhs(const MeshView &mv, const SchurArgs &a, const EllOp *ops, bool lrn, int32_t ngl, int c_end,
+                        hipStream_t st);
+
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
     const int32_t pm = a.precond == GRF_PRECOND_LEARNED ? PM_LEARNED : a.precond == GRF_PRECOND_NN ? PM_NN : PM_JACOBI;
@@ -1066,6 +1109,9 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     const dim3 eg((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)));
     hipLaunchKernelGGL(k_ell_diag, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0].dh);
     hipLaunchKernelGGL(k_ell_ops, eg, dim3(256), 0, st, mv, a.sd, a.so, a.LB, ops[0], pm, lo, ops[1], ops[2]);
+    const int64_t nsys_all = (int64_t)mv.ng * a.LB * a.S;
+    GRF_REQUIRE(nsys_all < ((int64_t)1 << 31), "too many systems in one shift block");
+    hipLaunchKernelGGL(k_rhs_range, dim3((unsigned)nsys_all), dim3(256), 0, st, mv, a.gT, a.gexp, a.LB, a.S);
     GRF_LAUNCH_CHECK();
     // on-chip classes: Jacobi everywhere; Neumann-Neumann in the classes that hold both
     // vectors (the others take the global-memory kernel); learned: per class as chosen
@@ -1083,7 +1129,13 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     }
     // graphs beyond the on-chip classes
     const int32_t ngl = mv.cls_off[kPcgClasses + 1] - mv.cls_off[c_end];
-    if (ngl == 0) return;
+    if (ngl > 0) launch_mrhs(mv, a, ops, lrn, ngl, c_end, st);
+    hipLaunchKernelGGL(k_rhs_unrange, dim3((unsigned)nsys_all), dim3(256), 0, st, mv, a.gT, a.xT, a.gexp, a.LB, a.S);
+    GRF_LAUNCH_CHECK();
+}
+
+static void launch_mrhs(const MeshView &mv, const SchurArgs &a, const EllOp *ops, bool lrn, int32_t ngl, int c_end,
+                        hipStream_t st) {
     const int sb = mrhs_sb(ngl, a.LB, a.S);
     const int64_t units = (int64_t)ngl * a.LB * ((a.S + sb - 1) / sb);
     const int64_t blocks = std::min<int64_t>(units, (int64_t)a.pcg_blocks * (kMrhsMaxSB / sb));

@@ -148,6 +148,7 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     w.xT.reserve(8 * (size_t)lb * S * g.V);
     w.ug.reserve(8 * (size_t)lb * g.V * ps.Sp);
     w.its.reserve(4 * (size_t)ps.ng * ps.L * S);
+    w.gexp.reserve(4 * (size_t)ps.ng * ps.L * S);
     w.res.reserve(8 * (size_t)ps.ng * ps.L * S);
     w.pcg_scr.reserve(pcg_scratch_bytes(mv, ps.p.pcg_blocks));
     w.pcg_ops.reserve(pcg_ops_bytes(mv, lb, o.precond));
@@ -259,6 +260,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.scr = w.pcg_scr.as<double>();
         sc.ops = w.pcg_ops.as<double>();
         sc.its = w.its.as<int32_t>() + (size_t)ps.ng * l0 * S;  // [ng][lb][S] per shift block
+        sc.gexp = w.gexp.as<int32_t>() + (size_t)ps.ng * l0 * S;
         sc.res = w.res.as<double>() + (size_t)ps.ng * l0 * S;
         sc.LB = lb;
         sc.LBp = LBp;
@@ -544,9 +546,9 @@ int grf_noise(grf_graph *g, int64_t n_samples, uint64_t seed, double *out, const
     GRF_API_END
 }
 
-int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
-               double *out, const grf_opts *opts) {
-    GRF_API_BEGIN
+// grf_sample and grf_sample_from_noise: W from the Philox draw (noise null) or the caller
+static int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
+                       const double *noise, double *out, const grf_opts *opts) {
     GRF_REQUIRE(g, "graph is NULL");
     GRF_REQUIRE(std::isfinite(kappa) && kappa > 0, "kappa must be finite and > 0");
     GRF_REQUIRE(n_samples >= 0, "n_samples must be >= 0");
@@ -554,6 +556,7 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
     Shifts sh = make_shifts(beta, quad_step, g->h, o);
     if (n_samples == 0) return GRF_OK;
     GRF_REQUIRE(out, "out is NULL");
+    GRF_REQUIRE(noise != out, "noise and out may not alias");
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
     hipStream_t st = (hipStream_t)o.stream;
@@ -565,8 +568,13 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
     const MeshView mv = g->view();
     if (o.stats) *o.stats = grf_stats{};
     KTimer T(o.timing != 0, st);
-    T.begin(GRF_K_NOISE);
-    launch_noise(mv, n_samples, o.sample_offset, seed, w.X.as<double>(), st);
+    if (noise) {
+        T.begin(GRF_K_LAYOUT);
+        launch_to_interleaved(noise, n_samples, g->N, w.X.as<double>(), st);
+    } else {
+        T.begin(GRF_K_NOISE);
+        launch_noise(mv, n_samples, o.sample_offset, seed, w.X.as<double>(), st);
+    }
     T.end();
     int code = GRF_OK;
     try {
@@ -581,6 +589,20 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
     GRF_HIP(hipStreamSynchronize(st));
     T.collect(o.stats);
     return code;
+}
+
+int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
+               double *out, const grf_opts *opts) {
+    GRF_API_BEGIN
+    return sample_impl(g, kappa, beta, quad_step, n_samples, seed, nullptr, out, opts);
+    GRF_API_END
+}
+
+int grf_sample_from_noise(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples,
+                          const double *noise, double *out, const grf_opts *opts) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(noise || n_samples == 0, "noise is NULL");
+    return sample_impl(g, kappa, beta, quad_step, n_samples, 0, noise, out, opts);
     GRF_API_END
 }
 

@@ -19,6 +19,7 @@ struct grf_graph::Work {
     grf::DevBuf pcg_scr;          // PCG vectors in global memory (large graphs)
     grf::DevBuf pcg_ops;          // per-shift-block vertex operators of the global-memory PCG
     grf::DevBuf its, res;         // [LB][S] int32 iterations, double relative residual
+    grf::DevBuf gexp;             // [ng][LB][S] int32: right-hand side scaled by 2^gexp for the PCG
     grf::DevBuf Bm, Xacc, nrm;    // mixed-precision refinement: right-hand sides, iterate, norm partials
     std::vector<int32_t> h_its;
     std::vector<double> h_res;
@@ -132,6 +133,7 @@ struct SchurArgs {
     double *scr;          // PCG scratch (large graphs)
     double *ops;          // vertex operators of the block for the global-memory PCG (pcg_ops_bytes)
     int32_t *its;         // [LB][S]
+    int32_t *gexp;        // [ng][LB][S] scale exponents of the right-hand sides (k_rhs_range)
     double *res;          // [LB][S]
     int32_t LB, LBp, nb, Sp;
     int64_t S;

@@ -66,6 +66,8 @@ _SIGS = [
     ("grf_noise", C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.POINTER(Opts)]),
     ("grf_sample", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_uint64, C.c_void_p,
                              C.POINTER(Opts)]),
+    ("grf_sample_from_noise", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p,
+                                        C.c_void_p, C.POINTER(Opts)]),
     ("grf_solve_shifted", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p,
                                     C.c_void_p, C.POINTER(Opts)]),
     ("grf_sample_batched", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_int64,
@@ -214,6 +216,24 @@ class Graph:
         allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
         _check(load().grf_sample(self.handle, kappa, beta, quad_step, n_samples, seed, out.data_ptr(), C.byref(o)),
                allow)
+        return out, st.as_dict()
+
+    def sample_from_noise(self, kappa: float, beta: float, quad_step: float, noise, out=None,
+                          allow_noconv: bool = False, **kw):
+        """The sample for given noise (float64 [n_samples, n_dof] on cuda, e.g. from
+        noise()); returns (samples, stats dict)."""
+        import torch
+
+        assert noise.dtype == torch.float64 and noise.is_cuda and noise.is_contiguous()
+        assert noise.dim() == 2 and noise.shape[1] == self.n_dof
+        n = noise.shape[0]
+        if out is None:
+            out = torch.empty((n, self.n_dof), dtype=torch.float64, device="cuda")
+        st = Stats()
+        o = make_opts(stats=st, **kw)
+        allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
+        _check(load().grf_sample_from_noise(self.handle, kappa, beta, quad_step, n, noise.data_ptr(), out.data_ptr(),
+                                            C.byref(o)), allow)
         return out, st.as_dict()
 
     def solve_shifted(self, kappa: float, c_I: float, c_L: float, rhs, out=None, allow_noconv=False, **kw):

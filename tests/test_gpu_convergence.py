@@ -1,0 +1,170 @@
+"""The sampler with caller-supplied noise, and the paper's convergence rates
+(Table 1) reproduced with the GPU sampler as the engine, scaled down.
+
+* grf_sample_from_noise on the noise grf_noise draws equals grf_sample bit for
+  bit, and equals the oracle's direct solve with the same noise to 1e-10.
+* Convergence on the unit interval (section "Numerical Experiments", Table 1),
+  as the oracle test of the same rates does it, with every solve on the GPU:
+  kappa = 1, the paper's step k = -1/(beta ln h), 100 noise realisations drawn
+  on an overkill mesh of 2^11 elements and projected onto the coarse meshes
+  (2^2..2^5 elements) through the hat functions, so that all levels see the
+  same white noise.  The strong error is the RMS over realisations of the
+  lumped L2 norm of (overkill sample - prolonged coarse sample); the
+  covariance error is the lumped L2(Gamma x Gamma) norm on the 2^9 mesh of the
+  difference between the method's covariance there and on the coarse mesh,
+  each covariance F M_L F^T from the solution operator F that the sampler
+  applies to unit loads.  Bars as in the oracle test: strong slope within 0.04
+  of 2 beta - 1/2 and of the paper's measurement, covariance slope in
+  [min(4 beta - 1/2, 2) - 0.1, + 0.35].
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh
+from oracle import noise as onoise
+from oracle import solve as osolve
+from workloads import config_c1
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel_ml(u, ref, ML):
+    num = np.sqrt(((u - ref) ** 2 * ML).sum(axis=-1))
+    den = np.sqrt((ref ** 2 * ML).sum(axis=-1))
+    return float(np.max(num / den))
+
+
+def test_from_noise_matches_sample_and_oracle(grf):
+    import torch
+
+    cfg = config_c1()
+    g = cfg["graph"]
+    G = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    args = (cfg["kappa"], cfg["beta"], cfg["quad_step"])
+    S = cfg["n_samples"]
+    W = G.noise(S, cfg["seed"])
+    u0, _ = G.sample(*args, S, cfg["seed"])
+    u1, st = G.sample_from_noise(*args, W)
+    assert st["n_unconverged"] == 0
+    assert torch.equal(u0, u1)
+    m = omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    ML = omesh.lumped_mass(m)
+    Wr = np.random.default_rng(3).standard_normal((5, m.n_dof)) * np.sqrt(ML)  # any load, not only Philox noise
+    u2, _ = G.sample_from_noise(*args, torch.from_numpy(Wr).cuda())
+    ref = osolve.sample(m, cfg["kappa"], cfg["beta"], cfg["quad_step"], Wr)
+    assert _rel_ml(u2.cpu().numpy(), ref, ML) <= 1e-10
+    with pytest.raises(grf.GrfError, match="alias"):
+        G.sample_from_noise(*args, W, out=W)
+
+
+# ---- convergence rates ------------------------------------------------------------
+
+def _order(n):
+    """DOF order of the interval mesh -> node index (interior 1..n-1, then x = 0, x = 1)."""
+    return np.concatenate([np.arange(1, n), [0, n]])
+
+
+def _prolong(nc, nf):
+    """Nodal values on the fine mesh of the coarse hat functions ([nf+1, nc+1])."""
+    r = nf // nc
+    P = np.zeros((nf + 1, nc + 1))
+    for f in range(nf + 1):
+        c, t = divmod(f, r)
+        if c == nc:
+            P[f, nc] = 1.0
+        else:
+            P[f, c] += 1 - t / r
+            P[f, c + 1] += t / r
+    return P
+
+
+def _weights(n):
+    w = np.full(n + 1, 1.0 / n)
+    w[0] = w[-1] = 0.5 / n
+    return w
+
+
+class _Interval:
+    """The unit interval meshed with n elements, sampled on the GPU (node order in and out)."""
+
+    def __init__(self, grf, n):
+        self.n = n
+        self.o = _order(n)
+        self.G = grf.Graph(2, np.array([[0, 1]]), np.array([1.0]), 1.0 / n, "ceil")
+        assert self.G.n_dof == n + 1
+
+    def sample(self, kappa, beta, W_nodes):
+        import torch
+
+        noise = torch.from_numpy(np.ascontiguousarray(W_nodes[:, self.o])).cuda()
+        u, st = self.G.sample_from_noise(kappa, beta, 0.0, noise)  # 0: the paper's step for this h
+        assert st["n_unconverged"] == 0
+        out = np.zeros(W_nodes.shape)
+        out[:, self.o] = u.cpu().numpy()
+        return out
+
+    def operator(self, kappa, beta):
+        """F (node order): column j is the sample for a unit load at node j."""
+        return self.sample(kappa, beta, np.eye(self.n + 1)).T
+
+    def close(self):
+        self.G.close()
+
+
+def _rates_gpu(grf, beta, kappa=1.0, pf=11, levels=(2, 3, 4, 5), R=100):
+    nf = 2 ** pf
+    wf = _weights(nf)
+    rng = np.random.default_rng(0)
+    Wn = rng.standard_normal((R, nf + 1)) * np.sqrt(wf)
+    fine = _Interval(grf, nf)
+    uf = fine.sample(kappa, beta, Wn)
+    fine.close()
+    n9 = 2 ** 9
+    w9 = _weights(n9)
+    m9 = _Interval(grf, n9)
+    F9 = m9.operator(kappa, beta)
+    m9.close()
+    C9 = F9 @ np.diag(w9) @ F9.T
+    strong, cov, hs = [], [], []
+    for lv in levels:
+        nc = 2 ** lv
+        P = _prolong(nc, nf)
+        coarse = _Interval(grf, nc)
+        uc = coarse.sample(kappa, beta, Wn @ P)
+        e = uf - uc @ P.T
+        strong.append(math.sqrt(((e * e) * wf).sum(axis=1).mean()))
+        P9 = _prolong(nc, n9)
+        Fc = P9 @ coarse.operator(kappa, beta) @ P9.T
+        coarse.close()
+        D = C9 - Fc @ np.diag(w9) @ Fc.T
+        cov.append(math.sqrt((D * D * w9[:, None] * w9[None, :]).sum()))
+        hs.append(1.0 / nc)
+    lh = np.log(hs)
+    return np.polyfit(lh, np.log(strong), 1)[0], np.polyfit(lh, np.log(cov), 1)[0]
+
+
+def _table1():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_table1_rates.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(x) for x in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("row", range(5))
+def test_convergence_rates_table1_gpu(grf, row):
+    beta, strong_paper, cov_paper, strong_th, cov_th = _table1()[row]
+    strong, cov = _rates_gpu(grf, beta)
+    print(f"beta {beta}: strong slope {strong:.3f} (paper {strong_paper}, theory {strong_th}); "
+          f"covariance slope {cov:.3f} (paper {cov_paper}, theory {cov_th})", flush=True)
+    assert abs(strong - strong_th) <= 0.04
+    assert abs(strong - strong_paper) <= 0.04
+    assert cov >= cov_th - 0.1
+    assert cov <= cov_th + 0.35
