@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
                 // restart from it (z^ and p from the true residual)
                 double t[3] = {0.0, 0.0, 0.0};  // r^.z^, ||g - S x||^2, ||r^||^2
 #pragma unroll 1
-        for (int v = vs; v < V; v += VS) {
+                for (int v = vs; v < V; v += VS) {
                     if (!fresh) break;
                     const int i = v * SB + s;
                     const double rv = Gh[i] - applyS(X, v);
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
                 if (LRN) {
                     __syncthreads();  // r^ complete: the preconditioner reads neighbours
 #pragma unroll 1
-        for (int v = vs; v < V; v += VS) {
+                    for (int v = vs; v < V; v += VS) {
                         if (!(fresh && lz)) break;
                         const int i = v * SB + s;
                         const double zv = applyP(R, v);
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
             ++it;
             double t1[1] = {0.0};  // p.q
 #pragma unroll 1
-        for (int v = vs; v < V; v += VS) {
+            for (int v = vs; v < V; v += VS) {
                 if (done) break;
                 const int i = v * SB + s;
                 const double qv = applyS(P, v);
@@ -422,12 +422,11 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
             }
             ssum(t1);
             const double alpha = done ? 0.0 : rz / t1[0];
-            double t2[2] = {0.0, 0.0};  // ||r^||^2, r^.z^
+            double t2[2] = {0.0, 0.0};  // ||r^||^2, r^.z^ (x^ is updated with p below)
 #pragma unroll 1
-        for (int v = vs; v < V; v += VS) {
+            for (int v = vs; v < V; v += VS) {
                 if (done) break;
                 const int i = v * SB + s;
-                X[i] += alpha * P[i];
                 const double rv = R[i] - alpha * Q[i];
                 R[i] = rv;
                 t2[0] += rv * rv;
@@ -435,7 +434,7 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
             if (LRN) {
                 __syncthreads();  // r^ complete: the preconditioner reads neighbours
 #pragma unroll 1
-        for (int v = vs; v < V; v += VS) {
+                for (int v = vs; v < V; v += VS) {
                     if (done || !lz) break;
                     const int i = v * SB + s;
                     const double zv = applyP(R, v);
@@ -447,15 +446,22 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
             if (!done) {
                 if (t2[0] <= thr) {
                     fresh = true;  // test with the true residual (and restart if it fails)
+#pragma unroll 1
+                    for (int v = vs; v < V; v += VS) {
+                        const int i = v * SB + s;
+                        X[i] += alpha * P[i];
+                    }
                 } else {
                     rel = sqrt(t2[0] * rr / (rh > 0.0 ? rh : 1.0) / gg);  // estimate
                     const double rzn = (LRN && lz) ? t2[1] : t2[0];
                     const double beta = rzn / rz;
                     rz = rzn;
 #pragma unroll 1
-        for (int v = vs; v < V; v += VS) {
+                    for (int v = vs; v < V; v += VS) {
                         const int i = v * SB + s;
-                        P[i] = ((LRN && lz) ? Q[i] : R[i]) + beta * P[i];
+                        const double pv = P[i];
+                        X[i] += alpha * pv;
+                        P[i] = ((LRN && lz) ? Q[i] : R[i]) + beta * pv;
                     }
                 }
             }
