@@ -77,3 +77,15 @@ def test_null_handles_are_rejected():
     assert lib.grf_sample(None, 1.0, 0.5, 0.3, 1, 0, None, None) == grf.GRF_EINVAL
     assert lib.grf_noise(None, 1, 0, None, None) == grf.GRF_EINVAL
     assert lib.grf_solve_shifted(None, 1.0, 1.0, 1.0, 1, None, None, None) == grf.GRF_EINVAL
+
+
+def test_class_mode_encoding():
+    """pcg_class_modes: GRF_PCG_MODES_SET | (variant of class c) << 2c, decoded back by
+    class_modes (3 is reported for classes that run the global-memory kernel)."""
+    modes = ["op", "guess", "jacobi", "op", "guess", "jacobi"]
+    o = grf.make_opts(pcg_class_modes=modes, stream=False)
+    assert o.pcg_class_modes == grf.PCG_MODES_SET | 0 | 1 << 2 | 2 << 4 | 0 << 6 | 1 << 8 | 2 << 10
+    assert grf.class_modes(o.pcg_class_modes) == modes
+    assert grf.class_modes(3 << 10) == ["op"] * 5 + ["global"]
+    assert grf.make_opts(stream=False).pcg_class_modes == 0
+    assert grf.make_opts(precond="nn", stream=False).precond == 2
