@@ -344,6 +344,8 @@ def bench_batched(args) -> int:
     if args.precond == "learned":
         net = train_network()[0]
         kw["learned"] = net
+        if args.learned_variants == "op":
+            kw["pcg_class_modes"] = ["op"] * 5 + ["guess"]
     elif args.precond == "nn":
         kw["precond"] = "nn"
     r = run_batched(cfg, Gs, outs, args.steps, args.warmup, **kw)
@@ -352,7 +354,8 @@ def bench_batched(args) -> int:
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"64 uneven graphs (trees + lattices, 100..20000 edges) h=1/128 beta=0.75 "
-                               f"S={r['samples']} PCG tol {kw['tol']:g} batched-{args.precision}-{args.precond}",
+                               f"S={r['samples']} PCG tol {kw['tol']:g} batched-{args.precision}-{args.precond}"
+                               + ("-op" if "pcg_class_modes" in kw else ""),
                    "n_dof": r["n_dof"], "shifts": r["shifts"], "samples": r["samples"], "graphs": r["graphs"],
                    "parallelism": "1 GPU"},
         "roofline": None, "cpu_baseline": None, "first_call_s": r["first_call_s"], "pcg": r["pcg"],
@@ -376,6 +379,9 @@ def main() -> int:
                     help="PCG tolerance of the batched64 workload (0: the configuration's, 1e-12)")
     ap.add_argument("--precond", choices=["jacobi", "learned", "nn"], default="jacobi",
                     help="vertex PCG preconditioner of the batched64 workload (learned: trained first, on the GPU)")
+    ap.add_argument("--learned-variants", choices=["auto", "op"], default="auto",
+                    help="batched64 with the learned preconditioner: PCG variant per size class as the autotuner "
+                         "picks it, or the learned operator forced in every class")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed / batched / learned forms")
     ap.add_argument("--workload", choices=["lattice64", "batched64", "rgg100k"], default="lattice64",

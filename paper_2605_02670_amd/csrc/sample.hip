@@ -786,18 +786,28 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
             // per size class, the fastest PCG variant: the learned operator and initial
             // guess, the initial guess only, or Jacobi.  Each class is its own launch,
             // so one timed run per variant (after one that loads it) times every class.
-            double cms[3][kPcgClasses];
+            // Any learned variant also costs the network's forward pass, which only the
+            // whole run sees: a mix is kept only if it beats Jacobi everywhere (where the
+            // forward pass is skipped) as a whole.
+            double cms[3][kPcgClasses], tot[3];
             for (int m = 0; m < 3; ++m) {
                 int8_t md[kPcgClasses];
                 for (int c = 0; c < kPcgClasses; ++c) md[c] = (int8_t)(chip_mode_valid(c, m) ? m : CM_GUESS);
                 (void)timed_run(B, sh, n_samples, seed, run, md);
-                (void)timed_run(B, sh, n_samples, seed, run, md, cms[m]);
+                tot[m] = timed_run(B, sh, n_samples, seed, run, md, cms[m]);
             }
+            bool all_jacobi = true;
             for (int c = 0; c < kPcgClasses; ++c) {
                 int bm = CM_JACOBI;
                 for (int m = 0; m < 3; ++m)
                     if (chip_mode_valid(c, m) && cms[m][c] < cms[bm][c]) bm = m;
                 B.tuned_mode[c] = (int8_t)bm;
+                all_jacobi &= bm == CM_JACOBI || mv.cls_off[c + 1] == mv.cls_off[c];
+            }
+            if (!all_jacobi) {
+                const double tmix = timed_run(B, sh, n_samples, seed, run, B.tuned_mode);
+                if (tmix >= tot[CM_JACOBI])
+                    for (int c = 0; c < kPcgClasses; ++c) B.tuned_mode[c] = CM_JACOBI;
             }
             B.modes_tuned = true;
             B.tuned_key = tune_key();
