@@ -168,3 +168,43 @@ def test_convergence_rates_table1_gpu(grf, row):
     assert abs(strong - strong_paper) <= 0.04
     assert cov >= cov_th - 0.1
     assert cov <= cov_th + 0.35
+
+
+def _four_edges(grf, h=1.0 / 64):
+    edges = np.array([[0, 1], [1, 2], [2, 0], [2, 3]])
+    lengths = np.array([2.0, 1.5, 1.0, 3.0])
+    return grf.Graph(4, edges, lengths, h, "ceil"), omesh.build_mesh(4, edges, lengths, h, "ceil")
+
+
+@pytest.mark.parametrize("cI,cL", [(1e3, 1e-3), (1e4, 1e-4), (1.0, 1.0), (1e-6, 1e6)])
+def test_point_loads_reach_the_oracle(grf, cI, cL):
+    """Unit loads at the middle of each edge, at an edge's first node and at a vertex.
+    At the two mass-dominated shifts the middle loads reach the vertices as 6e-77 down
+    to 6e-230 (1e3, 1e-3) and 8e-141 down to 0 (1e4, 1e-4): their squared norms leave
+    the double range and the systems are rescaled exactly.  Every system converges and
+    the solution matches the direct solve."""
+    import torch
+
+    G, m = _four_edges(grf)
+    rows = [int(m.offsets[e] + m.m(e) // 2) for e in range(4)] + [int(m.offsets[0]), m.n_interior + 3]
+    B = np.zeros((len(rows), m.n_dof))
+    B[np.arange(len(rows)), rows] = 1.0
+    x, st = G.solve_shifted(2.0, cI, cL, torch.from_numpy(B).cuda())
+    ref = osolve.solve_shifted(m, 2.0, cI, cL, B)
+    assert st["n_unconverged"] == 0
+    assert _rel_ml(x.cpu().numpy(), ref, omesh.lumped_mass(m)) <= 1e-10
+
+
+@pytest.mark.parametrize("k", [-500, 500])
+def test_range_scaling_is_exact(grf, k):
+    """Solving for 2^k B gives exactly 2^k times the solution for B, bit for bit (power-of-two
+    scaling is exact); without the range scaling the stopping test of these systems under- or
+    overflows."""
+    import torch
+
+    G, m = _four_edges(grf)
+    B = torch.from_numpy(np.random.default_rng(9).standard_normal((5, m.n_dof))).cuda()
+    x1, _ = G.solve_shifted(3.0, 0.7, 1.9, B)
+    x2, st = G.solve_shifted(3.0, 0.7, 1.9, torch.ldexp(B, torch.tensor(k, device="cuda")))
+    assert st["n_unconverged"] == 0
+    assert torch.equal(x2, torch.ldexp(x1, torch.tensor(k, device="cuda")))
