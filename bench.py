@@ -24,7 +24,8 @@ oracle timed on a bounded sample of the same workload, and (unless
                          (trained on the GPU in this run on small graphs of the same kinds),
                          with the PCG variant of each size class picked by the autotuner;
   batch_learned_mixed_op the same with the learned operator and initial guess in every class.
---workload rgg100k times the learned preconditioner's held-out graph (98k vertices) instead.
+--workload rgg100k times the learned preconditioner's held-out graph (98k vertices) instead;
+--workload lattice256 the 256x256 lattice (66.7M DOFs) in FP64 and mixed precision.
 """
 
 from __future__ import annotations
@@ -333,6 +334,69 @@ def bench_rgg(args) -> int:
     return 0
 
 
+def bench_lattice256(args) -> int:
+    """The 256x256 lattice (65,536 vertices, 130,560 edges, h = 1/512, about 66.7M DOFs),
+    kappa = 20, beta = 0.55, step 0.2 with |l| <= 46 (93 shifts, e^{2y} in [1e-8, 1e8]),
+    64 samples: one grf_sample call per step in FP64 and with FP32 edge sweeps; the mixed
+    sample's error against the FP64 one (8 samples, lumped-mass norm) is reported.
+    value: the mixed form."""
+    import numpy as np
+    import torch
+
+    from oracle import mesh as omesh
+    from paper_2605_02670_amd import grf
+    from workloads import config_c4
+
+    cfg = config_c4()
+    g = cfg["graph"]
+    S = cfg["n_samples"]
+    steps = max(1, min(args.steps, 3))
+    outs, forms = {}, {}
+    for name, prec in (("fp64", "fp64"), ("mixed", "mixed")):
+        # a handle per form: each plans its shift blocks with the whole memory (a handle keeps its workspace)
+        G = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+        out = torch.empty((S, G.n_dof), dtype=torch.float64, device="cuda")
+        kw = dict(tol=cfg["tol"], precision=prec, k_minus=cfg["k_minus"], k_plus=cfg["k_plus"],
+                  shift_block=args.shift_block)
+        G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=out, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"], out=out, timing=True,
+                          **kw)[1] for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = stats[0]
+        forms[name] = {"value": G.n_dof * st["n_shifts"] * S / dt, "ms_per_step": dt * 1e3,
+                       "shift_block": st["shift_block"],
+                       "kernel_ms_per_step": {k: sum(s_["kernel_ms"][k] for s_ in stats) / steps
+                                              for k in st["kernel_ms"] if st["kernel_ms"][k] > 0},
+                       "pcg": {"max_iterations": st["max_iterations"],
+                               "mean_iterations": st["total_iterations"] / max(1, st["n_systems"])}}
+        outs[name] = out[:8].clone()
+        n_dof = G.n_dof
+        del out
+        G.close()
+        torch.cuda.empty_cache()
+        print(f"# {name}: {dt * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
+    ML = omesh.lumped_mass(omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"]))
+    d = (outs["mixed"] - outs["fp64"]).cpu().numpy()
+    r = outs["fp64"].cpu().numpy()
+    forms["mixed"]["rel_err_vs_fp64_8_samples"] = float(np.max(np.sqrt((d * d * ML).sum(1) / (r * r * ML).sum(1))))
+    forms["mixed"]["speedup_vs_fp64"] = forms["fp64"]["ms_per_step"] / forms["mixed"]["ms_per_step"]
+    mf = forms["mixed"]
+    line = {
+        "metric": METRIC, "value": mf["value"], "unit": "DOF-shift-solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": mf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"lattice256x256 U[0.5,1.5] h=1/512 kappa=20 beta=0.55 k=0.2 |l|<=46 S={S} "
+                               f"mixed-fp32sweeps-jacobi", "n_dof": n_dof, "shifts": stats[0]["n_shifts"],
+                   "samples": S, "parallelism": "1 GPU"},
+        "roofline": None, "cpu_baseline": None, "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_batched(args) -> int:
     """64 uneven graphs (preferential-attachment trees and lattices, 100..20000
     edges, h = 1/128), one kappa per graph, all 176 shifts x 32 samples in one
@@ -384,9 +448,10 @@ def main() -> int:
                          "picks it, or the learned operator forced in every class")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed / batched / learned forms")
-    ap.add_argument("--workload", choices=["lattice64", "batched64", "rgg100k"], default="lattice64",
+    ap.add_argument("--workload", choices=["lattice64", "batched64", "rgg100k", "lattice256"], default="lattice64",
                     help="lattice64: one 64x64 lattice (default); batched64: 64 uneven graphs in one batched call; "
-                         "rgg100k: the learned preconditioner's held-out random geometric graph")
+                         "rgg100k: the learned preconditioner's held-out random geometric graph; lattice256: the "
+                         "256x256 lattice in FP64 and mixed precision")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -407,6 +472,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "rgg100k":
         return bench_rgg(args)
+    if args.workload == "lattice256":
+        return bench_lattice256(args)
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

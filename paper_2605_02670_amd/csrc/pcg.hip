@@ -984,16 +984,7 @@ __global__ void __launch_bounds__(256) k_rhs_unrange(MeshView mv, double *__rest
 }
 
 size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks) {
-    return (size_t)blocks * 5 * kMrhsMaxSB * (size_t)mv.maxVg * sizeof(double);
-}
-
-// samples per block of the multi-system kernel: the largest of 16, 8, 4 whose
-// blocks fill every compute unit once (wider rows gather better; more blocks keep
-// more compute units busy)
-static int mrhs_sb(int64_t ngl, int64_t LB, int64_t S) {
-    for (int sb = kMrhsMaxSB; sb > 4; sb /= 2)
-        if (S >= sb && ngl * LB * ((S + sb - 1) / sb) >= 256) return sb;
-    return 4;
+    return (size_t)blocks * 5 * kMrhsSB * (size_t)mv.maxVg * sizeof(double);
 }
 
 // diag, dh, coef [4], ovf of each shift, for S^ (and P^, Q^ with the learned preconditioner)
@@ -1142,30 +1133,20 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
 
 static void launch_mrhs(const MeshView &mv, const SchurArgs &a, const EllOp *ops, bool lrn, int32_t ngl, int c_end,
                         hipStream_t st) {
-    const int sb = mrhs_sb(ngl, a.LB, a.S);
-    const int64_t units = (int64_t)ngl * a.LB * ((a.S + sb - 1) / sb);
-    const int64_t blocks = std::min<int64_t>(units, (int64_t)a.pcg_blocks * (kMrhsMaxSB / sb));
+    // four samples per block: on the 98k-vertex random geometric graph, 8 and 16 took
+    // 1.6x and 2.5x longer (fewer workgroups), and 8 was slower even at equal workgroup
+    // counts (a block runs until its slowest system has converged)
+    const int64_t units = (int64_t)ngl * a.LB * ((a.S + kMrhsSB - 1) / kMrhsSB);
+    const int64_t blocks = std::min<int64_t>(units, (int64_t)a.pcg_blocks);
     GRF_REQUIRE(blocks >= 1 && blocks < ((int64_t)1 << 31), "internal: no scratch for the multi-system PCG");
-    GRF_REQUIRE((int64_t)mv.maxVg * kMrhsMaxSB < ((int64_t)1 << 31), "a graph too large for the vertex PCG");
+    GRF_REQUIRE((int64_t)mv.maxVg * kMrhsSB < ((int64_t)1 << 31), "a graph too large for the vertex PCG");
     const int32_t *glist = mv.gord + mv.cls_off[c_end];
-    auto launch = [&](auto sbc, auto lrnc) {
-        hipLaunchKernelGGL((k_pcg_mrhs<decltype(sbc)::value, decltype(lrnc)::value>), dim3((unsigned)blocks),
-                           dim3(1024), 0, st, mv, ops[0], ops[1], ops[2], glist, ngl, a.gT, a.xT, a.scr, a.its,
-                           a.res, a.LB, a.S, a.tol, a.maxit);
-    };
-    using T4 = std::integral_constant<int, 4>;
-    using T8 = std::integral_constant<int, 8>;
-    using T16 = std::integral_constant<int, 16>;
-    static_assert(kMrhsMaxSB == 16, "the launch covers SB = 4, 8, 16");
-    if (lrn) {
-        if (sb == 16) launch(T16{}, std::true_type{});
-        else if (sb == 8) launch(T8{}, std::true_type{});
-        else launch(T4{}, std::true_type{});
-    } else {
-        if (sb == 16) launch(T16{}, std::false_type{});
-        else if (sb == 8) launch(T8{}, std::false_type{});
-        else launch(T4{}, std::false_type{});
-    }
+    if (lrn)
+        hipLaunchKernelGGL((k_pcg_mrhs<kMrhsSB, true>), dim3((unsigned)blocks), dim3(1024), 0, st, mv, ops[0], ops[1],
+                           ops[2], glist, ngl, a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
+    else
+        hipLaunchKernelGGL((k_pcg_mrhs<kMrhsSB, false>), dim3((unsigned)blocks), dim3(1024), 0, st, mv, ops[0], ops[1],
+                           ops[2], glist, ngl, a.gT, a.xT, a.scr, a.its, a.res, a.LB, a.S, a.tol, a.maxit);
     GRF_LAUNCH_CHECK();
 }
 

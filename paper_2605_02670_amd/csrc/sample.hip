@@ -50,6 +50,19 @@ static int32_t auto_bl(int32_t L) {
     return 8;
 }
 
+// bytes this graph's per-pass buffers already hold: a new plan reuses them (they grow
+// by release-then-allocate), so they count as free; otherwise a second call would see
+// the first call's buffers as used and plan smaller shift blocks into them
+static size_t held_pass_bytes(const grf_graph &g) {
+    if (!g.work) return 0;
+    const grf_graph::Work &w = *g.work;
+    const DevBuf *bufs[] = {&w.rho, &w.fwdt, &w.bwdt, &w.btab, &w.ztab, &w.babs, &w.rhom, &w.sd,   &w.so,
+                            &w.ends, &w.gT, &w.xT,   &w.ug,   &w.its,  &w.res,  &w.gexp, &w.pcg_ops};
+    size_t t = 0;
+    for (const DevBuf *b : bufs) t += b->bytes;
+    return t;
+}
+
 static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &o) {
     Plan p;
     p.blocked = (o.sweep_block == 0);
@@ -57,13 +70,15 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     const int64_t nb = (S + 63) / 64, Sp = 64 * nb;
     // bytes per shift of the per-pass buffers
     // streamed: rho + two double2 step rows per interior DOF; blocked: per-block operand tables
+    // (table elements are FP32 with mixed precision)
     const double rows = p.blocked ? 0.0 : 5.0;
     const double btab = p.blocked ? (1296.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
-    const double per_shift = 8.0 * (rows * g.NI + btab + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V +
-                                    (double)g.V * Sp) + 12.0 * S * (double)(g.gv0.size() - 1);
+    const double tbytes = o.precision == GRF_PREC_MIXED ? 4.0 : 8.0;
+    const double per_shift = 8.0 * (rows * g.NI + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V + (double)g.V * Sp) +
+                             tbytes * btab + 12.0 * S * (double)(g.gv0.size() - 1);
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)64 << 30;
-    double budget = 0.5 * (double)freeb;
+    double budget = 0.5 * (double)(freeb + held_pass_bytes(g));
     int64_t lb = o.shift_block > 0 ? o.shift_block : (int64_t)std::floor(budget / per_shift);
     if (p.blocked) lb = std::min<int64_t>(lb, 128);
     lb = std::min<int64_t>(lb, L);
@@ -71,11 +86,11 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     lb = std::max<int64_t>(1, std::min<int64_t>(lb, L));
     p.LB = (int32_t)lb;
     // multi-system PCG (graphs no on-chip variant takes): resident blocks of
-    // kMrhsMaxSB samples, 5 vectors each, up to one per block of the pass and 16 GiB
+    // kMrhsSB samples, 5 vectors each, up to one per block of the pass and 16 GiB
     const int c0 = o.precond == GRF_PRECOND_NN ? kChipOpClasses : kPcgClasses;
     const int64_t nglob = g.cls_off[kPcgClasses + 1] - g.cls_off[c0];
-    const int64_t units = nglob * lb * ((S + kMrhsMaxSB - 1) / kMrhsMaxSB);
-    const double ubytes = 5.0 * kMrhsMaxSB * sizeof(double) * std::max<int32_t>(g.maxVg, 1);
+    const int64_t units = nglob * lb * ((S + kMrhsSB - 1) / kMrhsSB);
+    const double ubytes = 5.0 * kMrhsSB * sizeof(double) * std::max<int32_t>(g.maxVg, 1);
     const int64_t cap = (int64_t)std::max(1.0, std::floor(16.0 * (double)(1ull << 30) / ubytes));
     p.pcg_blocks = (int32_t)std::min<int64_t>(std::min<int64_t>(units, cap), 4096);
     return p;
@@ -136,8 +151,9 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
         w.bwdt.reserve(16 * nir);
     } else {
         ensure_block_offsets(g, w, st, ps.nblocks);
-        w.btab.reserve(8 * (size_t)std::max<int64_t>(ps.nblocks, 1) * block_tab_doubles(LBp / 16));
-        w.ztab.reserve(8 * (size_t)std::max<int64_t>(ps.nblocks, 1) * 512 * (LBp / 16));
+        const size_t tb = o.precision == GRF_PREC_MIXED ? sizeof(float) : sizeof(double);  // table element
+        w.btab.reserve(tb * (size_t)std::max<int64_t>(ps.nblocks, 1) * block_tab_doubles(LBp / 16));
+        w.ztab.reserve(tb * (size_t)std::max<int64_t>(ps.nblocks, 1) * 512 * (LBp / 16));
     }
     w.babs.reserve(8 * (size_t)g.E * LBp + 8);
     w.rhom.reserve(8 * (size_t)g.E * LBp + 8);

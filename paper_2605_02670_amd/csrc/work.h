@@ -151,7 +151,7 @@ struct SchurArgs {
 // CM_GLOBAL (reported only): the class runs the multi-system kernel instead.
 enum ChipMode : int8_t { CM_OP = 0, CM_GUESS = 1, CM_JACOBI = 2, CM_GLOBAL = 3 };
 constexpr int kChipOpClasses = 5;  // size classes whose LDS holds r^ and p (CM_OP)
-constexpr int kMrhsMaxSB = 16;     // most samples per block of the multi-system PCG kernel
+constexpr int kMrhsSB = 4;         // samples per block of the multi-system PCG kernel
 constexpr int kClassTimerId = 100;
 void default_chip_modes(int32_t precond, int8_t *mode);  // [kPcgClasses]
 bool chip_mode_valid(int c, int mode);
@@ -159,7 +159,7 @@ void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st);
 void prepare_pcg(const MeshView &mv);  // one-time kernel attributes, before any graph capture
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st);
-size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);  // blocks of kMrhsMaxSB samples
+size_t pcg_scratch_bytes(const MeshView &mv, int32_t blocks);  // resident blocks of kMrhsSB samples
 size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, int32_t precond);
 
 }  // namespace grf
