@@ -76,11 +76,11 @@ HIP_KERNEL = {
 # FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0 KiB: the factors a 1 GiB plain copy
 # reads on these counters), valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = "paper_2605_02670_amd/csrc/blocked.hip"
-TRAFFIC_SHA256 = "b15bf4daa88be39378d78990fdb99715f354e87543e20dc5d77f2799ae370518"
+TRAFFIC_SHA256 = "b5424157395d2f2b3b597d6e6e3f5f1c07ed98724fe20071b9f0b5bf62bcaf72"
 TRAFFIC = {  # kernel id: (fetch KiB, write KiB) per launch
-    "ends_fwd": (4579871.125, 5996584.0),
-    "ends_bwd": (6625983.75, 5980456.0),
-    "acc_fwd": (5998387.8125, 4125736.0),
+    "ends_fwd": (4574936.625, 5996584.0),
+    "ends_bwd": (6621697.6875, 5980456.0),
+    "acc_fwd": (5980624.25, 4125736.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 

@@ -194,7 +194,9 @@ __device__ __forceinline__ void put16(const double (&v)[16], OT *__restrict__ ds
     }
 }
 
-// One workgroup per 16-position edge block, thread = shift l (base = 16 beta,
+// 128 / SLOT 16-position edge blocks per workgroup, SLOT >= LBp threads per block,
+// thread = shift l of its block (several blocks per workgroup when the shift block
+// is short, so that the threads are not mostly idle); per block (base = 16 beta,
 // i* = last position of the block, all products from the closed form above):
 //   Lam[i][j] = w^{i-j} E(base+j+1) / E(base+i+1)       (j <= i)
 //   lam[i]    = w^{i+1} E(base) / E(base+i+1)
@@ -209,18 +211,24 @@ __device__ __forceinline__ void put16(const double (&v)[16], OT *__restrict__ ds
 // off-diagonal Lam of a shift with theta > 40 (relative size below e^{-40}, far
 // under the rounding of its own diagonal term) is replaced by an equally
 // negligible value.
-template <typename OT>
+template <typename OT, bool PACK>
 __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int32_t *__restrict__ boff,
                                                           const double *__restrict__ shift, int32_t LB, int32_t LBp,
-                                                          int32_t NT, OT *__restrict__ tab, OT *__restrict__ ztab) {
+                                                          int32_t NT, int32_t SLOT, int64_t nblocks,
+                                                          OT *__restrict__ tab, OT *__restrict__ ztab) {
     constexpr bool F32L = sizeof(OT) == 4;  // FP32 operand tables for the mixed-precision sweeps
-    // Ghat split factors, rows of ld = LBp + 4 doubles: Af rows 0..16 (dg / (w^i E(base+i+1))),
-    // Bm rows 0..15 (E(base+j+1)), then w / w_split
+    // per block slot, Ghat split factors in rows of ld = LBp + 4 doubles: Af rows 0..16
+    // (dg / (w^i E(base+i+1))), Bm rows 0..15 (E(base+j+1)), then w / w_split
     extern __shared__ double sfac[];
+    __shared__ int sistar[kTabThreads / 16];  // i* of each block slot, for the Ghat products
     const int ld = LBp + 4;
-    double *sAf = sfac, *sBm = sfac + 17 * ld, *srw = sfac + 33 * ld;
+    const int NBW = PACK ? kTabThreads / SLOT : 1;  // blocks per workgroup (SLOT = 128 unless PACK)
     const int tid = threadIdx.x, wv = tid >> 6;
-    const int64_t blk = blockIdx.x;
+    const int slot = PACK ? tid / SLOT : 0;
+    double *sAf = sfac + (int64_t)slot * 34 * ld, *sBm = sAf + 17 * ld, *srw = sAf + 33 * ld;
+    const int64_t blk0 = (int64_t)blockIdx.x * NBW;
+    const bool bvalid = blk0 + slot < nblocks;  // the last workgroup may hold fewer blocks
+    const int64_t blk = bvalid ? blk0 + slot : nblocks - 1;
     const int e = find_edge(boff, (int)mv.E, blk);
     const int beta = (int)(blk - boff[e]);
     const int m = mv.m[e];
@@ -229,8 +237,10 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     const TabLayout TL{NT};
     OT *T = tab + blk * TL.size();
     OT *Z = ztab + blk * (int64_t)(512 * NT);
-    const int l = tid;
-    const bool live = l < LB;
+    const int l = tid - slot * SLOT;
+    if (PACK && l == 0) sistar[slot] = istar;  // read after the barrier below
+    const bool live = bvalid && l < LB;
+    const bool put = bvalid && l < LBp;  // a (padded) shift of a real block: its values are stored
     double th = 0.0, w = 0.0, E1 = 0.0, bab = 1.0, sh2 = 1.0;
     if (live) {
         const EdgeShift s = edge_shift(shift[2 * l], shift[2 * l + 1], mv.kap2[e], mv.he[e]);
@@ -267,14 +277,14 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
 #pragma unroll
         for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? pw * lam0 * Q[i] : 0.0;
     }
-    if (l < LBp) put16<false, F32L>(v, T + TL.HF(), l);
+    if (put) put16<false, F32L>(v, T + TL.HF(), l);
     // H_bwd[i] = of_i lam_i = w^{i+2} E(base) E(m-base-i-1) / (...)
     {
         double pw = w * w;  // w^{i+2}
 #pragma unroll
         for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? pw * lam0 * Q[i + 1] : 0.0;
     }
-    if (l < LBp) put16<false, F32L>(v, T + TL.HB(), l);
+    if (put) put16<false, F32L>(v, T + TL.HB(), l);
     // Z_tail[i] = w^{base+1+i} E(m-base-i) K
     {
         const double wb = live ? exp(-(double)(base + 1) * th) * K : 0.0;
@@ -282,7 +292,7 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
 #pragma unroll
         for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? wb * pw * Q[i] : 0.0;
     }
-    if (l < LBp) put16<false, F32L>(v, Z, l);
+    if (put) put16<false, F32L>(v, Z, l);
     // C[j] = w^{i*-j} E(base+j+1) / E(base+i*+1), d = w^{i*+1} E(base) / E(base+i*+1), and
     // Z_head[i] = w^{m-base-i} E(base+i+1) K: descending chains from i*
     double dval = 0.0;
@@ -295,16 +305,16 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
             if (j <= istar) pw *= w;
         }
         dval = live ? pw * Ef[0] * inv : 0.0;  // pw = w^{i*+1}
-        if (l < LBp) put16<true, F32L>(v, T + TL.CT(), l);
+        if (put) put16<true, F32L>(v, T + TL.CT(), l);
         double zh = live ? exp(-(double)(m - base - istar) * th) * K : 0.0;
 #pragma unroll
         for (int j = 15; j >= 0; --j) {
             v[j] = (live && j <= istar) ? zh * Ef[j + 1] : 0.0;
             if (j <= istar) zh *= w;
         }
-        if (l < LBp) put16<false, F32L>(v, Z + 256 * NT, l);
+        if (put) put16<false, F32L>(v, Z + 256 * NT, l);
     }
-    if (l < LBp) T[TL.DT() + l] = (OT)dval;
+    if (put) T[TL.DT() + l] = (OT)dval;
     // Ghat operands (split factors); rows past i*+1 (Af) / i* (Bm) are zero
     {
         const double thc = fmin(th, kThetaSplit);
@@ -324,23 +334,30 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
         if (l < ld) srw[l] = live ? exp(thc - th) : 0.0;  // w / w_c
     }
     __syncthreads();
-    // Ghat^T = B^T A^T (D layout of the transpose = the A-operand table layout):
-    // wave 0 the forward operand (A = Af rows i), wave 1 the backward one (A = Af rows i+1 times w/w_c)
-    {
+    // Ghat^T = B^T A^T (D layout of the transpose = the A-operand table layout) for every
+    // block of the workgroup: wave 0 the forward operands (A = Af rows i), wave 1 the
+    // backward ones (A = Af rows i+1 times w/w_c); waves 2, 3 (if any) have none
+    if (wv < 2) {
         const int lane = tid & 63;
         const int n = lane & 15, q = lane >> 4;
-        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-        for (int c = 0; c < LBp / 4; ++c) {
-            const int ll = 4 * c + q;
-            const double a = sBm[n * ld + ll];
-            const double b = (wv == 0) ? sAf[n * ld + ll] : sAf[(n + 1) * ld + ll] * srw[ll];
-            acc = mfma(a, b, acc);
-        }
-        OT *G = T + (wv == 0 ? TL.GF() : TL.GB());
+        for (int sb = 0; sb < NBW; ++sb) {
+            const int64_t bk = blk0 + sb;
+            if (bk >= nblocks) break;  // uniform over the wavefront
+            const double *bAf = sfac + (int64_t)sb * 34 * ld, *bBm = bAf + 17 * ld, *brw = bAf + 33 * ld;
+            const int bistar = PACK ? sistar[sb] : istar;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int c = 0; c < LBp / 4; ++c) {
+                const int ll = 4 * c + q;
+                const double a = bBm[n * ld + ll];
+                const double b = (wv == 0) ? bAf[n * ld + ll] : bAf[(n + 1) * ld + ll] * brw[ll];
+                acc = mfma(a, b, acc);
+            }
+            OT *G = tab + bk * TL.size() + (wv == 0 ? TL.GF() : TL.GB());
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int jj = 4 * r + q;  // D row of the transpose = column j of Ghat; lane row n = i
-            G[r * 64 + lane] = (OT)((jj <= n && n <= istar) ? acc[r] : 0.0);
+            for (int r = 0; r < 4; ++r) {
+                const int jj = 4 * r + q;  // D row of the transpose = column j of Ghat; lane row n = i
+                G[r * 64 + lane] = (OT)((jj <= n && n <= bistar) ? acc[r] : 0.0);
+            }
         }
     }
 }
@@ -843,18 +860,33 @@ void launch_edge_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
     GRF_LAUNCH_CHECK();
 }
 
-static size_t blocktab_lds(int32_t LBp) { return sizeof(double) * 34 * (size_t)(LBp + 4); }
+// threads per edge block in the table kernel: the smallest of 16, 32, 64, 128 that holds LBp
+static int32_t blocktab_slot(int32_t LBp) {
+    int32_t s = 16;
+    while (s < LBp) s *= 2;
+    return s;
+}
+static size_t blocktab_lds(int32_t LBp) {
+    return sizeof(double) * 34 * (size_t)(LBp + 4) * (kTabThreads / blocktab_slot(LBp));
+}
 
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return;
     GRF_REQUIRE(a.LBp == 16 * a.NT && a.NT >= 1 && a.NT <= 8, "internal: blocked sweeps need 16..128 padded shifts");
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
-    if (a.mixed)
-        hipLaunchKernelGGL(k_blocktab<float>, dim3((unsigned)a.nblocks), dim3(kTabThreads), blocktab_lds(a.LBp), st, mv,
-                           a.boff, a.shift, a.LB, a.LBp, a.NT, a.tab32, a.ztab32);
-    else
-        hipLaunchKernelGGL(k_blocktab<double>, dim3((unsigned)a.nblocks), dim3(kTabThreads), blocktab_lds(a.LBp), st, mv,
-                           a.boff, a.shift, a.LB, a.LBp, a.NT, a.tab, a.ztab);
+    const int32_t slot = blocktab_slot(a.LBp);
+    const int64_t nbw = kTabThreads / slot;
+    const dim3 grid((unsigned)((a.nblocks + nbw - 1) / nbw));
+    const bool pack = nbw > 1;  // one block per workgroup compiles to the plain single-block kernel
+    if (a.mixed) {
+        auto *kern = pack ? k_blocktab<float, true> : k_blocktab<float, false>;
+        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.shift, a.LB, a.LBp,
+                           a.NT, slot, a.nblocks, a.tab32, a.ztab32);
+    } else {
+        auto *kern = pack ? k_blocktab<double, true> : k_blocktab<double, false>;
+        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.shift, a.LB, a.LBp,
+                           a.NT, slot, a.nblocks, a.tab, a.ztab);
+    }
     GRF_LAUNCH_CHECK();
 }
 
