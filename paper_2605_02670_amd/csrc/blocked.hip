@@ -363,38 +363,39 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
 }
 
 // Staging of one block's operands in LDS, shared by the four wavefronts of a
-// workgroup (one edge, 64 samples): every thread loads its share of the next
-// block into registers while the current block is computed, then writes it to
-// the other LDS buffer.
-
-template <typename ET, int NE>
-constexpr int stage_per() { return (NE * (int)sizeof(ET) / 16 + 255) / 256; }
-
-template <typename ET, int NE>
-using StageRegs = typename V16<ET>::type[stage_per<ET, NE>()];
-
-// copy NE elements [src1, src1 + n1) ++ [src2, ...) (n1 and both sources 16-byte aligned) into registers
-template <typename ET, int NE>
-__device__ __forceinline__ void stage_load(StageRegs<ET, NE> &r, const ET *src1, int n1, const ET *src2) {
-    constexpr int EPV = 16 / (int)sizeof(ET), NV = NE / EPV;
+// workgroup (one edge, 64 samples), double-buffered: while the current block is
+// computed, the loads of the next block's operands write the other LDS buffer
+// themselves (global_load_lds_dwordx4: lane j of a wavefront's load lands 16 j
+// bytes past the wavefront-uniform LDS address), so no registers carry them.
+// The table is copied as contiguous 16-byte vectors, vector i by thread i mod 256;
+// the caller waits with stage_wait before the barrier that publishes the buffer.
+// bytes [src1, src1 + n1b) ++ [src2, ...), nbytes in all (multiples of 16, sources 16-byte aligned)
+__device__ __forceinline__ void stage_direct_bytes(const char *src1, int n1b, const char *src2, char *dst, int nbytes) {
+    const int nv = nbytes / 16;
+    const int w = wave_id(), lane = (int)threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < stage_per<ET, NE>(); ++k) {
-        const int i = (int)threadIdx.x + 256 * k;
-        const int d = EPV * min(i, NV - 1);
-        const ET *p = d < n1 ? src1 + d : src2 + (d - n1);
-        r[k] = *reinterpret_cast<const typename V16<ET>::type *>(p);
+    for (int k = 0; k < (nv + 255) / 256; ++k) {
+        const int v0 = 256 * k + 64 * w;  // first vector of this wavefront's load
+        const int i = v0 + lane;
+        if (i < nv) {  // lanes past the table write nothing
+            const int d = 16 * i;
+            const char *p = d < n1b ? src1 + d : src2 + (d - n1b);
+            __builtin_amdgcn_global_load_lds(p, (__attribute__((address_space(3))) void *)(dst + 16 * v0), 16, 0, 0);
+        }
     }
 }
-
-template <typename ET, int NE>
-__device__ __forceinline__ void stage_store(const StageRegs<ET, NE> &r, ET *dst) {
-    constexpr int EPV = 16 / (int)sizeof(ET), NV = NE / EPV;
-#pragma unroll
-    for (int k = 0; k < stage_per<ET, NE>(); ++k) {
-        const int i = (int)threadIdx.x + 256 * k;
-        if (i < NV) reinterpret_cast<typename V16<ET>::type *>(dst)[i] = r[k];
-    }
+// ne elements: [src1, src1 + n1) ++ [src2, ...) into dst
+__device__ __forceinline__ void stage_direct(const double *src1, int n1, const double *src2, double *dst, int ne) {
+    stage_direct_bytes((const char *)src1, 8 * n1, (const char *)src2, (char *)dst, 8 * ne);
 }
+__device__ __forceinline__ void stage_direct(const float *src1, int n1, const float *src2, float *dst, int ne) {
+    stage_direct_bytes((const char *)src1, 4 * n1, (const char *)src2, (char *)dst, 4 * ne);
+}
+
+// the direct-staging loads of this wavefront have written LDS: s_waitcnt vmcnt(0)
+// (expcnt and lgkmcnt at their maxima), as a builtin so that the compiler's own
+// wait placement counts it
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Pass A: workgroup = (edge, 64 samples), wavefront = 16 samples, all
 // (padded) shifts.  LDS per buffer (doubles), forward: H 0, C 256NT, G 512NT,
@@ -446,15 +447,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     // position read at step p, and where its output goes (backward: T^{-1}'s upper part lands one before)
     auto inpos = [&](int p) -> int64_t { return FWD ? (int64_t)p : (int64_t)(m - 1 - p); };
     auto outpos = [&](int p) -> int { return FWD ? p : m - 2 - p; };
-    StageRegs<double, TS> stg;
-    stage_load<double, TS>(stg, src1(0), N1, src2(0));
+    stage_direct(src1(0), N1, src2(0), sbuf, TS);
     double R[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int p = 4 * c + kq;
         R[c] = (live && p < m) ? xb[inpos(p) * 64] : 0.0;
     }
-    stage_store<double, TS>(stg, sbuf);
+    stage_wait();
     __syncthreads();
     d4 Y[NT];
 #pragma unroll
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         const bool more = beta + 1 < nblk;
         double Rn[4] = {0.0, 0.0, 0.0, 0.0};
         if (more) {
-            stage_load<double, TS>(stg, src1(beta + 1), N1, src2(beta + 1));
+            stage_direct(src1(beta + 1), N1, src2(beta + 1), sbuf + ((beta + 1) & 1) * TS, TS);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 16 * (beta + 1) + 4 * c + kq;
@@ -491,10 +491,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
             for (int c = 0; c < 4; ++c) F[c] = mfma(G[c * 64 + L], R[c], d4{0.0, 0.0, 0.0, 0.0});
             if (beta > 0) {
+                double ha[NT][4];
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) F[r] = mfma(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
+                    for (int r = 0; r < 4; ++r) ha[t][r] = H[(t * 4 + r) * 64 + L];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) F[r] = mfma(ha[t][r], Y[t][r], F[r]);
+                // order: the operand reads of the first LA tiles, then per tile its four
+                // products followed by the reads of the tile LA ahead, so that the LDS
+                // latency runs under the matrix-core work
+                constexpr int LA = NT < 2 ? NT : 2;
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 * LA, 0);
+#pragma unroll
+                for (int t = 0; t < NT - LA; ++t) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 4 * LA, 0);
             }
             // carry: Y <- d .* Y + C R
 #pragma unroll
@@ -514,7 +530,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                 if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + f;
             }
         }
-        if (more) stage_store<double, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
+        if (more) stage_wait();
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) R[c] = Rn[c];
@@ -561,8 +577,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     const int vt = eu_[e], vh = ev_[e];
     const double *z0 = ztab + (int64_t)boff[e] * TS;
-    StageRegs<double, TS> stg;
-    stage_load<double, TS>(stg, z0, TS, z0);
+    stage_direct(z0, TS, z0, sbuf, TS);
     double ct[NT][4], ch[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -574,14 +589,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             ct[t][r] = live ? bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n] : 0.0;
             ch[t][r] = live ? bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n] : 0.0;
         }
-    stage_store<double, TS>(stg, sbuf);
+    stage_wait();
     __syncthreads();
     const int nblk = (m + 15) >> 4;
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
         const double *Z = sbuf + (beta & 1) * TS;
         const bool more = beta + 1 < nblk;
-        if (more) stage_load<double, TS>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        if (more) stage_direct(z0 + (int64_t)(beta + 1) * TS, TS, z0, sbuf + ((beta + 1) & 1) * TS, TS);
         if (live) {
         double uo[4];
 #pragma unroll
@@ -592,20 +607,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             d4 F[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) F[c] = d4{0.0, 0.0, 0.0, 0.0};
+            double zt[NT][4], zh[NT][4];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    F[r & 1] = mfma(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
-                    F[2 + (r & 1)] = mfma(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+                    zt[t][r] = Z[(t * 4 + r) * 64 + L];
+                    zh[t][r] = Z[256 * NT + (t * 4 + r) * 64 + L];
                 }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    F[r & 1] = mfma(zt[t][r], ct[t][r], F[r & 1]);
+                    F[2 + (r & 1)] = mfma(zh[t][r], ch[t][r], F[2 + (r & 1)]);
+                }
+            // order: the operand reads of the first LA tiles, then per tile its eight
+            // products followed by the reads of the tile LA ahead (LDS latency under
+            // the matrix-core work)
+            constexpr int LA = NT < 2 ? NT : 2;
+            __builtin_amdgcn_sched_group_barrier(0x100, 4 * LA, 0);
+#pragma unroll
+            for (int t = 0; t < NT - LA; ++t) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 8 * LA, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int pp = 16 * beta + 4 * r + kq;
                 if (pp < m) ub[(int64_t)pp * 64] = uo[r] + ((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
             }
         }
-        if (more) stage_store<double, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
+        if (more) stage_wait();
         __syncthreads();
     }
 }
@@ -656,15 +690,14 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
     auto src2 = [&](int beta) { return tab0 + beta * TL.size() + (FWD ? TL.GF() : TL.DT()); };
     auto inpos = [&](int p) -> int64_t { return FWD ? (int64_t)p : (int64_t)(m - 1 - p); };
     auto outpos = [&](int p) -> int { return FWD ? p : m - 2 - p; };
-    StageRegs<float, TS> stg;
-    stage_load<float, TS>(stg, src1(0), N1, src2(0));
+    stage_direct(src1(0), N1, src2(0), sbuf, TS);
     float R[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int p = 4 * c + kq;
         R[c] = (live && p < m) ? (float)xb[inpos(p) * 64] : 0.0f;
     }
-    stage_store<float, TS>(stg, sbuf);
+    stage_wait();
     __syncthreads();
     f4 Y[NT];
 #pragma unroll
@@ -676,7 +709,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
         const bool more = beta + 1 < nblk;
         float Rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (more) {
-            stage_load<float, TS>(stg, src1(beta + 1), N1, src2(beta + 1));
+            stage_direct(src1(beta + 1), N1, src2(beta + 1), sbuf + ((beta + 1) & 1) * TS, TS);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 16 * (beta + 1) + 4 * c + kq;
@@ -701,10 +734,24 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
 #pragma unroll
             for (int c = 0; c < 4; ++c) F[c] = mfma32(G[c * 64 + L], R[c], f4{0.0f, 0.0f, 0.0f, 0.0f});
             if (beta > 0) {
+                float ha[NT][4];
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) F[r] = mfma32(H[(t * 4 + r) * 64 + L], Y[t][r], F[r]);
+                    for (int r = 0; r < 4; ++r) ha[t][r] = H[(t * 4 + r) * 64 + L];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) F[r] = mfma32(ha[t][r], Y[t][r], F[r]);
+                // reads LA tiles ahead of the products, as in the FP64 kernel
+                constexpr int LA = NT < 2 ? NT : 2;
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 * LA, 0);
+#pragma unroll
+                for (int t = 0; t < NT - LA; ++t) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 4 * LA, 0);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
@@ -722,7 +769,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
                 if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + (double)f;
             }
         }
-        if (more) stage_store<float, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
+        if (more) stage_wait();
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) R[c] = Rn[c];
@@ -761,8 +808,7 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
     double *ub = U + ((int64_t)b * N + off) * 64 + 16 * (g & 3) + n;
     const int vt = eu_[e], vh = ev_[e];
     const float *z0 = ztab + (int64_t)boff[e] * TS;
-    StageRegs<float, TS> stg;
-    stage_load<float, TS>(stg, z0, TS, z0);
+    stage_direct(z0, TS, z0, sbuf, TS);
     float ct[NT][4], ch[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -774,14 +820,14 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
             ct[t][r] = live ? (float)(bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n]) : 0.0f;
             ch[t][r] = live ? (float)(bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n]) : 0.0f;
         }
-    stage_store<float, TS>(stg, sbuf);
+    stage_wait();
     __syncthreads();
     const int nblk = (m + 15) >> 4;
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
         const float *Z = sbuf + (beta & 1) * TS;
         const bool more = beta + 1 < nblk;
-        if (more) stage_load<float, TS>(stg, z0 + (int64_t)(beta + 1) * TS, TS, z0);
+        if (more) stage_direct(z0 + (int64_t)(beta + 1) * TS, TS, z0, sbuf + ((beta + 1) & 1) * TS, TS);
         if (live) {
         double uo[4];
 #pragma unroll
@@ -792,20 +838,37 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
             f4 F[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) F[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            float zt[NT][4], zh[NT][4];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    F[r & 1] = mfma32(Z[(t * 4 + r) * 64 + L], ct[t][r], F[r & 1]);
-                    F[2 + (r & 1)] = mfma32(Z[256 * NT + (t * 4 + r) * 64 + L], ch[t][r], F[2 + (r & 1)]);
+                    zt[t][r] = Z[(t * 4 + r) * 64 + L];
+                    zh[t][r] = Z[256 * NT + (t * 4 + r) * 64 + L];
                 }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    F[r & 1] = mfma32(zt[t][r], ct[t][r], F[r & 1]);
+                    F[2 + (r & 1)] = mfma32(zh[t][r], ch[t][r], F[2 + (r & 1)]);
+                }
+            // reads LA tiles ahead of the products, as in the FP64 kernel
+            constexpr int LA = NT < 2 ? NT : 2;
+            __builtin_amdgcn_sched_group_barrier(0x100, 4 * LA, 0);
+#pragma unroll
+            for (int t = 0; t < NT - LA; ++t) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 8 * LA, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int pp = 16 * beta + 4 * kq + r;
                 if (pp < m) ub[(int64_t)pp * 64] = uo[r] + (double)((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
             }
         }
-        if (more) stage_store<float, TS>(stg, sbuf + ((beta + 1) & 1) * TS);
+        if (more) stage_wait();
         __syncthreads();
     }
 }
