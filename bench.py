@@ -76,11 +76,11 @@ HIP_KERNEL = {
 # FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0 KiB: the factors a 1 GiB plain copy
 # reads on these counters), valid only for the kernel source they were taken on.
 TRAFFIC_SOURCE = "paper_2605_02670_amd/csrc/blocked.hip"
-TRAFFIC_SHA256 = "b5424157395d2f2b3b597d6e6e3f5f1c07ed98724fe20071b9f0b5bf62bcaf72"
+TRAFFIC_SHA256 = "567b9b8afdc3c9e0fc035d721ca3a88746bc6740cf9ab833f2b62ac144c70747"
 TRAFFIC = {  # kernel id: (fetch KiB, write KiB) per launch
-    "ends_fwd": (4574936.625, 5996584.0),
-    "ends_bwd": (6621697.6875, 5980456.0),
-    "acc_fwd": (5980624.25, 4125736.0),
+    "ends_fwd": (4425197.5625, 5996584.0),
+    "ends_bwd": (6568436.125, 5980456.0),
+    "acc_fwd": (5662891.1875, 4125736.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -235,7 +235,10 @@ def train_network(seed: int = 0):
     t0 = time.perf_counter()
     losses = np.concatenate([net.train(graphs, kappas, 0.75, 0.0, n_samples=4, seed=seed + 11 + 7 * k, n_steps=n,
                                        shifts_per_step=16, lr=lr) for k, (n, lr) in enumerate(TRAIN_PHASES)])
-    return net, time.perf_counter() - t0, float(losses[:400].mean()), float(losses[-400:].mean())
+    t = time.perf_counter() - t0
+    for G in graphs:
+        G.close()
+    return net, t, float(losses[:400].mean()), float(losses[-400:].mean())
 
 
 def _batch_rel_err(Gs, cfg, outs, ref):
@@ -543,6 +546,7 @@ def main() -> int:
         check["rel_err_vs_fp64"] = float(np.max(np.sqrt((d * d * ML).sum(1) / (r * r * ML).sum(1))))
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, L, S)
+    n_dof, n_interior = G.n_dof, G.n_interior
     forms = None
     if not args.no_forms and args.precision == "fp64":
         forms = {"plain": {"value": value, "ms_per_step": dt * 1e3}}
@@ -577,6 +581,11 @@ def main() -> int:
                        "pcg": {"max_iterations": max(s_["max_iterations"] for s_ in stn),
                                "mean_iterations": stn[0]["total_iterations"] / max(1, stn[0]["n_systems"])}}
         del outm
+        # the lattice handle's workspace would otherwise shrink the batch's shift blocks
+        n_dof, n_interior = G.n_dof, G.n_interior
+        G.close()
+        del out
+        torch.cuda.empty_cache()
         # the 64-graph batch, every form at the metric's accuracy: PCG tolerance
         # METRIC_TOL, error against the FP64 batch at tol 1e-12 reported
         from workloads import config_c3
@@ -597,6 +606,7 @@ def main() -> int:
             r_["rel_err_vs_fp64_tol1e-12"] = _batch_rel_err(Gs, bcfg, bouts, ref)
             forms[name] = dict(r_, workload=BATCH_WORKLOAD + "; one batched call, " + what)
         net, t_train, l0, l1 = train_network()
+        torch.cuda.empty_cache()
         bl = run_batched(bcfg, Gs, bouts, bsteps, 1, tol=METRIC_TOL, learned=net, precision="mixed")
         bl["rel_err_vs_fp64_tol1e-12"] = _batch_rel_err(Gs, bcfg, bouts, ref)
         bl["training"] = {"seconds": t_train, "steps": TRAIN_STEPS, "phases": TRAIN_PHASES, "loss_first400": l0,
@@ -621,7 +631,7 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"lattice64x64 U[0.5,1.5] h=1/256 kappa=10 beta={cfg['beta']} k=0.3 "
                                f"S={S} {'plain-fp64' if args.precision == 'fp64' else 'mixed-fp32sweeps'}-jacobi",
-                   "n_dof": G.n_dof, "n_interior": G.n_interior, "shifts": L, "samples": S,
+                   "n_dof": n_dof, "n_interior": n_interior, "shifts": L, "samples": S,
                    "shift_block": stats[0]["shift_block"], "sweep_block": stats[0]["sweep_block"],
                    "parallelism": "1 GPU"},
         "roofline": roof,
