@@ -116,6 +116,29 @@ def test_sample_ragged_multipass(grf, shift_block, sweep_block):
     assert st["n_shifts"] == sum(oquad.limits(beta, k)) + 1
 
 
+@pytest.mark.parametrize("k,shift_block,precision", [
+    (0.3, 0, "fp64"),       # 116 shifts in one pass: 128 padded, one edge block per table workgroup
+    (0.3, 90, "fp64"),      # passes of 90 and 26: 96 padded (one block per workgroup), 32 padded (four)
+    (0.45, 25, "fp64"),     # passes of 25, 25, 3: four and eight blocks per table workgroup
+    (0.45, 25, "mixed"),    # the same with FP32 operand tables
+    (0.3, 0, "mixed"),
+])
+def test_sample_ragged_table_packing(grf, k, shift_block, precision):
+    """The table kernel packs 128 / SLOT edge blocks into a workgroup (SLOT = 16, 32, 64
+    or 128 threads, the smallest power of two that holds the padded shift block); this
+    graph has 35 edge blocks, so the last workgroup of a packed launch is partly empty.
+    FP64 against the oracle to 1e-10; mixed precision to 1e-6 (its error bound)."""
+    V, E, L = _ragged_graph()
+    m = omesh.build_mesh(V, E, L, 0.05, "round")
+    G = grf.Graph(V, E, L, 0.05, "round")
+    kappa, beta, S, seed = 4.0, 0.6, 70, 5
+    u, st = G.sample(kappa, beta, k, S, seed, shift_block=shift_block, precision=precision)
+    W = onoise.white_noise(omesh.lumped_mass(m), seed, S)
+    ref = osolve.sample(m, kappa, beta, k, W)
+    assert st["n_shifts"] == sum(oquad.limits(beta, k)) + 1 and st["n_unconverged"] == 0
+    assert _rel_ml(u.cpu().numpy(), ref, omesh.lumped_mass(m)) <= (TOL if precision == "fp64" else 1e-6)
+
+
 def test_sample_interval_single_edge(grf):
     g = interval(1.7)
     m = omesh.build_mesh(2, g.edges, g.lengths, 1 / 100, "ceil")
