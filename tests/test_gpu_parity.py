@@ -122,6 +122,9 @@ def test_sample_ragged_multipass(grf, shift_block, sweep_block):
     (0.45, 25, "fp64"),     # passes of 25, 25, 3: four and eight blocks per table workgroup
     (0.45, 25, "mixed"),    # the same with FP32 operand tables
     (0.3, 0, "mixed"),
+    (0.3, 70, "fp64"),      # 80 + 48 padded: shift tiles 5 and 3 in the sweeps
+    (0.3, 100, "fp64"),     # 112 + 16 padded: shift tiles 7 and 1
+    (0.3, 100, "mixed"),
 ])
 def test_sample_ragged_table_packing(grf, k, shift_block, precision):
     """The table kernel packs 128 / SLOT edge blocks into a workgroup (SLOT = 16, 32, 64
