@@ -159,7 +159,11 @@ int grf_graph_destroy(grf_graph *g);
 /*
  * Quadrature limits for (beta, quad_step) on this graph: quad_step == 0
  * selects the paper's step k = -1/(beta ln h); opts->k_minus/k_plus >= 0
- * override the paper's limits (paper: "Strong error" subsection).  Host only.
+ * override the paper's limits (paper: "Strong error" subsection).  g may be
+ * NULL when quad_step > 0 (h enters only the paper's step rule).  Host only.
+ * Errors (here and in every sampling call): GRF_EINVAL for beta outside
+ * (0, 1), more than 1e6 shifts, or limits so wide that some c_I or c_L is
+ * not finite and positive.
  */
 int grf_shift_count(const grf_graph *g, double beta, double quad_step, const grf_opts *opts,
                     int32_t *k_minus, int32_t *k_plus, double *step_used);

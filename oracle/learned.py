@@ -35,10 +35,13 @@ x_hat = D^{1/2} x*):
   L = (||P_hat g_hat - x_hat||^2 + ||Q_hat g_hat - x_hat||^2) / ||x_hat||^2,
 averaged over the right-hand sides of a batch.
 
-Parity pins (tests/test_oracle_learned.py): the autograd gradient against
-central finite differences, P_hat SPD for random parameters, the Jacobi limit,
-and the edge Schur complements against the dense Schur complement of the
-assembled system.
+Parity pins (tests/test_oracle_learned.py): the features against values worked
+out by hand on a graph with a multi-edge and a self-loop; the autograd gradient
+against central finite differences; P_hat SPD for random parameters; the Jacobi
+limit; the edge Schur complements against the dense Schur complement of the
+assembled system; the reference PCG against plain CG written out step by step
+(true-residual stop, zero right-hand side, non-convergence flag) and its
+fallback to Jacobi after maxit // 2 iterations.
 """
 
 from __future__ import annotations
@@ -243,26 +246,47 @@ def preconditioner(theta_eff, f, w, edges, V, D):
     return P, Q
 
 
-def pcg(S, g, P, x0, tol, maxit=10000):
-    """Reference PCG with preconditioner matrix P and initial guess x0 (same
-    stopping rule as the method: ||g - S x|| <= tol ||g|| on the true residual)."""
-    x = x0.copy()
-    r = g - S @ x
+def pcg(S, g, P, x0, tol, maxit=10000, fallback=None):
+    """Reference PCG on S x = g with preconditioner matrix P from x0.
+
+    Stopping rule (reading A8, paper "Phase 4"): the iteration ends at the
+    first iterate whose residual recomputed from x, g - S x, satisfies
+    ||g - S x||_2 <= tol ||g||_2; the recursively updated residual is never
+    used for the decision.  g = 0 returns x = 0 after 0 iterations.
+    Fallback (readings L4 and N2): when ``fallback`` (a matrix, the Jacobi
+    preconditioner D^{-1}) is given, once max(1, maxit // 2) iterations have
+    been taken with P the iteration restarts from the current iterate with
+    the fallback (r = g - S x, z = fallback r, p = z).
+    Returns (x, iterations), iterations = maxit + 1 if tol was not reached."""
     gg = float(g @ g)
     if gg == 0.0:
         return np.zeros_like(g), 0
-    z = P @ r
-    p = z.copy()
-    rz = float(r @ z)
-    for it in range(1, maxit + 1):
-        if float(r @ r) <= tol * tol * gg:
-            return x, it - 1
+    x = x0.copy()
+    M = P
+    switch_at = max(1, maxit // 2)
+
+    def start():
+        r = g - S @ x
+        z = M @ r
+        return r, z, z.copy(), float(r @ z)
+
+    r, z, p, rz = start()
+    it = 0
+    while True:
+        rt = g - S @ x
+        if float(rt @ rt) <= tol * tol * gg:
+            return x, it
+        if it == maxit:
+            return x, maxit + 1
+        if fallback is not None and M is P and it == switch_at:
+            M = fallback
+            r, z, p, rz = start()
+        it += 1
         q = S @ p
         a = rz / float(p @ q)
         x += a * p
         r -= a * q
-        z = P @ r
+        z = M @ r
         rz_new = float(r @ z)
         p = z + (rz_new / rz) * p
         rz = rz_new
-    return x, maxit + 1

@@ -317,12 +317,18 @@ Shifts make_shifts(double beta, double step, double h, const grf_opts &o) {
     GRF_REQUIRE(km < 1e6 && kp < 1e6, "quadrature step too small: %g shifts", km + kp + 1);
     sh.kminus = o.k_minus >= 0 ? o.k_minus : (int32_t)km;
     sh.kplus = o.k_plus >= 0 ? o.k_plus : (int32_t)kp;
+    GRF_REQUIRE((int64_t)sh.kminus + (int64_t)sh.kplus + 1 <= 1000000,
+                "k_minus + k_plus + 1 = %lld shifts: at most 1e6", (long long)sh.kminus + sh.kplus + 1);
     double cconst = pi / (2.0 * sh.k * std::sin(pi * beta));
     for (int32_t l = -sh.kminus; l <= sh.kplus; ++l) {
         double y = (double)l * sh.k;
         double ci = cconst * std::exp(-2.0 * beta * y);
+        double cl = ci * std::exp(2.0 * y);
+        GRF_REQUIRE(std::isfinite(ci) && ci > 0 && std::isfinite(cl) && cl > 0,
+                    "shift l = %d: c_I = %g, c_L = %g are not finite and positive (limits too wide for step %g)",
+                    l, ci, cl, sh.k);
         sh.cI.push_back(ci);
-        sh.cL.push_back(ci * std::exp(2.0 * y));
+        sh.cL.push_back(cl);
     }
     return sh;
 }
@@ -469,9 +475,9 @@ int grf_graph_destroy(grf_graph *g) {
 int grf_shift_count(const grf_graph *g, double beta, double quad_step, const grf_opts *opts, int32_t *k_minus,
                     int32_t *k_plus, double *step_used) {
     GRF_API_BEGIN
-    GRF_REQUIRE(g, "graph is NULL");
+    GRF_REQUIRE(g || quad_step > 0, "graph is NULL (it may be NULL only with quad_step > 0)");
     grf_opts o = resolve_opts(opts);
-    Shifts sh = make_shifts(beta, quad_step, g->h, o);
+    Shifts sh = make_shifts(beta, quad_step, g ? g->h : 0.5, o);
     if (k_minus) *k_minus = sh.kminus;
     if (k_plus) *k_plus = sh.kplus;
     if (step_used) *step_used = sh.k;

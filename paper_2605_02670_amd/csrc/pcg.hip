@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
                 any_fresh |= flag[1][k] != 0;
             }
             if (!any_act) break;
-            if (!switched && it + 1 == switch_at) {  // fallback: Jacobi from the current iterate
+            if (!switched && it == switch_at) {  // fallback after maxit / 2 iterations: Jacobi from the current iterate
                 switched = true;
                 if (!done && lz) {
                     lz = false;
@@ -799,7 +799,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 it_n = maxit + 1;
                 break;
             }
-            if (LP && lz && it_n + 1 == switch_at) {  // fallback: Jacobi from the current iterate
+            if (LP && lz && it_n == switch_at) {  // fallback after maxit / 2 iterations: Jacobi from the current iterate
                 lz = false;
                 fresh = true;
                 continue;

@@ -107,6 +107,27 @@ def _check(code: int, allow=(GRF_OK,)) -> int:
     return code
 
 
+def check_array(t, n_rows: int, n_cols: int, name: str, device=None):
+    """Raises ValueError unless t is a contiguous float64 CUDA tensor of shape
+    (n_rows, n_cols) (on ``device`` if given): the library writes or reads
+    exactly n_rows * n_cols doubles through its pointer."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, got {t.dtype}")
+    if tuple(t.shape) != (n_rows, n_cols):
+        raise ValueError(f"{name} must have shape ({n_rows}, {n_cols}), got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a CUDA (HIP) device, got {t.device}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the graph on cuda:{device}")
+    return t
+
+
 def _stream_handle(stream=None) -> int:
     import torch
 
@@ -172,6 +193,9 @@ class Graph:
         offs = np.zeros(self.n_edges + 1, dtype=np.int64)
         _check(lib.grf_graph_info(self.handle, C.byref(nd), C.byref(ni), offs.ctypes.data))
         self.n_dof, self.n_interior, self.offsets = nd.value, ni.value, offs
+        import torch
+
+        self.device = torch.cuda.current_device()
 
     @classmethod
     def from_workload(cls, g, h: float, rule: str = "ceil") -> "Graph":
@@ -199,7 +223,8 @@ class Graph:
         import torch
 
         if out is None:
-            out = torch.empty((n_samples, self.n_dof), dtype=torch.float64, device="cuda")
+            out = torch.empty((n_samples, self.n_dof), dtype=torch.float64, device=f"cuda:{self.device}")
+        check_array(out, n_samples, self.n_dof, "out", self.device)
         o = make_opts(**kw)
         _check(load().grf_noise(self.handle, n_samples, seed, out.data_ptr(), C.byref(o)))
         return out
@@ -210,7 +235,8 @@ class Graph:
         import torch
 
         if out is None:
-            out = torch.empty((n_samples, self.n_dof), dtype=torch.float64, device="cuda")
+            out = torch.empty((n_samples, self.n_dof), dtype=torch.float64, device=f"cuda:{self.device}")
+        check_array(out, n_samples, self.n_dof, "out", self.device)
         st = Stats()
         o = make_opts(stats=st, **kw)
         allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
@@ -224,11 +250,15 @@ class Graph:
         noise()); returns (samples, stats dict)."""
         import torch
 
-        assert noise.dtype == torch.float64 and noise.is_cuda and noise.is_contiguous()
-        assert noise.dim() == 2 and noise.shape[1] == self.n_dof
+        if not isinstance(noise, torch.Tensor) or noise.dim() != 2:
+            raise ValueError("noise must be a 2-d tensor [n_samples, n_dof]")
         n = noise.shape[0]
+        check_array(noise, n, self.n_dof, "noise", self.device)
         if out is None:
-            out = torch.empty((n, self.n_dof), dtype=torch.float64, device="cuda")
+            out = torch.empty((n, self.n_dof), dtype=torch.float64, device=f"cuda:{self.device}")
+        check_array(out, n, self.n_dof, "out", self.device)
+        if out.data_ptr() == noise.data_ptr():
+            raise ValueError("noise and out may not alias")
         st = Stats()
         o = make_opts(stats=st, **kw)
         allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
@@ -239,11 +269,21 @@ class Graph:
     def solve_shifted(self, kappa: float, c_I: float, c_L: float, rhs, out=None, allow_noconv=False, **kw):
         import torch
 
+        if not isinstance(rhs, torch.Tensor) or rhs.dim() == 0 or rhs.shape[-1] != self.n_dof:
+            raise ValueError(f"rhs must be a tensor [..., {self.n_dof}]")
         rhs = rhs.contiguous()
-        assert rhs.dtype == torch.float64 and rhs.is_cuda and rhs.shape[-1] == self.n_dof
         r2 = rhs.reshape(-1, self.n_dof)
+        check_array(r2, r2.shape[0], self.n_dof, "rhs", self.device)
         if out is None:
             out = torch.empty_like(r2)
+        else:
+            if not isinstance(out, torch.Tensor) or tuple(out.shape) != tuple(rhs.shape):
+                raise ValueError(f"out must have the shape of rhs, {tuple(rhs.shape)}")
+            if out.is_contiguous():
+                out = out.view(-1, self.n_dof)
+        check_array(out, r2.shape[0], self.n_dof, "out", self.device)
+        if out.data_ptr() == r2.data_ptr():
+            raise ValueError("rhs and out may not alias")
         st = Stats()
         o = make_opts(stats=st, **kw)
         allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
@@ -258,7 +298,11 @@ def sample_batched(graphs, kappas, beta: float, quad_step: float, n_samples: int
 
     n = len(graphs)
     if outs is None:
-        outs = [torch.empty((n_samples, g.n_dof), dtype=torch.float64, device="cuda") for g in graphs]
+        outs = [torch.empty((n_samples, g.n_dof), dtype=torch.float64, device=f"cuda:{g.device}") for g in graphs]
+    if len(outs) != n:
+        raise ValueError(f"need one output per graph: {len(outs)} outputs for {n} graphs")
+    for i, (g, o_) in enumerate(zip(graphs, outs)):
+        check_array(o_, n_samples, g.n_dof, f"outs[{i}]", g.device)
     harr = (C.c_void_p * n)(*[g.handle for g in graphs])
     karr = (C.c_double * n)(*[float(k) for k in kappas])
     oarr = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
@@ -292,6 +336,9 @@ class Learned:
 
     def loss_grad(self, graph, kappa: float, c_I: float, c_L: float, rhs, sol, **kw):
         """rhs, sol: device float64 tensors [n_rhs][V]; returns (loss, grad numpy float32)."""
+        n = rhs.shape[0] if hasattr(rhs, "shape") and len(rhs.shape) == 2 else -1
+        check_array(rhs, n, graph.n_vertices, "rhs", graph.device)
+        check_array(sol, n, graph.n_vertices, "sol", graph.device)
         loss = C.c_double()
         grad = np.zeros(self.n_params, dtype=np.float32)
         o = make_opts(**kw)

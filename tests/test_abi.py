@@ -89,3 +89,48 @@ def test_class_mode_encoding():
     assert grf.class_modes(3 << 10) == ["op"] * 5 + ["global"]
     assert grf.make_opts(stream=False).pcg_class_modes == 0
     assert grf.make_opts(precond="nn", stream=False).precond == 2
+
+
+def test_shift_count_bounds():
+    """The shift schedule rejects overrides that overflow the shift count or the
+    coefficients c_I = pi/(2k sin(pi beta)) e^{-2 beta l k}, c_L = c_I e^{2 l k}."""
+    lib = grf.load()
+    km, kp, k = C.c_int32(), C.c_int32(), C.c_double()
+
+    def count(k_minus=-1, k_plus=-1, beta=0.75, step=0.5):
+        o = grf.make_opts(k_minus=k_minus, k_plus=k_plus, stream=False)
+        return lib.grf_shift_count(None, beta, step, C.byref(o), C.byref(km), C.byref(kp), C.byref(k))
+
+    # the paper's rule at k = 0.5, beta = 0.75: K- = ceil(pi^2/(4 k^2 beta)) = 14, K+ = ceil(pi^2/(4 k^2/4)) = 40
+    assert count() == grf.GRF_OK and (km.value, kp.value, k.value) == (14, 40, 0.5)
+    assert count(k_minus=3, k_plus=5) == grf.GRF_OK and (km.value, kp.value) == (3, 5)
+    assert count(k_plus=2 ** 31 - 1) == grf.GRF_EINVAL
+    assert count(k_minus=600000, k_plus=600000) == grf.GRF_EINVAL
+    # e^{2 y} overflows at y = 1000 * 0.5 ... for l k > 354
+    assert count(k_plus=1000) == grf.GRF_EINVAL
+    assert b"not finite" in lib.grf_last_error()
+    # e^{-2 beta y} overflows for y -> -infinity too
+    assert count(k_minus=1000, beta=0.9) == grf.GRF_EINVAL
+    assert count(beta=1.0) == grf.GRF_EINVAL
+    # without a graph the paper's step rule (quad_step = 0) needs h
+    assert count(step=0.0) == grf.GRF_EINVAL
+
+
+def test_binding_checks_arrays():
+    """The binding refuses any array the library would read or write past: the
+    wrong dtype, shape, layout or device (checked before any library call)."""
+    import torch
+
+    good = torch.zeros((3, 10), dtype=torch.float64)
+    with pytest.raises(ValueError, match="float64"):
+        grf.check_array(good.float(), 3, 10, "out")
+    with pytest.raises(ValueError, match="shape"):
+        grf.check_array(good[:2], 3, 10, "out")
+    with pytest.raises(ValueError, match="shape"):
+        grf.check_array(good.reshape(-1), 3, 10, "out")
+    with pytest.raises(ValueError, match="contiguous"):
+        grf.check_array(torch.zeros((10, 3), dtype=torch.float64).t(), 3, 10, "out")
+    with pytest.raises(ValueError, match="device"):
+        grf.check_array(good, 3, 10, "out")
+    with pytest.raises(ValueError, match="tensor"):
+        grf.check_array(np.zeros((3, 10)), 3, 10, "out")
