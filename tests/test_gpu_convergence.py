@@ -58,8 +58,12 @@ def test_from_noise_matches_sample_and_oracle(grf):
     u2, _ = G.sample_from_noise(*args, torch.from_numpy(Wr).cuda())
     ref = osolve.sample(m, cfg["kappa"], cfg["beta"], cfg["quad_step"], Wr)
     assert _rel_ml(u2.cpu().numpy(), ref, ML) <= 1e-10
-    with pytest.raises(grf.GrfError, match="alias"):
-        G.sample_from_noise(*args, W, out=W)
+    with pytest.raises(ValueError, match="alias"):
+        G.sample_from_noise(*args, W, out=W)  # the binding's check
+    # the library's own check, through the C ABI
+    o = grf.make_opts()
+    code = grf.load().grf_sample_from_noise(G.handle, *args, S, W.data_ptr(), W.data_ptr(), grf.C.byref(o))
+    assert code == grf.GRF_EINVAL and b"alias" in grf.load().grf_last_error()
 
 
 # ---- convergence rates ------------------------------------------------------------
