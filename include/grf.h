@@ -206,6 +206,28 @@ int grf_sample_from_noise(grf_graph *g, double kappa, double beta, double quad_s
                           const double *noise, double *out, const grf_opts *opts);
 
 /*
+ * grf_sample for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and statuses as grf_sample; the call allocates nothing.
+ * Its whole workspace lives in a fixed 128 MiB device array that the library
+ * holds on every device it runs on until the process ends (the graph's own
+ * mesh, uploaded by grf_graph_create, is not part of it).
+ *   - GRF_EINVAL (before or during the call, message names the sizes) when the
+ *     workspace of (graph, shifts, n_samples) needs more than the 128 MiB;
+ *     roughly, 16 * ceil(n_samples/64) * 64 * n_dof bytes for the noise and
+ *     accumulator plus per-shift tables must fit.
+ *   - GRF_EINVAL for GRF_PRECOND_LEARNED (the network keeps its own workspace)
+ *     or when the current device is not the graph's.
+ *   - opts->timing is ignored (no per-kernel events are created).
+ * Every call on a device shares that device's array: calls that overlap on one
+ * device (two threads, or two streams running at once) race and give wrong
+ * results.  The array keeps the last call's contents; the path clears what it
+ * reads before writing it.
+ */
+int grf_sample_noalloc(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples,
+                       uint64_t seed, double *out, const grf_opts *opts);
+
+/*
  * One shifted solve for n_rhs right-hand sides:
  *   out[r] = ((c_I + c_L kappa^2) M_L + c_L G)^{-1} rhs[r]
  * (paper: eq. spde_approx_fem for a single l, solved by eq. global_schur).

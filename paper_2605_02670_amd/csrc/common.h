@@ -42,9 +42,28 @@ struct Error {
 #define GRF_LAUNCH_CHECK() GRF_HIP(hipGetLastError())
 
 // ---- device buffers ---------------------------------------------------------
+// Memory a caller lends for the duration of one call: while an Arena is
+// installed on the calling thread (ArenaScope), DevBuf::reserve carves
+// 256-byte aligned ranges from it instead of calling hipMalloc, and throws
+// GRF_EINVAL when the arena is exhausted.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    const char *owner = "";  // named in the error when the arena is exhausted
+};
+Arena *current_arena();
+struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope &) = delete;
+    ArenaScope &operator=(const ArenaScope &) = delete;
+};
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;  // carved from an Arena: never freed here
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;

@@ -27,18 +27,40 @@ void set_error(const char *fmt, ...) {
     va_end(ap);
 }
 
+static thread_local Arena *g_arena = nullptr;
+
+Arena *current_arena() { return g_arena; }
+
+ArenaScope::ArenaScope(Arena *a) : prev(g_arena) { g_arena = a; }
+
+ArenaScope::~ArenaScope() { g_arena = prev; }
+
 DevBuf::~DevBuf() { release(); }
 
 void DevBuf::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !borrowed) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+    borrowed = false;
 }
 
 void DevBuf::reserve(size_t n) {
     if (n <= bytes) return;
     release();
     if (n == 0) return;
+    if (Arena *a = g_arena) {
+        const size_t at = (a->used + 255) & ~(size_t)255;
+        if (at > a->size || n > a->size - at) {
+            set_error("%s: the workspace needs more than its %zu-byte scratch (%zu bytes more requested with "
+                      "%zu in use)", a->owner, a->size, n, at);
+            throw Error{GRF_EINVAL};
+        }
+        ptr = a->base + at;
+        bytes = n;
+        borrowed = true;
+        a->used = at + n;
+        return;
+    }
     hipError_t e = hipMalloc(&ptr, n);
     if (e != hipSuccess) {
         ptr = nullptr;

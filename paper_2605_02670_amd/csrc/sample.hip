@@ -76,9 +76,15 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     const double tbytes = o.precision == GRF_PREC_MIXED ? 4.0 : 8.0;
     const double per_shift = 8.0 * (rows * g.NI + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V + (double)g.V * Sp) +
                              tbytes * btab + 12.0 * S * (double)(g.gv0.size() - 1);
-    size_t freeb = 0, totalb = 0;
-    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)64 << 30;
-    double budget = 0.5 * (double)(freeb + held_pass_bytes(g));
+    double budget;
+    if (const Arena *a = current_arena()) {
+        // lent memory: most of what is left of it (the estimate above is not exact)
+        budget = 0.75 * (double)(a->size - std::min(a->size, a->used));
+    } else {
+        size_t freeb = 0, totalb = 0;
+        if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)64 << 30;
+        budget = 0.5 * (double)(freeb + held_pass_bytes(g));
+    }
     int64_t lb = o.shift_block > 0 ? o.shift_block : (int64_t)std::floor(budget / per_shift);
     if (p.blocked) lb = std::min<int64_t>(lb, 128);
     lb = std::min<int64_t>(lb, L);
@@ -91,7 +97,8 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     const int64_t nglob = g.cls_off[kPcgClasses + 1] - g.cls_off[c0];
     const int64_t units = nglob * lb * ((S + kMrhsSB - 1) / kMrhsSB);
     const double ubytes = 5.0 * kMrhsSB * sizeof(double) * std::max<int32_t>(g.maxVg, 1);
-    const int64_t cap = (int64_t)std::max(1.0, std::floor(16.0 * (double)(1ull << 30) / ubytes));
+    const double scr_budget = current_arena() ? 0.25 * budget : 16.0 * (double)(1ull << 30);
+    const int64_t cap = (int64_t)std::max(1.0, std::floor(scr_budget / ubytes));
     p.pcg_blocks = (int32_t)std::min<int64_t>(std::min<int64_t>(units, cap), 4096);
     return p;
 }
@@ -562,8 +569,11 @@ int grf_noise(grf_graph *g, int64_t n_samples, uint64_t seed, double *out, const
     GRF_API_END
 }
 
+}  // extern "C"
+
+namespace grf {
 // grf_sample and grf_sample_from_noise: W from the Philox draw (noise null) or the caller
-static int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
+int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
                        const double *noise, double *out, const grf_opts *opts) {
     GRF_REQUIRE(g, "graph is NULL");
     GRF_REQUIRE(std::isfinite(kappa) && kappa > 0, "kappa must be finite and > 0");
@@ -606,6 +616,9 @@ static int sample_impl(grf_graph *g, double kappa, double beta, double quad_step
     T.collect(o.stats);
     return code;
 }
+}  // namespace grf
+
+extern "C" {
 
 int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
                double *out, const grf_opts *opts) {

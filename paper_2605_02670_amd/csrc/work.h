@@ -30,6 +30,11 @@ namespace grf {
 void free_work(grf_graph &g);
 grf_graph::Work &work(grf_graph &g);
 
+// The whole path of grf_sample (noise null) and grf_sample_from_noise (noise given):
+// status GRF_OK or GRF_ENOCONV; throws Error on any other failure.
+int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples, uint64_t seed,
+                const double *noise, double *out, const grf_opts *opts);
+
 // ---- launchers (each .hip file implements its own) -------------------------
 // noise: X[b][j][lane] = msqrt[j] * Z(seed, soff + b*64 + lane, j) for b*64+lane < S, 0 otherwise
 void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, double *X, hipStream_t st);

@@ -66,6 +66,8 @@ _SIGS = [
     ("grf_noise", C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.POINTER(Opts)]),
     ("grf_sample", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_uint64, C.c_void_p,
                              C.POINTER(Opts)]),
+    ("grf_sample_noalloc", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_uint64,
+                                     C.c_void_p, C.POINTER(Opts)]),
     ("grf_sample_from_noise", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p,
                                         C.c_void_p, C.POINTER(Opts)]),
     ("grf_solve_shifted", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p,
