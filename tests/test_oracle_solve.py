@@ -80,6 +80,27 @@ def test_interval_closed_form(length, h, kappa, beta, k):
     assert np.abs(u - uc).max() <= 1e-11 * np.abs(uc).max()
 
 
+@pytest.mark.parametrize("length,h,kappa,beta,k", [(1.0, 1 / 32, 3.0, 0.75, 0.4), (2.5, 0.1, 0.7, 0.55, 0.3),
+                                                   (0.3, 0.05, 25.0, 0.85, 0.5)])
+def test_interval_closed_form_consistent_mass(length, h, kappa, beta, k):
+    """Consistent mass in the shifted systems (the paper's Phase 2 consistent
+    entries): the direct solves equal the cosine expansion with the consistent
+    eigenvalue ratio c_n = (2 + cos theta_n)/3.  The shifts span matrices whose
+    interior coupling alpha h/6 - gamma/h takes both signs."""
+    g = interval(length)
+    m = mesh.build_mesh(2, g.edges, g.lengths, h, "ceil")
+    W = noise.white_noise(mesh.lumped_mass(m), 4, 3)
+    u = solve.sample(m, kappa, beta, k, W, method="sparse", mass="consistent")
+    uc = spectral.interval_sample(length, int(m.n_el[0]), kappa, beta, k, W, mass="consistent")
+    assert np.abs(u - uc).max() <= 1e-11 * np.abs(uc).max()
+    ul = spectral.interval_sample(length, int(m.n_el[0]), kappa, beta, k, W)
+    assert np.abs(ul - uc).max() > 1e-6 * np.abs(uc).max()  # the two systems differ
+    _, cI, cL = quadrature.shifts(beta, k)
+    hh = length / int(m.n_el[0])
+    b = (cI + cL * kappa * kappa) * hh / 6.0 - cL / hh
+    assert (b > 0).any() and (b < 0).any()
+
+
 def test_conservation_per_shift_and_sum():
     V, E, L = _graphs()[2]
     m = mesh.build_mesh(V, E, L, 0.07, "round")
