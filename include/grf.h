@@ -55,6 +55,13 @@ typedef enum grf_status {
 /* grf_graph_create flags */
 #define GRF_MESH_CEIL 0u  /* n_e = ceil(l_e/h)  (paper, Phase 1) */
 #define GRF_MESH_ROUND 1u /* n_e = floor(l_e/h + 1/2) */
+/* OR-ed with a mesh rule: the shifted systems use the consistent mass matrix
+   (element matrices (h_e/6)[[2,1],[1,2]], paper Phase 2, consistent entries)
+   instead of the lumped one.  The noise of grf_sample / grf_noise stays the
+   lumped W = M_L^{1/2} xi (grf_sample_from_noise takes any load).  Runs the
+   streamed edge sweeps (sweep_block 0 picks their width); GRF_PREC_MIXED
+   returns GRF_EUNSUP. */
+#define GRF_MASS_CONSISTENT_SYS 2u
 
 /* grf_opts.precision */
 #define GRF_PREC_FP64 0  /* every step in FP64 */

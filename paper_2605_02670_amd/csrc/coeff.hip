@@ -27,6 +27,21 @@
 //   s_d = delta - b^2 (T^{-1})_{11} = alpha h / 2 + |b| eps_{m-1} / (1 + eps_{m-1})
 //   s_o = -b^2 (T^{-1})_{1m}        = -|b| prod_p rho_p
 // (an edge with no interior node has s_d = delta, s_o = b).
+//
+// Consistent mass in the system (GRF_MASS_CONSISTENT_SYS; paper Phase 2,
+// consistent entries): a = 2 alpha h / 3 + 2 gamma / h, b = alpha h / 6 -
+// gamma / h and delta = alpha h / 3 + gamma / h, so b takes either sign across
+// the shifts.  With sigma = -sign(b) and D = diag(sigma^p), T = D T' D where
+// T' = |b| tridiag(-1, tau, -1) has the form above, tau - 2 = eps = (a - 2|b|)
+// / |b| (alpha h / |b| when b < 0, (alpha h / 3 + 4 gamma / h) / |b| when
+// b > 0, both free of cancellation).  Hence (T^{-1})_{pq} = sigma^{p+q}
+// (T'^{-1})_{pq}: the multipliers rho and the off-diagonal of T^{-1} carry the
+// factor sigma, the diagonal does not, the end values and the recovery use
+// -b = sigma |b| where the lumped form has |b|, and
+//   s_d = (delta - |b|) + |b| eps_{m-1} / (1 + eps_{m-1}),
+//   s_o = -|b| sigma^{m-1} prod_p rho_p   (b for an edge with no interior node),
+// with delta - |b| = alpha h / 2 (b < 0) or alpha h / 6 + 2 gamma / h (b > 0).
+// b = 0 makes T = a I (no coupling to the vertices).  Lumped: sigma = 1.
 #include <algorithm>
 
 #include "work.h"
@@ -61,26 +76,59 @@ __global__ void __launch_bounds__(64) k_coeff(MeshView mv, const double *__restr
     const double h = mv.he[e];
     const double alpha = shift[2 * l] + shift[2 * l + 1] * mv.kap2[e];
     const double gamma = shift[2 * l + 1];
-    const double bab = gamma / h;
-    const double eps = alpha * h * h / gamma;
-    // pass 1: pivots eps_p (kept in fwdt.y as scratch), multipliers rho_p, prod rho_p
+    double bab, eps, c0, sg;  // |b|, tau - 2, delta - |b|, sigma = -sign(b)
+    if (!mv.consistent) {
+        bab = gamma / h;
+        eps = alpha * h * h / gamma;
+        c0 = alpha * h * 0.5;
+        sg = 1.0;
+    } else {
+        const double b = alpha * h / 6.0 - gamma / h;
+        if (b == 0.0) {  // T = a I: no multipliers, no coupling to the vertices
+            const double dg = 1.0 / (2.0 * alpha * h / 3.0 + 2.0 * gamma / h);
+            for (int p = 0; p < m; ++p) {
+                rho[at(p)] = 0.0;
+                fwdt[at(p)] = make_double2(0.0, dg);
+                bwdt[at(p)] = make_double2(0.0, 0.0);
+            }
+            babs[e * LBp + l] = 0.0;
+            rhom[e * LBp + l] = 0.0;
+            sd[(int64_t)l * E + e] = alpha * h / 3.0 + gamma / h;
+            so[(int64_t)l * E + e] = 0.0;
+            return;
+        }
+        if (b < 0.0) {
+            bab = -b;
+            eps = alpha * h / bab;
+            c0 = alpha * h * 0.5;
+            sg = 1.0;
+        } else {
+            bab = b;
+            eps = (alpha * h / 3.0 + 4.0 * gamma / h) / bab;
+            c0 = alpha * h / 6.0 + 2.0 * gamma / h;
+            sg = -1.0;
+        }
+    }
+    // pass 1: pivots eps_p (kept in fwdt.y as scratch), multipliers sigma rho_p, prod rho_p
     double ep = 1.0 + eps, prod = 1.0, ep_last = 0.0, r_last = 0.0, r_prev = 0.0;
     for (int p = 0; p < m; ++p) {
         const double r = 1.0 / (1.0 + ep);
-        rho[at(p)] = r;
-        fwdt[at(p)] = make_double2(r_prev, ep);  // .x = rho_{p-1}
-        bwdt[at(p)].x = r_prev;
+        rho[at(p)] = sg * r;
+        fwdt[at(p)] = make_double2(sg * r_prev, ep);  // .x = sigma rho_{p-1}
+        bwdt[at(p)].x = sg * r_prev;
         prod *= r;
         ep_last = ep;
         r_last = r;
         r_prev = r;
         ep = eps + ep * r;
     }
-    babs[e * LBp + l] = bab;
-    rhom[e * LBp + l] = (m > 0) ? r_last : 0.0;
-    sd[(int64_t)l * E + e] = alpha * h * 0.5 + ((m > 0) ? bab * (ep_last * r_last) : bab);
-    so[(int64_t)l * E + e] = (m > 0) ? -bab * prod : -bab;
+    babs[e * LBp + l] = sg * bab;
+    rhom[e * LBp + l] = (m > 0) ? sg * r_last : 0.0;
+    sd[(int64_t)l * E + e] = c0 + ((m > 0) ? bab * (ep_last * r_last) : bab);
+    const double par = (sg < 0.0 && (m & 1) == 0) ? -1.0 : 1.0;  // sigma^{m-1}
+    so[(int64_t)l * E + e] = (m > 0) ? -bab * prod * par : -sg * bab;
     // pass 2: diagonal and first off-diagonal of T^{-1}, outside-in in pairs
+    // (rho holds sigma rho_p, so the off-diagonal carries its sigma)
     for (int p = 0; 2 * p < m; ++p) {
         const int q = m - 1 - p;
         const double ep_p = fwdt[at(p)].y;

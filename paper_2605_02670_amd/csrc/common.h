@@ -112,6 +112,7 @@ struct MeshView {
     const int32_t *gv0, *ge0;
     const int64_t *segs;
     int32_t maxVg, maxEg;  // largest graph of the batch (host-side dispatch)
+    int32_t consistent;    // shifted systems with the consistent mass matrix (GRF_MASS_CONSISTENT_SYS)
     int64_t maxNg;
     // first four edge ends of every vertex (column-major [4][V]: the other vertex, or the
     // vertex itself past its degree; eend: 2 edge + side, or -1 past the degree) and the degree

@@ -109,7 +109,7 @@ void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const 
     GRF_REQUIRE(E >= 0 && E < (int64_t(1) << 30), "n_edges must be in [0, 2^30)");
     GRF_REQUIRE(E == 0 || (edges && lengths), "edges and lengths must be non-NULL");
     GRF_REQUIRE(std::isfinite(h) && h > 0, "h must be finite and > 0");
-    GRF_REQUIRE(flags == GRF_MESH_CEIL || flags == GRF_MESH_ROUND, "unknown mesh flag %u", flags);
+    GRF_REQUIRE((flags & ~(GRF_MESH_ROUND | GRF_MASS_CONSISTENT_SYS)) == 0, "unknown mesh flag %u", flags);
     g.V = V;
     g.E = E;
     g.h = h;
@@ -128,7 +128,7 @@ void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const 
         GRF_REQUIRE(u >= 0 && u < V && v >= 0 && v < V, "edge %lld endpoint out of range", (long long)e);
         GRF_REQUIRE(std::isfinite(L) && L > 0, "edge %lld length must be finite and > 0", (long long)e);
         double q = L / h;
-        double n = (flags == GRF_MESH_CEIL) ? std::ceil(q) : std::floor(q + 0.5);
+        double n = (flags & GRF_MESH_ROUND) ? std::floor(q + 0.5) : std::ceil(q);
         double nmin = (u == v) ? 2.0 : 1.0;
         if (n < nmin) n = nmin;
         GRF_REQUIRE(n < 1e9, "edge %lld needs too many elements", (long long)e);
@@ -402,6 +402,7 @@ grf::MeshView grf_graph::view() const {
     v.adj_s = d_adj_s.as<int8_t>();
     v.msqrt = d_msqrt.as<double>();
     v.ng = (int32_t)gv0.size() - 1;
+    v.consistent = (flags & GRF_MASS_CONSISTENT_SYS) ? 1 : 0;
     v.gv0 = d_gv0.as<int32_t>();
     v.ge0 = d_ge0.as<int32_t>();
     v.segs = d_segs.as<int64_t>();

@@ -36,6 +36,14 @@ static void set_kappa2(grf_graph &g, double kappa, hipStream_t st) {
     g.kap2_loaded = k2;
 }
 
+// FP32 matrix-core sweeps and the mixed refinement residual are written for the lumped system
+static void require_supported(const grf_graph &g, const grf_opts &o) {
+    if ((g.flags & GRF_MASS_CONSISTENT_SYS) && o.precision != GRF_PREC_FP64) {
+        set_error("mixed precision is not available for a graph with GRF_MASS_CONSISTENT_SYS");
+        throw Error{GRF_EUNSUP};
+    }
+}
+
 struct Plan {
     bool blocked = true;  // matrix-core sweeps (otherwise streamed recurrences)
     int32_t LB = 0;       // shifts per pass
@@ -65,8 +73,11 @@ static size_t held_pass_bytes(const grf_graph &g) {
 
 static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &o) {
     Plan p;
-    p.blocked = (o.sweep_block == 0);
-    p.BL = p.blocked ? 16 : o.sweep_block;
+    // the matrix-core sweeps' closed forms need the lumped system's b < 0; a
+    // consistent-mass system runs the streamed sweeps (width picked here when not given)
+    const bool consistent = (g.flags & GRF_MASS_CONSISTENT_SYS) != 0;
+    p.blocked = (o.sweep_block == 0) && !consistent;
+    p.BL = p.blocked ? 16 : (o.sweep_block != 0 ? o.sweep_block : auto_bl(L));
     const int64_t nb = (S + 63) / 64, Sp = 64 * nb;
     // bytes per shift of the per-pass buffers
     // streamed: rho + two double2 step rows per interior DOF; blocked: per-block operand tables
@@ -583,6 +594,7 @@ int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64
     if (n_samples == 0) return GRF_OK;
     GRF_REQUIRE(out, "out is NULL");
     GRF_REQUIRE(noise != out, "noise and out may not alias");
+    require_supported(*g, o);
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
     hipStream_t st = (hipStream_t)o.stream;
@@ -646,6 +658,7 @@ int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_
     if (n_rhs == 0) return GRF_OK;
     GRF_REQUIRE(rhs && out, "rhs/out is NULL");
     GRF_REQUIRE(rhs != out, "rhs and out may not alias");
+    require_supported(*g, o);
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
     hipStream_t st = (hipStream_t)o.stream;
@@ -748,6 +761,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     if (n_samples == 0) return GRF_OK;
     GRF_REQUIRE(outs, "outs is NULL");
     for (int32_t k = 0; k < n_graphs; ++k) GRF_REQUIRE(outs[k], "outs[%d] is NULL", k);
+    require_supported(*graphs[0], o);
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
     hipStream_t st = (hipStream_t)o.stream;
@@ -786,6 +800,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
                 cand.push_back({32, 0});
                 cand.push_back({64, 0});
             }
+            if (U.flags & GRF_MASS_CONSISTENT_SYS) cand = {{32, 0}, {64, 0}, {32, 64}};  // streamed sweeps only
             grf_opts t = run;
             if (has_given) t.pcg_class_modes = 0;  // the sweeps are tuned with the default variants
             double best = 0.0;

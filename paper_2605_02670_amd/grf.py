@@ -18,6 +18,7 @@ _lib = None
 
 GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP = 0, -1, -2, -3, -4, -5
 MESH = {"ceil": 0, "round": 1}
+MASS = {"lumped": 0, "consistent": 2}  # GRF_MASS_CONSISTENT_SYS
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
 PCG_MODES = {"op": 0, "guess": 1, "jacobi": 2}  # grf_stats also reports 3: "global"
@@ -179,17 +180,22 @@ def class_modes(word: int) -> list[str]:
 class Graph:
     """A metric graph and its mesh on the current HIP device."""
 
-    def __init__(self, n_vertices: int, edges, lengths, h: float, rule: str = "ceil"):
+    def __init__(self, n_vertices: int, edges, lengths, h: float, rule: str = "ceil", mass: str = "lumped"):
+        """mass: the mass matrix of the shifted systems, "lumped" or "consistent"
+        (GRF_MASS_CONSISTENT_SYS); the noise is lumped either way."""
         lib = load()
+        if mass not in MASS:
+            raise ValueError(f"mass must be one of {sorted(MASS)}, got {mass!r}")
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
         L = np.ascontiguousarray(np.asarray(lengths, dtype=np.float64).reshape(-1))
         self.n_vertices = int(n_vertices)
         self.n_edges = int(e.shape[0])
         self.h = float(h)
         self.rule = rule
+        self.mass = mass
         handle = C.c_void_p()
         _check(lib.grf_graph_create(self.n_vertices, self.n_edges, e.ctypes.data, L.ctypes.data, self.h,
-                                    MESH[rule], C.byref(handle)))
+                                    MESH[rule] | MASS[mass], C.byref(handle)))
         self.handle = handle.value
         nd, ni = C.c_int64(), C.c_int64()
         offs = np.zeros(self.n_edges + 1, dtype=np.int64)
