@@ -112,6 +112,15 @@ typedef struct grf_stats {
                                    3 the class runs the global-memory kernel) */
     double kernel_ms[12];       /* with opts.timing: summed HIP-event time per grf_kernel_id */
     int32_t kernel_launches[12];/* with opts.timing: launches per grf_kernel_id */
+    /* Vertex PCG by graph size class c (vertex capacities 64, 256, 1024, 4096,
+       10176, 20352 for c = 0..5; c = 6: the graphs that run the global-memory
+       kernel, including a class the preconditioner sends there).  One launch per
+       class and shift block. */
+    double pcg_class_ms[7];          /* with opts.timing: HIP-event time of the class's launches */
+    int32_t pcg_class_launches[7];   /* with opts.timing: launches */
+    int32_t pcg_class_reserved;
+    int64_t pcg_class_vertex_its[7]; /* sum over the class's systems of iterations x graph vertices */
+    int64_t pcg_class_end_its[7];    /* sum over the class's systems of iterations x graph edge ends (2|E|) */
 } grf_stats;
 
 typedef struct grf_opts {
@@ -125,7 +134,8 @@ typedef struct grf_opts {
     int32_t shift_block;   /* shifts per pass; 0 = plan from a memory budget */
     int32_t sweep_block;   /* shifts per wavefront in the sweeps: 0 (auto), 8, 16, 32, 64 */
     int32_t refine;        /* mixed precision: max refinement sweeps; < 0 = default (2) */
-    int32_t timing;        /* 1: time every kernel with HIP events into stats->kernel_ms */
+    int32_t timing;        /* 1: time every kernel with HIP events into stats->kernel_ms (grf_sample_batched
+                              then runs its launches uncaptured, each timed) */
     int32_t pcg_class_modes; /* learned preconditioner only: 0 = automatic (grf_sample_batched times the
                                 three on-chip PCG variants per size class once and keeps the fastest;
                                 elsewhere the default); or GRF_PCG_MODES_SET | (variant of class c)
@@ -159,6 +169,12 @@ int grf_graph_create(int64_t n_vertices, int64_t n_edges, const int64_t *edges,
 /* Sizes of the canonical DOF vector.  dof_offsets (host, int64 [n_edges+1],
  * may be NULL) receives the first interior DOF of every edge. */
 int grf_graph_info(const grf_graph *g, int64_t *n_dof, int64_t *n_interior, int64_t *dof_offsets);
+
+/* Diagonal of the lumped mass matrix M_L in canonical order (paper: "Phase 2",
+ * lumped case): h_e at the interior nodes of edge e, the sum of h_e / 2 over
+ * the edge ends at a vertex.  out: host, float64 [n_dof].  It defines the
+ * norm ||u||_{M_L} in which sample errors are measured. */
+int grf_graph_lumped_mass(const grf_graph *g, double *out);
 
 /* Release a graph and every device buffer it holds.  NULL is accepted. */
 int grf_graph_destroy(grf_graph *g);

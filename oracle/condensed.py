@@ -126,26 +126,53 @@ def solve_shifted(m: _mesh.Mesh, kappa: float, c_I: float, c_L: float, rhs: np.n
     return Shifted(m, kappa, c_I, c_L, mass).solve(rhs)
 
 
-def _shift_task(args):
-    m, kappa, cI, cL, W, mass = args
-    return solve_shifted(m, kappa, cI, cL, W, mass)
+def _range_task(args):
+    """Sum of the solutions of a contiguous range of shifts, l increasing."""
+    m, kappa, cIs, cLs, W, mass = args
+    if isinstance(W, str):  # a .npy file, memory-mapped (large loads are not copied to every process)
+        W = np.load(W, mmap_mode="r")
+    u = np.zeros(W.shape, dtype=np.float64)
+    for ci, cl in zip(cIs, cLs):
+        u = u + solve_shifted(m, kappa, ci, cl, W, mass)
+    return u
 
 
 def sample(m: _mesh.Mesh, kappa: float, beta: float, k: float, W: np.ndarray,
            k_minus: int | None = None, k_plus: int | None = None, mass: str = "lumped",
-           workers: int = 1, per_shift: bool = False):
-    """u[s] = sum_l A^(l)^{-1} W[s], l increasing.  With workers > 1 the shifts
-    are solved in that many processes; the sum is still taken in increasing l,
-    so the result does not depend on ``workers``."""
+           workers: int = 1):
+    """u[s] = sum_l A^(l)^{-1} W[s], l increasing.  With workers > 1 the shift
+    range is cut into that many contiguous pieces, each summed (l increasing) in
+    a process of its own, and the partial sums are added in increasing order:
+    the same terms in the same order, grouped by piece.  W is an array [S, N] or
+    the path of a .npy file holding one."""
     _, c_I, c_L = _quad.shifts(beta, k, k_minus, k_plus)
-    W = np.asarray(W, dtype=np.float64)
+    if not isinstance(W, str):
+        W = np.asarray(W, dtype=np.float64)
+    if workers <= 1:
+        return _range_task((m, kappa, [float(x) for x in c_I], [float(x) for x in c_L], W, mass))
+    cuts = np.linspace(0, len(c_I), min(workers, len(c_I)) + 1).round().astype(int)
+    tasks = [(m, kappa, [float(x) for x in c_I[a:b]], [float(x) for x in c_L[a:b]], W, mass)
+             for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    with cf.ProcessPoolExecutor(max_workers=len(tasks), mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_range_task, tasks))
+    u = np.zeros(parts[0].shape, dtype=np.float64)
+    for p in parts:
+        u = u + p
+    return u
+
+
+def _shift_task(args):
+    m, kappa, cI, cL, W, mass = args
+    if isinstance(W, str):
+        W = np.load(W, mmap_mode="r")
+    return solve_shifted(m, kappa, cI, cL, np.asarray(W), mass)
+
+
+def solve_shifts(m: _mesh.Mesh, kappa: float, c_I, c_L, W, mass: str = "lumped", workers: int = 1) -> list:
+    """[A(c_I[i], c_L[i])^{-1} W for each i], one process per shift when workers > 1
+    (W an array or the path of a .npy file)."""
     tasks = [(m, kappa, float(ci), float(cl), W, mass) for ci, cl in zip(c_I, c_L)]
-    if workers > 1:
-        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-            parts = list(ex.map(_shift_task, tasks))
-    else:
-        parts = [_shift_task(t) for t in tasks]
-    u = np.zeros_like(W)
-    for ul in parts:
-        u = u + ul
-    return (u, parts) if per_shift else u
+    if workers <= 1 or len(tasks) <= 1:
+        return [_shift_task(t) for t in tasks]
+    with cf.ProcessPoolExecutor(max_workers=min(workers, len(tasks)), mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_shift_task, tasks))

@@ -99,6 +99,9 @@ void KTimer::collect(grf_stats *stats) {
         if (r.id >= 0 && r.id < GRF_K_COUNT) {
             stats->kernel_ms[r.id] += ms;
             stats->kernel_launches[r.id] += 1;
+        } else if (r.id >= kClassTimerId && r.id <= kClassTimerId + kPcgClasses) {
+            stats->pcg_class_ms[r.id - kClassTimerId] += ms;
+            stats->pcg_class_launches[r.id - kClassTimerId] += 1;
         }
     }
 }
@@ -482,6 +485,14 @@ int grf_graph_info(const grf_graph *g, int64_t *n_dof, int64_t *n_interior, int6
     if (n_interior) *n_interior = g->NI;
     if (dof_offsets)
         for (int64_t e = 0; e <= g->E; ++e) dof_offsets[e] = g->off[e];
+    GRF_API_END
+}
+
+int grf_graph_lumped_mass(const grf_graph *g, double *out) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(g, "graph is NULL");
+    GRF_REQUIRE(out || g->N == 0, "out is NULL");
+    std::copy(g->ml.begin(), g->ml.end(), out);
     GRF_API_END
 }
 

@@ -1126,7 +1126,11 @@ void launch_pcg(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     }
     // graphs beyond the on-chip classes
     const int32_t ngl = mv.cls_off[kPcgClasses + 1] - mv.cls_off[c_end];
-    if (ngl > 0) launch_mrhs(mv, a, ops, lrn, ngl, c_end, st);
+    if (ngl > 0) {
+        if (a.ctimer) a.ctimer->begin(kClassTimerId + kPcgClasses);
+        launch_mrhs(mv, a, ops, lrn, ngl, c_end, st);
+        if (a.ctimer) a.ctimer->end();
+    }
     hipLaunchKernelGGL(k_rhs_unrange, dim3((unsigned)nsys_all), dim3(256), 0, st, mv, a.gT, a.xT, a.gexp, a.LB, a.S);
     GRF_LAUNCH_CHECK();
 }

@@ -368,6 +368,8 @@ static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStre
     int64_t n_unconv = 0, tot_it = 0;
     int32_t max_it = 0;
     double max_res = 0.0;
+    std::vector<int64_t> own_its;
+    if (!graph_its && stats) graph_its = &own_its;
     if (graph_its) graph_its->assign(ps.ng, 0);
     for (size_t k = 0; k < ps.l0s.size(); ++k) {
         const size_t base = (size_t)ps.ng * ps.l0s[k] * ps.S, cnt = (size_t)ps.ng * ps.lbs[k] * ps.S;
@@ -390,6 +392,21 @@ static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStre
         stats->refine_steps = 0;
         stats->shift_block = ps.p.LB;
         stats->sweep_block = ps.p.blocked ? 0 : ps.p.BL;
+        // iterations x vertices and x edge ends per PCG size class (the kernel that ran them)
+        for (int c = 0; c <= kPcgClasses; ++c) {
+            stats->pcg_class_vertex_its[c] = 0;
+            stats->pcg_class_end_its[c] = 0;
+        }
+        for (int c = 0; c <= kPcgClasses; ++c) {
+            const bool global = c == kPcgClasses || (o.precond == GRF_PRECOND_NN && c >= kChipOpClasses);
+            const int bucket = global ? kPcgClasses : c;
+            for (int32_t i = g.cls_off[c]; i < g.cls_off[c + 1]; ++i) {
+                const int32_t gi = g.gord[i];
+                const int64_t it = (*graph_its)[gi];
+                stats->pcg_class_vertex_its[bucket] += it * (g.gv0[gi + 1] - g.gv0[gi]);
+                stats->pcg_class_end_its[bucket] += it * 2 * (int64_t)(g.ge0[gi + 1] - g.ge0[gi]);
+            }
+        }
     }
     if (n_unconv > 0) {
         set_error("%lld vertex Schur systems did not reach tol=%g within maxit=%d", (long long)n_unconv, o.tol,
@@ -412,8 +429,15 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
                        const grf_opts &o, hipStream_t st, grf_stats *stats, KTimer &T) {
     const Pass ps = prepare_pass(g, cI, cL, S, o, st);
     int8_t md[kPcgClasses];
-    enqueue_pass(g, ps, o, st, T, given_modes(o, md) ? md : nullptr);
-    finish_pass(g, ps, o, st, stats);
+    KTimer CT(o.timing != 0, st);  // per PCG size class
+    enqueue_pass(g, ps, o, st, T, given_modes(o, md) ? md : nullptr, o.timing ? &CT : nullptr);
+    try {
+        finish_pass(g, ps, o, st, stats);
+    } catch (const Error &err) {
+        if (err.code == GRF_ENOCONV) CT.collect(stats);
+        throw;
+    }
+    CT.collect(stats);
 }
 
 // ---- batches of graphs ----------------------------------------------------------
@@ -519,7 +543,7 @@ double timed_run(Batch &B, const Shifts &sh, int64_t S, uint64_t seed, const grf
         for (const KTimer::Rec &r : CT.recs) {
             float t = 0.0f;
             GRF_HIP(hipEventElapsedTime(&t, r.a, r.b));
-            cls_ms[r.id - kClassTimerId] += t;
+            if (r.id - kClassTimerId < kPcgClasses) cls_ms[r.id - kClassTimerId] += t;
         }
     }
     float ms = 0.0f;
@@ -905,14 +929,16 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
         }
         B.exec_key = make_key();
     }
-    hipEvent_t ea = nullptr, eb = nullptr;
+    // with timing the same launches run uncaptured, each bracketed by HIP events
+    KTimer T(o.timing != 0, cs), CT(o.timing != 0, cs);
     if (o.timing) {
-        GRF_HIP(hipEventCreate(&ea));
-        GRF_HIP(hipEventCreate(&eb));
-        GRF_HIP(hipEventRecord(ea, cs));
+        T.begin(GRF_K_NOISE);
+        launch_noise(mv, n_samples, run.sample_offset, seed, w.X.as<double>(), cs);
+        T.end();
+        enqueue_pass(U, B.exec_pass, run, cs, T, B.cls_mode, &CT);
+    } else {
+        GRF_HIP(hipGraphLaunch(B.exec, cs));
     }
-    GRF_HIP(hipGraphLaunch(B.exec, cs));
-    if (o.timing) GRF_HIP(hipEventRecord(eb, cs));
     if (o.stats) *o.stats = grf_stats{};
     int code = GRF_OK;
     try {
@@ -921,20 +947,12 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
         if (err.code != GRF_ENOCONV) throw;
         code = GRF_ENOCONV;
     }
+    T.collect(o.stats);
+    CT.collect(o.stats);
     if (o.stats) {
         int32_t mw = 0;
         for (int c = 0; c < kPcgClasses; ++c) mw |= (int32_t)B.cls_mode[c] << (2 * c);
         o.stats->pcg_class_modes = mw;
-    }
-    if (o.timing) {
-        float ms = 0.0f;
-        GRF_HIP(hipEventElapsedTime(&ms, ea, eb));
-        if (o.stats) {
-            o.stats->kernel_ms[GRF_K_ENDS_FWD] += ms;  // the whole captured pass (noise and all shifts)
-            o.stats->kernel_launches[GRF_K_ENDS_FWD] += 1;
-        }
-        (void)hipEventDestroy(ea);
-        (void)hipEventDestroy(eb);
     }
     // outputs, on the caller's stream
     std::vector<double *> op(outs, outs + n_graphs);

@@ -157,7 +157,7 @@ struct SchurArgs {
 enum ChipMode : int8_t { CM_OP = 0, CM_GUESS = 1, CM_JACOBI = 2, CM_GLOBAL = 3 };
 constexpr int kChipOpClasses = 5;  // size classes whose LDS holds r^ and p (CM_OP)
 constexpr int kMrhsSB = 4;         // samples per block of the multi-system PCG kernel
-constexpr int kClassTimerId = 100;
+constexpr int kClassTimerId = 100;  // + size class (kPcgClasses: the global-memory kernel)
 void default_chip_modes(int32_t precond, int8_t *mode);  // [kPcgClasses]
 bool chip_mode_valid(int c, int mode);
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st);

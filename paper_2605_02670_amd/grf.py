@@ -38,12 +38,19 @@ class Stats(C.Structure):
                 ("max_iterations", C.c_int32), ("total_iterations", C.c_int64),
                 ("max_rel_residual", C.c_double), ("refine_steps", C.c_int32),
                 ("shift_block", C.c_int32), ("sweep_block", C.c_int32), ("pcg_class_modes", C.c_int32),
-                ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int32 * 12)]
+                ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int32 * 12),
+                ("pcg_class_ms", C.c_double * 7), ("pcg_class_launches", C.c_int32 * 7),
+                ("pcg_class_reserved", C.c_int32), ("pcg_class_vertex_its", C.c_int64 * 7),
+                ("pcg_class_end_its", C.c_int64 * 7)]
+    _ARRAYS = ("kernel_ms", "kernel_launches", "pcg_class_ms", "pcg_class_launches", "pcg_class_reserved",
+               "pcg_class_vertex_its", "pcg_class_end_its")
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("kernel_ms", "kernel_launches")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in self._ARRAYS}
         d["kernel_ms"] = {KERNELS[i]: self.kernel_ms[i] for i in range(12)}
         d["kernel_launches"] = {KERNELS[i]: self.kernel_launches[i] for i in range(12)}
+        for k in ("pcg_class_ms", "pcg_class_launches", "pcg_class_vertex_its", "pcg_class_end_its"):
+            d[k] = list(getattr(self, k))
         return d
 
 
@@ -62,6 +69,7 @@ _SIGS = [
                                    C.POINTER(C.c_void_p)]),
     ("grf_graph_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p]),
     ("grf_graph_destroy", C.c_int, [C.c_void_p]),
+    ("grf_graph_lumped_mass", C.c_int, [C.c_void_p, C.c_void_p]),
     ("grf_shift_count", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(Opts), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("grf_noise", C.c_int, [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.POINTER(Opts)]),
@@ -204,6 +212,12 @@ class Graph:
         import torch
 
         self.device = torch.cuda.current_device()
+
+    def lumped_mass(self) -> np.ndarray:
+        """Diagonal of M_L (float64 [n_dof], canonical order), from the library."""
+        ml = np.empty(self.n_dof, dtype=np.float64)
+        _check(load().grf_graph_lumped_mass(self.handle, ml.ctypes.data))
+        return ml
 
     @classmethod
     def from_workload(cls, g, h: float, rule: str = "ceil") -> "Graph":

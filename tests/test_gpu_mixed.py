@@ -7,7 +7,8 @@ Bars (lumped-mass norm, max over right-hand sides / samples):
     the throughput metric counts a result;
   * one shifted system (grf_solve_shifted) after two refinement steps: within
     1e-10 relative of the oracle at every shift of a span e^{2y} in [1e-8, 1e8],
-    each shift's error reported.
+    each shift's error reported; without refinement (the edge arithmetic of the
+    sampled path, per shift) within 1e-6.
 """
 
 import numpy as np
@@ -22,12 +23,20 @@ from workloads import config_c1, lattice, preferential_attachment
 pytestmark = pytest.mark.gpu
 SUM_TOL = 1e-6
 REFINED_TOL = 1e-10
+# one shift with FP32 edge sweeps and no refinement (the per-shift arithmetic of the
+# sampled mixed path): FP32 unit roundoff 6e-8 times a small factor; measured at most
+# 1.9e-7 over e^{2y} in [1e-8, 1e8], on this lattice and on the full 256x256 one
+UNREFINED_TOL = 1e-6
 
 
 def _rel_ml(u, ref, ML):
+    """Worst sample's relative error, the larger of the lumped-mass norm
+    ||u - ref||_{M_L} / ||ref||_{M_L} and the element-wise max |u - ref| / max |ref|
+    (a local error that the norm would dilute fails the second)."""
     num = np.sqrt(((u - ref) ** 2 * ML).sum(axis=-1))
     den = np.sqrt((ref ** 2 * ML).sum(axis=-1))
-    return float(np.max(num / den))
+    el = np.abs(u - ref).max(axis=-1) / np.abs(ref).max(axis=-1)
+    return float(max(np.max(num / den), np.max(el)))
 
 
 def test_mixed_sample_c1(grf):
@@ -85,7 +94,7 @@ def test_mixed_solve_refined_per_shift(grf):
         report.append((int(ls[i]), e0, e2, st["max_rel_residual"]))
         assert st["refine_steps"] == 2
         assert e2 <= REFINED_TOL, f"shift l={ls[i]}: refined error {e2:.3e}"
-        assert e0 <= 1e-4, f"shift l={ls[i]}: unrefined FP32-sweep error {e0:.3e}"
+        assert e0 <= UNREFINED_TOL, f"shift l={ls[i]}: unrefined FP32-sweep error {e0:.3e}"
     for l, e0, e2, r in report:
         print(f"l={l:+d} e^2y={np.exp(2 * l * k):.1e}: FP32 sweeps {e0:.2e}, refined x2 {e2:.2e}, residual {r:.1e}")
 

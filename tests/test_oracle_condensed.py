@@ -43,8 +43,9 @@ def test_condensed_sample_c1_serial_and_parallel():
     ref = solve.sample(m, cfg["kappa"], cfg["beta"], cfg["quad_step"], W)
     u1 = condensed.sample(m, cfg["kappa"], cfg["beta"], cfg["quad_step"], W)
     u2 = condensed.sample(m, cfg["kappa"], cfg["beta"], cfg["quad_step"], W, workers=2)
-    assert np.array_equal(u1, u2)  # the shift sum is taken in the same order
+    assert np.abs(u1 - u2).max() <= 1e-15 * np.abs(u1).max() * 55  # the same terms, grouped by piece
     assert np.abs(u1 - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(u2 - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_condensed_lattice_with_random_lengths():
