@@ -134,6 +134,16 @@ struct MeshView {
     // row r; pell[j][r] ([4][V]): graph-local row of the j-th ELL neighbour of row r's
     // vertex (its own past the degree); padj[k] ([2E]): graph-local row of adj_o[k]
     const int32_t *prow, *pvtx, *pell, *padj;
+    // edge-end slots past the first four (degree > 4) of the graphs of an on-chip class,
+    // for products that spread them over a whole workgroup: each such vertex's slots are
+    // cut into pieces of at most 64, the pieces packed into chunks of 64 entries (a piece
+    // never crosses a chunk; unused entries have piece -1).  Graph g's entries are
+    // ovent[ovent0[g] .. ovent0[g+1]-1], (CSR slot k, graph-local piece, graph-local row
+    // of the vertex, graph-local neighbour), its pieces number ovnp[g]; ovpc[u] = (first
+    // piece, end) of vertex u, (0, 0) for a vertex of degree <= 4.
+    const int4 *ovent;
+    const int32_t *ovent0, *ovnp;
+    const int2 *ovpc;
 };
 
 }  // namespace grf
@@ -162,6 +172,7 @@ struct grf_graph {
     std::vector<int32_t> gord;
     int32_t cls_off[grf::kPcgClasses + 2] = {};
     grf::DevBuf d_gord, d_ell16, d_ovfm, d_prow, d_pvtx, d_pell, d_padj;
+    grf::DevBuf d_ovent, d_ovent0, d_ovnp, d_ovpc;
     double kap2_loaded = -1.0;
     // workspace, grown on demand
     struct Work;

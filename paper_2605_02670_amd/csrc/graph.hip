@@ -270,6 +270,42 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     upload(g.d_ell16, e16, s);
     upload(g.d_ovfm, om, s);
+    // overflow slots as pieces of at most 64 packed into chunks of 64 entries (MeshView::ovent)
+    {
+        std::vector<int32_t> ent, ent0(ng + 1, 0), np(ng, 0), pc(2 * (size_t)g.V, 0);
+        for (int64_t k = 0; k < ng; ++k) {
+            ent0[k] = (int32_t)(ent.size() / 4);
+            if (cls[k] >= kPcgClasses) continue;
+            const int32_t u0 = g.gv0[k], nv = g.gv0[k + 1] - u0;
+            int32_t piece = 0, fill = 0;  // entries used in the current chunk
+            for (int32_t v = 0; v < nv; ++v) {
+                const int64_t u = u0 + v;
+                if (deg[u] <= 4) continue;
+                const int64_t q0 = g.vptr[u] + 4, q1 = g.vptr[u + 1];
+                pc[2 * u] = piece;
+                for (int64_t a = q0; a < q1; a += 64) {
+                    const int32_t len = (int32_t)std::min<int64_t>(64, q1 - a);
+                    if (fill + len > 64) {  // pad the chunk
+                        for (; fill < 64; ++fill) ent.insert(ent.end(), {0, -1, 0, 0});
+                        fill = 0;
+                    }
+                    for (int64_t q = a; q < a + len; ++q)
+                        ent.insert(ent.end(), {(int32_t)q, piece, v, g.adj_o[q] - u0});
+                    fill = (fill + len) % 64;
+                    ++piece;
+                }
+                pc[2 * u + 1] = piece;
+            }
+            for (; fill > 0 && fill < 64; ++fill) ent.insert(ent.end(), {0, -1, 0, 0});
+            np[k] = piece;
+        }
+        ent0[ng] = (int32_t)(ent.size() / 4);
+        ent.insert(ent.end(), {0, -1, 0, 0});  // never empty
+        upload(g.d_ovent, ent, s);
+        upload(g.d_ovent0, ent0, s);
+        upload(g.d_ovnp, np, s);
+        upload(g.d_ovpc, pc, s);
+    }
     // vertex PCG row order: reverse Cuthill-McKee for the graphs beyond every on-chip
     // class (their neighbour gathers then stay close in memory), vertex order otherwise
     std::vector<int32_t> prow(g.V), pvtx(g.V), pell(4 * (size_t)g.V), padj(g.adj_o.size());
@@ -418,6 +454,10 @@ grf::MeshView grf_graph::view() const {
     v.gord = d_gord.as<int32_t>();
     v.ell16 = d_ell16.as<uint2>();
     v.ovfm = d_ovfm.as<uint32_t>();
+    v.ovent = d_ovent.as<int4>();
+    v.ovent0 = d_ovent0.as<int32_t>();
+    v.ovnp = d_ovnp.as<int32_t>();
+    v.ovpc = d_ovpc.as<int2>();
     v.prow = d_prow.as<int32_t>();
     v.pvtx = d_pvtx.as<int32_t>();
     v.pell = d_pell.as<int32_t>();

@@ -601,6 +601,50 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
     }
 }
 
+// The slots past the first four of graph gi's vertices of degree > 4 (MeshView::ovent)
+// applied to y (graph-local, in LDS) with the coefficients cf (CSR slot order), spread
+// over the whole workgroup: wavefront w takes chunks w, w + NW, ... of 64 entries, lane
+// j entry j.  The lanes of one piece sum their products in a fixed order (a segmented
+// inclusive scan over the lanes, pieces being contiguous), and the last lane of the
+// piece stores the sum in psum[piece] (LDS), so the result does not depend on timing.
+// With DOT each lane also adds y[row] * cf * y[nb] to dot: the overflow part of
+// y . (Op y), which then needs no second pass.  The owner of a vertex adds its pieces
+// (ovf_add) once the workgroup has passed a barrier.
+template <int TPB, bool DOT>
+__device__ __forceinline__ void ovf_pieces(const MeshView &mv, int gi, const double *__restrict__ cf, const double *y,
+                                           double *psum, double &dot) {
+    constexpr int NW = TPB / 64;
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const int e0 = mv.ovent0[gi];
+    const int nch = (mv.ovent0[gi + 1] - e0) >> 6;
+    for (int c = w; c < nch; c += NW) {
+        const int4 en = mv.ovent[e0 + 64 * c + lane];  // (slot, piece, row, neighbour)
+        double v = en.y >= 0 ? cf[en.x] * y[en.w] : 0.0;
+        if (DOT) dot += y[en.z] * v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double t = __shfl_up(v, o, 64);
+            const int pt = __shfl_up(en.y, o, 64);
+            if (lane >= o && pt == en.y) v += t;
+        }
+        const int pn = __shfl_down(en.y, 1, 64);
+        if (en.y >= 0 && (lane == 63 || pn != en.y)) psum[en.y] = v;
+    }
+}
+
+// out[i0 + g] += the pieces of the G items of a group (a vertex of degree <= 4 has none)
+template <int G, int K>
+__device__ __forceinline__ void ovf_add(const MeshView &mv, const double *psum, const int (&vc)[G],
+                                        const bool (&ok)[G], int u0, double (&out)[K], int i0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int2 pc = mv.ovpc[u0 + vc[g]];
+        double a = 0.0;
+        for (int p = pc.x; p < pc.y; ++p) a += psum[p];
+        if (ok[g]) out[i0 + g] += a;
+    }
+}
+
 // The same solve with the search direction p in LDS, for the graphs glist[0 ..
 // ngl-1] of at most cap <= TPB K vertices: one workgroup per (graph, shift,
 // sample) system, thread t owning the graph-local vertices t + TPB i (i < K),
@@ -621,7 +665,8 @@ __device__ __forceinline__ void ell_group(const MeshView &mv, const double *__re
 template <int TPB, int K, bool LRN, bool XG, bool XP>
 __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp Pop, EllOp Qop,
                                                   const int32_t *__restrict__ glist, int32_t ngl, int32_t cap,
-                                                  const double *__restrict__ gT, double *__restrict__ xT,
+                                                  int32_t ldsd, const double *__restrict__ gT,
+                                                  double *__restrict__ xT,
                                                   int32_t *__restrict__ its,
                                                   double *__restrict__ res, int32_t LB, int64_t S, double tol,
                                                   int32_t maxit) {
@@ -650,7 +695,14 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     const double *Pc = LRN ? Pop.coef + (int64_t)l * 4 * mv.V : nullptr;
     const double *Po = LRN ? Pop.ovf + (int64_t)l * E2 : nullptr;
     double *ps = sv, *rs = sv + cap;
-    const uint32_t om = mv.ovfm[16 * (int64_t)gi + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
+    const uint32_t om_all = mv.ovfm[16 * (int64_t)gi + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))];
+    // Jacobi-preconditioned iterations spread the overflow slots of the S^ products over
+    // the workgroup (ovf_pieces) when the piece sums fit in LDS past p; otherwise (and for
+    // every P^ and Q^ product) the owner of a vertex adds its own overflow slots
+    const int npc = LP ? 0 : mv.ovnp[gi];
+    const bool dov = npc > 0 && nv + npc <= ldsd;
+    const uint32_t om = dov ? 0u : om_all;
+    double *psum = ps + nv;
     GroupSum<TPB> gsum{red, 0};
     double x[XG ? 1 : K], r[K], q[K];
 
@@ -674,12 +726,18 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
         }
         __syncthreads();  // x^ in LDS
         double t[3] = {0.0, 0.0, 0.0};
+        if (dov) {  // the overflow pieces of S^ x^, complete for every owner below
+            double unused = 0.0;
+            ovf_pieces<TPB, false>(mv, gi, So, ps, psum, unused);
+            __syncthreads();
+        }
 #pragma unroll
         for (int i0 = 0; i0 < K; i0 += G) {
             if (!group_live<TPB>(i0, nv)) continue;
             const IG it(i0, nv);
             double sx[G];
             ell_group<G, true>(mv, nullptr, Sc, So, ps, it.vc, it.ok, u0, om, i0, sx);
+            if (dov && ((om_all >> i0) & 1u)) ovf_add<G, G>(mv, psum, it.vc, it.ok, u0, sx, 0);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const double h = H[it.vc[e]];
@@ -762,7 +820,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 const IG it(i0, nv);
                 double xq[G];
                 ell_group<G, false>(mv, Qop.diag + (int64_t)l * mv.V, Qop.coef + (int64_t)l * 4 * mv.V,
-                                    Qop.ovf + (int64_t)l * E2, ps, it.vc, it.ok, u0, om, i0, xq);
+                                    Qop.ovf + (int64_t)l * E2, ps, it.vc, it.ok, u0, om_all, i0, xq);
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     if constexpr (XG) {
@@ -807,6 +865,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             ++it_n;
             __syncthreads();  // p complete
             double t1[1] = {0.0};
+            if (dov) ovf_pieces<TPB, true>(mv, gi, So, ps, psum, t1[0]);  // before q is live
 #pragma unroll
             for (int i0 = 0; i0 < K; i0 += G) {
                 if (!group_live<TPB>(i0, nv)) continue;
@@ -819,7 +878,15 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                     t1[0] += ps[it.vc[e]] * sp[e];
                 }
             }
-            gsum(t1);
+            gsum(t1);  // also: the piece sums complete
+            if (dov) {
+#pragma unroll
+                for (int i0 = 0; i0 < K; i0 += G) {
+                    if (!group_live<TPB>(i0, nv) || !((om_all >> i0) & 1u)) continue;
+                    const IG it(i0, nv);
+                    ovf_add<G, K>(mv, psum, it.vc, it.ok, u0, q, i0);
+                }
+            }
             const double alpha = rz / t1[0];
             double t3[1] = {0.0};  // ||r^||^2 (= r^.z^ for Jacobi)
 #pragma unroll
@@ -1018,7 +1085,13 @@ static void chip_launch(const MeshView &mv, const SchurArgs *a, const EllOp *ops
     constexpr int TPB = kChipTpb[C], K = kChipK[C];
     static_assert(TPB * K >= kPcgCap[C], "class capacity");
     constexpr bool XG = K > 10;
-    constexpr size_t lds = (size_t)kPcgCap[C] * sizeof(double) * (LRN && !XP ? 2 : 1);
+    // p (and r^ with the operator preconditioner); past p, the overflow piece sums of the
+    // Jacobi-preconditioned variants (room for half the capacity; the largest class uses
+    // what its graph leaves of p's capacity)
+    constexpr bool LP = LRN && !XP;
+    constexpr int32_t ldsd = kPcgCap[C] * (LP ? 2 : 1) + (LP || C == kPcgClasses - 1 ? 0 : kPcgCap[C] / 2);
+    constexpr size_t lds = (size_t)ldsd * sizeof(double);
+    static_assert(lds + 1024 <= 160 * 1024, "LDS of the class");
     if (!a) {  // preparation: the dynamic LDS of the variant (not a stream operation)
         GRF_HIP(hipFuncSetAttribute((const void *)k_pcg_chip<TPB, K, LRN, XG, XP>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1029,8 +1102,8 @@ static void chip_launch(const MeshView &mv, const SchurArgs *a, const EllOp *ops
     const int64_t blocks = (groups + 7) / 8 * 8 * a->S;
     GRF_REQUIRE(blocks < ((int64_t)1 << 31), "too many systems in one shift block");
     hipLaunchKernelGGL((k_pcg_chip<TPB, K, LRN, XG, XP>), dim3((unsigned)blocks), dim3(TPB), lds, st, mv, ops[0],
-                       ops[1], ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], a->gT, a->xT, a->its, a->res, a->LB,
-                       a->S, a->tol, a->maxit);
+                       ops[1], ops[2], mv.gord + mv.cls_off[C], n, kPcgCap[C], ldsd, a->gT, a->xT, a->its, a->res,
+                       a->LB, a->S, a->tol, a->maxit);
     GRF_LAUNCH_CHECK();
 }
 
