@@ -80,9 +80,22 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int v = v0 + vb + 4 * q;
-                if (v < mv.V && mv.deg[vc[q]] > 4)
-                    for (int64_t k = mv.vptr[v] + 4; k < mv.vptr[v + 1]; ++k)
-                        g[q] += el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
+                if (v < mv.V && mv.deg[vc[q]] > 4) {
+                    // the loads of eight slots in flight together, added in slot order
+                    int64_t k = mv.vptr[v] + 4;
+                    const int64_t ke = mv.vptr[v + 1];
+                    for (; k + 8 <= ke; k += 8) {
+                        int id[8];
+                        double ev[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) id[j] = 2 * mv.adj_e[k + j] + mv.adj_s[k + j];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) ev[j] = el[(int64_t)id[j] * Sp];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) g[q] += ev[j];
+                    }
+                    for (; k < ke; ++k) g[q] += el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
+                }
             }
         }
 #pragma unroll
