@@ -373,9 +373,9 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
 __device__ __forceinline__ void stage_direct_bytes(const char *src1, int n1b, const char *src2, char *dst, int nbytes) {
     const int nv = nbytes / 16;
     const int w = wave_id(), lane = (int)threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < (nv + 255) / 256; ++k) {
-        const int v0 = 256 * k + 64 * w;  // first vector of this wavefront's load
+    const int T = (int)blockDim.x;  // 64, 128 or 256 threads
+    for (int k = 0; k < (nv + T - 1) / T; ++k) {
+        const int v0 = T * k + 64 * w;  // first vector of this wavefront's load
         const int i = v0 + lane;
         if (i < nv) {  // lanes past the table write nothing
             const int d = 16 * i;
@@ -416,9 +416,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int L = threadIdx.x & 63;
     const int wv = wave_id();
     const int64_t wg = xcd_logical_block();
+    // nb: workgroups per edge; a workgroup of nw wavefronts covers 16 nw samples, wavefront
+    // wv the 16 samples of group g (64-sample block b of the layout, quarter g & 3)
+    const int nw = (int)(blockDim.x >> 6);
     const int e = (int)(wg / nb);
-    const int b = (int)(wg - (int64_t)e * nb);
-    const int g = 4 * b + wv;
+    const int g = nw * (int)(wg - (int64_t)e * nb) + wv;
+    const int b = g >> 2;
     const int s0 = 16 * g;
     const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
@@ -565,9 +568,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int L = threadIdx.x & 63;
     const int wv = wave_id();
     const int64_t wg = xcd_logical_block();
+    // nb: workgroups per edge; a workgroup of nw wavefronts covers 16 nw samples, wavefront
+    // wv the 16 samples of group g (64-sample block b of the layout, quarter g & 3)
+    const int nw = (int)(blockDim.x >> 6);
     const int e = (int)(wg / nb);
-    const int b = (int)(wg - (int64_t)e * nb);
-    const int g = 4 * b + wv;
+    const int g = nw * (int)(wg - (int64_t)e * nb) + wv;
+    const int b = g >> 2;
     const int s0 = 16 * g;
     const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
@@ -660,9 +666,12 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
     const int L = threadIdx.x & 63;
     const int wv = wave_id();
     const int64_t wg = xcd_logical_block();
+    // nb: workgroups per edge; a workgroup of nw wavefronts covers 16 nw samples, wavefront
+    // wv the 16 samples of group g (64-sample block b of the layout, quarter g & 3)
+    const int nw = (int)(blockDim.x >> 6);
     const int e = (int)(wg / nb);
-    const int b = (int)(wg - (int64_t)e * nb);
-    const int g = 4 * b + wv;
+    const int g = nw * (int)(wg - (int64_t)e * nb) + wv;
+    const int b = g >> 2;
     const int s0 = 16 * g;
     const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
@@ -796,9 +805,12 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
     const int L = threadIdx.x & 63;
     const int wv = wave_id();
     const int64_t wg = xcd_logical_block();
+    // nb: workgroups per edge; a workgroup of nw wavefronts covers 16 nw samples, wavefront
+    // wv the 16 samples of group g (64-sample block b of the layout, quarter g & 3)
+    const int nw = (int)(blockDim.x >> 6);
     const int e = (int)(wg / nb);
-    const int b = (int)(wg - (int64_t)e * nb);
-    const int g = 4 * b + wv;
+    const int g = nw * (int)(wg - (int64_t)e * nb) + wv;
+    const int b = g >> 2;
     const int s0 = 16 * g;
     const bool live = s0 < S;  // a wavefront of padding samples only stages operands
     const int n = L & 15, kq = L >> 4;
@@ -873,39 +885,51 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
     }
 }
 
+// Wavefronts per workgroup of the sweeps: 16 samples each, so that a call with
+// few samples has no wavefronts that only stage operands (32 samples: two per
+// workgroup, and more workgroups per compute unit); nb of the kernels is then the
+// number of workgroups per edge.
+static int sweep_waves(int64_t S) { return S > 32 ? 4 : (S > 16 ? 2 : 1); }
+static int32_t sweep_groups(int64_t S) {
+    const int nw = sweep_waves(S);
+    return (int32_t)((S + 16 * nw - 1) / (16 * nw));
+}
+
 template <int NT>
 void sweep_nt(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
-    dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
+    const int32_t wpe = sweep_groups(a.S);
+    const dim3 grid((unsigned)(mv.E * (int64_t)wpe)), block((unsigned)(64 * sweep_waves(a.S)));
     if (a.mixed) {
         if (fwd)
-            hipLaunchKernelGGL((k_sweep_blocked32<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                               a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first, a.S);
+            hipLaunchKernelGGL((k_sweep_blocked32<NT, true>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
+                               wpe, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first, a.S);
         else
-            hipLaunchKernelGGL((k_sweep_blocked32<NT, false>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E,
-                               mv.N, a.nb, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, 0, a.S);
+            hipLaunchKernelGGL((k_sweep_blocked32<NT, false>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E,
+                               mv.N, wpe, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, 0, a.S);
         GRF_LAUNCH_CHECK();
         return;
     }
     if (fwd)
-        hipLaunchKernelGGL((k_sweep_blocked<NT, true>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);
+        hipLaunchKernelGGL((k_sweep_blocked<NT, true>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
+                           wpe, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);
     else
-        hipLaunchKernelGGL((k_sweep_blocked<NT, false>), grid, dim3(256), 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           a.nb, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, 0, a.S);
+        hipLaunchKernelGGL((k_sweep_blocked<NT, false>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
+                           wpe, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, 0, a.S);
     GRF_LAUNCH_CHECK();
 }
 
 template <int NT>
 void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
-    dim3 grid((unsigned)(mv.E * (int64_t)a.nb));
+    const int32_t wpe = sweep_groups(a.S);
+    const dim3 grid((unsigned)(mv.E * (int64_t)wpe)), block((unsigned)(64 * sweep_waves(a.S)));
     if (a.mixed) {
-        hipLaunchKernelGGL((k_corr_blocked32<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E,
-                           mv.V, mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug, a.U, a.S);
+        hipLaunchKernelGGL((k_corr_blocked32<NT>), grid, block, 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E,
+                           mv.V, mv.N, wpe, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug, a.U, a.S);
         GRF_LAUNCH_CHECK();
         return;
     }
-    hipLaunchKernelGGL((k_corr_blocked<NT>), grid, dim3(256), 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E, mv.V,
-                       mv.N, a.nb, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U, a.S);
+    hipLaunchKernelGGL((k_corr_blocked<NT>), grid, block, 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E, mv.V,
+                       mv.N, wpe, a.Sp, a.LB, a.LBp, a.ztab, a.babs, a.ug, a.U, a.S);
     GRF_LAUNCH_CHECK();
 }
 
@@ -968,7 +992,7 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
 
 void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
     if (mv.E == 0 || a.LB == 0) return;
-    GRF_REQUIRE(mv.E * (int64_t)a.nb < (int64_t(1) << 31), "too many edge x sample-block workgroups");
+    GRF_REQUIRE(mv.E * (int64_t)sweep_groups(a.S) < (int64_t(1) << 31), "too many edge x sample-block workgroups");
 #define CALL_SWEEP(K) sweep_nt<K>(mv, a, fwd, st)
     GRF_NT_SWITCH(a.NT, CALL_SWEEP)
 #undef CALL_SWEEP
@@ -976,7 +1000,7 @@ void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipS
 
 void launch_corr_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (mv.E == 0 || a.LB == 0) return;
-    GRF_REQUIRE(mv.E * (int64_t)a.nb < (int64_t(1) << 31), "too many edge x sample-block workgroups");
+    GRF_REQUIRE(mv.E * (int64_t)sweep_groups(a.S) < (int64_t(1) << 31), "too many edge x sample-block workgroups");
 #define CALL_CORR(K) corr_nt<K>(mv, a, st)
     GRF_NT_SWITCH(a.NT, CALL_CORR)
 #undef CALL_CORR
