@@ -65,7 +65,10 @@ typedef enum grf_status {
 
 /* grf_opts.precision */
 #define GRF_PREC_FP64 0  /* every step in FP64 */
-#define GRF_PREC_MIXED 1 /* FP32 edge sweeps, FP64 Schur/PCG/residual/accumulation, refinement */
+#define GRF_PREC_MIXED 1 /* FP32 edge sweeps (products summed in FP32 within a tile of 16 shifts,
+                            tiles added in FP64), FP64 noise, Schur blocks, PCG, residual and
+                            accumulation; grf_solve_shifted refines against an FP64 residual
+                            (opts->refine), grf_sample rejects refine > 0 */
 
 /* grf_opts.pcg_class_modes: marks the per-class variants as given */
 #define GRF_PCG_MODES_SET (1 << 12)
@@ -133,7 +136,8 @@ typedef struct grf_opts {
     int32_t k_plus;        /*   K^- = ceil(pi^2/(4k^2 beta)), K^+ = ceil(pi^2/(4k^2(1-beta))) */
     int32_t shift_block;   /* shifts per pass; 0 = plan from a memory budget */
     int32_t sweep_block;   /* shifts per wavefront in the sweeps: 0 (auto), 8, 16, 32, 64 */
-    int32_t refine;        /* mixed precision: max refinement sweeps; < 0 = default (2) */
+    int32_t refine;        /* mixed precision, grf_solve_shifted: refinement sweeps; < 0 = default (2);
+                              the sampling calls accept only < 0 or 0 */
     int32_t timing;        /* 1: time every kernel with HIP events into stats->kernel_ms (grf_sample_batched
                               then runs its launches uncaptured, each timed) */
     int32_t pcg_class_modes; /* learned preconditioner only: 0 = automatic (grf_sample_batched times the

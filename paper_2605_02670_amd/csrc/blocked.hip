@@ -651,7 +651,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 }
 
 // Mixed precision (FP32 operand tables and matrix-core products, FP64 noise,
-// accumulator and end values).  Same structure as the FP64 kernels; the
+// accumulator and end values).  The products of each tile of 16 shifts are summed in
+// FP32 on the matrix cores, and the tiles are added in FP64, so the sum over the
+// quadrature shifts is FP64 (the position sum of Ghat R runs over one block's 16
+// positions, its shift sum is inside Ghat, formed in FP64).  Same structure as the
+// FP64 kernels; the
 // carried state Y[t] item r of lane L is shift 16t + 4 (L/16) + r and the
 // block output item r of lane L is position 4 (L/16) + r.
 template <int NT, bool FWD>
@@ -742,6 +746,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
             f4 F[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) F[c] = mfma32(G[c * 64 + L], R[c], f4{0.0f, 0.0f, 0.0f, 0.0f});
+            double A64[4] = {0.0, 0.0, 0.0, 0.0};
             if (beta > 0) {
                 float ha[NT][4];
 #pragma unroll
@@ -749,9 +754,13 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
 #pragma unroll
                     for (int r = 0; r < 4; ++r) ha[t][r] = H[(t * 4 + r) * 64 + L];
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
+                for (int t = 0; t < NT; ++t) {
+                    f4 P = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) F[r] = mfma32(ha[t][r], Y[t][r], F[r]);
+                    for (int r = 0; r < 4; ++r) P = mfma32(ha[t][r], Y[t][r], P);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) A64[i] += (double)P[i];
+                }
                 // reads LA tiles ahead of the products, as in the FP64 kernel
                 constexpr int LA = NT < 2 ? NT : 2;
                 __builtin_amdgcn_sched_group_barrier(0x100, 2 * LA, 0);
@@ -775,7 +784,7 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
                 const int p = 16 * beta + 4 * kq + r;
                 const int op = outpos(p);
                 const float f = (F[0][r] + F[1][r]) + (F[2][r] + F[3][r]);
-                if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + (double)f;
+                if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + ((double)f + A64[r]);
             }
         }
         if (more) stage_wait();
@@ -858,13 +867,18 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
                     zt[t][r] = Z[(t * 4 + r) * 64 + L];
                     zh[t][r] = Z[256 * NT + (t * 4 + r) * 64 + L];
                 }
+            double A64[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t) {
+                f4 P0 = f4{0.0f, 0.0f, 0.0f, 0.0f}, P1 = P0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    F[r & 1] = mfma32(zt[t][r], ct[t][r], F[r & 1]);
-                    F[2 + (r & 1)] = mfma32(zh[t][r], ch[t][r], F[2 + (r & 1)]);
+                    P0 = mfma32(zt[t][r], ct[t][r], P0);
+                    P1 = mfma32(zh[t][r], ch[t][r], P1);
                 }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) A64[i] += (double)(P0[i] + P1[i]);
+            }
             // reads LA tiles ahead of the products, as in the FP64 kernel
             constexpr int LA = NT < 2 ? NT : 2;
             __builtin_amdgcn_sched_group_barrier(0x100, 4 * LA, 0);
@@ -877,7 +891,7 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int pp = 16 * beta + 4 * kq + r;
-                if (pp < m) ub[(int64_t)pp * 64] = uo[r] + (double)((F[0][r] + F[1][r]) + (F[2][r] + F[3][r]));
+                if (pp < m) ub[(int64_t)pp * 64] = uo[r] + A64[r];
             }
         }
         if (more) stage_wait();

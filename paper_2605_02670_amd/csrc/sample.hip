@@ -621,6 +621,7 @@ int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64
     require_supported(*g, o);
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
+    GRF_REQUIRE(o.refine <= 0, "refinement (opts.refine > 0) applies to grf_solve_shifted only");
     hipStream_t st = (hipStream_t)o.stream;
     set_kappa2(*g, kappa, st);
     grf_graph::Work &w = work(*g);
@@ -788,6 +789,7 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     require_supported(*graphs[0], o);
     GRF_REQUIRE(o.precision == GRF_PREC_FP64 || o.sweep_block == 0,
                 "mixed precision runs with the blocked edge sweeps (sweep_block = 0)");
+    GRF_REQUIRE(o.refine <= 0, "refinement (opts.refine > 0) applies to grf_solve_shifted only");
     hipStream_t st = (hipStream_t)o.stream;
     Batch &B = *get_batch(graphs, n_graphs);
     grf_graph &U = B.U;

@@ -197,5 +197,5 @@ def test_c4_fp64_and_mixed_against_oracle(grf):
         ea, eb = _rel_ml(a, r, ML), _rel_ml(b, r, ML)
         print(f"  shift l={ls[i]:+d} (e^2y={np.exp(2 * ls[i] * cfg['quad_step']):.1e}): mixed unrefined {ea:.2e} "
               f"(element-wise {_elem(a, r):.2e}), refined {eb:.2e}")
-        assert ea <= 1e-6  # FP32 sweeps, one shift (measured <= 1.9e-7)
+        assert ea <= 1e-6  # FP32 sweeps, one shift (measured <= 2.1e-7)
         assert eb <= 1e-10

@@ -25,7 +25,7 @@ SUM_TOL = 1e-6
 REFINED_TOL = 1e-10
 # one shift with FP32 edge sweeps and no refinement (the per-shift arithmetic of the
 # sampled mixed path): FP32 unit roundoff 6e-8 times a small factor; measured at most
-# 1.9e-7 over e^{2y} in [1e-8, 1e8], on this lattice and on the full 256x256 one
+# 2.1e-7 over e^{2y} in [1e-8, 1e8], on this lattice and on the full 256x256 one
 UNREFINED_TOL = 1e-6
 
 
@@ -119,3 +119,10 @@ def test_mixed_rejects_streamed_sweeps(grf):
     with pytest.raises(grf.GrfError) as ei:
         G.sample(5.0, 0.75, 0.5, 2, 0, precision="mixed", sweep_block=16)
     assert ei.value.code == grf.GRF_EINVAL
+    # refinement is a property of single-shift solves; the sampling calls reject a request for it
+    with pytest.raises(grf.GrfError, match="refine") as ei:
+        G.sample(5.0, 0.75, 0.5, 2, 0, precision="mixed", refine=1)
+    assert ei.value.code == grf.GRF_EINVAL
+    with pytest.raises(grf.GrfError, match="refine"):
+        grf.sample_batched([G], [5.0], 0.75, 0.5, 2, 0, precision="mixed", refine=2)
+    G.sample(5.0, 0.75, 0.5, 2, 0, precision="mixed", refine=0)  # 0: accepted
