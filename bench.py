@@ -67,7 +67,8 @@ PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32_mfma": 157.3}
 EDGE_FLOPS = {"ends_fwd": 2.5, "ends_bwd": 2.5, "acc_fwd": 5.0}
 # Algorithmic HBM bytes of the streaming steps, per unit:
 #   noise    8 per (DOF, sample) written
-#   coeff    the Thomas rows of every (interior DOF, shift): 8 (FP64) or 4 (FP32 tables)
+#   coeff    32 per (edge, shift): |b|, rho_{m-1} and the Schur block (s_d, s_o) written
+#   table    the Thomas rows of every (interior DOF, shift): 8 (FP64) or 4 (FP32 tables)
 #   condense 16 per (edge, shift, sample) of end values read + 8 per (vertex, shift, sample) written
 #   scatter  24 per (vertex, shift, sample)
 #   layout   16 per (DOF, sample) (the output transpose)
@@ -80,9 +81,9 @@ PCG_FLOPS_PER_END, PCG_FLOPS_PER_VERTEX = 2.0, 11.0
 def _hip_kernels(mode: str) -> dict:
     if mode == "mixed":
         return {"ends_fwd": "k_sweep_blocked32<NT, true>", "ends_bwd": "k_sweep_blocked32<NT, false>",
-                "acc_fwd": "k_corr_blocked32<NT>", "coeff": "k_blocktab<float> + k_edge_coeff"}
+                "acc_fwd": "k_corr_blocked32<NT>", "table": "k_blocktab<float, PACK>"}
     return {"ends_fwd": "k_sweep_blocked<NT, true>", "ends_bwd": "k_sweep_blocked<NT, false>",
-            "acc_fwd": "k_corr_blocked<NT>", "coeff": "k_blocktab<double> + k_edge_coeff"}
+            "acc_fwd": "k_corr_blocked<NT>", "table": "k_blocktab<double, PACK>"}
 
 
 PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<256, 4>", "k_pcg_chip<512, 8>",
@@ -167,8 +168,9 @@ def roofline(st: dict, n_dof: int, n_interior: int, n_vertices: int, n_edges: in
             cands.append((ms[k], k, names[k], "mfma", w / nl[k], ms[k] / nl[k], "TFLOP/s", flops_peak,
                           f"{EDGE_FLOPS[k]} flops per (interior DOF, shift, sample)"))
     hb = {"noise": (8.0 * n_dof * S, "8 B per (DOF, sample)", "k_noise"),
-          "coeff": ((4.0 if mode == "mixed" else 8.0) * n_interior * L,
-                    f"{4 if mode == 'mixed' else 8} B per (interior DOF, shift)", names["coeff"]),
+          "coeff": (32.0 * n_edges * L, "32 B per (edge, shift)", "k_edge_coeff"),
+          "table": ((4.0 if mode == "mixed" else 8.0) * n_interior * L,
+                    f"{4 if mode == 'mixed' else 8} B per (interior DOF, shift) (the Thomas rows)", names["table"]),
           "condense": ((16.0 * n_edges + 8.0 * n_vertices) * L * S,
                        "16 B per (edge, shift, sample) + 8 B per (vertex, shift, sample)", "k_condense"),
           "scatter": (24.0 * n_vertices * L * S, "24 B per (vertex, shift, sample)", "k_vertex_scatter"),

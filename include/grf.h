@@ -85,7 +85,8 @@ typedef struct grf_learned grf_learned;
 /* Kernel classes of grf_stats.kernel_ms / kernel_launches. */
 enum grf_kernel_id {
     GRF_K_NOISE = 0,     /* lumped white noise */
-    GRF_K_COEFF = 1,     /* per-(shift, edge) Thomas rows and Schur blocks */
+    GRF_K_COEFF = 1,     /* per-(shift, edge) Thomas rows and Schur blocks (k_edge_coeff, or the
+                            streamed path's rows) */
     GRF_K_ENDS_FWD = 2,  /* condensed-rhs sweep, head ends */
     GRF_K_ENDS_BWD = 3,  /* condensed-rhs sweep, tail ends */
     GRF_K_CONDENSE = 4,  /* vertex right-hand sides */
@@ -96,7 +97,8 @@ enum grf_kernel_id {
     GRF_K_LAYOUT = 9,    /* layout changes and fills */
     GRF_K_MIXED = 10,    /* mixed-precision residual and refinement kernels */
     GRF_K_LEARNED = 11,  /* learned preconditioner */
-    GRF_K_COUNT = 12
+    GRF_K_TABLE = 12,    /* blocked sweeps: the per-(16-position block, shift) operand tables */
+    GRF_K_COUNT = 13
 };
 
 /* Solver statistics, filled when grf_opts.stats is non-NULL (host struct). */
@@ -113,8 +115,9 @@ typedef struct grf_stats {
     int32_t pcg_class_modes;    /* grf_sample_batched: on-chip PCG variant of size class c in bits 2c..2c+1
                                    (0 operator preconditioner, 1 learned initial guess only, 2 Jacobi,
                                    3 the class runs the global-memory kernel) */
-    double kernel_ms[12];       /* with opts.timing: summed HIP-event time per grf_kernel_id */
-    int32_t kernel_launches[12];/* with opts.timing: launches per grf_kernel_id */
+    double kernel_ms[16];       /* with opts.timing: summed HIP-event time per grf_kernel_id
+                                   (entries from GRF_K_COUNT on stay 0) */
+    int32_t kernel_launches[16];/* with opts.timing: launches per grf_kernel_id */
     /* Vertex PCG by graph size class c (vertex capacities 64, 256, 1024, 4096,
        10176, 20352 for c = 0..5; c = 6: the graphs that run the global-memory
        kernel, including a class the preconditioner sends there).  One launch per

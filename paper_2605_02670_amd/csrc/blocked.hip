@@ -106,30 +106,56 @@ __device__ __forceinline__ double Ek(double th, int k) { return -expm1(-2.0 * th
 //   rho_{m-1} = w E(m) / E(m+1),
 //   s_d = alpha h / 2 + |b| (1 - rho_{m-1}) = alpha h / 2 + |b| (1 - w)(1 + w^{2m+1}) / E(m+1),
 //   s_o = -|b| prod_p rho_p = -|b| w^m E(1) / E(m+1)
-// (m = 0 gives s_d = delta, s_o = b).  Thread = (shift, edge), edge fastest.
+// (m = 0 gives s_d = delta, s_o = b).  Thread = (edge, shift), shift fastest.
+// With etab, also the scalars every 16-position block of the edge needs for its
+// operand tables (k_blocktab), so that the transcendental functions of one
+// (edge, shift) run once, not once per block: [E][kEdgeTabFields][LBp], fields
+// theta, w, E(1), |b|, 2 sinh(theta) and the split factors of theta_c = min(theta, 40):
+// e^{-theta_c}, e^{7.5 theta_c}, e^{-7.5 theta_c}, e^{theta_c}, e^{theta_c - theta}.
+enum EdgeTabField { ET_TH, ET_W, ET_E1, ET_BAB, ET_SH2, ET_WC, ET_FA, ET_FB, ET_IWC, ET_RW };
+static_assert(ET_RW + 1 == kEdgeTabFields, "etab fields");
+constexpr double kThetaSplit = 40.0;      // see k_blocktab
+
 __global__ void __launch_bounds__(256) k_edge_coeff(MeshView mv, const double *__restrict__ shift, int32_t LB,
                                                     int32_t LBp, double *__restrict__ babs,
                                                     double *__restrict__ rhom, double *__restrict__ sd,
-                                                    double *__restrict__ so) {
+                                                    double *__restrict__ so, double *__restrict__ etab) {
     const int64_t n = mv.E * (int64_t)LBp;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int l = (int)(idx / mv.E);
-        const int64_t e = idx - (int64_t)l * mv.E;
+        const int64_t e = idx / LBp;
+        const int l = (int)(idx - e * LBp);
+        const int64_t il = (int64_t)l * mv.E + e;
+        double *et = etab ? etab + e * kEdgeTabFields * LBp + l : nullptr;
         if (l >= LB) {
-            babs[e * LBp + l] = 0.0;
-            rhom[e * LBp + l] = 0.0;
-            sd[idx] = 1.0;
-            so[idx] = 0.0;
+            babs[idx] = 0.0;
+            rhom[idx] = 0.0;
+            sd[il] = 1.0;
+            so[il] = 0.0;
+            if (et)
+                for (int f = 0; f < kEdgeTabFields; ++f) et[f * LBp] = 0.0;
             continue;
         }
         const int m = mv.m[e];
         const EdgeShift s = edge_shift(shift[2 * l], shift[2 * l + 1], mv.kap2[e], mv.he[e]);
         const double Em1 = Ek(s.th, m + 1);
-        babs[e * LBp + l] = s.bab;
-        rhom[e * LBp + l] = (m > 0) ? s.w * Ek(s.th, m) / Em1 : 0.0;
-        sd[idx] = s.ah + s.bab * (-expm1(-s.th)) * (1.0 + exp(-(2.0 * m + 1.0) * s.th)) / Em1;
-        so[idx] = -s.bab * exp(-(double)m * s.th) * s.E1 / Em1;
+        babs[idx] = s.bab;
+        rhom[idx] = (m > 0) ? s.w * Ek(s.th, m) / Em1 : 0.0;
+        sd[il] = s.ah + s.bab * (-expm1(-s.th)) * (1.0 + exp(-(2.0 * m + 1.0) * s.th)) / Em1;
+        so[il] = -s.bab * exp(-(double)m * s.th) * s.E1 / Em1;
+        if (et) {
+            const double thc = fmin(s.th, kThetaSplit);
+            et[ET_TH * LBp] = s.th;
+            et[ET_W * LBp] = s.w;
+            et[ET_E1 * LBp] = s.E1;
+            et[ET_BAB * LBp] = s.bab;
+            et[ET_SH2 * LBp] = s.sh2;
+            et[ET_WC * LBp] = exp(-thc);
+            et[ET_FA * LBp] = exp(7.5 * thc);
+            et[ET_FB * LBp] = exp(-7.5 * thc);
+            et[ET_IWC * LBp] = exp(thc);
+            et[ET_RW * LBp] = exp(thc - s.th);
+        }
     }
 }
 
@@ -157,7 +183,6 @@ __device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk
 }
 
 constexpr int kTabThreads = 128;          // one thread per (padded) shift, LBp <= 128
-constexpr double kThetaSplit = 40.0;      // see k_blocktab
 
 // 16-byte vectors of the table element type
 template <typename ET> struct V16;
@@ -213,7 +238,7 @@ __device__ __forceinline__ void put16(const double (&v)[16], OT *__restrict__ ds
 // negligible value.
 template <typename OT, bool PACK>
 __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int32_t *__restrict__ boff,
-                                                          const double *__restrict__ shift, int32_t LB, int32_t LBp,
+                                                          const double *__restrict__ etab, int32_t LB, int32_t LBp,
                                                           int32_t NT, int32_t SLOT, int64_t nblocks,
                                                           OT *__restrict__ tab, OT *__restrict__ ztab) {
     constexpr bool F32L = sizeof(OT) == 4;  // FP32 operand tables for the mixed-precision sweeps
@@ -241,14 +266,15 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     if (PACK && l == 0) sistar[slot] = istar;  // read after the barrier below
     const bool live = bvalid && l < LB;
     const bool put = bvalid && l < LBp;  // a (padded) shift of a real block: its values are stored
+    // the edge's per-shift scalars (k_edge_coeff)
+    const double *et = etab + (int64_t)e * kEdgeTabFields * LBp + l;
     double th = 0.0, w = 0.0, E1 = 0.0, bab = 1.0, sh2 = 1.0;
     if (live) {
-        const EdgeShift s = edge_shift(shift[2 * l], shift[2 * l + 1], mv.kap2[e], mv.he[e]);
-        th = s.th;
-        w = s.w;
-        E1 = s.E1;
-        bab = s.bab;
-        sh2 = s.sh2;
+        th = et[ET_TH * LBp];
+        w = et[ET_W * LBp];
+        E1 = et[ET_E1 * LBp];
+        bab = et[ET_BAB * LBp];
+        sh2 = et[ET_SH2 * LBp];
     }
     // E values from two evaluations and the addition rule E(a + b) = E(a) + (1 - E(a)) E(b)
     // (positive terms only, no cancellation): Ef[k] = E(base + k), k = 0..16
@@ -256,8 +282,10 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     Ef[0] = live ? Ek(th, base) : 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) Ef[k + 1] = Ef[k] + (1.0 - Ef[k]) * E1;
-    // Q[i] = E(max(m - base - i, 0)), i = 0..16, upwards from Q[16] (rows past the edge
-    // are never used unmasked)
+    // Q[i] = E(max(m - base - i, 0)), i = 0..16, upwards from Q[16]: exactly 0 for the
+    // rows past the edge (i >= nr), which zeroes those rows of every operand with a Q
+    // factor (H, Z_tail, Af) without a mask; when the thread is not live, Q, w and the
+    // scale factors are 0 and so is every operand value
     const int nr = m - base;  // >= 1: positions of the edge from this block on
     double Q[17];
     Q[16] = live ? Ek(th, max(nr - 16, 0)) : 0.0;
@@ -275,14 +303,14 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     {
         double pw = w;  // w^{i+1}
 #pragma unroll
-        for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? pw * lam0 * Q[i] : 0.0;
+        for (int i = 0; i < 16; ++i, pw *= w) v[i] = pw * lam0 * Q[i];
     }
     if (put) put16<false, F32L>(v, T + TL.HF(), l);
     // H_bwd[i] = of_i lam_i = w^{i+2} E(base) E(m-base-i-1) / (...)
     {
         double pw = w * w;  // w^{i+2}
 #pragma unroll
-        for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? pw * lam0 * Q[i + 1] : 0.0;
+        for (int i = 0; i < 16; ++i, pw *= w) v[i] = pw * lam0 * Q[i + 1];
     }
     if (put) put16<false, F32L>(v, T + TL.HB(), l);
     // Z_tail[i] = w^{base+1+i} E(m-base-i) K
@@ -290,48 +318,54 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
         const double wb = live ? exp(-(double)(base + 1) * th) * K : 0.0;
         double pw = 1.0;  // w^i
 #pragma unroll
-        for (int i = 0; i < 16; ++i, pw *= w) v[i] = (live && i <= istar) ? wb * pw * Q[i] : 0.0;
+        for (int i = 0; i < 16; ++i, pw *= w) v[i] = wb * pw * Q[i];
     }
     if (put) put16<false, F32L>(v, Z, l);
     // C[j] = w^{i*-j} E(base+j+1) / E(base+i*+1), d = w^{i*+1} E(base) / E(base+i*+1), and
     // Z_head[i] = w^{m-base-i} E(base+i+1) K: descending chains from i*
     double dval = 0.0;
     {  // one chain at a time (fewer live registers)
-        double pw = 1.0, inv = 0.0;
+        double Eis = Ef[16];  // E(base + i* + 1), picked without a division per candidate
+#pragma unroll
+        for (int j = 0; j < 15; ++j) Eis = (j == istar) ? Ef[j + 1] : Eis;
+        const double inv = live ? 1.0 / Eis : 0.0;
+        // each chain factor is 0 above i* and starts at i* (1, resp. the scale of Z_head)
+        double pw = 0.0;
 #pragma unroll
         for (int j = 15; j >= 0; --j) {
-            if (j == istar) inv = 1.0 / Ef[j + 1];
-            v[j] = (live && j <= istar) ? pw * Ef[j + 1] * inv : 0.0;
-            if (j <= istar) pw *= w;
+            pw = (j == istar) ? 1.0 : pw;
+            v[j] = pw * Ef[j + 1] * inv;
+            pw *= w;
         }
-        dval = live ? pw * Ef[0] * inv : 0.0;  // pw = w^{i*+1}
+        dval = pw * Ef[0] * inv;  // pw = w^{i*+1}; 0 when not live (inv = 0)
         if (put) put16<true, F32L>(v, T + TL.CT(), l);
-        double zh = live ? exp(-(double)(m - base - istar) * th) * K : 0.0;
+        const double zh = live ? exp(-(double)(m - base - istar) * th) * K : 0.0;
+        double zc = 0.0;
 #pragma unroll
         for (int j = 15; j >= 0; --j) {
-            v[j] = (live && j <= istar) ? zh * Ef[j + 1] : 0.0;
-            if (j <= istar) zh *= w;
+            zc = (j == istar) ? zh : zc;
+            v[j] = zc * Ef[j + 1];
+            zc *= w;
         }
         if (put) put16<false, F32L>(v, Z + 256 * NT, l);
     }
     if (put) T[TL.DT() + l] = (OT)dval;
     // Ghat operands (split factors); rows past i*+1 (Af) / i* (Bm) are zero
     {
-        const double thc = fmin(th, kThetaSplit);
-        const double wc = live ? exp(-thc) : 0.0;
-        double fa = live ? exp(7.5 * thc) : 0.0;   // w_c^{i-7.5}
-        double fb = live ? exp(-7.5 * thc) : 0.0;  // w_c^{7.5-j}
-        const double iwc = live ? exp(thc) : 0.0;
+        const double wc = live ? et[ET_WC * LBp] : 0.0;     // w_c = e^{-theta_c}
+        double fa = live ? et[ET_FA * LBp] : 0.0;           // w_c^{i-7.5}
+        double fb = live ? et[ET_FB * LBp] : 0.0;           // w_c^{7.5-j}
+        const double iwc = live ? et[ET_IWC * LBp] : 0.0;
 #pragma unroll
         for (int i = 0; i < 17; ++i) {
             if (l < ld) {
-                sAf[i * ld + l] = (live && i <= istar + 1) ? Q[i] * ascale * fa : 0.0;
+                sAf[i * ld + l] = Q[i] * ascale * fa;
                 if (i < 16) sBm[i * ld + l] = (live && i <= istar) ? Ef[i + 1] * fb : 0.0;
             }
             fa *= wc;
             fb *= iwc;
         }
-        if (l < ld) srw[l] = live ? exp(thc - th) : 0.0;  // w / w_c
+        if (l < ld) srw[l] = live ? et[ET_RW * LBp] : 0.0;  // w / w_c
     }
     __syncthreads();
     // Ghat^T = B^T A^T (D layout of the transpose = the A-operand table layout) for every
@@ -957,7 +991,7 @@ void launch_edge_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st) {
     const int64_t n = mv.E * (int64_t)a.LBp;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_edge_coeff, dim3((unsigned)blocks), dim3(256), 0, st, mv, a.shift, a.LB, a.LBp, a.babs,
-                       a.rhom, a.sd, a.so);
+                       a.rhom, a.sd, a.so, a.etab);
     GRF_LAUNCH_CHECK();
 }
 
@@ -973,6 +1007,7 @@ static size_t blocktab_lds(int32_t LBp) {
 
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return;
+    GRF_REQUIRE(a.etab != nullptr, "internal: blocked tables need the per-edge scalars");
     GRF_REQUIRE(a.LBp == 16 * a.NT && a.NT >= 1 && a.NT <= 8, "internal: blocked sweeps need 16..128 padded shifts");
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
     const int32_t slot = blocktab_slot(a.LBp);
@@ -981,11 +1016,11 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const bool pack = nbw > 1;  // one block per workgroup compiles to the plain single-block kernel
     if (a.mixed) {
         auto *kern = pack ? k_blocktab<float, true> : k_blocktab<float, false>;
-        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.shift, a.LB, a.LBp,
+        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.etab, a.LB, a.LBp,
                            a.NT, slot, a.nblocks, a.tab32, a.ztab32);
     } else {
         auto *kern = pack ? k_blocktab<double, true> : k_blocktab<double, false>;
-        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.shift, a.LB, a.LBp,
+        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.etab, a.LB, a.LBp,
                            a.NT, slot, a.nblocks, a.tab, a.ztab);
     }
     GRF_LAUNCH_CHECK();

@@ -77,6 +77,9 @@ KTimer::~KTimer() {
     }
 }
 
+static_assert(GRF_K_COUNT <= 16, "kernel ids fit grf_stats.kernel_ms");
+static_assert(offsetof(grf_stats, pcg_class_ms) == 240 && sizeof(grf_stats) == 440, "grf_stats layout");
+
 void KTimer::begin(int id) {
     if (!on) return;
     Rec r{id, nullptr, nullptr};

@@ -64,8 +64,8 @@ static int32_t auto_bl(int32_t L) {
 static size_t held_pass_bytes(const grf_graph &g) {
     if (!g.work) return 0;
     const grf_graph::Work &w = *g.work;
-    const DevBuf *bufs[] = {&w.rho, &w.fwdt, &w.bwdt, &w.btab, &w.ztab, &w.babs, &w.rhom, &w.sd,   &w.so,
-                            &w.ends, &w.gT, &w.xT,   &w.ug,   &w.its,  &w.res,  &w.gexp, &w.pcg_ops};
+    const DevBuf *bufs[] = {&w.rho,  &w.fwdt, &w.bwdt, &w.btab, &w.ztab, &w.babs, &w.rhom,   &w.etab, &w.sd,
+                            &w.so,   &w.ends, &w.gT,   &w.xT,   &w.ug,   &w.its,  &w.res,    &w.gexp, &w.pcg_ops};
     size_t t = 0;
     for (const DevBuf *b : bufs) t += b->bytes;
     return t;
@@ -85,7 +85,9 @@ static Plan plan_pass(const grf_graph &g, int32_t L, int64_t S, const grf_opts &
     const double rows = p.blocked ? 0.0 : 5.0;
     const double btab = p.blocked ? (1296.0 / 16.0 + 32.0) * ((double)g.NI / 16.0 + (double)g.E) : 0.0;
     const double tbytes = o.precision == GRF_PREC_MIXED ? 4.0 : 8.0;
-    const double per_shift = 8.0 * (rows * g.NI + 4.0 * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V + (double)g.V * Sp) +
+    const double edge_scalars = p.blocked ? 14.0 : 4.0;  // per (edge, shift): |b|, rho, s_d, s_o (+ table scalars)
+    const double per_shift = 8.0 * (rows * g.NI + edge_scalars * g.E + 2.0 * g.E * Sp + 2.0 * S * g.V +
+                                    (double)g.V * Sp) +
                              tbytes * btab + 12.0 * S * (double)(g.gv0.size() - 1);
     double budget;
     if (const Arena *a = current_arena()) {
@@ -172,6 +174,7 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
         const size_t tb = o.precision == GRF_PREC_MIXED ? sizeof(float) : sizeof(double);  // table element
         w.btab.reserve(tb * (size_t)std::max<int64_t>(ps.nblocks, 1) * block_tab_doubles(LBp / 16));
         w.ztab.reserve(tb * (size_t)std::max<int64_t>(ps.nblocks, 1) * 512 * (LBp / 16));
+        w.etab.reserve(8 * (size_t)g.E * kEdgeTabFields * LBp + 8);
     }
     w.babs.reserve(8 * (size_t)g.E * LBp + 8);
     w.rhom.reserve(8 * (size_t)g.E * LBp + 8);
@@ -218,6 +221,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         ca.rhom = w.rhom.as<double>();
         ca.sd = w.sd.as<double>();
         ca.so = w.so.as<double>();
+        ca.etab = p.blocked ? w.etab.as<double>() : nullptr;
         T.begin(GRF_K_COEFF);
         if (p.blocked)
             launch_edge_coeff(mv, ca, st);
@@ -251,6 +255,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
             ba.shift = ca.shift;
             ba.babs = ca.babs;
             ba.rhom = ca.rhom;
+            ba.etab = ca.etab;
             ba.tab = w.btab.as<double>();
             ba.ztab = w.ztab.as<double>();
             ba.X = sa.X;
@@ -264,7 +269,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
             ba.mixed = (o.precision == GRF_PREC_MIXED) ? 1 : 0;
             ba.tab32 = w.btab.as<float>();
             ba.ztab32 = w.ztab.as<float>();
-            T.begin(GRF_K_COEFF);
+            T.begin(GRF_K_TABLE);
             launch_blocktab(mv, ba, st);
             T.end();
             T.begin(GRF_K_ENDS_FWD);

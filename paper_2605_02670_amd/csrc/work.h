@@ -11,6 +11,7 @@ struct grf_graph::Work {
     grf::DevBuf ztab;             // pass-B operand tables per edge block
     grf::DevBuf boff;             // [E+1] first block of every edge
     grf::DevBuf babs, rhom;       // per-edge [E][LBp]: |b| = gamma/h_e, rho_{m-1}
+    grf::DevBuf etab;             // per (edge, shift) closed-form scalars of the operand tables [E][10][LBp]
     grf::DevBuf sd, so;           // per-edge Schur 2x2 [LBp][E]: diagonal, off-diagonal
     grf::DevBuf shift;            // [LBp][2]: c_I, c_L of the shifts in the block
     grf::DevBuf ends;             // [LB][E][2][Sp]: |b| * (A_II^{-1} W_I) at both ends of every edge
@@ -56,11 +57,13 @@ struct CoeffArgs {
     double2 *fwdt, *bwdt;   // [NI][LBp] (streamed sweeps)
     double *babs, *rhom;    // [E][LBp]
     double *sd, *so;        // [LBp][E]
+    double *etab;           // [E][10][LBp] scalars of the blocked operand tables (null: not written)
 };
 // recurrence form: Thomas rows and the per-edge quantities
 void launch_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
 // closed form: the per-edge quantities only (the blocked sweeps build their operands in blocked.hip)
 void launch_edge_coeff(const MeshView &mv, const CoeffArgs &a, hipStream_t st);
+constexpr int kEdgeTabFields = 10;  // CoeffArgs::etab values per (edge, shift)
 
 // sweeps over edge interiors (lanes = samples, shifts in registers)
 struct SweepArgs {
@@ -86,6 +89,7 @@ struct BlockArgs {
     int32_t LB, LBp;        // real / padded shifts (LBp = 16 NT)
     const double *shift;    // [LBp][2] c_I, c_L
     const double *babs, *rhom;         // [E][LBp]
+    const double *etab;     // [E][10][LBp] per-(edge, shift) scalars (k_edge_coeff)
     double *tab;            // pass-A operands, block_tab_doubles(NT) per block
     double *ztab;           // pass-B operands (first/last columns of T^{-1}), 512 NT per block
     const double *X;        // [nb][N][64]

@@ -24,7 +24,7 @@ PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
 PCG_MODES = {"op": 0, "guess": 1, "jacobi": 2}  # grf_stats also reports 3: "global"
 PCG_MODES_SET = 1 << 12
 KERNELS = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd",
-           "layout", "mixed", "learned"]
+           "layout", "mixed", "learned", "table"]
 
 
 class GrfError(RuntimeError):
@@ -38,7 +38,7 @@ class Stats(C.Structure):
                 ("max_iterations", C.c_int32), ("total_iterations", C.c_int64),
                 ("max_rel_residual", C.c_double), ("refine_steps", C.c_int32),
                 ("shift_block", C.c_int32), ("sweep_block", C.c_int32), ("pcg_class_modes", C.c_int32),
-                ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int32 * 12),
+                ("kernel_ms", C.c_double * 16), ("kernel_launches", C.c_int32 * 16),
                 ("pcg_class_ms", C.c_double * 7), ("pcg_class_launches", C.c_int32 * 7),
                 ("pcg_class_reserved", C.c_int32), ("pcg_class_vertex_its", C.c_int64 * 7),
                 ("pcg_class_end_its", C.c_int64 * 7)]
@@ -47,8 +47,8 @@ class Stats(C.Structure):
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in self._ARRAYS}
-        d["kernel_ms"] = {KERNELS[i]: self.kernel_ms[i] for i in range(12)}
-        d["kernel_launches"] = {KERNELS[i]: self.kernel_launches[i] for i in range(12)}
+        d["kernel_ms"] = {k: self.kernel_ms[i] for i, k in enumerate(KERNELS)}
+        d["kernel_launches"] = {k: self.kernel_launches[i] for i, k in enumerate(KERNELS)}
         for k in ("pcg_class_ms", "pcg_class_launches", "pcg_class_vertex_its", "pcg_class_end_its"):
             d[k] = list(getattr(self, k))
         return d

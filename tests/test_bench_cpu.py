@@ -28,7 +28,7 @@ def test_multi_gpu_request_exits_with_message():
 
 def _stats(ms, launches, pcg_ms=None, pcg_launches=None, vit=None, eit=None):
     keys = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd", "layout",
-            "mixed", "learned"]
+            "mixed", "learned", "table"]
     return {"kernel_ms": {k: ms.get(k, 0.0) for k in keys},
             "kernel_launches": {k: launches.get(k, 0) for k in keys},
             "pcg_class_ms": pcg_ms or [0.0] * 7, "pcg_class_launches": pcg_launches or [0] * 7,

@@ -125,6 +125,8 @@ def test_batched_timing_run_matches_replay(grf):
         assert ms[k] > 0.0, k
     nblocks = st["kernel_launches"]["condense"]
     assert nblocks >= 1
+    if st["sweep_block"] == 0:  # blocked sweeps: one operand-table launch per shift block
+        assert ms["table"] > 0.0 and st["kernel_launches"]["table"] == nblocks
     launched = [c for c in range(7) if st["pcg_class_launches"][c] > 0]
     assert launched and all(st["pcg_class_launches"][c] == nblocks for c in launched)
     assert sum(st["pcg_class_ms"]) <= ms["pcg"] * (1 + 1e-6)
