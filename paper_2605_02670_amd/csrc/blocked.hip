@@ -173,13 +173,11 @@ struct TabLayout {
     __host__ __device__ int64_t size() const { return 784 * (int64_t)NT + 512; }
 };
 
-__device__ __forceinline__ int find_edge(const int32_t *boff, int E, int64_t blk) {
-    int lo = 0, hi = E;  // boff[lo] <= blk < boff[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (boff[mid] <= blk) lo = mid; else hi = mid;
-    }
-    return lo;
+// bmap[b] = (edge, index of the block within the edge) for every 16-position block;
+// thread = edge
+__global__ void k_block_map(const int32_t *__restrict__ boff, int64_t E, int2 *__restrict__ bmap) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t b = boff[e]; b < boff[e + 1]; ++b) bmap[b] = make_int2((int)e, b - boff[e]);
 }
 
 constexpr int kTabThreads = 128;          // one thread per (padded) shift, LBp <= 128
@@ -237,7 +235,7 @@ __device__ __forceinline__ void put16(const double (&v)[16], OT *__restrict__ ds
 // under the rounding of its own diagonal term) is replaced by an equally
 // negligible value.
 template <typename OT, bool PACK>
-__global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int32_t *__restrict__ boff,
+__global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int2 *__restrict__ bmap,
                                                           const double *__restrict__ etab, int32_t LB, int32_t LBp,
                                                           int32_t NT, int32_t SLOT, int64_t nblocks,
                                                           OT *__restrict__ tab, OT *__restrict__ ztab) {
@@ -254,8 +252,8 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
     const int64_t blk0 = (int64_t)blockIdx.x * NBW;
     const bool bvalid = blk0 + slot < nblocks;  // the last workgroup may hold fewer blocks
     const int64_t blk = bvalid ? blk0 + slot : nblocks - 1;
-    const int e = find_edge(boff, (int)mv.E, blk);
-    const int beta = (int)(blk - boff[e]);
+    const int2 eb = bmap[blk];
+    const int e = eb.x, beta = eb.y;
     const int m = mv.m[e];
     const int base = 16 * beta;
     const int istar = min(15, m - 1 - base);
@@ -1005,9 +1003,16 @@ static size_t blocktab_lds(int32_t LBp) {
     return sizeof(double) * 34 * (size_t)(LBp + 4) * (kTabThreads / blocktab_slot(LBp));
 }
 
+void launch_block_map(const int32_t *boff, int64_t E, int2 *bmap, hipStream_t st) {
+    if (E == 0) return;
+    hipLaunchKernelGGL(k_block_map, dim3((unsigned)std::min<int64_t>((E + 255) / 256, 65536)), dim3(256), 0, st, boff,
+                       E, bmap);
+    GRF_LAUNCH_CHECK();
+}
+
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (a.nblocks == 0) return;
-    GRF_REQUIRE(a.etab != nullptr, "internal: blocked tables need the per-edge scalars");
+    GRF_REQUIRE(a.etab != nullptr && a.bmap != nullptr, "internal: blocked tables need the per-edge scalars");
     GRF_REQUIRE(a.LBp == 16 * a.NT && a.NT >= 1 && a.NT <= 8, "internal: blocked sweeps need 16..128 padded shifts");
     GRF_REQUIRE(a.nblocks < (int64_t(1) << 31), "too many edge blocks");
     const int32_t slot = blocktab_slot(a.LBp);
@@ -1016,11 +1021,11 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const bool pack = nbw > 1;  // one block per workgroup compiles to the plain single-block kernel
     if (a.mixed) {
         auto *kern = pack ? k_blocktab<float, true> : k_blocktab<float, false>;
-        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.etab, a.LB, a.LBp,
+        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.bmap, a.etab, a.LB, a.LBp,
                            a.NT, slot, a.nblocks, a.tab32, a.ztab32);
     } else {
         auto *kern = pack ? k_blocktab<double, true> : k_blocktab<double, false>;
-        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.boff, a.etab, a.LB, a.LBp,
+        hipLaunchKernelGGL(kern, grid, dim3(kTabThreads), blocktab_lds(a.LBp), st, mv, a.bmap, a.etab, a.LB, a.LBp,
                            a.NT, slot, a.nblocks, a.tab, a.ztab);
     }
     GRF_LAUNCH_CHECK();

@@ -121,6 +121,8 @@ static void ensure_block_offsets(grf_graph &g, grf_graph::Work &w, hipStream_t s
     for (int64_t e = 0; e < g.E; ++e) bo[e + 1] = bo[e] + (g.m[e] + 15) / 16;
     nblocks = bo[g.E];
     upload(w.boff, bo, st);
+    w.bmap.reserve(sizeof(int2) * (size_t)std::max<int64_t>(nblocks, 1));
+    launch_block_map(w.boff.as<int32_t>(), g.E, w.bmap.as<int2>(), st);
 }
 
 // One run of the shift schedule over the right-hand sides in w.X, in three
@@ -248,6 +250,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         BlockArgs ba{};
         if (p.blocked) {
             ba.boff = w.boff.as<int32_t>();
+            ba.bmap = w.bmap.as<int2>();
             ba.nblocks = ps.nblocks;
             ba.NT = LBp / 16;
             ba.LB = lb;

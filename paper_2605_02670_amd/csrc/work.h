@@ -10,6 +10,7 @@ struct grf_graph::Work {
     grf::DevBuf btab;             // matrix-core operand tables per 16-position edge block
     grf::DevBuf ztab;             // pass-B operand tables per edge block
     grf::DevBuf boff;             // [E+1] first block of every edge
+    grf::DevBuf bmap;             // [nblocks] int2: (edge, block index within the edge)
     grf::DevBuf babs, rhom;       // per-edge [E][LBp]: |b| = gamma/h_e, rho_{m-1}
     grf::DevBuf etab;             // per (edge, shift) closed-form scalars of the operand tables [E][10][LBp]
     grf::DevBuf sd, so;           // per-edge Schur 2x2 [LBp][E]: diagonal, off-diagonal
@@ -84,6 +85,7 @@ void launch_sweep_acc(const MeshView &mv, const SweepArgs &a, bool fwd, hipStrea
 // blocked (matrix-core) sweeps: 16-position edge blocks, shifts padded to 16*NT
 struct BlockArgs {
     const int32_t *boff;    // [E+1] first block of every edge
+    const int2 *bmap;       // [nblocks] (edge, block index within the edge)
     int64_t nblocks;        // blocks of the whole graph
     int32_t NT;             // shift tiles of 16
     int32_t LB, LBp;        // real / padded shifts (LBp = 16 NT)
@@ -103,6 +105,7 @@ struct BlockArgs {
     float *tab32, *ztab32;  // the FP32 tables (same layout sizes as tab / ztab)
 };
 int64_t block_tab_doubles(int32_t NT);
+void launch_block_map(const int32_t *boff, int64_t E, int2 *bmap, hipStream_t st);
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st);
 void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st);
 void launch_corr_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st);
