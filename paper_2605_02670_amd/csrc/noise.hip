@@ -143,6 +143,14 @@ __device__ __forceinline__ void box_muller(uint64_t xa, uint64_t xb, double &z_c
 // Graph z of the batch (blockIdx.z): local DOF j (the counter index of the
 // noise definition) lives at row j of its interior range or, for j >= NI_z, at
 // row (j - NI_z) of its vertex range.
+// lanes of one DOF group in a block of 64 samples holding Sb real ones: the
+// samples round up to 16, 32 or 64 lanes, so that a wavefront takes 4, 2 or 1
+// DOF groups and no wavefront computes for more than 15 padding samples
+__host__ __device__ inline int noise_group_lanes(int64_t Sb) { return Sb <= 16 ? 16 : (Sb <= 32 ? 32 : 64); }
+
+// Thread = (group of 4 DOFs, sample).  Lanes past the real samples store 0 (the
+// sweeps read whole 16-sample wavefronts); with 16 or 32 lanes per group the
+// lanes of the block past them are not written.
 __global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt, const int64_t *__restrict__ segs,
                                                int64_t N, int64_t S, int64_t soff, uint64_t seed,
                                                double *__restrict__ X) {
@@ -151,10 +159,16 @@ __global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt,
     const int64_t n = segs[4 * z], ni = segs[4 * z + 1], ri = segs[4 * z + 2], rv = segs[4 * z + 3];
     const int64_t ngrp = (n + 3) / 4;
     const int64_t b = blockIdx.y;
-    const int64_t s = b * 64 + lane;
-    const bool live = s < S;
-    double *Xb = X + b * N * 64 + lane;
-    for (int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); g < ngrp; g += (int64_t)gridDim.x * 4) {
+    const int64_t Sb = S - b * 64 < 64 ? S - b * 64 : 64;
+    const int lpg = noise_group_lanes(Sb), gpw = 64 / lpg;
+    const int sl = lane & (lpg - 1), gs = lane / lpg;
+    const int64_t s = b * 64 + sl;
+    const bool live = sl < Sb;
+    double *Xb = X + b * N * 64 + sl;
+    for (int64_t g0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * gpw; g0 < ngrp;
+         g0 += (int64_t)gridDim.x * 4 * gpw) {
+        const int64_t g = g0 + gs;
+        if (g >= ngrp) continue;
         double zz[4] = {0.0, 0.0, 0.0, 0.0};
         if (live) {
             Words w = philox4x64_10((uint64_t)g, seed, (uint64_t)(soff + s));
@@ -177,7 +191,8 @@ __global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt,
 void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, double *X, hipStream_t st) {
     int64_t nb = (S + 63) / 64;
     int64_t ngrp = (mv.maxNg + 3) / 4;
-    int64_t gx = (ngrp + 3) / 4;
+    const int64_t per = 4 * (64 / noise_group_lanes(S < 64 ? S : 64));  // DOF groups per workgroup pass
+    int64_t gx = (ngrp + per - 1) / per;
     if (gx > 8192) gx = 8192;
     if (gx < 1) gx = 1;
     GRF_REQUIRE(nb < 65536 && mv.ng < 65536, "too many samples or graphs in one call");
