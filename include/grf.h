@@ -290,9 +290,11 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
  * D^{-1/2} g (D = diag S).  P_hat = I is exactly the Jacobi preconditioner,
  * which is also the fallback: a system not converged after maxit/2 iterations
  * restarts from its iterate with Jacobi; the recomputed true residual decides
- * convergence as for Jacobi.  Weights are bfloat16 (products on the FP32
- * matrix cores); training runs on the GPU (own forward / backward kernels,
- * Adam) on the method's own condensed right-hand sides and FP64 Schur solutions.
+ * convergence as for Jacobi.  Weights are bfloat16.  The sampler's forward keeps
+ * the hidden activations in bfloat16 (64 -> 64 layer products on the bfloat16
+ * matrix cores, FP32 accumulation); training runs on the GPU with FP32
+ * activations (own forward / backward kernels, Adam) on the method's own
+ * condensed right-hand sides and FP64 Schur solutions.
  * A network handle is used by one call at a time (its workspace is shared).
  */
 /* Number of float parameters of the network. */
@@ -312,6 +314,23 @@ int grf_learned_destroy(grf_learned *net);
 int grf_learned_loss_grad(grf_learned *net, grf_graph *g, double kappa, double c_I, double c_L,
                           int64_t n_rhs, const double *rhs, const double *sol, double *loss,
                           float *grad, const grf_opts *opts);
+/*
+ * The network's operators for one shift (c_I, c_L) on graph g, on the
+ * Jacobi-scaled system (the learned operator above): device float64 outputs
+ *   p_diag [V]  diagonal of P_hat (delta, the edge-end terms p and a self-loop's coupling)
+ *   p_edge [E]  coupling q_e = rho sqrt(p_u p_v) of every edge
+ *   q_diag [V]  diagonal of Q_hat (gamma, plus a self-loop's eta)
+ *   q_edge [E]  coupling eta_e of every edge
+ * activations: GRF_ACT_BF16 is the forward the sampler runs (bfloat16 hidden
+ * activations and messages, 64 -> 64 products on the bfloat16 matrix cores),
+ * GRF_ACT_FP32 the one training runs (FP32 activations).  p_edge and q_edge may
+ * be NULL when E = 0.  Returns after the outputs are written.
+ */
+#define GRF_ACT_FP32 0
+#define GRF_ACT_BF16 1
+int grf_learned_operators(grf_learned *net, grf_graph *g, double kappa, double c_I, double c_L,
+                          int32_t activations, double *p_diag, double *p_edge, double *q_diag, double *q_edge,
+                          const grf_opts *opts);
 /*
  * Train in place: draws n_samples noise samples per graph (seed + graph index),
  * runs the method with Jacobi PCG (FP64, opts->tol) over every shift of the

@@ -79,6 +79,38 @@ __host__ __device__ inline uint16_t to_bf16(float x) {
     return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
 }
 
+// eight consecutive activations (16- or 32-byte aligned; FP32 or bfloat16 storage) as
+// FP32, and the store of one activation
+__device__ __forceinline__ void act_load8(const float *p, float (&x)[8]) {
+    const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+    x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w, x[4] = b.x, x[5] = b.y, x[6] = b.z, x[7] = b.w;
+}
+__device__ __forceinline__ void act_load8(const uint16_t *p, float (&x)[8]) {
+    const uint4 a = reinterpret_cast<const uint4 *>(p)[0];
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        x[2 * q] = __uint_as_float(w[q] << 16);
+        x[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+    }
+}
+template <typename AT> __device__ __forceinline__ AT act_store(float x);
+template <> __device__ __forceinline__ float act_store<float>(float x) { return x; }
+template <> __device__ __forceinline__ uint16_t act_store<uint16_t>(float x) { return to_bf16(x); }
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ s4 pack4(uint32_t lo, uint32_t hi) {
+    s4 v;
+    v[0] = (short)(lo & 0xffffu);
+    v[1] = (short)(lo >> 16);
+    v[2] = (short)(hi & 0xffffu);
+    v[3] = (short)(hi >> 16);
+    return v;
+}
+__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 __global__ void k_refresh_bf16(const float *__restrict__ w, uint16_t *__restrict__ wb, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) wb[i] = to_bf16(w[i]);
@@ -177,11 +209,11 @@ __global__ void k_lrn_agg(MeshView mv, const float *__restrict__ w, const float 
 // and supplies column 16 m + 4 (L/16) + j in matrix-core step (m, j); the B
 // operand takes the same k from LDS.  Accumulator item j of lane L is row
 // 4 (L/16) + j, column L%16 of its 16x16 tile.
-template <int K>
+template <int K, typename OT>
 __global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ A, const float *__restrict__ B,
                                                       const uint16_t *__restrict__ Ws, const uint16_t *__restrict__ Wn,
                                                       const float *__restrict__ bias, int64_t R,
-                                                      float *__restrict__ Out) {
+                                                      OT *__restrict__ Out) {
     static_assert(K % 4 == 0, "16-byte chunks");
     constexpr int NC = K / 4;             // chunks per row
     constexpr int CPL = NC >= 4 ? NC / 4 : 1;  // chunks per lane
@@ -227,8 +259,113 @@ __global__ void __launch_bounds__(256) k_lrn_gemm_fwd(const float *__restrict__ 
             for (int j = 0; j < 4; ++j) {
                 const int64_t r = r0 + 4 * (L >> 4) + j;
                 const int n = 16 * t + (L & 15);
-                if (r < R) Out[r * HID + n] = fmaxf(acc[t][j] + bias[n], 0.0f);
+                if (r < R) Out[r * HID + n] = act_store<OT>(fmaxf(acc[t][j] + bias[n], 0.0f));
             }
+    }
+}
+
+// ---- inference forward with bfloat16 activations -----------------------------------
+// The sampler's forward stores the hidden activations (and the aggregated
+// messages of layers 2 and 3) as bfloat16, rounded to nearest even, and runs the
+// 64 -> 64 layer products on the bfloat16 matrix cores with FP32 accumulation;
+// the first layer (8 inputs) and every sum stay FP32.  Training keeps FP32
+// activations (its backward reads them).
+
+// M[l][v][c] = sum over the edge ends at v of w_e H[l][other][c], bfloat16 rows of 64
+// channels: a thread takes eight channels of a row (16-byte loads, FP32 sums in CSR order)
+__global__ void k_lrn_agg_bf(MeshView mv, const float *__restrict__ w, const uint16_t *__restrict__ H, int32_t LB,
+                             uint16_t *__restrict__ M) {
+    constexpr int C8 = HID / 8;
+    const int64_t n = (int64_t)LB * mv.V * C8;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / C8;
+        const int c8 = (int)(i - row * C8);
+        const int l = (int)(row / mv.V), v = (int)(row - (int64_t)l * mv.V);
+        const uint4 *Hl = reinterpret_cast<const uint4 *>(H + (int64_t)l * mv.V * HID);
+        const float *wl = w + (int64_t)l * mv.E;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+            const float we = wl[mv.adj_e[k]];
+            const uint4 h = Hl[(int64_t)mv.adj_o[k] * C8 + c8];
+            const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[2 * q] += we * __uint_as_float(hw[q] << 16);
+                acc[2 * q + 1] += we * __uint_as_float(hw[q] & 0xffff0000u);
+            }
+        }
+        uint4 o;
+        o.x = (uint32_t)to_bf16(acc[0]) | ((uint32_t)to_bf16(acc[1]) << 16);
+        o.y = (uint32_t)to_bf16(acc[2]) | ((uint32_t)to_bf16(acc[3]) << 16);
+        o.z = (uint32_t)to_bf16(acc[4]) | ((uint32_t)to_bf16(acc[5]) << 16);
+        o.w = (uint32_t)to_bf16(acc[6]) | ((uint32_t)to_bf16(acc[7]) << 16);
+        reinterpret_cast<uint4 *>(M)[i] = o;
+    }
+}
+
+// Out[r][n] = relu( sum_k A[r][k] Ws[n][k] + sum_k B[r][k] Wn[n][k] + bias[n] ), 64 -> 64,
+// bfloat16 A, B, W and Out, on v_mfma_f32_16x16x16_bf16 (FP32 accumulation).  Computed
+// transposed, Out^T = Ws A^T + Wn B^T, so that a lane's accumulator items are four
+// consecutive channels of one row (8-byte stores).  Operand layout: lane L supplies
+// A-operand row L%16 (channel) and B-operand column L%16 (row r), K items 4 (L/16) + j;
+// matrix-core step s takes the logical k = 16 (L/16) + 4 s + j, so a lane reads 32
+// contiguous bytes of its row once.  Accumulator item j of lane L is channel
+// 4 (L/16) + j of the tile, row L%16.
+__global__ void __launch_bounds__(256) k_lrn_gemm_bf(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+                                                     const uint16_t *__restrict__ Ws, const uint16_t *__restrict__ Wn,
+                                                     const float *__restrict__ bias, int64_t R,
+                                                     uint16_t *__restrict__ Out) {
+    constexpr int LDW = HID + 8;  // padded LDS row (bfloat16 elements)
+    __shared__ __align__(16) uint16_t sW[2][HID][LDW];  // sW[m][n][k] = W_m[n][k]
+    for (int i = threadIdx.x; i < 2 * HID * HID; i += blockDim.x) {
+        const int m = i / (HID * HID), rem = i - m * (HID * HID);
+        const int n = rem / HID, k = rem - n * HID;
+        sW[m][n][k] = (m ? Wn : Ws)[n * HID + k];
+    }
+    __syncthreads();
+    const int L = threadIdx.x & 63;
+    const int q = L >> 4, c = L & 15;
+    const int64_t ntiles = (R + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t ra = tile * 16 + c;
+        const bool rok = ra < R;
+        uint4 a[2], b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            a[h] = rok ? reinterpret_cast<const uint4 *>(A + ra * HID + 16 * q)[h] : make_uint4(0u, 0u, 0u, 0u);
+            b[h] = rok ? reinterpret_cast<const uint4 *>(B + ra * HID + 16 * q)[h] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        f4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const uint32_t a0 = st < 2 ? (st == 0 ? a[0].x : a[0].z) : (st == 2 ? a[1].x : a[1].z);
+            const uint32_t a1 = st < 2 ? (st == 0 ? a[0].y : a[0].w) : (st == 2 ? a[1].y : a[1].w);
+            const uint32_t b0 = st < 2 ? (st == 0 ? b[0].x : b[0].z) : (st == 2 ? b[1].x : b[1].z);
+            const uint32_t b1 = st < 2 ? (st == 0 ? b[0].y : b[0].w) : (st == 2 ? b[1].y : b[1].w);
+            const s4 av = pack4(a0, a1), bv = pack4(b0, b1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int n = 16 * t + c;
+                const s4 ws = *reinterpret_cast<const s4 *>(&sW[0][n][16 * q + 4 * st]);
+                const s4 wn = *reinterpret_cast<const s4 *>(&sW[1][n][16 * q + 4 * st]);
+                acc[t] = mfma_bf16(ws, av, acc[t]);
+                acc[t] = mfma_bf16(wn, bv, acc[t]);
+            }
+        }
+        if (rok) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int n0 = 16 * t + 4 * q;
+                uint2 o;
+                o.x = (uint32_t)to_bf16(fmaxf(acc[t][0] + bias[n0], 0.0f)) |
+                      ((uint32_t)to_bf16(fmaxf(acc[t][1] + bias[n0 + 1], 0.0f)) << 16);
+                o.y = (uint32_t)to_bf16(fmaxf(acc[t][2] + bias[n0 + 2], 0.0f)) |
+                      ((uint32_t)to_bf16(fmaxf(acc[t][3] + bias[n0 + 3], 0.0f)) << 16);
+                *reinterpret_cast<uint2 *>(Out + ra * HID + n0) = o;
+            }
+        }
     }
 }
 
@@ -342,20 +479,28 @@ struct Heads {
     double *Pd, *Pq, *Qd, *Qe;      // [LB][V], [LB][E], [LB][V], [LB][E]
 };
 
-__global__ void k_lrn_ehead(MeshView mv, const float *__restrict__ H, const uint16_t *__restrict__ wb,
+template <typename AT>
+__global__ void k_lrn_ehead(MeshView mv, const AT *__restrict__ H, const uint16_t *__restrict__ wb,
                             const float *__restrict__ w32, int32_t LB, Heads hd) {
     const int64_t n = (int64_t)LB * mv.E;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(i / mv.E), e = (int)(i - (int64_t)l * mv.E);
-        const float *hu = H + ((int64_t)l * mv.V + mv.eu[e]) * HID;
-        const float *hv = H + ((int64_t)l * mv.V + mv.ev[e]) * HID;
+        const AT *hu = H + ((int64_t)l * mv.V + mv.eu[e]) * HID;
+        const AT *hv = H + ((int64_t)l * mv.V + mv.ev[e]) * HID;
         float zt = w32[P_CP], zh = w32[P_CP], zr = w32[P_CR], et = w32[P_CE];
-        for (int c = 0; c < HID; ++c) {
-            const float a1 = bf(wb, P_AP1 + c), a2 = bf(wb, P_AP2 + c);
-            zt += a1 * hu[c] + a2 * hv[c];
-            zh += a1 * hv[c] + a2 * hu[c];
-            zr += bf(wb, P_AR + c) * (hu[c] + hv[c]);
-            et += bf(wb, P_AE + c) * (hu[c] + hv[c]);
+        for (int c8 = 0; c8 < HID; c8 += 8) {
+            float xu[8], xv[8];
+            act_load8(hu + c8, xu);
+            act_load8(hv + c8, xv);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = c8 + j;
+                const float a1 = bf(wb, P_AP1 + c), a2 = bf(wb, P_AP2 + c);
+                zt += a1 * xu[j] + a2 * xv[j];
+                zh += a1 * xv[j] + a2 * xu[j];
+                zr += bf(wb, P_AR + c) * (xu[j] + xv[j]);
+                et += bf(wb, P_AE + c) * (xu[j] + xv[j]);
+            }
         }
         hd.zt[i] = zt;
         hd.zh[i] = zh;
@@ -367,16 +512,22 @@ __global__ void k_lrn_ehead(MeshView mv, const float *__restrict__ H, const uint
     }
 }
 
-__global__ void k_lrn_vhead(MeshView mv, const float *__restrict__ H, const uint16_t *__restrict__ wb,
+template <typename AT>
+__global__ void k_lrn_vhead(MeshView mv, const AT *__restrict__ H, const uint16_t *__restrict__ wb,
                             const float *__restrict__ w32, int32_t LB, Heads hd) {
     const int64_t n = (int64_t)LB * mv.V;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(i / mv.V), v = (int)(i - (int64_t)l * mv.V);
-        const float *h = H + i * HID;
+        const AT *h = H + i * HID;
         float zd = w32[P_CD], g = w32[P_CG];
-        for (int c = 0; c < HID; ++c) {
-            zd += bf(wb, P_AD + c) * h[c];
-            g += bf(wb, P_AG + c) * h[c];
+        for (int c8 = 0; c8 < HID; c8 += 8) {
+            float x[8];
+            act_load8(h + c8, x);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                zd += bf(wb, P_AD + c8 + j) * x[j];
+                g += bf(wb, P_AG + c8 + j) * x[j];
+            }
         }
         hd.zd[i] = zd;
         hd.gam[i] = g;
@@ -683,7 +834,7 @@ void learned_copy_grad(grf_learned &net, float *host, hipStream_t st) {
 
 // Forward of the network over LB shifts of a mesh: fills net.{Dh, Pd, Pq, Qd, Qe} (and the activations).
 void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, const double *sd, const double *so,
-                     int32_t LB, hipStream_t st) {
+                     int32_t LB, hipStream_t st, bool bf16act) {
     const int64_t R = (int64_t)LB * mv.V, RE = (int64_t)LB * mv.E;
     GRF_REQUIRE(net.Dh.bytes >= (size_t)(8 * R) && net.Qe.bytes >= (size_t)(8 * RE),
                 "internal: learned workspace not reserved");
@@ -702,25 +853,46 @@ void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, 
     // layer 1 (8 -> 64), 2, 3 (64 -> 64)
     hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * F_IN / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
                        net.X0.as<float>(), LB, F_IN, net.M0.as<float>());
-    hipLaunchKernelGGL((k_lrn_gemm_fwd<F_IN>), dim3(gblocks), dim3(256), 0, st, net.X0.as<float>(), net.M0.as<float>(),
-                       wb + P_W1S, wb + P_W1N, w32 + P_B1, R, net.H1.as<float>());
-    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
-                       net.H1.as<float>(), LB, HID, net.M1.as<float>());
-    hipLaunchKernelGGL((k_lrn_gemm_fwd<HID>), dim3(gblocks), dim3(256), 0, st, net.H1.as<float>(), net.M1.as<float>(),
-                       wb + P_W2S, wb + P_W2N, w32 + P_B2, R, net.H2.as<float>());
-    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
-                       net.H2.as<float>(), LB, HID, net.M2.as<float>());
-    hipLaunchKernelGGL((k_lrn_gemm_fwd<HID>), dim3(gblocks), dim3(256), 0, st, net.H2.as<float>(), net.M2.as<float>(),
-                       wb + P_W3S, wb + P_W3N, w32 + P_B3, R, net.H3.as<float>());
-    GRF_LAUNCH_CHECK();
     Heads hd{net.zd.as<float>(), net.gam.as<float>(), net.zt.as<float>(), net.zh.as<float>(), net.zr.as<float>(),
              net.eta.as<float>(), net.Pd.as<double>(), net.Pq.as<double>(), net.Qd.as<double>(),
              net.Qe.as<double>()};
+    if (bf16act) {  // bfloat16 activations in the FP32 buffers (half of each used)
+        uint16_t *H1 = net.H1.as<uint16_t>(), *M1 = net.M1.as<uint16_t>(), *H2 = net.H2.as<uint16_t>(),
+                 *M2 = net.M2.as<uint16_t>(), *H3 = net.H3.as<uint16_t>();
+        const unsigned ablocks = (unsigned)blocks_for(R * HID / 8);
+        hipLaunchKernelGGL((k_lrn_gemm_fwd<F_IN, uint16_t>), dim3(gblocks), dim3(256), 0, st, net.X0.as<float>(),
+                           net.M0.as<float>(), wb + P_W1S, wb + P_W1N, w32 + P_B1, R, H1);
+        hipLaunchKernelGGL(k_lrn_agg_bf, dim3(ablocks), dim3(256), 0, st, mv, net.w.as<float>(), H1, LB, M1);
+        hipLaunchKernelGGL(k_lrn_gemm_bf, dim3(gblocks), dim3(256), 0, st, H1, M1, wb + P_W2S, wb + P_W2N, w32 + P_B2,
+                           R, H2);
+        hipLaunchKernelGGL(k_lrn_agg_bf, dim3(ablocks), dim3(256), 0, st, mv, net.w.as<float>(), H2, LB, M2);
+        hipLaunchKernelGGL(k_lrn_gemm_bf, dim3(gblocks), dim3(256), 0, st, H2, M2, wb + P_W3S, wb + P_W3N, w32 + P_B3,
+                           R, H3);
+        GRF_LAUNCH_CHECK();
+        if (RE > 0)
+            hipLaunchKernelGGL(k_lrn_ehead<uint16_t>, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv, H3, wb,
+                               w32, LB, hd);
+        hipLaunchKernelGGL(k_lrn_vhead<uint16_t>, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, H3, wb, w32,
+                           LB, hd);
+        GRF_LAUNCH_CHECK();
+        return;
+    }
+    hipLaunchKernelGGL((k_lrn_gemm_fwd<F_IN, float>), dim3(gblocks), dim3(256), 0, st, net.X0.as<float>(),
+                       net.M0.as<float>(), wb + P_W1S, wb + P_W1N, w32 + P_B1, R, net.H1.as<float>());
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
+                       net.H1.as<float>(), LB, HID, net.M1.as<float>());
+    hipLaunchKernelGGL((k_lrn_gemm_fwd<HID, float>), dim3(gblocks), dim3(256), 0, st, net.H1.as<float>(),
+                       net.M1.as<float>(), wb + P_W2S, wb + P_W2N, w32 + P_B2, R, net.H2.as<float>());
+    hipLaunchKernelGGL(k_lrn_agg, dim3((unsigned)blocks_for(R * HID / 4)), dim3(256), 0, st, mv, net.w.as<float>(),
+                       net.H2.as<float>(), LB, HID, net.M2.as<float>());
+    hipLaunchKernelGGL((k_lrn_gemm_fwd<HID, float>), dim3(gblocks), dim3(256), 0, st, net.H2.as<float>(),
+                       net.M2.as<float>(), wb + P_W3S, wb + P_W3N, w32 + P_B3, R, net.H3.as<float>());
+    GRF_LAUNCH_CHECK();
     if (RE > 0)
-        hipLaunchKernelGGL(k_lrn_ehead, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv, net.H3.as<float>(), wb,
-                           w32, LB, hd);
-    hipLaunchKernelGGL(k_lrn_vhead, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, net.H3.as<float>(), wb, w32,
-                       LB, hd);
+        hipLaunchKernelGGL(k_lrn_ehead<float>, dim3((unsigned)blocks_for(RE)), dim3(256), 0, st, mv, net.H3.as<float>(),
+                           wb, w32, LB, hd);
+    hipLaunchKernelGGL(k_lrn_vhead<float>, dim3((unsigned)blocks_for(R)), dim3(256), 0, st, mv, net.H3.as<float>(), wb,
+                       w32, LB, hd);
     GRF_LAUNCH_CHECK();
 }
 

@@ -331,7 +331,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         if (net_used) {
             grf_learned &net = *const_cast<grf_learned *>(o.learned);
             T.begin(GRF_K_LEARNED);
-            learned_forward(net, mv, ca.shift, ca.sd, ca.so, lb, st);
+            learned_forward(net, mv, ca.shift, ca.sd, ca.so, lb, st, true);
             T.end();
             lops = learned_ops(net);
             sc.learned = &lops;
@@ -1001,9 +1001,50 @@ int grf_learned_loss_grad(grf_learned *net, grf_graph *g, double kappa, double c
     ca.so = w.so.as<double>();
     launch_edge_coeff(mv, ca, st);
     learned_reserve(*net, mv, 1);
-    learned_forward(*net, mv, ca.shift, ca.sd, ca.so, 1, st);
+    learned_forward(*net, mv, ca.shift, ca.sd, ca.so, 1, st, false);
     *loss = learned_backward(*net, mv, rhs, sol, 1, n_rhs, st);
     learned_copy_grad(*net, grad, st);
+    GRF_API_END
+}
+
+int grf_learned_operators(grf_learned *net, grf_graph *g, double kappa, double c_I, double c_L, int32_t activations,
+                          double *p_diag, double *p_edge, double *q_diag, double *q_edge, const grf_opts *opts) {
+    GRF_API_BEGIN
+    GRF_REQUIRE(net && g, "net/graph is NULL");
+    GRF_REQUIRE(std::isfinite(kappa) && kappa > 0, "kappa must be finite and > 0");
+    GRF_REQUIRE(std::isfinite(c_I) && c_I > 0 && std::isfinite(c_L) && c_L > 0, "c_I and c_L must be finite and > 0");
+    GRF_REQUIRE(activations == GRF_ACT_FP32 || activations == GRF_ACT_BF16, "unknown activations %d", activations);
+    GRF_REQUIRE(p_diag && q_diag && (g->E == 0 || (p_edge && q_edge)), "output pointers are NULL");
+    grf_opts o = resolve_opts(opts);
+    hipStream_t st = (hipStream_t)o.stream;
+    set_kappa2(*g, kappa, st);
+    grf_graph::Work &w = work(*g);
+    const MeshView mv = g->view();
+    std::vector<double> sh = {c_I, c_L};
+    upload(w.shift, sh, st);
+    w.babs.reserve(8 * (size_t)g->E + 8);
+    w.rhom.reserve(8 * (size_t)g->E + 8);
+    w.sd.reserve(8 * (size_t)g->E + 8);
+    w.so.reserve(8 * (size_t)g->E + 8);
+    CoeffArgs ca{};
+    ca.shift = w.shift.as<double>();
+    ca.LB = 1;
+    ca.LBp = 1;
+    ca.babs = w.babs.as<double>();
+    ca.rhom = w.rhom.as<double>();
+    ca.sd = w.sd.as<double>();
+    ca.so = w.so.as<double>();
+    launch_edge_coeff(mv, ca, st);
+    learned_reserve(*net, mv, 1);
+    learned_forward(*net, mv, ca.shift, ca.sd, ca.so, 1, st, activations == GRF_ACT_BF16);
+    const LearnedOps ops = learned_ops(*net);
+    GRF_HIP(hipMemcpyAsync(p_diag, ops.Pd, 8 * (size_t)g->V, hipMemcpyDeviceToDevice, st));
+    GRF_HIP(hipMemcpyAsync(q_diag, ops.Qd, 8 * (size_t)g->V, hipMemcpyDeviceToDevice, st));
+    if (g->E > 0) {
+        GRF_HIP(hipMemcpyAsync(p_edge, ops.Pq, 8 * (size_t)g->E, hipMemcpyDeviceToDevice, st));
+        GRF_HIP(hipMemcpyAsync(q_edge, ops.Qe, 8 * (size_t)g->E, hipMemcpyDeviceToDevice, st));
+    }
+    GRF_HIP(hipStreamSynchronize(st));
     GRF_API_END
 }
 
@@ -1095,7 +1136,7 @@ int grf_learned_train(grf_learned *net, grf_graph *const *graphs, int32_t n_grap
         ca.so = w.so.as<double>();
         launch_edge_coeff(mv, ca, st);
         learned_reserve(*net, mv, nl);
-        learned_forward(*net, mv, ca.shift, ca.sd, ca.so, nl, st);
+        learned_forward(*net, mv, ca.shift, ca.sd, ca.so, nl, st, false);
         const size_t off = (size_t)ws * n_samples * g.V;
         const double L_t = learned_backward(*net, mv, d.G.as<double>() + off, d.X.as<double>() + off, nl, n_samples, st);
         learned_adam(*net, lr, st);

@@ -125,8 +125,10 @@ struct LearnedOps {
     const double *Dh, *Pd, *Pq, *Qd, *Qe;
 };
 void learned_reserve(grf_learned &net, const MeshView &mv, int32_t LB);
+// bf16act: bfloat16 hidden activations (the sampler's inference forward); false: FP32
+// activations, as the training backward needs them
 void learned_forward(grf_learned &net, const MeshView &mv, const double *shift, const double *sd, const double *so,
-                     int32_t LB, hipStream_t st);
+                     int32_t LB, hipStream_t st, bool bf16act);
 LearnedOps learned_ops(grf_learned &net);
 double learned_backward(grf_learned &net, const MeshView &mv, const double *g, const double *x, int32_t LB, int64_t S,
                         hipStream_t st);

@@ -21,6 +21,7 @@ MESH = {"ceil": 0, "round": 1}
 MASS = {"lumped": 0, "consistent": 2}  # GRF_MASS_CONSISTENT_SYS
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
+ACTIVATIONS = {"fp32": 0, "bf16": 1}  # GRF_ACT_*
 PCG_MODES = {"op": 0, "guess": 1, "jacobi": 2}  # grf_stats also reports 3: "global"
 PCG_MODES_SET = 1 << 12
 KERNELS = ["noise", "coeff", "ends_fwd", "ends_bwd", "condense", "pcg", "scatter", "acc_fwd", "acc_bwd",
@@ -89,6 +90,8 @@ _SIGS = [
     ("grf_learned_destroy", C.c_int, [C.c_void_p]),
     ("grf_learned_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int64,
                                         C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.POINTER(Opts)]),
+    ("grf_learned_operators", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Opts)]),
     ("grf_learned_train", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double,
                                     C.c_int64, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                                     C.POINTER(Opts)]),
@@ -368,6 +371,20 @@ class Learned:
                                             rhs.data_ptr(), sol.data_ptr(), C.byref(loss), grad.ctypes.data,
                                             C.byref(o)))
         return loss.value, grad
+
+    def operators(self, graph, kappa: float, c_I: float, c_L: float, activations: str = "bf16", **kw):
+        """The network's operators for one shift: device float64 tensors (P_hat diagonal [V],
+        P_hat edge couplings [E], Q_hat diagonal [V], Q_hat edge couplings [E])."""
+        import torch
+
+        dev = f"cuda:{graph.device}"
+        V, E = graph.n_vertices, graph.n_edges
+        pd, qd = (torch.empty(V, dtype=torch.float64, device=dev) for _ in range(2))
+        pe, qe = (torch.empty(max(E, 1), dtype=torch.float64, device=dev) for _ in range(2))
+        o = make_opts(**kw)
+        _check(load().grf_learned_operators(self.handle, graph.handle, kappa, c_I, c_L, ACTIVATIONS[activations],
+                                            pd.data_ptr(), pe.data_ptr(), qd.data_ptr(), qe.data_ptr(), C.byref(o)))
+        return pd, pe[:E], qd, qe[:E]
 
     def train(self, graphs, kappas, beta: float, quad_step: float, n_samples: int, seed: int, n_steps: int,
               shifts_per_step: int = 16, lr: float = 1e-3, **kw) -> np.ndarray:

@@ -4,6 +4,10 @@
   matrix cores, bfloat16 weights) against the FP64 autograd oracle of the same
   network, loss and bfloat16-rounded weights: loss within 1e-4, gradient
   within 1e-3 relative (norm);
+* the network's operators P_hat, Q_hat (grf_learned_operators) against the
+  oracle's FP64 forward: FP32 activations (training's forward) within 1e-5,
+  bfloat16 activations (the sampler's forward) within 2e-2 of each array's
+  largest value;
 * PCG with any network (here an untrained, random one) reaches the oracle's
   result to the FP64 bar (1e-10): the preconditioner is SPD by construction and
   the true residual decides convergence;
@@ -73,6 +77,48 @@ def test_loss_and_gradient_match_oracle(grf, cI, cL):
         gr, gg = g_ref[o:o + n], grad[o:o + n]
         assert np.linalg.norm(gg - gr) <= 1e-3 * max(np.linalg.norm(gr), 1e-6 * np.linalg.norm(g_ref)), name
         o += n
+
+
+def _op_err(got, ref):
+    """max |got - ref| / max |ref| (values near zero are judged on the array's scale)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(got.cpu().numpy() - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+# the operators of the network against the oracle's FP64 forward (bfloat16-rounded
+# weights): FP32 activations to 1e-5 of each array's largest value (measured
+# <= 1.1e-6); bfloat16
+# activations (unit roundoff 2^-9 = 2e-3, rounded at every layer output and
+# message: at most about 6 roundings on a path through the three layers) to 2e-2
+ACT_TOL = {"fp32": 1e-5, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("activations", ["fp32", "bf16"])
+@pytest.mark.parametrize("which", ["ragged", "tree300"])
+def test_operators_match_oracle(grf, activations, which):
+    if which == "ragged":
+        V, E, L = _ragged()
+    else:  # 301 vertices: 19 full 16-row tiles and a ragged one, hubs of high degree
+        g = preferential_attachment(301, 1, lengths=(0.05, 1.7), seed=5)
+        V, E, L = g.n_vertices, g.edges, g.lengths
+    h, kappa = 0.05, 4.0
+    m = omesh.build_mesh(V, E, L, h, "round")
+    G = grf.Graph(V, E, L, h, "round")
+    theta = init_params(3, head_scale=0.3)
+    net = grf.Learned(theta)
+    worst = 0.0
+    for cI, cL in ((0.7, 1.9), (30.0, 0.02), (1e-3, 40.0)):
+        pd, pe, qd, qe = net.operators(G, kappa, cI, cL, activations=activations)
+        sd, so = ol.edge_schur(m, np.full(len(E), kappa), cI, cL)
+        f, w, D = ol.features(m, E, L, sd, so, cI, cL, np.full(V, kappa))
+        Ph, Qh, heads = ol.forward(ol.effective_params(theta), f, w, E, V)
+        _, _, p_t, p_h, rho, eta = (x.detach().numpy() for x in heads)
+        errs = [_op_err(pd, np.diag(Ph.numpy())), _op_err(pe, rho * np.sqrt(p_t * p_h)),
+                _op_err(qd, np.diag(Qh.numpy())), _op_err(qe, eta)]
+        print(f"{which} {activations} c_I={cI:g} c_L={cL:g}: P diag {errs[0]:.1e}, P edge {errs[1]:.1e}, "
+              f"Q diag {errs[2]:.1e}, Q edge {errs[3]:.1e}")
+        worst = max(worst, *errs)
+    assert worst <= ACT_TOL[activations]
 
 
 def test_learned_pcg_reaches_oracle(grf):
