@@ -93,8 +93,14 @@ PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<256, 4>", "
 # copy reads on these counters) per step, recorded for these sources only
 COUNTER_SOURCES = ["paper_2605_02670_amd/csrc/" + f for f in
                    ("blocked.hip", "pcg.hip", "sample.hip", "noise.hip", "layout.hip")]
-COUNTER_SHA = None  # sha256 over COUNTER_SOURCES when the counters below were taken
-COUNTERS = {}  # workload -> {"step_bytes": B, "kernels": {kernel id: bytes per launch}}
+COUNTER_SHA = "2b0b01a1d3850ecc604e0db74132cc6854ad5ff3c007c47944dd107529936f9c"  # sha256 over COUNTER_SOURCES when the counters below were taken
+# workload -> {"step_bytes": B, "kernels": {kernel id: bytes per launch}}, from the two counter passes
+# of profiles/grf_sample_batched64_S32_hbm_counters.md and grf_sample_lattice64_S256_hbm_counters.md
+COUNTERS = {
+    "batched64": {"step_bytes": 586382065550, "kernels": {"table": 65915942902}},
+    "lattice64_beta0.6": {"step_bytes": 86993738990, "kernels": {"ends_bwd": 19619765251, "ends_fwd": 15203152349,
+                                                                 "table": 12284347246}},
+}
 
 
 def _sources_sha() -> str:
@@ -193,6 +199,14 @@ def roofline(st: dict, n_dof: int, n_interior: int, n_vertices: int, n_edges: in
             "launches_per_step": (nl[kid] if kid in nl else st["pcg_class_launches"][int(kid[-1])]),
             "work_per_launch": work, "work_rule": rule,
             "share_of_step": tot / max(1e-9, sum(ms.values()))}
+
+
+def with_traffic(roof: dict, workload: str) -> dict:
+    """roofline["traffic"]: the dominant kernel's counter bytes per launch, when counters were taken
+    on these sources for this workload and kernel (else None)."""
+    c = _counters(workload)
+    roof["traffic"] = None if c is None else c["kernels"].get(roof["kernel_id"])
+    return roof
 
 
 def step_hbm(n_dof: int, n_interior: int, L: int, S: int, n_passes: int, mode: str, step_ms: float,
@@ -442,7 +456,7 @@ def bench_batched(args, with_forms: bool = True) -> dict:
         base = forms["plain_per_graph"]["value"]
         forms["speedup_vs_plain_per_graph"] = {k: forms[k]["value"] / base for k in forms
                                                if k.startswith("batch_")}
-    roof = roofline(stk, n_dof, n_int, n_v, n_e, L, S, "mixed")
+    roof = with_traffic(roofline(stk, n_dof, n_int, n_v, n_e, L, S, "mixed"), "batched64")
     res = {"value": head["value"], "ms_per_step": head["ms_per_step"], "median_ms": head["median_ms"],
            "n_dof": n_dof, "shifts": L, "samples": S, "graphs": len(Gs), "shift_block": st_h["shift_block"],
            "roofline": roof, "kernel_ms_per_step": {k: v for k, v in stk["kernel_ms"].items() if v > 0},
@@ -485,7 +499,8 @@ def bench_lattice64(args, beta: float, with_forms: bool = True) -> dict:
            "pcg": {"mean_iterations": st["total_iterations"] / max(1, st["n_systems"]),
                    "max_iterations": st["max_iterations"]},
            "kernel_ms_per_step": {k: v for k, v in stk["kernel_ms"].items() if v > 0},
-           "roofline": roofline(stk, G.n_dof, G.n_interior, g.n_vertices, g.edges.shape[0], L, S, "fp64"),
+           "roofline": with_traffic(roofline(stk, G.n_dof, G.n_interior, g.n_vertices, g.edges.shape[0], L, S, "fp64"),
+                                    f"lattice64_beta{beta}"),
            "hbm": step_hbm(G.n_dof, G.n_interior, L, S, stk["kernel_launches"]["condense"], "fp64", dt * 1e3,
                            f"lattice64_beta{beta}"),
            "workload": f"lattice64x64 U[0.5,1.5] h=1/256 kappa=10 beta={beta} k=0.3 S={S} FP64 Jacobi tol 1e-12"}

@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) k_to_interleaved(const double *__restrict
     }
 }
 
-// X[b][j][lane] -> out[s][j] for s < S
+// X[b][j][lane] -> out[s][j] for s < S (lanes of padding samples are not read)
 __global__ void __launch_bounds__(256) k_from_interleaved(const double *__restrict__ X, int64_t S, int64_t N,
                                                           double *__restrict__ out) {
     __shared__ double tile[kT][kT + 1];
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_from_interleaved(const double *__restri
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int ji = ty; ji < kT; ji += 4) {
         int64_t j = j0 + ji;
-        tile[ji][tx] = (j < N) ? X[(b * N + j) * 64 + tx] : 0.0;
+        tile[ji][tx] = (j < N && b * kT + tx < S) ? X[(b * N + j) * 64 + tx] : 0.0;  // no padding lanes read
     }
     __syncthreads();
     for (int si = ty; si < kT; si += 4) {
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_from_interleaved_seg(const double *__re
     for (int ji = ty; ji < kT; ji += 4) {
         const int64_t j = j0 + ji;
         const int64_t row = j < ni ? ri + j : rv + (j - ni);
-        tile[ji][tx] = (j < n) ? X[(b * N + row) * 64 + tx] : 0.0;
+        tile[ji][tx] = (j < n && b * kT + tx < S) ? X[(b * N + row) * 64 + tx] : 0.0;  // no padding lanes read
     }
     __syncthreads();
     for (int si = ty; si < kT; si += 4) {

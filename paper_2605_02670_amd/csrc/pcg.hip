@@ -994,6 +994,9 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int v0 = blockIdx.x * 64;
     const int b = blockIdx.y;
+    // lanes read by the recovery sweeps: the samples rounded up to a 16-sample wavefront
+    // (padding lanes among them get 0); lanes past them are not written
+    const bool lw = (int64_t)b * 64 + lane < ((S + 15) / 16) * 16;
     double acc[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0;
@@ -1010,14 +1013,14 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
             const int vi = wv + 4 * i;
             const int v = v0 + vi;
             const double val = tile[lane][vi];
-            if (v < mv.V) ug[((int64_t)l * mv.V + v) * Sp + (int64_t)b * 64 + lane] = val;
+            if (v < mv.V && lw) ug[((int64_t)l * mv.V + v) * Sp + (int64_t)b * 64 + lane] = val;
             acc[i] += val;
         }
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int v = v0 + wv + 4 * i;
-        if (v < mv.V) U[((int64_t)b * mv.N + mv.NI + v) * 64 + lane] += acc[i];
+        if (v < mv.V && lw) U[((int64_t)b * mv.N + mv.NI + v) * 64 + lane] += acc[i];
     }
 }
 
