@@ -62,8 +62,8 @@ PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32_mfma": 157.3}
 # Algorithmic FP64/FP32 flops per (interior DOF, real shift, sample) of the edge
 # work, 10 in all (the plain Thomas solve and recovery of one DOF-shift-solve):
 # the solve of T w = W (forward elimination 2, back substitution 3) split evenly
-# over the two directions of pass A, and pass B's two end-column updates (4)
-# plus the accumulation into u (1).
+# over the two directions of pass A (5 for the blocked launch that runs both), and
+# pass B's two end-column updates (4) plus the accumulation into u (1).
 EDGE_FLOPS = {"ends_fwd": 2.5, "ends_bwd": 2.5, "acc_fwd": 5.0}
 # Algorithmic HBM bytes of the streaming steps, per unit:
 #   noise    8 per (DOF, sample) written
@@ -80,9 +80,9 @@ PCG_FLOPS_PER_END, PCG_FLOPS_PER_VERTEX = 2.0, 11.0
 
 def _hip_kernels(mode: str) -> dict:
     if mode == "mixed":
-        return {"ends_fwd": "k_sweep_blocked32<NT, true>", "ends_bwd": "k_sweep_blocked32<NT, false>",
+        return {"ends_fwd": "k_sweep_blocked32<NT>", "ends_bwd": "k_sweep_ends<BL, false>",
                 "acc_fwd": "k_corr_blocked32<NT>", "table": "k_blocktab<float, PACK>"}
-    return {"ends_fwd": "k_sweep_blocked<NT, true>", "ends_bwd": "k_sweep_blocked<NT, false>",
+    return {"ends_fwd": "k_sweep_blocked<NT>", "ends_bwd": "k_sweep_ends<BL, false>",
             "acc_fwd": "k_corr_blocked<NT>", "table": "k_blocktab<double, PACK>"}
 
 
@@ -170,9 +170,11 @@ def roofline(st: dict, n_dof: int, n_interior: int, n_vertices: int, n_edges: in
     ms, nl = st["kernel_ms"], st["kernel_launches"]
     for k in ("ends_fwd", "ends_bwd", "acc_fwd"):
         if nl[k]:
-            w = EDGE_FLOPS[k] * n_interior * L * S
+            # the blocked pass A runs both directions in one launch (no separate backward launches)
+            fl = EDGE_FLOPS[k] * (2 if k == "ends_fwd" and not nl["ends_bwd"] else 1)
+            w = fl * n_interior * L * S
             cands.append((ms[k], k, names[k], "mfma", w / nl[k], ms[k] / nl[k], "TFLOP/s", flops_peak,
-                          f"{EDGE_FLOPS[k]} flops per (interior DOF, shift, sample)"))
+                          f"{fl} flops per (interior DOF, shift, sample)"))
     hb = {"noise": (8.0 * n_dof * S, "8 B per (DOF, sample)", "k_noise"),
           "coeff": (32.0 * n_edges * L, "32 B per (edge, shift)", "k_edge_coeff"),
           "table": ((4.0 if mode == "mixed" else 8.0) * n_interior * L,

@@ -87,8 +87,9 @@ enum grf_kernel_id {
     GRF_K_NOISE = 0,     /* lumped white noise */
     GRF_K_COEFF = 1,     /* per-(shift, edge) Thomas rows and Schur blocks (k_edge_coeff, or the
                             streamed path's rows) */
-    GRF_K_ENDS_FWD = 2,  /* condensed-rhs sweep, head ends */
-    GRF_K_ENDS_BWD = 3,  /* condensed-rhs sweep, tail ends */
+    GRF_K_ENDS_FWD = 2,  /* condensed-rhs sweeps: blocked, both directions in one launch;
+                            streamed, the forward sweep (head ends) */
+    GRF_K_ENDS_BWD = 3,  /* condensed-rhs sweep, streamed: the backward sweep (tail ends) */
     GRF_K_CONDENSE = 4,  /* vertex right-hand sides */
     GRF_K_PCG = 5,       /* vertex Schur PCG */
     GRF_K_SCATTER = 6,   /* vertex solutions to the sample layout */

@@ -435,19 +435,16 @@ __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70
 // (the forward pass of the first shift block) the accumulator is written,
 // not updated.
 template <int NT, bool FWD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sweep_blocked(const int64_t *__restrict__ off_,
-                                                       const int32_t *__restrict__ m_,
-                                                       const int32_t *__restrict__ boff, int32_t E, int64_t N,
-                                                       int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
-                                                       const double *__restrict__ tab, const double *__restrict__ X,
-                                                       double *__restrict__ U, const double *__restrict__ rhom,
-                                                       double *__restrict__ ends, int32_t first, int64_t S) {
+__device__ __forceinline__ void sweep_blocked_dir(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
+                                                  const int32_t *__restrict__ boff, int32_t E, int64_t N, int32_t nb,
+                                                  int32_t Sp, int32_t LB, int32_t LBp, const double *__restrict__ tab,
+                                                  const double *__restrict__ X, double *__restrict__ U,
+                                                  const double *__restrict__ rhom, double *__restrict__ ends,
+                                                  int32_t first, int64_t S, double *__restrict__ sbuf, int64_t wg) {
     constexpr int TS = 528 * NT + 256;  // doubles per buffer
     constexpr int N1 = 512 * NT;        // first contiguous range
-    __shared__ double sbuf[2 * TS];
     const int L = threadIdx.x & 63;
     const int wv = wave_id();
-    const int64_t wg = xcd_logical_block();
     // nb: workgroups per edge; a workgroup of nw wavefronts covers 16 nw samples, wavefront
     // wv the 16 samples of group g (64-sample block b of the layout, quarter g & 3)
     const int nw = (int)(blockDim.x >> 6);
@@ -581,6 +578,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         }
 }
 
+// Pass A, both directions in one launch: a workgroup runs the forward sweep of
+// its (edge, samples), then the backward one over the same edge, whose reads of
+// W and of the forward part of u_I then come from the caches rather than HBM.
+// The barrier between them publishes the forward part (written by other lanes
+// of the same wavefronts) and frees the staging buffers.
+template <int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_sweep_blocked(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
+                int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp, const double *__restrict__ tab,
+                const double *__restrict__ X, double *__restrict__ U, const double *__restrict__ rhom,
+                double *__restrict__ ends, int32_t first, int64_t S) {
+    __shared__ double sbuf[2 * (528 * NT + 256)];
+    const int64_t wg = xcd_logical_block();
+    sweep_blocked_dir<NT, true>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, first, S, sbuf, wg);
+    __syncthreads();
+    sweep_blocked_dir<NT, false>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, 0, S, sbuf, wg);
+}
+
 // Pass B: u_I += sum_l |b_l| (u_tail^l Z_tail^l + u_head^l Z_head^l), with
 // Z_tail = (T^{-1})_{.,0} and Z_head = (T^{-1})_{.,m-1} in operand layout
 // ([t][r][64] tail, then [t][r][64] head, 512 NT doubles per block), staged
@@ -691,17 +706,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 // carried state Y[t] item r of lane L is shift 16t + 4 (L/16) + r and the
 // block output item r of lane L is position 4 (L/16) + r.
 template <int NT, bool FWD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
-k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
-                  int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
-                  const float *__restrict__ tab, const double *__restrict__ X, double *__restrict__ U,
-                  const double *__restrict__ rhom, double *__restrict__ ends, int32_t first, int64_t S) {
+__device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
+                                                    const int32_t *__restrict__ boff, int32_t E, int64_t N, int32_t nb,
+                                                    int32_t Sp, int32_t LB, int32_t LBp, const float *__restrict__ tab,
+                                                    const double *__restrict__ X, double *__restrict__ U,
+                                                    const double *__restrict__ rhom, double *__restrict__ ends,
+                                                    int32_t first, int64_t S, float *__restrict__ sbuf, int64_t wg) {
     constexpr int TS = 528 * NT + 256;  // floats per buffer
     constexpr int N1 = 512 * NT;
-    __shared__ float sbuf[2 * TS];
     const int L = threadIdx.x & 63;
     const int wv = wave_id();
-    const int64_t wg = xcd_logical_block();
     // nb: workgroups per edge; a workgroup of nw wavefronts covers 16 nw samples, wavefront
     // wv the 16 samples of group g (64-sample block b of the layout, quarter g & 3)
     const int nw = (int)(blockDim.x >> 6);
@@ -834,6 +848,20 @@ k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ 
         }
 }
 
+// Pass A with FP32 operands, both directions in one launch (as k_sweep_blocked).
+template <int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
+k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
+                  int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
+                  const float *__restrict__ tab, const double *__restrict__ X, double *__restrict__ U,
+                  const double *__restrict__ rhom, double *__restrict__ ends, int32_t first, int64_t S) {
+    __shared__ float sbuf[2 * (528 * NT + 256)];
+    const int64_t wg = xcd_logical_block();
+    sweep_blocked32_dir<NT, true>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, first, S, sbuf, wg);
+    __syncthreads();
+    sweep_blocked32_dir<NT, false>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, 0, S, sbuf, wg);
+}
+
 template <int NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
 k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ eu_,
@@ -942,25 +970,15 @@ static int32_t sweep_groups(int64_t S) {
 }
 
 template <int NT>
-void sweep_nt(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
+void sweep_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const int32_t wpe = sweep_groups(a.S);
     const dim3 grid((unsigned)(mv.E * (int64_t)wpe)), block((unsigned)(64 * sweep_waves(a.S)));
-    if (a.mixed) {
-        if (fwd)
-            hipLaunchKernelGGL((k_sweep_blocked32<NT, true>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                               wpe, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first, a.S);
-        else
-            hipLaunchKernelGGL((k_sweep_blocked32<NT, false>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E,
-                               mv.N, wpe, a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, 0, a.S);
-        GRF_LAUNCH_CHECK();
-        return;
-    }
-    if (fwd)
-        hipLaunchKernelGGL((k_sweep_blocked<NT, true>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           wpe, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);
+    if (a.mixed)
+        hipLaunchKernelGGL((k_sweep_blocked32<NT>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe, a.Sp,
+                           a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first, a.S);
     else
-        hipLaunchKernelGGL((k_sweep_blocked<NT, false>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N,
-                           wpe, a.Sp, a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, 0, a.S);
+        hipLaunchKernelGGL((k_sweep_blocked<NT>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe, a.Sp,
+                           a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);
     GRF_LAUNCH_CHECK();
 }
 
@@ -1044,10 +1062,10 @@ void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
         default: GRF_REQUIRE(false, "internal: NT out of range");  \
     }
 
-void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st) {
+void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     if (mv.E == 0 || a.LB == 0) return;
     GRF_REQUIRE(mv.E * (int64_t)sweep_groups(a.S) < (int64_t(1) << 31), "too many edge x sample-block workgroups");
-#define CALL_SWEEP(K) sweep_nt<K>(mv, a, fwd, st)
+#define CALL_SWEEP(K) sweep_nt<K>(mv, a, st)
     GRF_NT_SWITCH(a.NT, CALL_SWEEP)
 #undef CALL_SWEEP
 }

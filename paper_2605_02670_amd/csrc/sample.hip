@@ -275,11 +275,8 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
             T.begin(GRF_K_TABLE);
             launch_blocktab(mv, ba, st);
             T.end();
-            T.begin(GRF_K_ENDS_FWD);
-            launch_sweep_blocked(mv, ba, true, st);
-            T.end();
-            T.begin(GRF_K_ENDS_BWD);
-            launch_sweep_blocked(mv, ba, false, st);
+            T.begin(GRF_K_ENDS_FWD);  // both directions
+            launch_sweep_blocked(mv, ba, st);
             T.end();
         } else {
             T.begin(GRF_K_ENDS_FWD);

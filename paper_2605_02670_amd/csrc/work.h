@@ -107,7 +107,8 @@ struct BlockArgs {
 int64_t block_tab_doubles(int32_t NT);
 void launch_block_map(const int32_t *boff, int64_t E, int2 *bmap, hipStream_t st);
 void launch_blocktab(const MeshView &mv, const BlockArgs &a, hipStream_t st);
-void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, bool fwd, hipStream_t st);
+// pass A, both directions in one launch
+void launch_sweep_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st);
 void launch_corr_blocked(const MeshView &mv, const BlockArgs &a, hipStream_t st);
 
 // mixed-precision refinement (mixed.hip): R = B - A X on the interleaved layout (A of one shift),

@@ -55,3 +55,8 @@ def test_roofline_picks_the_dominant_kernel_and_counts_its_work():
     r = bench.roofline(st, 1000, 900, 100, 200, 40, 64, "mixed")
     assert r["kernel_id"] == "pcg_class5" and r["bound"] == "alu" and r["launches_per_step"] == 2
     assert abs(r["work_per_launch"] - (2 * 3000 + 11 * 1000) / 2) < 1e-9
+    # the blocked pass A runs both directions in one launch: 5 flops per unit
+    st = _stats({"ends_fwd": 12.0, "acc_fwd": 4.0}, {"ends_fwd": 2, "acc_fwd": 2})
+    r = bench.roofline(st, 1000, 900, 100, 200, 40, 64, "fp64")
+    assert r["kernel_id"] == "ends_fwd" and abs(r["work_per_launch"] - 5.0 * 900 * 40 * 64 / 2) < 1e-6
+    assert bench.with_traffic(dict(r), "no such workload")["traffic"] is None
