@@ -833,13 +833,19 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
             }
             if (U.flags & GRF_MASS_CONSISTENT_SYS) cand = {{32, 0}, {64, 0}, {32, 64}};  // streamed sweeps only
             grf_opts t = run;
-            if (has_given) t.pcg_class_modes = 0;  // the sweeps are tuned with the default variants
+            if (has_given) t.pcg_class_modes = 0;
+            // the sweeps are tuned with Jacobi PCG in every size class (the choice of sweep form
+            // and shift block does not depend on the PCG variant, and the learned variants would
+            // add their forward pass and their own run-to-run spread to every trial)
+            int8_t jac[kPcgClasses];
+            for (int c = 0; c < kPcgClasses; ++c) jac[c] = CM_JACOBI;
+            const int8_t *tmode = o.precond == GRF_PRECOND_LEARNED ? jac : nullptr;
             double best = 0.0;
             for (size_t c = 0; c < cand.size(); ++c) {
                 t.sweep_block = cand[c].first;
                 t.shift_block = cand[c].second;
-                if (c == 0) (void)timed_run(B, sh, n_samples, seed, t);  // first launches of the kernels
-                const double ms = timed_run(B, sh, n_samples, seed, t);
+                if (c == 0) (void)timed_run(B, sh, n_samples, seed, t, tmode);  // first launches of the kernels
+                const double ms = timed_run(B, sh, n_samples, seed, t, tmode);
                 if (c == 0 || ms < best) {
                     best = ms;
                     B.sweep_block = t.sweep_block;
