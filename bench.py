@@ -93,14 +93,14 @@ PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<256, 4>", "
 # copy reads on these counters) per step, recorded for these sources only
 COUNTER_SOURCES = ["paper_2605_02670_amd/csrc/" + f for f in
                    ("blocked.hip", "pcg.hip", "sample.hip", "noise.hip", "layout.hip")]
-COUNTER_SHA = "2b0b01a1d3850ecc604e0db74132cc6854ad5ff3c007c47944dd107529936f9c"  # sha256 over COUNTER_SOURCES when the counters below were taken
+COUNTER_SHA = "f3e414171c2f961504af544a128d872566bc96d1728a375e115b98ff7236dc3e"  # sha256 over COUNTER_SOURCES when the counters below were taken
 # workload -> {"step_bytes": B, "kernels": {kernel id: bytes per launch}}, from the two counter passes
 # of profiles/grf_sample_batched64_S32_hbm_counters.md and grf_sample_lattice64_S256_hbm_counters.md
 COUNTERS = {
-    "batched64": {"step_bytes": 586382065550, "kernels": {"table": 65915942902}},
-    "lattice64_beta0.6": {"step_bytes": 86993738990, "kernels": {"ends_bwd": 19619765251, "ends_fwd": 15203152349,
-                                                                 "table": 12284347246}},
+    "batched64": {"step_bytes": 572057754226, "kernels": {"ends_fwd": 95359330334, "table": 65911912614}},
+    "lattice64_beta0.6": {"step_bytes": 87643254906, "kernels": {"ends_fwd": 35456881879, "table": 12284291975}},
 }
+
 
 
 def _sources_sha() -> str:

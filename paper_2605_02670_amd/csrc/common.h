@@ -114,6 +114,9 @@ struct MeshView {
     int32_t maxVg, maxEg;  // largest graph of the batch (host-side dispatch)
     int32_t consistent;    // shifted systems with the consistent mass matrix (GRF_MASS_CONSISTENT_SYS)
     int64_t maxNg;
+    // 64-DOF tiles of the batch's graphs: graph g's tiles are tile0[g] .. tile0[g+1]-1
+    const int64_t *tile0;  // [ng+1]
+    int64_t ntiles;
     // first four edge ends of every vertex (column-major [4][V]: the other vertex, or the
     // vertex itself past its degree; eend: 2 edge + side, or -1 past the degree) and the degree
     const int32_t *ell, *eend, *deg;
@@ -168,7 +171,8 @@ struct grf_graph {
     std::vector<int64_t> segs;
     int32_t max_deg = 0, maxVg = 0, maxEg = 0;
     int64_t maxNg = 0;
-    grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_eend, d_deg;
+    std::vector<int64_t> tile0;  // [ng+1] first 64-DOF tile of every graph
+    grf::DevBuf d_gv0, d_ge0, d_segs, d_ell, d_eend, d_deg, d_tile0;
     std::vector<int32_t> gord;
     int32_t cls_off[grf::kPcgClasses + 2] = {};
     grf::DevBuf d_gord, d_ell16, d_ovfm, d_prow, d_pvtx, d_pell, d_padj;

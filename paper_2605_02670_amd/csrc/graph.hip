@@ -205,6 +205,7 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     const int64_t ng = (int64_t)g.gv0.size() - 1;
     g.segs.assign(4 * ng, 0);
+    g.tile0.assign(ng + 1, 0);
     g.maxVg = g.maxEg = 0;
     g.maxNg = 0;
     for (int64_t k = 0; k < ng; ++k) {
@@ -217,6 +218,7 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
         g.maxVg = std::max<int32_t>(g.maxVg, (int32_t)vk);
         g.maxEg = std::max<int32_t>(g.maxEg, g.ge0[k + 1] - g.ge0[k]);
         g.maxNg = std::max<int64_t>(g.maxNg, g.segs[4 * k]);
+        g.tile0[k + 1] = g.tile0[k] + (g.segs[4 * k] + 63) / 64;
     }
     g.max_deg = 0;
     for (int64_t u = 0; u < g.V; ++u) g.max_deg = std::max<int32_t>(g.max_deg, (int32_t)(g.vptr[u + 1] - g.vptr[u]));
@@ -364,6 +366,7 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     upload(g.d_gv0, g.gv0, s);
     upload(g.d_ge0, g.ge0, s);
     upload(g.d_segs, g.segs, s);
+    upload(g.d_tile0, g.tile0, s);
     g.d_kap2.reserve(sizeof(double) * (g.E + 1));
     g.kap2_loaded = -1.0;
     GRF_HIP(hipStreamSynchronize(s));
@@ -451,6 +454,8 @@ grf::MeshView grf_graph::view() const {
     v.maxVg = maxVg;
     v.maxEg = maxEg;
     v.maxNg = maxNg;
+    v.tile0 = d_tile0.as<int64_t>();
+    v.ntiles = tile0.empty() ? 0 : tile0.back();
     v.ell = d_ell.as<int32_t>();
     v.eend = d_eend.as<int32_t>();
     v.deg = d_deg.as<int32_t>();

@@ -51,28 +51,37 @@ __global__ void k_fill(double *__restrict__ p, size_t n, double v) {
         p[i] = v;
 }
 
-// Graph z of a batch (blockIdx.z): X[b][row(j)][lane] -> outs[z][s][j], local DOF j
-// of the graph at row ri + j (interior) or rv + j - ni (vertices)
+// X[b][row][lane] -> outs[z][s][j] for every graph z of a batch, local DOF j of the
+// graph at row ri + j (interior) or rv + j - ni (vertices).  Workgroup = one 64-DOF
+// tile of one graph (the tiles of all graphs numbered in a row, tile0), 64 samples.
 __global__ void __launch_bounds__(256) k_from_interleaved_seg(const double *__restrict__ X, int64_t S, int64_t N,
                                                               const int64_t *__restrict__ segs,
-                                                              double *const *__restrict__ outs) {
+                                                              const int64_t *__restrict__ tile0, int32_t ng,
+                                                              int64_t ntiles, double *const *__restrict__ outs) {
     __shared__ double tile[kT][kT + 1];
-    const int64_t z = blockIdx.z;
-    const int64_t n = segs[4 * z], ni = segs[4 * z + 1], ri = segs[4 * z + 2], rv = segs[4 * z + 3];
-    const int64_t j0 = (int64_t)blockIdx.x * kT;
-    if (j0 >= n) return;  // uniform over the workgroup
-    double *out = outs[z];
     const int64_t b = blockIdx.y;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int ji = ty; ji < kT; ji += 4) {
-        const int64_t j = j0 + ji;
-        const int64_t row = j < ni ? ri + j : rv + (j - ni);
-        tile[ji][tx] = (j < n && b * kT + tx < S) ? X[(b * N + row) * 64 + tx] : 0.0;  // no padding lanes read
-    }
-    __syncthreads();
-    for (int si = ty; si < kT; si += 4) {
-        const int64_t s = b * kT + si, j = j0 + tx;
-        if (s < S && j < n) out[s * n + j] = tile[tx][si];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int lo = 0, hi = ng;  // tile0[lo] <= t < tile0[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tile0[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int64_t z = lo;
+        const int64_t n = segs[4 * z], ni = segs[4 * z + 1], ri = segs[4 * z + 2], rv = segs[4 * z + 3];
+        const int64_t j0 = (t - tile0[z]) * kT;
+        double *out = outs[z];
+        for (int ji = ty; ji < kT; ji += 4) {
+            const int64_t j = j0 + ji;
+            const int64_t row = j < ni ? ri + j : rv + (j - ni);
+            tile[ji][tx] = (j < n && b * kT + tx < S) ? X[(b * N + row) * 64 + tx] : 0.0;  // no padding lanes read
+        }
+        __syncthreads();
+        for (int si = ty; si < kT; si += 4) {
+            const int64_t s = b * kT + si, j = j0 + tx;
+            if (s < S && j < n) out[s * n + j] = tile[tx][si];
+        }
+        __syncthreads();  // the tile is rewritten by the next pass
     }
 }
 
@@ -99,11 +108,11 @@ void launch_fill_rows(double *p, int64_t nb, int64_t N, int64_t r0, int64_t nrow
 void launch_from_interleaved_seg(const MeshView &mv, const double *X, int64_t S, double *const *outs,
                                  hipStream_t st) {
     const int64_t nb = (S + 63) / 64;
-    if (nb == 0 || mv.maxNg == 0) return;
-    GRF_REQUIRE((mv.maxNg + kT - 1) / kT < (int64_t(1) << 31) && nb < 65536 && mv.ng < 65536, "batch too large");
-    hipLaunchKernelGGL(k_from_interleaved_seg, dim3((unsigned)((mv.maxNg + kT - 1) / kT), (unsigned)nb,
-                                                    (unsigned)mv.ng),
-                       dim3(256), 0, st, X, S, mv.N, mv.segs, outs);
+    if (nb == 0 || mv.ntiles == 0) return;
+    GRF_REQUIRE(nb < 65536, "batch too large");
+    const int64_t gx = std::min<int64_t>(mv.ntiles, int64_t(1) << 20);
+    hipLaunchKernelGGL(k_from_interleaved_seg, dim3((unsigned)gx, (unsigned)nb), dim3(256), 0, st, X, S, mv.N,
+                       mv.segs, mv.tile0, mv.ng, mv.ntiles, outs);
     GRF_LAUNCH_CHECK();
 }
 
