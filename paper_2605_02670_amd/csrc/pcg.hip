@@ -712,8 +712,12 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     // Jacobi-preconditioned iterations spread the overflow slots of the S^ products over
     // the workgroup (ovf_pieces) when the piece sums fit in LDS past p; otherwise (and for
     // every P^ and Q^ product) the owner of a vertex adds its own overflow slots
-    const int npc = LP ? 0 : mv.ovnp[gi];
-    const bool dov = npc > 0 && nv + npc <= ldsd;
+    // (with the operator preconditioner the piece sums sit past p inside p's region, r follows
+    // it; there they pay except in the 512-thread class: measured on the 64-graph batch with
+    // the learned operator, class 2 13.0 against 14.9 ms, class 3 57.1 against 52.9 ms,
+    // class 4 40.6 against 69.5 ms)
+    const int npc = (LP && TPB == 512) ? 0 : mv.ovnp[gi];
+    const bool dov = npc > 0 && nv + npc <= (LP ? cap : ldsd);
     const uint32_t om = dov ? 0u : om_all;
     double *psum = ps + nv;
     GroupSum<TPB> gsum{red, 0};
@@ -779,7 +783,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                 if (!group_live<TPB>(i0, nv)) continue;
                 const IG it(i0, nv);
                 double z[G];
-                ell_group<G, false>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om, i0, z);
+                ell_group<G, false>(mv, Pd, Pc, Po, rs, it.vc, it.ok, u0, om_all, i0, z);  // owners add overflow
 #pragma unroll
                 for (int e = 0; e < G; ++e) {
                     q[i0 + e] = z[e];
@@ -930,6 +934,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
             double rz_new = t3[0];
             if (LP && lz) {
                 double t4[1] = {0.0};
+                // the overflow slots of P^ r^ spread over the workgroup as for S^ p (r^ is
+                // complete in LDS behind the last sum; the S^ pieces were added before it)
+                if (dov) ovf_pieces<TPB, true>(mv, gi, Po, rs, psum, t4[0]);
 #pragma unroll
                 for (int i0 = 0; i0 < K; i0 += G) {
                     if (!group_live<TPB>(i0, nv)) continue;
@@ -942,7 +949,15 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
                         t4[0] += r[i0 + e] * z[e];
                     }
                 }
-                gsum(t4);
+                gsum(t4);  // also: the piece sums complete
+                if (dov) {
+#pragma unroll
+                    for (int i0 = 0; i0 < K; i0 += G) {
+                        if (!group_live<TPB>(i0, nv) || !((om_all >> i0) & 1u)) continue;
+                        const IG it(i0, nv);
+                        ovf_add<G, K>(mv, psum, it.vc, it.ok, u0, q, i0);
+                    }
+                }
                 rz_new = t4[0];
             }
             const double beta = rz_new / rz;
