@@ -55,17 +55,23 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     const int v0 = blockIdx.x * 64;
     const int b = blockIdx.y;
     const int l = blockIdx.z;
-    const bool real = (int64_t)b * 64 + lane < S;  // padding samples load nothing
-    const double *el = ends + (int64_t)l * 2 * mv.E * Sp + (int64_t)b * 64 + lane;  // row 2 e + side
-    for (int vb = wv; vb < 64; vb += 16) {
+    // a block of at most 32 real samples takes two vertices per wavefront step (lanes 0-31
+    // and 32-63), so that no half of the wavefront only waits
+    const int64_t Sb = S - (int64_t)b * 64 < 64 ? S - (int64_t)b * 64 : 64;
+    const int nvw = Sb <= 32 ? 2 : 1, lpv = 64 / nvw;
+    const int sl = lane & (lpv - 1), hv = lane / lpv;
+    const bool real = sl < Sb;  // padding samples load nothing
+    const double *el = ends + (int64_t)l * 2 * mv.E * Sp + (int64_t)b * 64 + sl;  // row 2 e + side
+    // tile vertex vb + 4 nvw q (q < 4) of step k: vb = nvw wv + hv + 16 nvw k covers the 64 once
+    for (int vb = nvw * wv + hv; vb < 64; vb += 16 * nvw) {
         double g[4] = {0.0, 0.0, 0.0, 0.0};
         if (real) {  // one lane mask per step; inside it no branch until the loads are issued
             int vc[4], id[4][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int v = v0 + vb + 4 * q;
+                const int v = v0 + vb + 4 * nvw * q;
                 vc[q] = min(v, mv.V - 1);
-                const double x = X[((int64_t)b * mv.N + mv.NI + vc[q]) * 64 + lane];
+                const double x = X[((int64_t)b * mv.N + mv.NI + vc[q]) * 64 + sl];
                 g[q] = v < mv.V ? x : 0.0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) id[q][j] = v < mv.V ? mv.eend[(int64_t)j * mv.V + vc[q]] : -1;
@@ -79,7 +85,7 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
                 }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int v = v0 + vb + 4 * q;
+                const int v = v0 + vb + 4 * nvw * q;
                 if (v < mv.V && mv.deg[vc[q]] > 4) {
                     // the loads of eight slots in flight together, added in slot order
                     int64_t k = mv.vptr[v] + 4;
@@ -99,7 +105,7 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tile[vb + 4 * q][lane] = g[q];
+        for (int q = 0; q < 4; ++q) tile[vb + 4 * nvw * q][sl] = g[q];
     }
     __syncthreads();
     for (int si = wv; si < 64; si += 4) {
@@ -1015,9 +1021,11 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
     double acc[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    // sample rows of the tile: up to the 16-sample wavefronts of the recovery (0 past S)
+    const int64_t rows = min((int64_t)64, ((S - (int64_t)b * 64 + 15) / 16) * 16);
     for (int l = 0; l < LB; ++l) {
         __syncthreads();
-        for (int si = wv; si < 64; si += 4) {
+        for (int si = wv; si < rows; si += 4) {
             const int64_t s = (int64_t)b * 64 + si;
             const int v = v0 + lane;
             tile[si][lane] = (s < S && v < mv.V) ? xT[((int64_t)l * S + s) * mv.V + v] : 0.0;
