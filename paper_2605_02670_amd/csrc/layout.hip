@@ -61,6 +61,10 @@ __global__ void __launch_bounds__(256) k_from_interleaved_seg(const double *__re
     __shared__ double tile[kT][kT + 1];
     const int64_t b = blockIdx.y;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    // a block of at most 32 real samples reads two DOF rows per wavefront step
+    const int64_t Sb = S - b * kT < kT ? S - b * kT : kT;
+    const int nvw = Sb <= 32 ? 2 : 1;
+    const int sl = tx & (kT / nvw - 1), hv = tx / (kT / nvw);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int lo = 0, hi = ng;  // tile0[lo] <= t < tile0[hi]
         while (hi - lo > 1) {
@@ -71,13 +75,13 @@ __global__ void __launch_bounds__(256) k_from_interleaved_seg(const double *__re
         const int64_t n = segs[4 * z], ni = segs[4 * z + 1], ri = segs[4 * z + 2], rv = segs[4 * z + 3];
         const int64_t j0 = (t - tile0[z]) * kT;
         double *out = outs[z];
-        for (int ji = ty; ji < kT; ji += 4) {
+        for (int ji = nvw * ty + hv; ji < kT; ji += 4 * nvw) {
             const int64_t j = j0 + ji;
             const int64_t row = j < ni ? ri + j : rv + (j - ni);
-            tile[ji][tx] = (j < n && b * kT + tx < S) ? X[(b * N + row) * 64 + tx] : 0.0;  // no padding lanes read
+            tile[ji][sl] = (j < n && sl < Sb) ? X[(b * N + row) * 64 + sl] : 0.0;  // no padding lanes read
         }
         __syncthreads();
-        for (int si = ty; si < kT; si += 4) {
+        for (int si = ty; si < Sb; si += 4) {
             const int64_t s = b * kT + si, j = j0 + tx;
             if (s < S && j < n) out[s * n + j] = tile[tx][si];
         }
