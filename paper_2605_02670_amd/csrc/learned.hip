@@ -811,6 +811,16 @@ void learned_reserve(grf_learned &net, const MeshView &mv, int32_t LB) {
     net.Qe.reserve(8 * RE + 8);
 }
 
+// Bytes of the forward's workspace (a new plan reuses it, so it counts as free memory there).
+size_t learned_held_bytes(const grf_learned &net) {
+    size_t t = 0;
+    for (const DevBuf *b : {&net.Dh, &net.w, &net.X0, &net.M0, &net.H1, &net.M1, &net.H2, &net.M2, &net.H3,
+                            &net.zd, &net.gam, &net.zt, &net.zh, &net.zr, &net.eta, &net.Pd, &net.Qd, &net.Pq,
+                            &net.Qe})
+        t += b->bytes;
+    return t;
+}
+
 // Identifies the device buffers a forward uses (weights and activations): a
 // captured graph that ran the forward stays valid while this is unchanged.
 uint64_t learned_signature(const grf_learned &net) {

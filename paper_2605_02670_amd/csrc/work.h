@@ -136,6 +136,7 @@ double learned_backward(grf_learned &net, const MeshView &mv, const double *g, c
 void learned_adam(grf_learned &net, double lr, hipStream_t st);
 void learned_copy_grad(grf_learned &net, float *host, hipStream_t st);
 uint64_t learned_signature(const grf_learned &net);
+size_t learned_held_bytes(const grf_learned &net);
 
 // vertex Schur complement: condensed rhs, PCG, layout changes, accumulation
 struct SchurArgs {
