@@ -86,7 +86,7 @@ def _hip_kernels(mode: str) -> dict:
             "acc_fwd": "k_corr_blocked<NT>", "table": "k_blocktab<double, PACK>"}
 
 
-PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<256, 4>", "k_pcg_chip<512, 8>",
+PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<128, 8>", "k_pcg_chip<512, 8>",
                "k_pcg_chip<1024, 10>", "k_pcg_chip<1024, 20>", "k_pcg_mrhs<4>"]
 
 # rocprofv3 counter bytes (FETCH_SIZE x 2 + WRITE_SIZE x 1 KiB, the factors a plain 1 GiB

@@ -87,8 +87,8 @@ constexpr int kPcgClasses = 6;
 constexpr int32_t kPcgCap[kPcgClasses] = {64, 256, 1024, 4096, 10176, 20352};
 // launch shape of each class: TPB threads, K vertices per thread (TPB K >= cap),
 // thread t owning the graph-local vertices t + TPB i
-constexpr int kChipTpb[kPcgClasses] = {64, 64, 256, 512, 1024, 1024};
-constexpr int kChipK[kPcgClasses] = {1, 4, 4, 8, 10, 20};
+constexpr int kChipTpb[kPcgClasses] = {64, 64, 128, 512, 1024, 1024};
+constexpr int kChipK[kPcgClasses] = {1, 4, 8, 8, 10, 20};
 
 struct MeshView {
     int32_t V, E;
