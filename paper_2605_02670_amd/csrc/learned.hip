@@ -16,9 +16,12 @@
 //   delta = softplus(a_d.h_v + c_d), gamma = a_g.h_v + c_g,
 //   p_u = softplus(a_p1.h_u + a_p2.h_v + c_p), p_v = softplus(a_p1.h_v + a_p2.h_u + c_p),
 //   rho = 0.95 tanh(a_r.(h_u + h_v) + c_r), eta = a_e.(h_u + h_v) + c_e.
-// Weights (matrices, head vectors) are stored and used as bfloat16; biases,
-// activations and accumulation are FP32 (the layer products on the FP32
-// matrix cores).  Training minimises, over Schur solutions x* of the method,
+// Weights (matrices, head vectors) are stored and used as bfloat16; biases and
+// accumulation are FP32.  Training's forward keeps FP32 activations (layer
+// products on the FP32 matrix cores, as its backward reads them); the sampler's
+// forward rounds the hidden activations and the messages of layers 2 and 3 to
+// bfloat16 and runs those layers on the bfloat16 matrix cores.  Training
+// minimises, over Schur solutions x* of the method,
 //   (||P_hat g_hat - x_hat||^2 + ||Q_hat g_hat - x_hat||^2) / ||x_hat||^2,
 // g_hat = D^{-1/2} g, x_hat = D^{1/2} x*, with Adam on FP32 master weights.
 #include <algorithm>
