@@ -92,7 +92,7 @@ PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<128, 8>", "
 # rocprofv3 counter bytes (FETCH_SIZE x 2 + WRITE_SIZE x 1 KiB, the factors a plain 1 GiB
 # copy reads on these counters) per step, recorded for these sources only
 COUNTER_SOURCES = ["paper_2605_02670_amd/csrc/" + f for f in
-                   ("blocked.hip", "pcg.hip", "sample.hip", "noise.hip", "layout.hip")]
+                   ("blocked.hip", "pcg.hip", "sample.hip", "noise.hip", "layout.hip", "graph.hip", "common.h")]
 COUNTER_SHA = "bb37c167edbbf44c726ef54b6752dc06f72720f84f0796f0ff76d9930d6c4d40"  # sha256 over COUNTER_SOURCES when the counters below were taken
 # workload -> {"step_bytes": B, "kernels": {kernel id: bytes per launch}}, from the two counter passes
 # of profiles/grf_sample_batched64_S32_hbm_counters.md and grf_sample_lattice64_S256_hbm_counters.md
