@@ -710,7 +710,7 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ boff, int32_t E, int64_t N, int32_t nb,
                                                     int32_t Sp, int32_t LB, int32_t LBp, const float *__restrict__ tab,
                                                     const double *__restrict__ X, double *__restrict__ U,
-                                                    const double *__restrict__ rhom, double *__restrict__ ends,
+                                                    const double *__restrict__ rhom, float *__restrict__ ends,
                                                     int32_t first, int64_t S, float *__restrict__ sbuf, int64_t wg) {
     constexpr int TS = 528 * NT + 256;  // floats per buffer
     constexpr int N1 = 512 * NT;
@@ -727,7 +727,7 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
     const int n = L & 15, kq = L >> 4;
     const int m = m_[e];
     const int side = FWD ? 1 : 0;
-    double *endp = ends + ((int64_t)e * 2 + side) * Sp + s0 + n;
+    float *endp = ends + ((int64_t)e * 2 + side) * Sp + s0 + n;
     const int64_t endstride = (int64_t)E * 2 * Sp;
     const TabLayout TL{NT};
     if (m == 0) {
@@ -736,7 +736,7 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int sh = 16 * t + 4 * kq + r;
-                if (sh < LB) endp[sh * endstride] = 0.0;
+                if (sh < LB) endp[sh * endstride] = 0.0f;
             }
         return;
     }
@@ -844,7 +844,7 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int sh = 16 * t + 4 * kq + r;
-            if (live && sh < LB) endp[sh * endstride] = rm[sh] * (double)Y[t][r];
+            if (live && sh < LB) endp[sh * endstride] = (float)(rm[sh] * (double)Y[t][r]);
         }
 }
 
@@ -854,7 +854,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
                   int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
                   const float *__restrict__ tab, const double *__restrict__ X, double *__restrict__ U,
-                  const double *__restrict__ rhom, double *__restrict__ ends, int32_t first, int64_t S) {
+                  const double *__restrict__ rhom, float *__restrict__ ends, int32_t first, int64_t S) {
     __shared__ float sbuf[2 * (528 * NT + 256)];
     const int64_t wg = xcd_logical_block();
     sweep_blocked32_dir<NT, true>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, first, S, sbuf, wg);
@@ -975,7 +975,7 @@ void sweep_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)(mv.E * (int64_t)wpe)), block((unsigned)(64 * sweep_waves(a.S)));
     if (a.mixed)
         hipLaunchKernelGGL((k_sweep_blocked32<NT>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe, a.Sp,
-                           a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends, a.first, a.S);
+                           a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends32, a.first, a.S);
     else
         hipLaunchKernelGGL((k_sweep_blocked<NT>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe, a.Sp,
                            a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);

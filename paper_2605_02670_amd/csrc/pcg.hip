@@ -47,8 +47,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds, int nwav
 // wavefront takes four vertices at a time with their first four edge ends from
 // the ELL table (all loads of a step in flight together); vertices of degree
 // > 4 add their remaining ends from the CSR lists.
+template <typename ET>
 __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__restrict__ X,
-                                                  const double *__restrict__ ends, int32_t Sp, int64_t S,
+                                                  const ET *__restrict__ ends, int32_t Sp, int64_t S,
                                                   double *__restrict__ gT) {
     __shared__ double tile[64][65];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
     const int nvw = Sb <= 32 ? 2 : 1, lpv = 64 / nvw;
     const int sl = lane & (lpv - 1), hv = lane / lpv;
     const bool real = sl < Sb;  // padding samples load nothing
-    const double *el = ends + (int64_t)l * 2 * mv.E * Sp + (int64_t)b * 64 + sl;  // row 2 e + side
+    const ET *el = ends + (int64_t)l * 2 * mv.E * Sp + (int64_t)b * 64 + sl;  // row 2 e + side
     // tile vertex vb + 4 nvw q (q < 4) of step k: vb = nvw wv + hv + 16 nvw k covers the 64 once
     for (int vb = nvw * wv + hv; vb < 64; vb += 16 * nvw) {
         double g[4] = {0.0, 0.0, 0.0, 0.0};
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double e = el[(int64_t)max(id[q][j], 0) * Sp];  // a valid row even past the degree
+                    const double e = (double)el[(int64_t)max(id[q][j], 0) * Sp];  // a valid row even past the degree
                     g[q] += id[q][j] >= 0 ? e : 0.0;
                 }
 #pragma unroll
@@ -96,11 +97,11 @@ __global__ void __launch_bounds__(256) k_condense(MeshView mv, const double *__r
 #pragma unroll
                         for (int j = 0; j < 8; ++j) id[j] = 2 * mv.adj_e[k + j] + mv.adj_s[k + j];
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) ev[j] = el[(int64_t)id[j] * Sp];
+                        for (int j = 0; j < 8; ++j) ev[j] = (double)el[(int64_t)id[j] * Sp];
 #pragma unroll
                         for (int j = 0; j < 8; ++j) g[q] += ev[j];
                     }
-                    for (; k < ke; ++k) g[q] += el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
+                    for (; k < ke; ++k) g[q] += (double)el[(int64_t)(2 * mv.adj_e[k] + mv.adj_s[k]) * Sp];
                 }
             }
         }
@@ -1106,8 +1107,11 @@ size_t pcg_ops_bytes(const MeshView &mv, int32_t LB, int32_t precond) {
 void launch_condense(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
     GRF_REQUIRE(a.LB < 65536 && a.nb < 65536, "internal: grid too large");
-    hipLaunchKernelGGL(k_condense, dim3((unsigned)((mv.V + 63) / 64), (unsigned)a.nb, (unsigned)a.LB), dim3(256), 0,
-                       st, mv, a.X, a.ends, a.Sp, a.S, a.gT);
+    const dim3 grid((unsigned)((mv.V + 63) / 64), (unsigned)a.nb, (unsigned)a.LB);
+    if (a.ends32)  // FP32 end values (mixed precision), summed in FP64
+        hipLaunchKernelGGL(k_condense<float>, grid, dim3(256), 0, st, mv, a.X, a.ends32, a.Sp, a.S, a.gT);
+    else
+        hipLaunchKernelGGL(k_condense<double>, grid, dim3(256), 0, st, mv, a.X, a.ends, a.Sp, a.S, a.gT);
     GRF_LAUNCH_CHECK();
 }
 

@@ -184,7 +184,9 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     w.rhom.reserve(8 * (size_t)g.E * LBp + 8);
     w.sd.reserve(8 * (size_t)g.E * LBp + 8);
     w.so.reserve(8 * (size_t)g.E * LBp + 8);
-    w.ends.reserve(8 * (size_t)lb * g.E * 2 * ps.Sp + 8);
+    // end values: FP32 where the FP32 sweeps write them (mixed precision, blocked)
+    const size_t eb = (ps.p.blocked && o.precision == GRF_PREC_MIXED) ? sizeof(float) : sizeof(double);
+    w.ends.reserve(eb * (size_t)lb * g.E * 2 * ps.Sp + 8);
     w.gT.reserve(8 * (size_t)lb * S * g.V);
     w.xT.reserve(8 * (size_t)lb * S * g.V);
     w.ug.reserve(8 * (size_t)lb * g.V * ps.Sp);
@@ -266,6 +268,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
             ba.X = sa.X;
             ba.U = sa.U;
             ba.ends = sa.ends;
+            ba.ends32 = w.ends.as<float>();
             ba.ug = sa.ug;
             ba.nb = nb;
             ba.Sp = Sp;
@@ -292,6 +295,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         SchurArgs sc{};
         sc.X = sa.X;
         sc.ends = sa.ends;
+        sc.ends32 = (p.blocked && o.precision == GRF_PREC_MIXED) ? w.ends.as<float>() : nullptr;
         sc.sd = ca.sd;
         sc.so = ca.so;
         sc.gT = w.gT.as<double>();

@@ -16,6 +16,7 @@ struct grf_graph::Work {
     grf::DevBuf sd, so;           // per-edge Schur 2x2 [LBp][E]: diagonal, off-diagonal
     grf::DevBuf shift;            // [LBp][2]: c_I, c_L of the shifts in the block
     grf::DevBuf ends;             // [LB][E][2][Sp]: |b| * (A_II^{-1} W_I) at both ends of every edge
+                                  // (FP32 with mixed precision)
     grf::DevBuf gT, xT;           // [LB][S][V]: condensed right-hand sides / vertex solutions
     grf::DevBuf ug;               // [LB][V][Sp]: vertex solutions, sample-interleaved
     grf::DevBuf pcg_scr;          // PCG vectors in global memory (large graphs)
@@ -97,6 +98,7 @@ struct BlockArgs {
     const double *X;        // [nb][N][64]
     double *U;              // [nb][N][64]
     double *ends;           // [LB][E][2][Sp]
+    float *ends32;          // the same, FP32 (mixed precision: written by the FP32 sweeps)
     const double *ug;       // [LB][V][Sp]
     int32_t nb, Sp;
     int32_t first;          // first shift block: the forward pass writes (not updates) the interior accumulator
@@ -142,6 +144,7 @@ size_t learned_held_bytes(const grf_learned &net);
 struct SchurArgs {
     const double *X;      // [nb][N][64] noise (vertex part used)
     const double *ends;   // [LB][E][2][Sp]
+    const float *ends32;  // the same, FP32 (mixed precision), or null
     const double *sd, *so;  // [LBp][E]
     double *gT, *xT;      // [LB][S][V]
     double *ug;           // [LB][V][Sp]
