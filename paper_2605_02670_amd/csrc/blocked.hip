@@ -867,7 +867,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4))
 k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ eu_,
                  const int32_t *__restrict__ ev_, const int32_t *__restrict__ boff, int32_t E, int32_t V, int64_t N,
                  int32_t nb, int32_t Sp, int32_t LB, int32_t LBp, const float *__restrict__ ztab,
-                 const double *__restrict__ babs, const double *__restrict__ ug, double *__restrict__ U,
+                 const double *__restrict__ babs, const float *__restrict__ ug, double *__restrict__ U,
                  int64_t S) {
     constexpr int TS = 512 * NT;
     __shared__ float sbuf[2 * TS];
@@ -898,8 +898,8 @@ k_corr_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m
             const int sh = 16 * t + 4 * kq + r;
             const int shc = min(sh, LB - 1);
             const double bb = (live && sh < LB) ? babs[(int64_t)e * LBp + sh] : 0.0;
-            ct[t][r] = live ? (float)(bb * ug[((int64_t)shc * V + vt) * Sp + s0 + n]) : 0.0f;
-            ch[t][r] = live ? (float)(bb * ug[((int64_t)shc * V + vh) * Sp + s0 + n]) : 0.0f;
+            ct[t][r] = live ? (float)(bb * (double)ug[((int64_t)shc * V + vt) * Sp + s0 + n]) : 0.0f;
+            ch[t][r] = live ? (float)(bb * (double)ug[((int64_t)shc * V + vh) * Sp + s0 + n]) : 0.0f;
         }
     stage_wait();
     __syncthreads();
@@ -988,7 +988,7 @@ void corr_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)(mv.E * (int64_t)wpe)), block((unsigned)(64 * sweep_waves(a.S)));
     if (a.mixed) {
         hipLaunchKernelGGL((k_corr_blocked32<NT>), grid, block, 0, st, mv.off, mv.m, mv.eu, mv.ev, a.boff, mv.E,
-                           mv.V, mv.N, wpe, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug, a.U, a.S);
+                           mv.V, mv.N, wpe, a.Sp, a.LB, a.LBp, a.ztab32, a.babs, a.ug32, a.U, a.S);
         GRF_LAUNCH_CHECK();
         return;
     }

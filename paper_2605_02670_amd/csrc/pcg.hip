@@ -1009,8 +1009,9 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
 
 // ug[l][v][s] = xT[l][s][v] (padded samples 0) and U[b][NI+v][s] += sum_l xT[l][s][v],
 // shifts summed in increasing order.
+template <typename GT>
 __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const double *__restrict__ xT, int32_t LB,
-                                                        int64_t S, int32_t Sp, double *__restrict__ ug,
+                                                        int64_t S, int32_t Sp, GT *__restrict__ ug,
                                                         double *__restrict__ U) {
     __shared__ double tile[64][65];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1037,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
             const int vi = wv + 4 * i;
             const int v = v0 + vi;
             const double val = tile[lane][vi];
-            if (v < mv.V && lw) ug[((int64_t)l * mv.V + v) * Sp + (int64_t)b * 64 + lane] = val;
+            if (v < mv.V && lw) ug[((int64_t)l * mv.V + v) * Sp + (int64_t)b * 64 + lane] = (GT)val;
             acc[i] += val;
         }
     }
@@ -1272,8 +1273,11 @@ static void launch_mrhs(const MeshView &mv, const SchurArgs &a, const EllOp *ops
 
 void launch_vertex_scatter(const MeshView &mv, const SchurArgs &a, hipStream_t st) {
     if (a.LB == 0 || a.S == 0) return;
-    hipLaunchKernelGGL(k_vertex_scatter, dim3((unsigned)((mv.V + 63) / 64), (unsigned)a.nb), dim3(256), 0, st, mv,
-                       a.xT, a.LB, a.S, a.Sp, a.ug, a.U);
+    const dim3 grid((unsigned)((mv.V + 63) / 64), (unsigned)a.nb);
+    if (a.ug32)  // FP32 copy for the FP32 recovery sweeps (mixed precision)
+        hipLaunchKernelGGL(k_vertex_scatter<float>, grid, dim3(256), 0, st, mv, a.xT, a.LB, a.S, a.Sp, a.ug32, a.U);
+    else
+        hipLaunchKernelGGL(k_vertex_scatter<double>, grid, dim3(256), 0, st, mv, a.xT, a.LB, a.S, a.Sp, a.ug, a.U);
     GRF_LAUNCH_CHECK();
 }
 

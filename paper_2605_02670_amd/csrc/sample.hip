@@ -189,7 +189,7 @@ static Pass prepare_pass(grf_graph &g, const std::vector<double> &cI, const std:
     w.ends.reserve(eb * (size_t)lb * g.E * 2 * ps.Sp + 8);
     w.gT.reserve(8 * (size_t)lb * S * g.V);
     w.xT.reserve(8 * (size_t)lb * S * g.V);
-    w.ug.reserve(8 * (size_t)lb * g.V * ps.Sp);
+    w.ug.reserve(eb * (size_t)lb * g.V * ps.Sp);  // FP32 where the FP32 recovery reads it
     w.its.reserve(4 * (size_t)ps.ng * ps.L * S);
     w.gexp.reserve(4 * (size_t)ps.ng * ps.L * S);
     w.res.reserve(8 * (size_t)ps.ng * ps.L * S);
@@ -269,6 +269,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
             ba.U = sa.U;
             ba.ends = sa.ends;
             ba.ends32 = w.ends.as<float>();
+            ba.ug32 = w.ug.as<float>();
             ba.ug = sa.ug;
             ba.nb = nb;
             ba.Sp = Sp;
@@ -296,6 +297,7 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
         sc.X = sa.X;
         sc.ends = sa.ends;
         sc.ends32 = (p.blocked && o.precision == GRF_PREC_MIXED) ? w.ends.as<float>() : nullptr;
+        sc.ug32 = (p.blocked && o.precision == GRF_PREC_MIXED) ? w.ug.as<float>() : nullptr;
         sc.sd = ca.sd;
         sc.so = ca.so;
         sc.gT = w.gT.as<double>();

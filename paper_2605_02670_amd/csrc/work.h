@@ -18,7 +18,7 @@ struct grf_graph::Work {
     grf::DevBuf ends;             // [LB][E][2][Sp]: |b| * (A_II^{-1} W_I) at both ends of every edge
                                   // (FP32 with mixed precision)
     grf::DevBuf gT, xT;           // [LB][S][V]: condensed right-hand sides / vertex solutions
-    grf::DevBuf ug;               // [LB][V][Sp]: vertex solutions, sample-interleaved
+    grf::DevBuf ug;               // [LB][V][Sp]: vertex solutions, sample-interleaved (FP32 with mixed precision)
     grf::DevBuf pcg_scr;          // PCG vectors in global memory (large graphs)
     grf::DevBuf pcg_ops;          // per-shift-block vertex operators of the global-memory PCG
     grf::DevBuf its, res;         // [LB][S] int32 iterations, double relative residual
@@ -100,6 +100,7 @@ struct BlockArgs {
     double *ends;           // [LB][E][2][Sp]
     float *ends32;          // the same, FP32 (mixed precision: written by the FP32 sweeps)
     const double *ug;       // [LB][V][Sp]
+    const float *ug32;      // the same, FP32 (mixed precision: read by the FP32 recovery)
     int32_t nb, Sp;
     int32_t first;          // first shift block: the forward pass writes (not updates) the interior accumulator
     int32_t mixed;          // FP32 operand tables and matrix-core products (mixed precision)
@@ -148,6 +149,7 @@ struct SchurArgs {
     const double *sd, *so;  // [LBp][E]
     double *gT, *xT;      // [LB][S][V]
     double *ug;           // [LB][V][Sp]
+    float *ug32;          // the same, FP32 (mixed precision, blocked sweeps), or null
     double *U;            // [nb][N][64]
     double *scr;          // PCG scratch (large graphs)
     double *ops;          // vertex operators of the block for the global-memory PCG (pcg_ops_bytes)
