@@ -49,7 +49,12 @@ typedef enum grf_status {
     GRF_ENOMEM = -2,  /* device or host allocation failed */
     GRF_EDEVICE = -3, /* a HIP call failed (message names it) */
     GRF_ENOCONV = -4, /* some vertex Schur PCG hit maxit; output still written */
-    GRF_EUNSUP = -5   /* a documented-but-unsupported combination */
+    GRF_EUNSUP = -5,  /* a documented-but-unsupported combination */
+    GRF_ENONFINITE = -6 /* a vertex Schur system had a NaN or Inf right-hand side or
+                           residual (a non-finite input reaches every vertex system
+                           it touches); output still written, the vertex values of
+                           those systems and the edges around them hold NaN.
+                           Takes precedence over GRF_ENOCONV. */
 } grf_status;
 
 /* grf_graph_create flags */
@@ -125,7 +130,7 @@ typedef struct grf_stats {
        class and shift block. */
     double pcg_class_ms[7];          /* with opts.timing: HIP-event time of the class's launches */
     int32_t pcg_class_launches[7];   /* with opts.timing: launches */
-    int32_t pcg_class_reserved;
+    int32_t n_nonfinite;             /* systems with a NaN/Inf right-hand side or residual (GRF_ENONFINITE) */
     int64_t pcg_class_vertex_its[7]; /* sum over the class's systems of iterations x graph vertices */
     int64_t pcg_class_end_its[7];    /* sum over the class's systems of iterations x graph edge ends (2|E|) */
 } grf_stats;

@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cstdint>
+#include <memory>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -189,7 +191,31 @@ namespace grf {
 // host-side mesh construction shared by single and batched graphs
 void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const double *lengths, double h,
                 uint32_t flags);
-void upload_mesh(grf_graph &g, hipStream_t s);
+// Host arrays bound for device buffers, copied by flush(): a mesh is prepared
+// completely on the host before its first HIP call.
+struct Uploads {
+    struct Item {
+        DevBuf *b;
+        std::shared_ptr<const void> hold;  // keeps the host array alive until the copy is done
+        const void *data;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    template <class T>
+    void add(DevBuf &b, std::vector<T> v) {  // by value: callers move arrays they no longer need
+        auto h = std::make_shared<std::vector<T>>(std::move(v));
+        items.push_back(Item{&b, h, h->data(), h->size() * sizeof(T)});
+    }
+    void flush(hipStream_t s) {
+        for (Item &it : items) {
+            it.b->reserve(it.bytes + 16);
+            if (it.bytes) GRF_HIP(hipMemcpyAsync(it.b->ptr, it.data, it.bytes, hipMemcpyHostToDevice, s));
+        }
+    }
+};
+void prepare_mesh(grf_graph &g, Uploads &up);                 // host: every derived array of the mesh
+void finish_upload(grf_graph &g, Uploads &up, hipStream_t s); // device: the copies, then a sync
+void upload_mesh(grf_graph &g, hipStream_t s);                // both
 
 // quadrature schedule (host, FP64)
 struct Shifts {

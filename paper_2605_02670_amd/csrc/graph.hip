@@ -181,7 +181,7 @@ void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const 
     }
 }
 
-void upload_mesh(grf_graph &g, hipStream_t s) {
+void prepare_mesh(grf_graph &g, Uploads &up) {
     std::vector<int32_t> eu(g.E), ev(g.E);
     for (int64_t e = 0; e < g.E; ++e) {
         eu[e] = (int32_t)g.eu[e];
@@ -189,16 +189,16 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
     }
     std::vector<double> msq(g.N);
     for (int64_t j = 0; j < g.N; ++j) msq[j] = std::sqrt(g.ml[j]);
-    upload(g.d_off, g.off, s);
-    upload(g.d_m, g.m, s);
-    upload(g.d_eu, eu, s);
-    upload(g.d_ev, ev, s);
-    upload(g.d_he, g.he, s);
-    upload(g.d_vptr, g.vptr, s);
-    upload(g.d_adj_e, g.adj_e, s);
-    upload(g.d_adj_o, g.adj_o, s);
-    upload(g.d_adj_s, g.adj_s, s);
-    upload(g.d_msqrt, msq, s);
+    up.add(g.d_off, g.off);
+    up.add(g.d_m, g.m);
+    up.add(g.d_eu, std::move(eu));
+    up.add(g.d_ev, std::move(ev));
+    up.add(g.d_he, g.he);
+    up.add(g.d_vptr, g.vptr);
+    up.add(g.d_adj_e, g.adj_e);
+    up.add(g.d_adj_o, g.adj_o);
+    up.add(g.d_adj_s, g.adj_s);
+    up.add(g.d_msqrt, std::move(msq));
     if (g.gv0.empty()) {
         g.gv0 = {0, (int32_t)g.V};
         g.ge0 = {0, (int32_t)g.E};
@@ -231,9 +231,9 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
             eend[(size_t)j * g.V + u] = j < deg[u] ? 2 * g.adj_e[k] + g.adj_s[k] : -1;
         }
     }
-    upload(g.d_ell, ell, s);
-    upload(g.d_eend, eend, s);
-    upload(g.d_deg, deg, s);
+    up.add(g.d_ell, ell);
+    up.add(g.d_eend, std::move(eend));
+    up.add(g.d_deg, deg);
     // PCG size classes, each ordered largest graph first
     std::vector<int32_t> cls(ng);
     for (int64_t k = 0; k < ng; ++k) {
@@ -253,7 +253,7 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
         for (int64_t k = 0; k < ng; ++k) n += cls[k] < c ? 1 : 0;
         g.cls_off[c] = n;
     }
-    upload(g.d_gord, g.gord, s);
+    up.add(g.d_gord, g.gord);
     // 16-bit local neighbour ids and overflow masks for the graphs of an on-chip class
     std::vector<uint32_t> e16(2 * (size_t)g.V, 0), om(16 * (size_t)ng, 0);
     for (int64_t k = 0; k < ng; ++k) {
@@ -273,8 +273,8 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
             }
         }
     }
-    upload(g.d_ell16, e16, s);
-    upload(g.d_ovfm, om, s);
+    up.add(g.d_ell16, std::move(e16));
+    up.add(g.d_ovfm, std::move(om));
     // overflow slots as pieces of at most 64 packed into chunks of 64 entries (MeshView::ovent)
     {
         std::vector<int32_t> ent, ent0(ng + 1, 0), np(ng, 0), pc(2 * (size_t)g.V, 0);
@@ -306,10 +306,10 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
         }
         ent0[ng] = (int32_t)(ent.size() / 4);
         ent.insert(ent.end(), {0, -1, 0, 0});  // never empty
-        upload(g.d_ovent, ent, s);
-        upload(g.d_ovent0, ent0, s);
-        upload(g.d_ovnp, np, s);
-        upload(g.d_ovpc, pc, s);
+        up.add(g.d_ovent, std::move(ent));
+        up.add(g.d_ovent0, std::move(ent0));
+        up.add(g.d_ovnp, std::move(np));
+        up.add(g.d_ovpc, std::move(pc));
     }
     // vertex PCG row order: reverse Cuthill-McKee for the graphs beyond every on-chip
     // class (their neighbour gathers then stay close in memory), vertex order otherwise
@@ -359,17 +359,27 @@ void upload_mesh(grf_graph &g, hipStream_t s) {
         for (int32_t u = u0; u < g.gv0[k + 1]; ++u)
             for (int64_t q = g.vptr[u]; q < g.vptr[u + 1]; ++q) padj[q] = prow[g.adj_o[q]] - u0;
     }
-    upload(g.d_prow, prow, s);
-    upload(g.d_pvtx, pvtx, s);
-    upload(g.d_pell, pell, s);
-    upload(g.d_padj, padj, s);
-    upload(g.d_gv0, g.gv0, s);
-    upload(g.d_ge0, g.ge0, s);
-    upload(g.d_segs, g.segs, s);
-    upload(g.d_tile0, g.tile0, s);
+    up.add(g.d_prow, std::move(prow));
+    up.add(g.d_pvtx, std::move(pvtx));
+    up.add(g.d_pell, std::move(pell));
+    up.add(g.d_padj, std::move(padj));
+    up.add(g.d_gv0, g.gv0);
+    up.add(g.d_ge0, g.ge0);
+    up.add(g.d_segs, g.segs);
+    up.add(g.d_tile0, g.tile0);
+}
+
+void finish_upload(grf_graph &g, Uploads &up, hipStream_t s) {
+    up.flush(s);
     g.d_kap2.reserve(sizeof(double) * (g.E + 1));
     g.kap2_loaded = -1.0;
     GRF_HIP(hipStreamSynchronize(s));
+}
+
+void upload_mesh(grf_graph &g, hipStream_t s) {
+    Uploads up;
+    prepare_mesh(g, up);
+    finish_upload(g, up, s);
 }
 
 Shifts make_shifts(double beta, double step, double h, const grf_opts &o) {
@@ -516,8 +526,10 @@ int grf_graph_create(int64_t n_vertices, int64_t n_edges, const int64_t *edges, 
     g->serial = next_serial++;
     try {
         build_mesh(*g, n_vertices, n_edges, edges, lengths, h, flags);
+        Uploads up;
+        prepare_mesh(*g, up);  // every host step before the first HIP call
         GRF_HIP(hipGetDevice(&g->device));
-        upload_mesh(*g, nullptr);
+        finish_upload(*g, up, nullptr);
     } catch (...) {
         delete g;
         throw;

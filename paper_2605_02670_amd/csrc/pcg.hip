@@ -353,7 +353,8 @@ __global__ void __launch_bounds__(1024) k_pcg_mrhs(MeshView mv, EllOp Sop, EllOp
                          *Qo = Qop.ovf + (int64_t)l * E2;
             for (int v = vs; v < V; v += VS) X[v * SB + s] = apply(std::false_type{}, Qd, Qc, Qo, Gh, v);
         }
-        bool done = !(gg > 0.0);  // a zero right-hand side (and a padding sample) keeps x = 0
+        bool done = !(gg > 0.0 && gg <= DBL_MAX);  // a zero right-hand side (and a padding sample) keeps x = 0;
+                                                   // a non-finite one is left to k_rhs_unrange
         bool fresh = LRN && !done;
         bool lz = LRN;            // the operator preconditioner is in use
         bool switched = !LRN;
@@ -868,7 +869,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_chip(MeshView mv, EllOp Sop, EllOp 
     bool lz = LP;       // the operator preconditioner is in use
     bool fresh = LRN;   // r^, z^ and p are to be recomputed from x^
     const int switch_at = max(1, maxit / 2);
-    if (gg > 0.0) {
+    if (gg > 0.0 && gg <= DBL_MAX) {  // a non-finite right-hand side is left to k_rhs_unrange
         for (;;) {
             if (fresh) {  // the only convergence test: the residual recomputed from x
                 restart(lz, rz, rr, rh);
@@ -1059,7 +1060,9 @@ __global__ void __launch_bounds__(256) k_vertex_scatter(MeshView mv, const doubl
 // scaled in place by the power of two 2^e that brings the sum into [1, 2)
 // (exact: the solve is unchanged but for the scale), and e is kept.  After the
 // PCG both g and x of such a system are scaled back by 2^-e.  Every other
-// system keeps e = 0 and is not touched again.  One workgroup per system.
+// system keeps e = 0 and is not touched again.  A system whose sum is NaN or
+// Inf gets e = kRangeNonFinite instead: the PCG leaves it alone, its x is set
+// to NaN afterwards, and the host reports it.  One workgroup per system.
 __global__ void __launch_bounds__(256) k_rhs_range(MeshView mv, double *__restrict__ gT, int32_t *__restrict__ gexp,
                                                    int32_t LB, int64_t S) {
     __shared__ double red[16];
@@ -1071,8 +1074,9 @@ __global__ void __launch_bounds__(256) k_rhs_range(MeshView mv, double *__restri
     for (int v = threadIdx.x; v < V; v += blockDim.x) t[0] += fabs(g[v]);
     block_sum<1>(t, red, blockDim.x >> 6);
     const double a = t[0];
-    const int e = (a > 0.0 && (a < 0x1p-300 || a > 0x1p300)) ? -ilogb(a) : 0;
-    if (threadIdx.x == 0) gexp[sys] = e;
+    const bool bad = !(a <= DBL_MAX);  // NaN or Inf
+    const int e = bad ? 0 : (a > 0.0 && (a < 0x1p-300 || a > 0x1p300)) ? -ilogb(a) : 0;
+    if (threadIdx.x == 0) gexp[sys] = bad ? kRangeNonFinite : e;
     if (e != 0)
         for (int v = threadIdx.x; v < V; v += blockDim.x) g[v] = ldexp(g[v], e);
 }
@@ -1085,6 +1089,10 @@ __global__ void __launch_bounds__(256) k_rhs_unrange(MeshView mv, double *__rest
     const int64_t s = sys % S, l = (sys / S) % LB, gi = sys / (S * LB);
     const int u0 = mv.gv0[gi], V = mv.gv0[gi + 1] - u0;
     double *g = gT + (l * S + s) * mv.V + u0, *x = xT + (l * S + s) * mv.V + u0;
+    if (e == kRangeNonFinite) {
+        for (int v = threadIdx.x; v < V; v += blockDim.x) x[v] = __builtin_nan("");
+        return;
+    }
     for (int v = threadIdx.x; v < V; v += blockDim.x) {
         g[v] = ldexp(g[v], -e);
         x[v] = ldexp(x[v], -e);

@@ -365,20 +365,26 @@ static void enqueue_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStr
     }
 }
 
-// Copies the iteration counts back, fills stats, throws GRF_ENOCONV if any
-// system hit maxit.  Per-graph iteration totals go to graph_its if given.
+// the errors after which a call still writes its output
+static bool soft_error(int code) { return code == GRF_ENOCONV || code == GRF_ENONFINITE; }
+
+// Copies the iteration counts back, fills stats, throws GRF_ENONFINITE if any
+// system had a NaN/Inf right-hand side or residual, else GRF_ENOCONV if any
+// hit maxit.  Per-graph iteration totals go to graph_its if given.
 static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStream_t st, grf_stats *stats,
                         std::vector<int64_t> *graph_its = nullptr) {
     grf_graph::Work &w = work(g);
     const size_t n = (size_t)ps.ng * ps.L * ps.S;
     w.h_its.resize(n);
     w.h_res.resize(n);
+    w.h_gexp.resize(n);
     if (n > 0) {
         GRF_HIP(hipMemcpyAsync(w.h_its.data(), w.its.ptr, 4 * n, hipMemcpyDeviceToHost, st));
         GRF_HIP(hipMemcpyAsync(w.h_res.data(), w.res.ptr, 8 * n, hipMemcpyDeviceToHost, st));
+        GRF_HIP(hipMemcpyAsync(w.h_gexp.data(), w.gexp.ptr, 4 * n, hipMemcpyDeviceToHost, st));
     }
     GRF_HIP(hipStreamSynchronize(st));
-    int64_t n_unconv = 0, tot_it = 0;
+    int64_t n_unconv = 0, n_bad = 0, tot_it = 0;
     int32_t max_it = 0;
     double max_res = 0.0;
     std::vector<int64_t> own_its;
@@ -388,6 +394,10 @@ static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStre
         const size_t base = (size_t)ps.ng * ps.l0s[k] * ps.S, cnt = (size_t)ps.ng * ps.lbs[k] * ps.S;
         for (size_t i = 0; i < cnt; ++i) {
             const int32_t it = w.h_its[base + i];
+            if (w.h_gexp[base + i] == kRangeNonFinite || !std::isfinite(w.h_res[base + i])) {
+                n_bad++;
+                continue;
+            }
             if (it > o.maxit) n_unconv++;
             tot_it += std::min(it, o.maxit);
             max_it = std::max(max_it, std::min(it, o.maxit));
@@ -399,6 +409,7 @@ static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStre
         stats->n_shifts = ps.L;
         stats->n_systems = (int32_t)std::min<int64_t>((int64_t)n, INT32_MAX);
         stats->n_unconverged = (int32_t)n_unconv;
+        stats->n_nonfinite = (int32_t)n_bad;
         stats->max_iterations = max_it;
         stats->total_iterations = tot_it;
         stats->max_rel_residual = max_res;
@@ -420,6 +431,12 @@ static void finish_pass(grf_graph &g, const Pass &ps, const grf_opts &o, hipStre
                 stats->pcg_class_end_its[bucket] += it * 2 * (int64_t)(g.ge0[gi + 1] - g.ge0[gi]);
             }
         }
+    }
+    if (n_bad > 0) {
+        set_error("%lld vertex Schur systems had a NaN or Inf right-hand side or residual (a non-finite input, or "
+                  "with mixed precision a value beyond the FP32 range); their vertex values are NaN",
+                  (long long)n_bad);
+        throw Error{GRF_ENONFINITE};
     }
     if (n_unconv > 0) {
         set_error("%lld vertex Schur systems did not reach tol=%g within maxit=%d", (long long)n_unconv, o.tol,
@@ -447,7 +464,7 @@ static void run_shifts(grf_graph &g, const std::vector<double> &cI, const std::v
     try {
         finish_pass(g, ps, o, st, stats);
     } catch (const Error &err) {
-        if (err.code == GRF_ENOCONV) CT.collect(stats);
+        if (soft_error(err.code)) CT.collect(stats);
         throw;
     }
     CT.collect(stats);
@@ -656,8 +673,8 @@ int sample_impl(grf_graph *g, double kappa, double beta, double quad_step, int64
     try {
         run_shifts(*g, sh.cI, sh.cL, n_samples, o, st, o.stats, T);
     } catch (const Error &err) {
-        if (err.code != GRF_ENOCONV) throw;
-        code = GRF_ENOCONV;
+        if (!soft_error(err.code)) throw;
+        code = err.code;
     }
     T.begin(GRF_K_LAYOUT);
     launch_from_interleaved(w.U.as<double>(), n_samples, g->N, out, st);
@@ -720,8 +737,8 @@ int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_
         try {
             run_shifts(*g, cI, cL, n_rhs, o, st, o.stats, T);
         } catch (const Error &err) {
-            if (err.code != GRF_ENOCONV) throw;
-            code = GRF_ENOCONV;
+            if (!soft_error(err.code)) throw;
+            if (code != GRF_ENONFINITE) code = err.code;
         }
     };
     double *result = w.U.as<double>();
@@ -967,8 +984,8 @@ int grf_sample_batched(grf_graph *const *graphs, int32_t n_graphs, const double 
     try {
         finish_pass(U, B.exec_pass, run, cs, o.stats);
     } catch (const Error &err) {
-        if (err.code != GRF_ENOCONV) throw;
-        code = GRF_ENOCONV;
+        if (!soft_error(err.code)) throw;
+        code = err.code;
     }
     T.collect(o.stats);
     CT.collect(o.stats);

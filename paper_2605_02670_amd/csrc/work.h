@@ -26,6 +26,7 @@ struct grf_graph::Work {
     grf::DevBuf Bm, Xacc, nrm;    // mixed-precision refinement: right-hand sides, iterate, norm partials
     std::vector<int32_t> h_its;
     std::vector<double> h_res;
+    std::vector<int32_t> h_gexp;
 };
 
 namespace grf {
@@ -173,6 +174,7 @@ struct SchurArgs {
 enum ChipMode : int8_t { CM_OP = 0, CM_GUESS = 1, CM_JACOBI = 2, CM_GLOBAL = 3 };
 constexpr int kChipOpClasses = 5;  // size classes whose LDS holds r^ and p (CM_OP)
 constexpr int kMrhsSB = 4;         // samples per block of the multi-system PCG kernel
+constexpr int32_t kRangeNonFinite = INT32_MIN;  // gexp of a system whose right-hand side holds NaN or Inf
 constexpr int kClassTimerId = 100;  // + size class (kPcgClasses: the global-memory kernel)
 void default_chip_modes(int32_t precond, int8_t *mode);  // [kPcgClasses]
 bool chip_mode_valid(int c, int mode);

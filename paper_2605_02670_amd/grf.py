@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgrf.so")
 _lib = None
 
-GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP = 0, -1, -2, -3, -4, -5
+GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP, GRF_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MESH = {"ceil": 0, "round": 1}
 MASS = {"lumped": 0, "consistent": 2}  # GRF_MASS_CONSISTENT_SYS
 PREC = {"fp64": 0, "mixed": 1}
@@ -41,9 +41,9 @@ class Stats(C.Structure):
                 ("shift_block", C.c_int32), ("sweep_block", C.c_int32), ("pcg_class_modes", C.c_int32),
                 ("kernel_ms", C.c_double * 16), ("kernel_launches", C.c_int32 * 16),
                 ("pcg_class_ms", C.c_double * 7), ("pcg_class_launches", C.c_int32 * 7),
-                ("pcg_class_reserved", C.c_int32), ("pcg_class_vertex_its", C.c_int64 * 7),
+                ("n_nonfinite", C.c_int32), ("pcg_class_vertex_its", C.c_int64 * 7),
                 ("pcg_class_end_its", C.c_int64 * 7)]
-    _ARRAYS = ("kernel_ms", "kernel_launches", "pcg_class_ms", "pcg_class_launches", "pcg_class_reserved",
+    _ARRAYS = ("kernel_ms", "kernel_launches", "pcg_class_ms", "pcg_class_launches",
                "pcg_class_vertex_its", "pcg_class_end_its")
 
     def as_dict(self) -> dict:
@@ -119,6 +119,12 @@ def _check(code: int, allow=(GRF_OK,)) -> int:
     if code not in allow:
         raise GrfError(code, load().grf_last_error().decode())
     return code
+
+
+def _allowed(noconv: bool, nonfinite: bool) -> tuple:
+    """Status codes a call may return without raising: GRF_ENOCONV and
+    GRF_ENONFINITE still write the output (the stats say which systems failed)."""
+    return (GRF_OK,) + ((GRF_ENOCONV,) if noconv else ()) + ((GRF_ENONFINITE,) if nonfinite else ())
 
 
 def check_array(t, n_rows: int, n_cols: int, name: str, device=None):
@@ -255,7 +261,7 @@ class Graph:
         return out
 
     def sample(self, kappa: float, beta: float, quad_step: float, n_samples: int, seed: int, out=None,
-               allow_noconv: bool = False, **kw):
+               allow_noconv: bool = False, allow_nonfinite: bool = False, **kw):
         """Returns (samples [n_samples, n_dof] float64 on cuda, stats dict)."""
         import torch
 
@@ -264,13 +270,13 @@ class Graph:
         check_array(out, n_samples, self.n_dof, "out", self.device)
         st = Stats()
         o = make_opts(stats=st, **kw)
-        allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
+        allow = _allowed(allow_noconv, allow_nonfinite)
         _check(load().grf_sample(self.handle, kappa, beta, quad_step, n_samples, seed, out.data_ptr(), C.byref(o)),
                allow)
         return out, st.as_dict()
 
     def sample_from_noise(self, kappa: float, beta: float, quad_step: float, noise, out=None,
-                          allow_noconv: bool = False, **kw):
+                          allow_noconv: bool = False, allow_nonfinite: bool = False, **kw):
         """The sample for given noise (float64 [n_samples, n_dof] on cuda, e.g. from
         noise()); returns (samples, stats dict)."""
         import torch
@@ -286,12 +292,13 @@ class Graph:
             raise ValueError("noise and out may not alias")
         st = Stats()
         o = make_opts(stats=st, **kw)
-        allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
+        allow = _allowed(allow_noconv, allow_nonfinite)
         _check(load().grf_sample_from_noise(self.handle, kappa, beta, quad_step, n, noise.data_ptr(), out.data_ptr(),
                                             C.byref(o)), allow)
         return out, st.as_dict()
 
-    def solve_shifted(self, kappa: float, c_I: float, c_L: float, rhs, out=None, allow_noconv=False, **kw):
+    def solve_shifted(self, kappa: float, c_I: float, c_L: float, rhs, out=None, allow_noconv=False,
+                      allow_nonfinite=False, **kw):
         import torch
 
         if not isinstance(rhs, torch.Tensor) or rhs.dim() == 0 or rhs.shape[-1] != self.n_dof:
@@ -311,7 +318,7 @@ class Graph:
             raise ValueError("rhs and out may not alias")
         st = Stats()
         o = make_opts(stats=st, **kw)
-        allow = (GRF_OK, GRF_ENOCONV) if allow_noconv else (GRF_OK,)
+        allow = _allowed(allow_noconv, allow_nonfinite)
         _check(load().grf_solve_shifted(self.handle, kappa, c_I, c_L, r2.shape[0], r2.data_ptr(), out.data_ptr(),
                                         C.byref(o)), allow)
         return out.reshape(rhs.shape), st.as_dict()

@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
     # grf_opts: double, 10 x int32, int64, 3 pointers
     assert C.sizeof(grf.Opts) == 8 + 10 * 4 + 8 + 3 * 8
     # grf_stats: 4 int32, int64, double, 4 int32, 16 double, 16 int32 (per kernel id),
-    # then 7 double, 7 int32 + 1 int32, 7 int64, 7 int64 (per PCG size class)
+    # then 7 double, 7 int32 (per PCG size class), int32 n_nonfinite, 7 int64, 7 int64 (per class)
     assert C.sizeof(grf.Stats) == 4 * 4 + 8 + 8 + 4 * 4 + 16 * 8 + 16 * 4 + 7 * 8 + 8 * 4 + 2 * 7 * 8
     assert grf.Stats.pcg_class_ms.offset == 240
     assert len(grf.KERNELS) == 13  # GRF_K_COUNT
