@@ -223,7 +223,9 @@ int grf_noise(grf_graph *g, int64_t n_samples, uint64_t seed, double *out, const
  *   beta       in (0, 1)
  *   quad_step  k > 0, or 0 for the paper's k = -1/(beta ln h)
  *   out        device, float64 [n_samples][n_dof], canonical order
- * Returns GRF_ENOCONV (with out written) if a Schur system hit maxit.
+ * Returns GRF_ENOCONV (with out written) if a Schur system hit maxit, and
+ * GRF_ENONFINITE (with out written, NaN in the affected samples) if one had a
+ * NaN or Inf right-hand side or residual.
  */
 int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples,
                uint64_t seed, double *out, const grf_opts *opts);
@@ -236,7 +238,9 @@ int grf_sample(grf_graph *g, double kappa, double beta, double quad_step, int64_
  *          grf_noise writes); read only, may not alias out
  *   out    device, float64 [n_samples][n_dof], canonical order
  * With noise = grf_noise(g, n_samples, seed) the result equals grf_sample's bit
- * for bit.  Returns GRF_ENOCONV (with out written) if a Schur system hit maxit.
+ * for bit.  Returns GRF_ENOCONV (with out written) if a Schur system hit maxit,
+ * GRF_ENONFINITE (with out written) if the noise holds a NaN or Inf: the
+ * samples it reaches are NaN, the others are solved.
  */
 int grf_sample_from_noise(grf_graph *g, double kappa, double beta, double quad_step, int64_t n_samples,
                           const double *noise, double *out, const grf_opts *opts);
@@ -269,6 +273,9 @@ int grf_sample_noalloc(grf_graph *g, double kappa, double beta, double quad_step
  * (paper: eq. spde_approx_fem for a single l, solved by eq. global_schur).
  *   c_I, c_L   > 0 and finite; kappa >= 0
  *   rhs, out   device, float64 [n_rhs][n_dof], canonical order; may not alias
+ * Returns GRF_ENOCONV or GRF_ENONFINITE with out written, as grf_sample does;
+ * a right-hand side holding NaN or Inf gives NaN in its row of out.  With
+ * GRF_PREC_MIXED a finite value beyond the FP32 range counts as Inf.
  */
 int grf_solve_shifted(grf_graph *g, double kappa, double c_I, double c_L, int64_t n_rhs,
                       const double *rhs, double *out, const grf_opts *opts);
