@@ -20,6 +20,27 @@ that the CPU and the GPU produce bit-identical values:
   round-to-nearest, no fused multiply-add), so that any IEEE-754 machine
   evaluates them identically.
 * DOF j takes component j % 4 of [r_a cos, r_a sin, r_b cos, r_b sin].
+
+Consistent-mass noise (Phase 2, consistent case; eq. wh_def asks for any R
+with M = R R^T, and the law of W = R xi does not depend on which): the paper
+factors M by Cholesky.  Here R is the assembly of per-element factors.  The
+consistent mass is the sum of the element matrices M_e = (h_e/6)[[2,1],[1,2]],
+and M_e = F_e F_e^T with F_e = [[a, c], [a, -c]], a = sqrt(h_e/4),
+c = sqrt(h_e/12) (the eigenvectors [1,1] and [1,-1] with eigenvalues h_e/2 and
+h_e/6).  With two independent normals (p, q) per element, W = sum_e F_e (p, q)
+has covariance sum_e M_e = M.  R is N x 2(#elements) and needs no
+factorisation.  The project's definition of the draws:
+
+* element g (global index over the edges in order, element k of edge e being
+  g = offsets[e] + e + k, between local nodes k and k+1) takes the Philox block
+  with counter (g // 2, 1, 0, 0) and the same key; (p, q) is the Box-Muller
+  pair (r_a cos, r_a sin) for even g and (r_b cos, r_b sin) for odd g;
+* element g adds t_left = a p + c q to its left node and t_right = a p - c q
+  to its right node;
+* an interior node adds its left element's t_right, then its right element's
+  t_left; a vertex adds, starting from 0, the t of each incident edge end in
+  increasing edge order, tail end before head end (t_left of the edge's first
+  element at the tail, t_right of its last element at the head).
 """
 
 from __future__ import annotations
@@ -70,11 +91,11 @@ def _mulhilo(a: np.ndarray, b: int):
     return hi, lo
 
 
-def philox4x64_10(ctr0: np.ndarray, k0: int, k1: int):
-    """Vectorised Philox4x64-10 for counters (ctr0, 0, 0, 0) and one key."""
+def philox4x64_10(ctr0: np.ndarray, k0: int, k1: int, ctr1: int = 0):
+    """Vectorised Philox4x64-10 for counters (ctr0, ctr1, 0, 0) and one key."""
     with np.errstate(over="ignore"):
         c0 = np.asarray(ctr0, dtype=np.uint64).copy()
-        c1 = np.zeros_like(c0)
+        c1 = np.full_like(c0, np.uint64(ctr1 & _MASK64))
         c2 = np.zeros_like(c0)
         c3 = np.zeros_like(c0)
         key0, key1 = np.uint64(k0 & _MASK64), np.uint64(k1 & _MASK64)
@@ -187,4 +208,69 @@ def white_noise(lumped_diag: np.ndarray, seed: int, n_samples: int, sample_offse
     W = np.empty((n_samples, n), dtype=np.float64)
     for s in range(n_samples):
         W[s] = scale * normals(seed, sample_offset + s, n)
+    return W
+
+
+# ---- consistent-mass noise (element factors) ----------------------------------
+
+
+def element_factor_coefficients(h_e: np.ndarray):
+    """(a, c) of F_e = [[a, c], [a, -c]] with F_e F_e^T = (h_e/6)[[2,1],[1,2]]."""
+    h_e = np.asarray(h_e, dtype=np.float64)
+    return np.sqrt(0.25 * h_e), np.sqrt(h_e / 12.0)
+
+
+def element_normals(seed: int, sample: int, n_elements: int) -> tuple[np.ndarray, np.ndarray]:
+    """(p[g], q[g]) for elements g = 0..n_elements-1 of one (seed, global sample)."""
+    nblk = (n_elements + 1) // 2
+    x0, x1, x2, x3 = philox4x64_10(np.arange(nblk, dtype=np.uint64), seed, sample, ctr1=1)
+    pa, qa = box_muller(x0, x1)
+    pb, qb = box_muller(x2, x3)
+    p = np.stack([pa, pb], axis=1).reshape(-1)[:n_elements]
+    q = np.stack([qa, qb], axis=1).reshape(-1)[:n_elements]
+    return p, q
+
+
+def consistent_noise_factor(mesh):
+    """R (sparse, N x 2 n_elements) with R R^T = the consistent mass; column 2g
+    carries p of element g, column 2g + 1 its q."""
+    import scipy.sparse as sp
+
+    a_node, b_node, h = mesh.element_nodes()
+    a, c = element_factor_coefficients(h)
+    g = np.arange(a_node.shape[0])
+    rows = np.concatenate([a_node, a_node, b_node, b_node])
+    cols = np.concatenate([2 * g, 2 * g + 1, 2 * g, 2 * g + 1])
+    vals = np.concatenate([a, c, a, -c])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(mesh.n_dof, 2 * a_node.shape[0]))
+
+
+def consistent_white_noise(mesh, seed: int, n_samples: int, sample_offset: int = 0) -> np.ndarray:
+    """W[s] = R (p, q) for the element factors R, in the fixed order of the
+    definition above, shape [S, N]."""
+    E, NI = mesh.n_edges, mesh.n_interior
+    n_el = np.asarray(mesh.n_el, dtype=np.int64)
+    first = np.asarray(mesh.offsets[:-1], dtype=np.int64) + np.arange(E, dtype=np.int64)  # g of element 0
+    a_e, c_e = element_factor_coefficients(mesh.h_e)
+    # interior node (e, k), k = 1..m_e: left element first + k - 1, right element first + k
+    ie = np.repeat(np.arange(E), n_el - 1)
+    ik = np.concatenate([np.arange(1, n) for n in n_el]) if E else np.zeros(0, dtype=np.int64)
+    gl, gr = first[ie] + ik - 1, first[ie] + ik
+    # vertex ends in increasing edge order, tail before head
+    ends = []
+    for e in range(E):
+        ends.append((int(mesh.edges[e, 0]), e, 0))
+        ends.append((int(mesh.edges[e, 1]), e, 1))
+    W = np.empty((n_samples, mesh.n_dof), dtype=np.float64)
+    n_elements = int(n_el.sum())
+    a_g, c_g = a_e[np.repeat(np.arange(E), n_el)], c_e[np.repeat(np.arange(E), n_el)]  # per element
+    for s in range(n_samples):
+        p, q = element_normals(seed, sample_offset + s, n_elements)
+        t_left = a_g * p + c_g * q
+        t_right = a_g * p - c_g * q
+        W[s, :NI] = t_right[gl] + t_left[gr]
+        wv = np.zeros(mesh.n_vertices, dtype=np.float64)
+        for v, e, side in ends:
+            wv[v] = wv[v] + (t_left[first[e]] if side == 0 else t_right[first[e] + n_el[e] - 1])
+        W[s, NI:] = wv
     return W

@@ -102,3 +102,67 @@ def test_white_noise_covariance_is_lumped_mass():
     assert np.max(np.abs(off)) < 5 / np.sqrt(W.shape[0])
     # sample_offset addresses the same stream
     assert np.array_equal(noise.white_noise(ML, 11, 3, sample_offset=5), W[5:8])
+
+
+# ---- consistent-mass noise (element factors; Phase 2 consistent case, eq. wh_def) ----
+
+
+def _ragged_mesh(rule="round"):
+    """Edges of 1..many elements, a multi-edge, a self-loop and a pendant vertex."""
+    edges = np.array([[0, 1], [1, 2], [2, 0], [0, 1], [3, 3], [2, 3], [3, 4]])
+    lengths = np.array([0.9, 0.13, 0.41, 0.27, 0.8, 0.05, 0.33])
+    return mesh.build_mesh(5, edges, lengths, 0.1, rule)
+
+
+def test_philox_second_counter_word():
+    c = np.arange(9, dtype=np.uint64)
+    got = noise.philox4x64_10(c, 77, 5, ctr1=1)
+    for i in range(9):
+        ref = noise.philox4x64_10_int([i, 1, 0, 0], [77, 5])
+        assert [int(w[i]) for w in got] == ref
+    # numpy's own Philox (it advances the counter before a block, carrying into word 1)
+    for i in (1, 2, 8):
+        bg = np.random.Philox(key=np.array([77, 5], dtype=np.uint64),
+                              counter=np.array([i - 1, 1, 0, 0], dtype=np.uint64))
+        assert [int(x) for x in bg.random_raw(4)] == [int(w[i]) for w in got]
+    # the element stream is not the DOF stream
+    assert not np.array_equal(got[0], noise.philox4x64_10(c, 77, 5)[0])
+
+
+@pytest.mark.parametrize("rule", ["round", "ceil"])
+def test_consistent_factor_reproduces_consistent_mass(rule):
+    m = _ragged_mesh(rule)
+    R = noise.consistent_noise_factor(m)
+    M = mesh.consistent_mass(m).toarray()
+    RRt = (R @ R.T).toarray()
+    assert np.abs(RRt - M).max() <= 1e-15 * np.abs(M).max()
+    # one element by hand: h = 0.6 gives a^2 + c^2 = 0.2 and a^2 - c^2 = 0.1 = (h/6)[2, 1]
+    a, c = noise.element_factor_coefficients(np.array([0.6]))
+    assert abs(a[0] ** 2 + c[0] ** 2 - 0.2) < 1e-16 and abs(a[0] ** 2 - c[0] ** 2 - 0.1) < 1e-16
+
+
+def test_consistent_noise_is_the_factor_times_the_element_draws():
+    m = _ragged_mesh()
+    R = noise.consistent_noise_factor(m)
+    n_el = R.shape[1] // 2
+    W = noise.consistent_white_noise(m, 4, 3, sample_offset=2)
+    for s in range(3):
+        p, q = noise.element_normals(4, 2 + s, n_el)
+        xi = np.stack([p, q], axis=1).reshape(-1)
+        assert np.abs(R @ xi - W[s]).max() <= 1e-15 * np.abs(W[s]).max()
+    assert np.array_equal(noise.consistent_white_noise(m, 4, 1, sample_offset=3), W[1:2])
+
+
+def test_consistent_noise_covariance_is_consistent_mass():
+    g = lattice(2, 2, lengths=(0.5, 1.5), seed=3)
+    m = mesh.build_mesh(g.n_vertices, g.edges, g.lengths, 0.25, "round")
+    M = mesh.consistent_mass(m).toarray()
+    S = 20000
+    W = noise.consistent_white_noise(m, 12, S)
+    C = W.T @ W / S  # zero mean
+    d = np.diag(M)
+    se = np.sqrt((np.outer(d, d) + M ** 2) / S)  # standard error of each covariance entry
+    assert np.all(np.abs(C - M) < 5 * se)
+    # the couplings are seen: every nonzero off-diagonal entry is resolved by its estimate
+    nz = (M != 0) & ~np.eye(M.shape[0], dtype=bool)
+    assert np.all(M[nz] > 5 * se[nz])
