@@ -67,6 +67,16 @@ typedef enum grf_status {
    streamed edge sweeps (sweep_block 0 picks their width); GRF_PREC_MIXED
    returns GRF_EUNSUP. */
 #define GRF_MASS_CONSISTENT_SYS 2u
+/* OR-ed with the others: grf_noise, grf_sample and grf_sample_batched draw the
+   consistent-mass noise W = R xi with R R^T = M (the consistent mass above;
+   paper eq. wh_def and Phase 2, consistent case) instead of M_L^{1/2} xi.  R is
+   the assembly of per-element factors F_e = [[a, c], [a, -c]], a = sqrt(h_e/4),
+   c = sqrt(h_e/12), F_e F_e^T = (h_e/6)[[2,1],[1,2]]: the same law as the
+   paper's Cholesky factor, O(N), with two normals per element from the Philox
+   block with counter (g / 2, 1, 0, 0) for element g (the element ordering and
+   the summation order are fixed in the project documentation, so the values are
+   reproducible bit for bit).  Works with either system mass. */
+#define GRF_NOISE_CONSISTENT 4u
 
 /* grf_opts.precision */
 #define GRF_PREC_FP64 0  /* every step in FP64 */
@@ -211,6 +221,8 @@ int grf_shift_count(const grf_graph *g, double beta, double quad_step, const grf
  * fixed-order Box-Muller transform specified in the project documentation;
  * the same (seed, sample, j) always gives the same bits.
  *   out   device, float64 [n_samples][n_dof], canonical order
+ * A graph created with GRF_NOISE_CONSISTENT gets the consistent-mass noise
+ * instead (see the flag).
  */
 int grf_noise(grf_graph *g, int64_t n_samples, uint64_t seed, double *out, const grf_opts *opts);
 

@@ -115,6 +115,7 @@ struct MeshView {
     const int64_t *segs;
     int32_t maxVg, maxEg;  // largest graph of the batch (host-side dispatch)
     int32_t consistent;    // shifted systems with the consistent mass matrix (GRF_MASS_CONSISTENT_SYS)
+    int32_t cnoise;        // consistent-mass noise (GRF_NOISE_CONSISTENT)
     int64_t maxNg;
     // 64-DOF tiles of the batch's graphs: graph g's tiles are tile0[g] .. tile0[g+1]-1
     const int64_t *tile0;  // [ng+1]

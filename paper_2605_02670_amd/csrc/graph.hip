@@ -115,7 +115,8 @@ void build_mesh(grf_graph &g, int64_t V, int64_t E, const int64_t *edges, const 
     GRF_REQUIRE(E >= 0 && E < (int64_t(1) << 30), "n_edges must be in [0, 2^30)");
     GRF_REQUIRE(E == 0 || (edges && lengths), "edges and lengths must be non-NULL");
     GRF_REQUIRE(std::isfinite(h) && h > 0, "h must be finite and > 0");
-    GRF_REQUIRE((flags & ~(GRF_MESH_ROUND | GRF_MASS_CONSISTENT_SYS)) == 0, "unknown mesh flag %u", flags);
+    GRF_REQUIRE((flags & ~(GRF_MESH_ROUND | GRF_MASS_CONSISTENT_SYS | GRF_NOISE_CONSISTENT)) == 0,
+                "unknown mesh flag %u", flags);
     g.V = V;
     g.E = E;
     g.h = h;
@@ -458,6 +459,7 @@ grf::MeshView grf_graph::view() const {
     v.msqrt = d_msqrt.as<double>();
     v.ng = (int32_t)gv0.size() - 1;
     v.consistent = (flags & GRF_MASS_CONSISTENT_SYS) ? 1 : 0;
+    v.cnoise = (flags & GRF_NOISE_CONSISTENT) ? 1 : 0;
     v.gv0 = d_gv0.as<int32_t>();
     v.ge0 = d_ge0.as<int32_t>();
     v.segs = d_segs.as<int64_t>();

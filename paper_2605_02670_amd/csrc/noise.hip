@@ -1,6 +1,7 @@
 // Lumped white noise W = M_L^{1/2} xi (paper: eq. wh_def; "Mass Lumping":
 // the Cholesky factor of the diagonal lumped mass is its element-wise square
-// root, so the noise costs O(N)).
+// root, so the noise costs O(N)); with GRF_NOISE_CONSISTENT the consistent-mass
+// noise of the element factors (k_noise_consistent, also O(N)).
 //
 // xi is this project's counter-based definition, identical bit for bit on any
 // IEEE-754 machine that evaluates the same operations in the same order:
@@ -26,8 +27,8 @@ struct Words {
     uint64_t x[4];
 };
 
-__device__ __forceinline__ Words philox4x64_10(uint64_t ctr, uint64_t key0, uint64_t key1) {
-    uint64_t c0 = ctr, c1 = 0, c2 = 0, c3 = 0;
+__device__ __forceinline__ Words philox4x64_10(uint64_t ctr, uint64_t key0, uint64_t key1, uint64_t ctr1 = 0) {
+    uint64_t c0 = ctr, c1 = ctr1, c2 = 0, c3 = 0;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
@@ -186,18 +187,138 @@ __global__ void __launch_bounds__(256) k_noise(const double *__restrict__ msqrt,
     }
 }
 
+// Consistent-mass noise W = R (p, q), R the assembly of the element factors
+// F_e = [[a, c], [a, -c]] of M_e = (h_e/6)[[2,1],[1,2]] (a = sqrt(h_e/4),
+// c = sqrt(h_e/12)), so that R R^T is the consistent mass (eq. wh_def with any R
+// of M = R R^T; the paper takes a Cholesky factor, of the same law).  Element g of
+// a graph (g = local first interior row of its edge + local edge index + k for the
+// element k between local nodes k and k+1) draws (p, q) from the Philox block with
+// counter (g / 2, 1, 0, 0): the first Box-Muller pair for even g, the second for odd.
+// It adds a p + c q to its left node and a p - c q to its right one.  Each DOF sums
+// its own terms in a fixed order (interior: left element, then right; vertex: its
+// edge ends in CSR order, increasing edge, tail before head), so no atomics and the
+// same bits on every run.  Lanes are samples (with the lane packing of k_noise); a
+// wavefront takes kRowsPerItem consecutive interior rows, so that an element shared
+// by two rows of one edge, and a Philox block shared by two elements, is drawn once.
+constexpr int kRowsPerItem = 8;
+
+struct ElementDraws {
+    uint64_t seed, smp;
+    uint64_t blk = ~0ull;  // Philox block held in w
+    Words w;
+    __device__ void pq(uint64_t g, double &p, double &q) {
+        if ((g >> 1) != blk) {
+            blk = g >> 1;
+            w = philox4x64_10(blk, seed, smp, 1);
+        }
+        if (g & 1)
+            box_muller(w.x[2], w.x[3], p, q);
+        else
+            box_muller(w.x[0], w.x[1], p, q);
+    }
+};
+
+__global__ void __launch_bounds__(256) k_noise_consistent(MeshView mv, int64_t S, int64_t soff, uint64_t seed,
+                                                          double *__restrict__ X) {
+    const int lane = threadIdx.x & 63;
+    const int64_t z = blockIdx.z;
+    const int64_t n = mv.segs[4 * z], ni = mv.segs[4 * z + 1], ri = mv.segs[4 * z + 2], rv = mv.segs[4 * z + 3];
+    const int32_t e0 = mv.ge0[z], e1 = mv.ge0[z + 1], v0 = mv.gv0[z];
+    const int64_t b = blockIdx.y;
+    const int64_t Sb = S - b * 64 < 64 ? S - b * 64 : 64;
+    const int lpg = noise_group_lanes(Sb), gpw = 64 / lpg;
+    const int sl = lane & (lpg - 1), gs = lane / lpg;
+    const bool live = sl < Sb;
+    double *Xb = X + b * mv.N * 64 + sl;
+    ElementDraws d{seed, (uint64_t)(soff + b * 64 + sl)};
+    // items: the chunks of interior rows, then the vertices
+    const int64_t nch = (ni + kRowsPerItem - 1) / kRowsPerItem, nitems = nch + (n - ni);
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * gpw; i0 < nitems;
+         i0 += (int64_t)gridDim.x * 4 * gpw) {
+        const int64_t it = i0 + gs;
+        if (it >= nitems) continue;
+        if (it < nch) {
+            const int64_t r0 = ri + it * kRowsPerItem;
+            const int64_t r1 = min(r0 + kRowsPerItem, ri + ni);
+            // the edge holding row r0: the last e with off[e] <= r0 (an edge without
+            // interior DOFs shares its offset with the next edge)
+            int32_t lo = e0, hi = e1;
+            while (hi - lo > 1) {
+                const int32_t mid = lo + (hi - lo) / 2;
+                if (mv.off[mid] <= r0) lo = mid; else hi = mid;
+            }
+            int32_t e = lo;
+            uint64_t gprev = ~0ull;  // the last right element drawn, and its (p, q)
+            double pp = 0.0, qp = 0.0;
+            for (int64_t row = r0; row < r1; ++row) {
+                while (mv.off[e + 1] <= row) ++e;
+                double w = 0.0;
+                if (live) {
+                    const double he = mv.he[e];
+                    const double a = sqrt(0.25 * he), c = sqrt(he / 12.0);
+                    const uint64_t gl = (uint64_t)((mv.off[e] - ri) + (e - e0) + (row - mv.off[e]));  // left element
+                    double pl, ql, pr, qr;
+                    if (gl == gprev) {
+                        pl = pp;
+                        ql = qp;
+                    } else {
+                        d.pq(gl, pl, ql);
+                    }
+                    d.pq(gl + 1, pr, qr);
+                    gprev = gl + 1;
+                    pp = pr;
+                    qp = qr;
+                    const double tr = a * pl - c * ql;  // the left element's term at its right node
+                    const double tl = a * pr + c * qr;  // the right element's term at its left node
+                    w = tr + tl;
+                }
+                Xb[row * 64] = w;
+            }
+        } else {
+            const int64_t vl = it - nch;
+            double w = 0.0;
+            if (live) {
+                const int64_t v = v0 + vl;
+                for (int64_t k = mv.vptr[v]; k < mv.vptr[v + 1]; ++k) {
+                    const int32_t e = mv.adj_e[k];
+                    const double he = mv.he[e];
+                    const double a = sqrt(0.25 * he), c = sqrt(he / 12.0);
+                    const uint64_t first = (uint64_t)((mv.off[e] - ri) + (e - e0));
+                    double p, q;
+                    if (mv.adj_s[k] == 0) {
+                        d.pq(first, p, q);
+                        const double t = a * p + c * q;
+                        w = w + t;
+                    } else {
+                        d.pq(first + (uint64_t)mv.m[e], p, q);  // element n_e - 1 = m_e
+                        const double t = a * p - c * q;
+                        w = w + t;
+                    }
+                }
+            }
+            Xb[(rv + vl) * 64] = w;
+        }
+    }
+}
+
 }  // namespace
 
 void launch_noise(const MeshView &mv, int64_t S, int64_t soff, uint64_t seed, double *X, hipStream_t st) {
     int64_t nb = (S + 63) / 64;
-    int64_t ngrp = (mv.maxNg + 3) / 4;
     const int64_t per = 4 * (64 / noise_group_lanes(S < 64 ? S : 64));  // DOF groups per workgroup pass
-    int64_t gx = (ngrp + per - 1) / per;
-    if (gx > 8192) gx = 8192;
-    if (gx < 1) gx = 1;
     GRF_REQUIRE(nb < 65536 && mv.ng < 65536, "too many samples or graphs in one call");
-    hipLaunchKernelGGL(k_noise, dim3((unsigned)gx, (unsigned)nb, (unsigned)mv.ng), dim3(256), 0, st, mv.msqrt,
-                       mv.segs, mv.N, S, soff, seed, X);
+    if (mv.cnoise) {  // items of kRowsPerItem interior rows, or one vertex
+        int64_t gx = (mv.maxNg / kRowsPerItem + mv.maxVg + per - 1) / per;
+        gx = std::max<int64_t>(1, std::min<int64_t>(gx, 8192));
+        hipLaunchKernelGGL(k_noise_consistent, dim3((unsigned)gx, (unsigned)nb, (unsigned)mv.ng), dim3(256), 0, st,
+                           mv, S, soff, seed, X);
+    } else {
+        int64_t ngrp = (mv.maxNg + 3) / 4;
+        int64_t gx = (ngrp + per - 1) / per;
+        gx = std::max<int64_t>(1, std::min<int64_t>(gx, 8192));
+        hipLaunchKernelGGL(k_noise, dim3((unsigned)gx, (unsigned)nb, (unsigned)mv.ng), dim3(256), 0, st, mv.msqrt,
+                           mv.segs, mv.N, S, soff, seed, X);
+    }
     GRF_LAUNCH_CHECK();
 }
 

@@ -19,6 +19,7 @@ _lib = None
 GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_ENOCONV, GRF_EUNSUP, GRF_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MESH = {"ceil": 0, "round": 1}
 MASS = {"lumped": 0, "consistent": 2}  # GRF_MASS_CONSISTENT_SYS
+NOISE = {"lumped": 0, "consistent": 4}  # GRF_NOISE_CONSISTENT
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "nn": 2}
 ACTIVATIONS = {"fp32": 0, "bf16": 1}  # GRF_ACT_*
@@ -197,12 +198,17 @@ def class_modes(word: int) -> list[str]:
 class Graph:
     """A metric graph and its mesh on the current HIP device."""
 
-    def __init__(self, n_vertices: int, edges, lengths, h: float, rule: str = "ceil", mass: str = "lumped"):
+    def __init__(self, n_vertices: int, edges, lengths, h: float, rule: str = "ceil", mass: str = "lumped",
+                 noise: str = "lumped"):
         """mass: the mass matrix of the shifted systems, "lumped" or "consistent"
-        (GRF_MASS_CONSISTENT_SYS); the noise is lumped either way."""
+        (GRF_MASS_CONSISTENT_SYS); noise: M_L^{1/2} xi ("lumped") or the
+        consistent-mass noise of the element factors ("consistent",
+        GRF_NOISE_CONSISTENT)."""
         lib = load()
         if mass not in MASS:
             raise ValueError(f"mass must be one of {sorted(MASS)}, got {mass!r}")
+        if noise not in NOISE:
+            raise ValueError(f"noise must be one of {sorted(NOISE)}, got {noise!r}")
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
         L = np.ascontiguousarray(np.asarray(lengths, dtype=np.float64).reshape(-1))
         self.n_vertices = int(n_vertices)
@@ -210,9 +216,10 @@ class Graph:
         self.h = float(h)
         self.rule = rule
         self.mass = mass
+        self.noise_kind = noise
         handle = C.c_void_p()
         _check(lib.grf_graph_create(self.n_vertices, self.n_edges, e.ctypes.data, L.ctypes.data, self.h,
-                                    MESH[rule] | MASS[mass], C.byref(handle)))
+                                    MESH[rule] | MASS[mass] | NOISE[noise], C.byref(handle)))
         self.handle = handle.value
         nd, ni = C.c_int64(), C.c_int64()
         offs = np.zeros(self.n_edges + 1, dtype=np.int64)

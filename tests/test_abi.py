@@ -64,7 +64,7 @@ def test_graph_create_rejects_bad_input(case):
     elif case == "h":
         h = -1.0
     elif case == "flags":
-        flags = 7
+        flags = 8  # no such flag
     elif case == "nan":
         L = np.array([1.0, np.nan])
     out = C.c_void_p()

@@ -136,3 +136,56 @@ def test_consistent_mixed_unsupported(grf):
     with pytest.raises(grf.GrfError) as ei:
         G.sample(2.0, 0.75, 0.5, 2, 0, precision="mixed")
     assert ei.value.code == grf.GRF_EUNSUP
+
+
+# ---- consistent-mass noise (GRF_NOISE_CONSISTENT; eq. wh_def with the element factors) ----
+
+
+@pytest.mark.parametrize("S,offset", [(20, 0), (70, 5), (1, 3)])
+def test_consistent_noise_bit_identical(grf, S, offset):
+    """Every DOF (interior, vertex, self-loop and multi-edge ends) and every sample
+    lane (16-, 32- and 64-lane groups, a ragged second block) bit for bit."""
+    V, E, L = _ragged_graph()
+    h, rule = 0.07, "round"
+    G = grf.Graph(V, E, L, h, rule, noise="consistent")
+    w = G.noise(S, 9, sample_offset=offset).cpu().numpy()
+    m = omesh.build_mesh(V, E, L, h, rule)
+    ref = onoise.consistent_white_noise(m, 9, S, sample_offset=offset)
+    assert np.array_equal(w.view(np.uint64), ref.view(np.uint64))
+    lumped = onoise.white_noise(omesh.lumped_mass(m), 9, S, sample_offset=offset)
+    assert not np.allclose(w, lumped)
+
+
+@pytest.mark.parametrize("mass", ["lumped", "consistent"])
+def test_consistent_noise_sample(grf, mass):
+    """The full consistent arm (consistent system and noise) and consistent noise on
+    the lumped system (blocked matrix-core sweeps) against the oracle."""
+    cfg = config_c1()
+    g = cfg["graph"]
+    G = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"], mass=mass, noise="consistent")
+    S = 8
+    u, st = G.sample(cfg["kappa"], cfg["beta"], cfg["quad_step"], S, cfg["seed"])
+    assert st["n_unconverged"] == 0
+    m = omesh.build_mesh(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"])
+    ML = omesh.lumped_mass(m)
+    W = onoise.consistent_white_noise(m, cfg["seed"], S)
+    ref = osolve.sample(m, cfg["kappa"], cfg["beta"], cfg["quad_step"], W, mass=mass)
+    u = u.cpu().numpy()
+    err, eel = _rel_ml(u, ref, ML), _elem(u, ref)
+    print(f"consistent noise, {mass} system: rel err {err:.2e}, element-wise {eel:.2e}")
+    assert err <= TOL and eel <= TOL
+
+
+def test_consistent_noise_batched_matches_single(grf):
+    specs = [_ragged_graph(), (lambda g: (g.n_vertices, g.edges, g.lengths))(lattice(4, 3, lengths=(0.3, 1.2),
+                                                                                        seed=2))]
+    h, rule, beta, k = 0.07, "round", 0.7, 0.45
+    Gs = [grf.Graph(V, E, L, h, rule, noise="consistent") for V, E, L in specs]
+    for G, (V, E, L) in zip(Gs, specs):  # the batch draws each graph's own stream
+        m = omesh.build_mesh(V, E, L, h, rule)
+        assert np.array_equal(G.noise(5, 2).cpu().numpy(), onoise.consistent_white_noise(m, 2, 5))
+    kappas = [3.0, 8.0]
+    outs, _ = grf.sample_batched(Gs, kappas, beta, k, 5, 2)
+    for G, kap, u in zip(Gs, kappas, outs):
+        single, _ = G.sample(kap, beta, k, 5, 2)
+        assert _elem(u.cpu().numpy(), single.cpu().numpy()) <= 1e-12
