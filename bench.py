@@ -476,7 +476,8 @@ def bench_batched(args, with_forms: bool = True) -> dict:
 
 def bench_lattice64(args, beta: float, with_forms: bool = True) -> dict:
     """The 64x64 lattice (2,066,964 DOFs), 256 samples: FP64 (timed, with its roofline),
-    and on beta = 0.6 mixed precision and the Neumann-Neumann preconditioner."""
+    and on beta = 0.6 mixed precision, the Neumann-Neumann preconditioner and the
+    consistent-mass arm."""
     import torch
 
     from paper_2605_02670_amd import grf
@@ -517,7 +518,26 @@ def bench_lattice64(args, beta: float, with_forms: bool = True) -> dict:
             res[name] = {"value": G.n_dof * L * S / dtf, "ms_per_step": dtf * 1e3, "median_ms": medf * 1e3,
                          "rel_err_vs_fp64": err,
                          "pcg": {"mean_iterations": stf["total_iterations"] / max(1, stf["n_systems"])}}
+        # the paper's consistent arm: consistent mass in the systems and consistent-mass
+        # noise (element factors), the same graph and shifts; a different method, so its
+        # result is not compared with the lumped one
+        Gc = grf.Graph(g.n_vertices, g.edges, g.lengths, cfg["h"], cfg["rule"], mass="consistent",
+                       noise="consistent")
+
+        def run_c():
+            return Gc.sample(*args_, out=o2, tol=cfg["tol"])[1]
+
+        o2 = torch.empty_like(out)
+        dtc, medc, stc = _timed(run_c, max(1, min(args.steps, 5)), 1)
+        stck = Gc.sample(*args_, out=o2, tol=cfg["tol"], timing=True)[1]
+        res["consistent_arm"] = {"value": Gc.n_dof * L * S / dtc, "ms_per_step": dtc * 1e3, "median_ms": medc * 1e3,
+                                 "vs_lumped_fp64": dt / dtc, "sweep_block": stc["sweep_block"],
+                                 "noise_ms": stck["kernel_ms"]["noise"],
+                                 "pcg": {"mean_iterations": stc["total_iterations"] / max(1, stc["n_systems"])},
+                                 "workload": "the same lattice and shifts, consistent mass in the shifted systems "
+                                             "and consistent-mass noise, FP64 streamed sweeps"}
         del o2
+        Gc.close()
     del out
     G.close()
     torch.cuda.empty_cache()
