@@ -705,7 +705,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 // FP64 kernels; the
 // carried state Y[t] item r of lane L is shift 16t + 4 (L/16) + r and the
 // block output item r of lane L is position 4 (L/16) + r.
-template <int NT, bool FWD>
+template <int NT, bool FWD, bool SB>
 __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_,
                                                     const int32_t *__restrict__ boff, int32_t E, int64_t N, int32_t nb,
                                                     int32_t Sp, int32_t LB, int32_t LBp, const float *__restrict__ tab,
@@ -764,11 +764,16 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
     const bool store_only = FWD && first;
 #pragma unroll 1
     for (int beta = 0; beta < nblk; ++beta) {
-        const float *sb = sbuf + (beta & 1) * TS;
+        if (SB && beta > 0) {  // single buffer: the block's operands after the last block's barrier
+            stage_direct(src1(beta), N1, src2(beta), sbuf, TS);
+            stage_wait();
+            __syncthreads();
+        }
+        const float *sb = SB ? sbuf : sbuf + (beta & 1) * TS;
         const bool more = beta + 1 < nblk;
         float Rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (more) {
-            stage_direct(src1(beta + 1), N1, src2(beta + 1), sbuf + ((beta + 1) & 1) * TS, TS);
+            if (!SB) stage_direct(src1(beta + 1), N1, src2(beta + 1), sbuf + ((beta + 1) & 1) * TS, TS);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int p = 16 * (beta + 1) + 4 * c + kq;
@@ -833,7 +838,7 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
                 if (p < m && op >= 0) ub[(int64_t)op * 64] = uo[r] + ((double)f + A64[r]);
             }
         }
-        if (more) stage_wait();
+        if (!SB && more) stage_wait();
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) R[c] = Rn[c];
@@ -849,17 +854,23 @@ __device__ __forceinline__ void sweep_blocked32_dir(const int64_t *__restrict__ 
 }
 
 // Pass A with FP32 operands, both directions in one launch (as k_sweep_blocked).
-template <int NT>
+// SB: one staging buffer instead of two (the block's operands load after the barrier
+// that ends the previous block), for workgroups of 1 or 2 wavefronts, where two
+// buffers would leave the LDS room for too few workgroups (64 graphs, 32 samples:
+// 10 -> 16 wavefronts per compute unit, pass A 42.5 -> 34.4 ms).  With 4 wavefronts
+// the registers already cap a compute unit at 16, and the FP64 kernels and pass B
+// measured slower single-buffered.
+template <int NT, bool SB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 4)))
 k_sweep_blocked32(const int64_t *__restrict__ off_, const int32_t *__restrict__ m_, const int32_t *__restrict__ boff,
                   int32_t E, int64_t N, int32_t nb, int32_t Sp, int32_t LB, int32_t LBp,
                   const float *__restrict__ tab, const double *__restrict__ X, double *__restrict__ U,
                   const double *__restrict__ rhom, float *__restrict__ ends, int32_t first, int64_t S) {
-    __shared__ float sbuf[2 * (528 * NT + 256)];
+    __shared__ float sbuf[(SB ? 1 : 2) * (528 * NT + 256)];
     const int64_t wg = xcd_logical_block();
-    sweep_blocked32_dir<NT, true>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, first, S, sbuf, wg);
+    sweep_blocked32_dir<NT, true, SB>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, first, S, sbuf, wg);
     __syncthreads();
-    sweep_blocked32_dir<NT, false>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, 0, S, sbuf, wg);
+    sweep_blocked32_dir<NT, false, SB>(off_, m_, boff, E, N, nb, Sp, LB, LBp, tab, X, U, rhom, ends, 0, S, sbuf, wg);
 }
 
 template <int NT>
@@ -973,9 +984,12 @@ template <int NT>
 void sweep_nt(const MeshView &mv, const BlockArgs &a, hipStream_t st) {
     const int32_t wpe = sweep_groups(a.S);
     const dim3 grid((unsigned)(mv.E * (int64_t)wpe)), block((unsigned)(64 * sweep_waves(a.S)));
-    if (a.mixed)
-        hipLaunchKernelGGL((k_sweep_blocked32<NT>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe, a.Sp,
-                           a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends32, a.first, a.S);
+    if (a.mixed && sweep_waves(a.S) < 4)
+        hipLaunchKernelGGL((k_sweep_blocked32<NT, true>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe,
+                           a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends32, a.first, a.S);
+    else if (a.mixed)
+        hipLaunchKernelGGL((k_sweep_blocked32<NT, false>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe,
+                           a.Sp, a.LB, a.LBp, a.tab32, a.X, a.U, a.rhom, a.ends32, a.first, a.S);
     else
         hipLaunchKernelGGL((k_sweep_blocked<NT>), grid, block, 0, st, mv.off, mv.m, a.boff, mv.E, mv.N, wpe, a.Sp,
                            a.LB, a.LBp, a.tab, a.X, a.U, a.rhom, a.ends, a.first, a.S);
