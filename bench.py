@@ -93,12 +93,12 @@ PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<128, 8>", "
 # copy reads on these counters) per step, recorded for these sources only
 COUNTER_SOURCES = ["paper_2605_02670_amd/csrc/" + f for f in
                    ("blocked.hip", "pcg.hip", "sample.hip", "noise.hip", "layout.hip", "graph.hip", "common.h")]
-COUNTER_SHA = "970835f5c6bcef604bd6569fe4001f3a195996fb78adfe6edb9de343824c807e"  # sha256 over COUNTER_SOURCES when the counters below were taken
+COUNTER_SHA = "6caa72af549b81e838e1bce649c594bd539bdf1abd3e6bc04f7c515d2942ab03"  # sha256 over COUNTER_SOURCES when the counters below were taken
 # workload -> {"step_bytes": B, "kernels": {kernel id: bytes per launch}}, from the two counter passes
 # of profiles/grf_sample_batched64_S32_hbm_counters.md and grf_sample_lattice64_S256_hbm_counters.md
 COUNTERS = {
-    "batched64": {"step_bytes": 542135470830, "kernels": {"ends_fwd": 90674225503, "table": 65917063159}},
-    "lattice64_beta0.6": {"step_bytes": 87606283888, "kernels": {"ends_fwd": 35463014710, "table": 12284169651}},
+    "batched64": {"step_bytes": 542071281247, "kernels": {"ends_fwd": 90680351508, "table": 65915528183}},
+    "lattice64_beta0.6": {"step_bytes": 87622251754, "kernels": {"ends_fwd": 35467184796, "table": 12284639114}},
 }
 
 
