@@ -181,6 +181,10 @@ __global__ void k_block_map(const int32_t *__restrict__ boff, int64_t E, int2 *_
 }
 
 constexpr int kTabThreads = 128;          // one thread per (padded) shift, LBp <= 128
+// LDS row padding of the Ghat factors: 2 doubles keeps a 96-shift block at 26.7 KB, so
+// that 6 workgroups (3 wavefronts per SIMD, the register limit) fit a compute unit;
+// 4 doubles allowed 5 (64 graphs, 32 samples: 35.8 -> 35.1 ms per step, mean of two runs)
+constexpr int kTabPad = 2;
 
 // 16-byte vectors of the table element type
 template <typename ET> struct V16;
@@ -240,11 +244,11 @@ __global__ void __launch_bounds__(kTabThreads) k_blocktab(MeshView mv, const int
                                                           int32_t NT, int32_t SLOT, int64_t nblocks,
                                                           OT *__restrict__ tab, OT *__restrict__ ztab) {
     constexpr bool F32L = sizeof(OT) == 4;  // FP32 operand tables for the mixed-precision sweeps
-    // per block slot, Ghat split factors in rows of ld = LBp + 4 doubles: Af rows 0..16
+    // per block slot, Ghat split factors in rows of ld = LBp + kTabPad doubles: Af rows 0..16
     // (dg / (w^i E(base+i+1))), Bm rows 0..15 (E(base+j+1)), then w / w_split
     extern __shared__ double sfac[];
     __shared__ int sistar[kTabThreads / 16];  // i* of each block slot, for the Ghat products
-    const int ld = LBp + 4;
+    const int ld = LBp + kTabPad;
     const int NBW = PACK ? kTabThreads / SLOT : 1;  // blocks per workgroup (SLOT = 128 unless PACK)
     const int tid = threadIdx.x, wv = tid >> 6;
     const int slot = PACK ? tid / SLOT : 0;
@@ -1032,7 +1036,7 @@ static int32_t blocktab_slot(int32_t LBp) {
     return s;
 }
 static size_t blocktab_lds(int32_t LBp) {
-    return sizeof(double) * 34 * (size_t)(LBp + 4) * (kTabThreads / blocktab_slot(LBp));
+    return sizeof(double) * 34 * (size_t)(LBp + kTabPad) * (kTabThreads / blocktab_slot(LBp));
 }
 
 void launch_block_map(const int32_t *boff, int64_t E, int2 *bmap, hipStream_t st) {
