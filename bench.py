@@ -93,12 +93,12 @@ PCG_KERNELS = ["k_pcg_chip<64, 1>", "k_pcg_chip<64, 4>", "k_pcg_chip<128, 8>", "
 # copy reads on these counters) per step, recorded for these sources only
 COUNTER_SOURCES = ["paper_2605_02670_amd/csrc/" + f for f in
                    ("blocked.hip", "pcg.hip", "sample.hip", "noise.hip", "layout.hip", "graph.hip", "common.h")]
-COUNTER_SHA = "6caa72af549b81e838e1bce649c594bd539bdf1abd3e6bc04f7c515d2942ab03"  # sha256 over COUNTER_SOURCES when the counters below were taken
+COUNTER_SHA = "28ad82b3c908de622f011a67d3af6a6d78fc1d08a464219e398dfc8d93c3b100"  # sha256 over COUNTER_SOURCES when the counters below were taken
 # workload -> {"step_bytes": B, "kernels": {kernel id: bytes per launch}}, from the two counter passes
 # of profiles/grf_sample_batched64_S32_hbm_counters.md and grf_sample_lattice64_S256_hbm_counters.md
 COUNTERS = {
-    "batched64": {"step_bytes": 542071281247, "kernels": {"ends_fwd": 90680351508, "table": 65915528183}},
-    "lattice64_beta0.6": {"step_bytes": 87622251754, "kernels": {"ends_fwd": 35467184796, "table": 12284639114}},
+    "batched64": {"step_bytes": 542124682750, "kernels": {"ends_fwd": 90680296214, "table": 65918028787}},
+    "lattice64_beta0.6": {"step_bytes": 87645906277, "kernels": {"ends_fwd": 35494569415, "table": 12285991058}},
 }
 
 
