@@ -68,6 +68,25 @@ def test_mixed_sample_ragged_multipass(grf):
     assert err <= SUM_TOL
 
 
+@pytest.mark.parametrize("S,shift_block", [(9, 0), (24, 0), (24, 40), (31, 16)])
+def test_mixed_sample_few_samples(grf, S, shift_block):
+    """1 and 2 wavefronts of 16 samples per edge workgroup (S <= 32), where the FP32
+    edge sweeps stage each block's operands through a single LDS buffer; edges of
+    up to three 16-position blocks, ragged sample lanes, one and several shift passes."""
+    g = preferential_attachment(12, 2, lengths=(0.05, 1.7), seed=11)
+    edges = np.vstack([g.edges, [[0, 1], [5, 5], [3, 12]]])
+    lengths = np.concatenate([g.lengths, [0.013, 0.9, 0.31]])
+    m = omesh.build_mesh(13, edges, lengths, 0.05, "round")
+    G = grf.Graph(13, edges, lengths, 0.05, "round")
+    kappa, beta, k, seed = 4.0, 0.6, 0.45, 8
+    u, st = G.sample(kappa, beta, k, S, seed, shift_block=shift_block, precision="mixed")
+    W = onoise.white_noise(omesh.lumped_mass(m), seed, S)
+    ref = osolve.sample(m, kappa, beta, k, W)
+    err = _rel_ml(u.cpu().numpy(), ref, omesh.lumped_mass(m))
+    print(f"mixed, {S} samples, shift block {st['shift_block']}: sample error {err:.3e}")
+    assert err <= SUM_TOL
+
+
 def _c4_shaped(n=12):
     """The 256x256 mixed-precision configuration's parameters on a smaller lattice."""
     g = lattice(n, n, lengths=(0.5, 1.5), seed=4)
