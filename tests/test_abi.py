@@ -44,6 +44,17 @@ def test_struct_layouts_match_header():
     assert len(grf.KERNELS) == 13  # GRF_K_COUNT
 
 
+def test_status_and_flag_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "grf.h")).read()
+    status = dict((k, int(v)) for k, v in re.findall(r"\b(GRF_E[A-Z]+|GRF_OK)\s*=\s*(-?\d+)", text))
+    for name in ("GRF_OK", "GRF_EINVAL", "GRF_ENOMEM", "GRF_EDEVICE", "GRF_ENOCONV", "GRF_EUNSUP", "GRF_ENONFINITE"):
+        assert status[name] == getattr(grf, name), name
+    flags = dict((k, int(v)) for k, v in re.findall(r"#define\s+(GRF_[A-Z_]+)\s+(\d+)u", text))
+    assert flags["GRF_MESH_ROUND"] == grf.MESH["round"] and flags["GRF_MESH_CEIL"] == grf.MESH["ceil"]
+    assert flags["GRF_MASS_CONSISTENT_SYS"] == grf.MASS["consistent"]
+    assert flags["GRF_NOISE_CONSISTENT"] == grf.NOISE["consistent"]
+
+
 def test_opts_defaults():
     o = grf.Opts()
     grf.load().grf_opts_init(C.byref(o))
