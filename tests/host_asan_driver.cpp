@@ -93,6 +93,9 @@ int main() {
         c.name = "ragged-ceil-consistent";
         c.flags = GRF_MESH_CEIL | GRF_MASS_CONSISTENT_SYS;
         cases.push_back(c);
+        c.name = "ragged-consistent-noise";
+        c.flags = GRF_MESH_ROUND | GRF_MASS_CONSISTENT_SYS | GRF_NOISE_CONSISTENT;
+        cases.push_back(c);
     }
     cases.push_back(lattice("lattice-30", 30, 0.05, 1));
     {  // a hub of degree 3000 (overflow pieces), on-chip size class
